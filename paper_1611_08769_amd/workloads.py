@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs for the encrypted FFT.
+
+This module only draws signals: it holds none of the transform's or the
+scheme's arithmetic, and both the library's callers and the tests' oracle
+consume what it returns (real-valued float64 signals; each side quantises
+them with its own code).
+
+The paper's experiments use random complex signals with values in [0, 1]
+(section "Experimental Results", 8 to 128 points) and ten 16x16 images that
+are not published.  The generators below produce signals of the same shapes;
+images are uniform 8-bit pixels scaled to [0, 1).
+
+Uniforms come from SplitMix64 (Steele, Lea and Flood 2014) in counter mode,
+domain 5: u_i = (word(seed, 5, i) >> 11) * 2^-53.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+_GAMMA = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def _mix(z: int) -> int:
+    z &= _M64
+    z ^= z >> 30
+    z = (z * 0xBF58476D1CE4E5B9) & _M64
+    z ^= z >> 27
+    z = (z * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+class Uniforms:
+    """Stream of float64 uniforms in [0, 1) from domain 5 of a seed."""
+
+    def __init__(self, seed: int):
+        self.base = _mix((seed + 5 * _GAMMA) & _M64)
+        self.i = 0
+
+    def next(self, n: int) -> np.ndarray:
+        out = np.empty(n, dtype=np.float64)
+        for j in range(n):
+            w = _mix((self.base + (self.i + 1) * _GAMMA) & _M64)
+            self.i += 1
+            out[j] = (w >> 11) * (2.0 ** -53)
+        return out
+
+
+@dataclass
+class Signal:
+    """One transform request: dims 1 (length points) or 2 (length x length
+    image), F-bit words with f fractional bits."""
+    dims: int
+    length: int
+    F: int
+    f: int
+    re: np.ndarray            # float64, shape (length,) or (length, length)
+    im: np.ndarray | None     # None for real input
+
+    @property
+    def is_complex(self) -> bool:
+        return self.im is not None
+
+    @property
+    def points(self) -> int:
+        return self.length if self.dims == 1 else self.length * self.length
+
+
+def uniform_pm1(seed: int, n: int, F: int, f: int, complex_: bool, length=None, stream=None):
+    """Uniform in [-1, 1) (real, or independent real/imaginary parts)."""
+    u = stream or Uniforms(seed)
+    re = 2.0 * u.next(n) - 1.0
+    im = (2.0 * u.next(n) - 1.0) if complex_ else None
+    return Signal(1, length or n, F, f, re, im)
+
+
+def gaussian_clipped(seed: int, n: int, F: int, f: int, sigma: float = 0.25):
+    """Complex signal, real and imaginary parts N(0, sigma^2) by Box-Muller
+    from consecutive uniform pairs, clipped to [-1, 1 - 2^-f]."""
+    u = Uniforms(seed)
+    vals = np.empty(2 * n)
+    for i in range(n):
+        u1, u2 = u.next(2)
+        r = math.sqrt(-2.0 * math.log(1.0 - u1))
+        vals[2 * i] = sigma * r * math.cos(2.0 * math.pi * u2)
+        vals[2 * i + 1] = sigma * r * math.sin(2.0 * math.pi * u2)
+    vals = np.clip(vals, -1.0, 1.0 - 2.0 ** -f)
+    return Signal(1, n, F, f, vals[0::2].copy(), vals[1::2].copy())
+
+
+def image(seed: int, side: int, F: int, f: int, stream=None):
+    """Real image of uniform integer pixels 0..255 scaled by 1/256."""
+    u = stream or Uniforms(seed)
+    pix = np.floor(256.0 * u.next(side * side))
+    return Signal(2, side, F, f, (pix / 256.0).reshape(side, side), None)
+
+
+# ---------------------------------------------------------------------------
+# the named workloads
+# ---------------------------------------------------------------------------
+WORKLOADS = {
+    "fft1d_n8_real_q8.4": "1D N=8 real, U[-1,1), Q(8,4), n_lwe=1",
+    "fft1d_n64_cplx_q16.8": "1D N=64 complex, N(0,0.25^2) clipped, Q(16,8), n_lwe=3",
+    "fft2d_16x16_real_q16.8": "2D 16x16 image, pixels 0..255 / 256, Q(16,8), n_lwe=1",
+}
+
+
+def workload(name: str):
+    """(Signal, n_lwe, seed) of a named single-request workload."""
+    if name == "fft1d_n8_real_q8.4":
+        return uniform_pm1(1, 8, 8, 4, False), 1, 1
+    if name == "fft1d_n64_cplx_q16.8":
+        return gaussian_clipped(2, 64, 16, 8), 3, 2
+    if name == "fft2d_16x16_real_q16.8":
+        return image(3, 16, 16, 8), 1, 3
+    raise KeyError(name)
+
+
+def batch_requests(seed: int = 4, count: int = 256):
+    """Independent 1D requests: length uniform in {8..128}, F uniform in
+    {12, 16, 24} with f = F/2, complex inputs uniform in [-1, 1)."""
+    u = Uniforms(seed)
+    reqs = []
+    for _ in range(count):
+        a, b = u.next(2)
+        n = (8, 16, 32, 64, 128)[min(int(a * 5), 4)]
+        F = (12, 16, 24)[min(int(b * 3), 2)]
+        reqs.append(uniform_pm1(seed, n, F, F // 2, True, stream=u))
+    return reqs
