@@ -1,0 +1,143 @@
+/*
+ * libsfft -- encrypted fixed-point FFT over GSW13 (q = 2^k) on gfx950.
+ *
+ * The calls follow the paper's client/server workflow (Shortell and
+ * Shokoufandeh, "Secure Fast Fourier Transform using Fully Homomorphic
+ * Encryption", section "Introduction" and its cloud-computing figure): the
+ * client generates keys (step 1) and encrypts its signal bit by bit (step 2);
+ * the server evaluates the FFT on the ciphertexts (step 4); the client
+ * decrypts (step 6).  Steps 3 and 5 (transport) are the caller's business.
+ *
+ * Scheme (section "Notation and Background"): Gentry-Sahai-Waters 2013 over
+ * LWE, q = 2^k, ell = k bits per element, ciphertext dimension
+ * Nct = (n+1)k, m = Nct, errors in {-1,0,1}.  A ciphertext is stored packed:
+ * Nct rows, each n+1 elements of k/32 little-endian uint32 limbs
+ * (Nct*Nct/8 bytes); its bits are the flattened binary ciphertext.
+ * THE SIZES USED HERE ARE NOT SECURE: k is sized for correctness (noise)
+ * only and the LWE dimension is tiny.
+ *
+ * Conventions for every call:
+ *  - return value 0 (SFFT_OK) or a negative status; nothing is thrown across
+ *    the ABI; sfft_last_error() gives a thread-local message for the last
+ *    failure;
+ *  - the caller owns every buffer it passes (host or device); the library
+ *    never frees or retains caller memory; plans own only their own
+ *    immutable tables;
+ *  - `hip_stream` is a hipStream_t (NULL = the null stream); device calls are
+ *    asynchronous on it unless stated; device faults surface as SFFT_EDEVICE
+ *    from a later call or synchronisation.
+ */
+#ifndef SFFT_H
+#define SFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFFT_OK 0
+#define SFFT_EINVAL (-1)        /* bad argument or shape */
+#define SFFT_ENOMEM (-2)        /* host or device allocation failed */
+#define SFFT_EDEVICE (-3)       /* HIP runtime error */
+#define SFFT_ENOISE (-4)        /* k too small for the circuit's noise bound */
+#define SFFT_EBUSY (-5)         /* server full (see sfft_server_submit) */
+#define SFFT_EUNSUPPORTED (-6)  /* valid but not implemented (e.g. eta != 1) */
+
+/* Scheme parameters: q = 2^k (k a positive multiple of 32), LWE dimension
+ * n_lwe >= 1, m = (n_lwe+1)*k samples, eta = 1 (errors in {-1,0,1}). */
+typedef struct {
+    int32_t n_lwe, k, m, eta;
+} sfft_params;
+
+/* Transform shape: dims 1 (len points) or 2 (len x len image, rows then
+ * columns); len a power of two in [2, 4096]; F-bit two's-complement words
+ * with f fractional bits (1 <= F <= 32, 0 <= f <= F); is_complex 0 for real
+ * input (imaginary parts are plaintext zero and not encrypted). */
+typedef struct {
+    int32_t dims, len, F, f, is_complex;
+} sfft_shape;
+
+typedef struct sfft_plan sfft_plan;
+
+/* Statistics of a compiled plan. */
+typedef struct {
+    int64_t nodes;          /* gates of the canonical netlist incl. inputs and NOTs */
+    int64_t gates;          /* AND + XOR + OR + XADD of the canonical netlist */
+    int64_t products;       /* distinct ciphertext products of the canonical netlist */
+    int64_t exec_products;  /* product items the plan executes (after sharing) */
+    int64_t levels;         /* product depth (launches) */
+    int64_t max_level_products;
+    int64_t n_inputs, n_outputs;  /* ciphertexts */
+    int64_t ws_cts;               /* workspace ciphertext slots */
+    int32_t k_required;           /* least multiple of 32 meeting the noise rule */
+    char netlist_sha256[65];      /* hex SHA-256 of the canonical netlist */
+} sfft_plan_info;
+
+const char* sfft_last_error(void);
+
+/* Least k (multiple of 32) for which every output's worst-case noise of the
+ * shape's canonical circuit stays below q/8 at n_lwe (Lemmas "encryption",
+ * "decryption", "evaluation": decryption is correct while noise < q/4).
+ * Fills out->{n_lwe, k, m = (n_lwe+1)k, eta = 1}. */
+int sfft_size_params(const sfft_shape* shape, int32_t n_lwe, sfft_params* out);
+
+/* Bytes of one ciphertext: Nct*Nct/8.  Negative status on bad params. */
+int64_t sfft_ct_bytes(const sfft_params* params);
+
+/* Key generation (workflow step 1).  pk_host: m x (n+1) elements, k/32 limbs
+ * each (sfft_ct_bytes bytes) = A = [B t + e | B]; sk_host: (n+1) elements of
+ * k/32 limbs = s = (1, -t).  Deterministic in seed (SplitMix64 domains 1-3). */
+int sfft_keygen(const sfft_params* params, uint64_t seed, uint32_t* pk_host, uint32_t* sk_host);
+
+/* Encryption (workflow step 2, Lemma "encryption"): each of n_values F-bit
+ * words (fixed_host, low F bits used) becomes F ciphertexts, LSB first:
+ * ciphertext i = value i/F, bit i%F; C' = mu G + R A with R drawn from
+ * SplitMix64 domain 4 at ciphertext id first_ct_id + i.  pk_dev: the public
+ * key in device memory; ct_dev: n_values*F ciphertexts (device). */
+int sfft_encrypt(const sfft_params* params, const uint32_t* pk_dev, const int32_t* fixed_host, int64_t n_values,
+                 int32_t F, uint64_t seed, uint64_t first_ct_id, uint32_t* ct_dev, void* hip_stream);
+
+/* Compile the FFT circuit for a shape (Theorem 1 / Lemma "evaluation": bit
+ * reversal, then log2 N butterfly stages of additions, subtractions and
+ * constant multiplications), levelise it and upload its work tables.  Fails
+ * with SFFT_ENOISE if params->k is below the circuit's requirement. */
+int sfft_plan_create(const sfft_shape* shape, const sfft_params* params, sfft_plan** out);
+int sfft_plan_info_get(const sfft_plan* plan, sfft_plan_info* info);
+/* Host-only compilation of the same circuit: fills `info` without touching
+ * any device (no allocation, no HIP call).  Same errors as plan creation. */
+int sfft_analyze(const sfft_shape* shape, const sfft_params* params, sfft_plan_info* info);
+/* Device workspace the caller must pass to sfft_execute. */
+int sfft_plan_workspace_bytes(const sfft_plan* plan, int64_t* bytes);
+void sfft_plan_destroy(sfft_plan* plan);
+
+/* Encrypted FFT (workflow step 4).  ct_in_dev: the shape's input ciphertexts,
+ * id (v*C + comp)*F + bit (v = point, row-major for images; C = 2 complex or
+ * 1 real; comp 0 = Re, 1 = Im); ct_out_dev: len (1D) or len*len (2D) complex
+ * outputs in natural order, id (v*2 + comp)*F + bit.  ws_dev: at least
+ * sfft_plan_workspace_bytes.  Enqueues only. */
+int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                 int64_t ws_bytes, void* hip_stream);
+
+/* Decryption (workflow step 6, Lemma "decryption"): n_values words of F
+ * ciphertexts each (LSB first) -> signed values sign-extended from F bits.
+ * ct: host or device (ct_on_device = 1; reads row k-1 of each ciphertext and
+ * synchronises the null stream). */
+int sfft_decrypt(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct, int64_t n_values,
+                 int32_t F, int ct_on_device, int32_t* fixed_out);
+/* Decryption of n_ct single bits. */
+int sfft_decrypt_bits(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct, int64_t n_ct,
+                      int ct_on_device, int32_t* bits_out);
+
+/* Single gates on device ciphertexts (section "Notation and Background":
+ * addition, multiplication and NAND of ciphertexts; Lemma "binary gates"):
+ * gate = 3 NOT (y ignored), 4 AND, 5 XOR, 6 OR, 7 XADD (addition; the result
+ * encrypts x+y, a bit only if x,y are never both 1), 8 NAND, 9 PRODUCT
+ * (= AND).  x, y, out: one ciphertext each, device; out must not alias. */
+int sfft_gate(const sfft_params* params, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev,
+              uint32_t* out_dev, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFFT_H */

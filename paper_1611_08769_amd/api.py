@@ -1,0 +1,139 @@
+"""Python front end: keys, encryption, plans and decryption over libsfft with
+device memory owned by torch tensors.  Argument marshalling only -- every
+ciphertext operation runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import sfft as S
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def quantize(x, F: int, f: int) -> np.ndarray:
+    """Real -> Q(F, f) by truncation (floor(x * 2^f)); must fit F bits."""
+    q = np.floor(np.asarray(x, dtype=np.float64) * float(1 << f)).astype(np.int64)
+    if np.any(q < -(1 << (F - 1))) or np.any(q >= (1 << (F - 1))):
+        raise ValueError("value does not fit Q(%d,%d)" % (F, f))
+    return q
+
+
+@dataclass
+class Keys:
+    params: S.sfft_params
+    pk_host: np.ndarray      # uint32, ct_words
+    sk_host: np.ndarray      # uint32, (n+1)*k/32
+    pk_dev: torch.Tensor     # int32 view of the same words, on the GPU
+
+    @property
+    def ct_words(self) -> int:
+        return S.sfft_ct_bytes(self.params) // 4
+
+
+def keygen(params: S.sfft_params, seed: int, device="cuda") -> Keys:
+    cw = S.sfft_ct_bytes(params) // 4
+    pk = np.zeros(cw, dtype=np.uint32)
+    sk = np.zeros((params.n_lwe + 1) * params.k // 32, dtype=np.uint32)
+    S.sfft_keygen(params, seed, pk.ctypes.data, sk.ctypes.data)
+    pk_dev = torch.from_numpy(pk.view(np.int32)).to(device)
+    return Keys(params, pk, sk, pk_dev)
+
+
+def alloc_cts(keys_or_params, n: int, device="cuda") -> torch.Tensor:
+    p = keys_or_params.params if isinstance(keys_or_params, Keys) else keys_or_params
+    cw = S.sfft_ct_bytes(p) // 4
+    return torch.empty((n, cw), dtype=torch.int32, device=device)
+
+
+def encrypt_words(keys: Keys, words, F: int, seed: int, first_ct_id: int = 0, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """F ciphertexts per word (LSB first) on the GPU."""
+    w = np.ascontiguousarray(np.asarray(words, dtype=np.int64).astype(np.int32).ravel())
+    n_ct = w.size * F
+    if out is None:
+        out = alloc_cts(keys, n_ct)
+    assert out.shape[0] >= n_ct and out.is_contiguous()
+    S.sfft_encrypt(keys.params, keys.pk_dev.data_ptr(), w.ctypes.data, w.size, F, seed, first_ct_id,
+                   out.data_ptr(), _stream_ptr(stream))
+    return out
+
+
+def decrypt_words(keys: Keys, cts: torch.Tensor, n_values: int, F: int) -> np.ndarray:
+    torch.cuda.synchronize()
+    out = np.zeros(n_values, dtype=np.int32)
+    S.sfft_decrypt(keys.params, keys.sk_host.ctypes.data, cts.data_ptr(), n_values, F, 1, out.ctypes.data)
+    return out.astype(np.int64)
+
+
+def decrypt_bits(keys: Keys, cts: torch.Tensor) -> np.ndarray:
+    torch.cuda.synchronize()
+    n = cts.shape[0]
+    out = np.zeros(n, dtype=np.int32)
+    S.sfft_decrypt_bits(keys.params, keys.sk_host.ctypes.data, cts.data_ptr(), n, 1, out.ctypes.data)
+    return out
+
+
+def gate(keys_or_params, g: int, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    p = keys_or_params.params if isinstance(keys_or_params, Keys) else keys_or_params
+    out = torch.empty_like(x)
+    S.sfft_gate(p, g, x.data_ptr(), (y if y is not None else x).data_ptr(), out.data_ptr(), _stream_ptr(stream))
+    return out
+
+
+class Plan:
+    """A compiled encrypted FFT for one shape and parameter set."""
+
+    def __init__(self, dims: int, length: int, F: int, f: int, is_complex: bool, params: S.sfft_params):
+        self.shape = S.shape(dims, length, F, f, is_complex)
+        self.params = params
+        self.handle = S.sfft_plan_create(self.shape, params)
+        self.info = S.sfft_plan_info_get(self.handle)
+        self.ws_bytes = S.sfft_plan_workspace_bytes(self.handle)
+        self.ct_words = S.sfft_ct_bytes(params) // 4
+        self._ws = None
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            self._ws = torch.empty(max(1, self.ws_bytes // 4), dtype=torch.int32, device="cuda")
+        return self._ws
+
+    def execute(self, ct_in: torch.Tensor, ct_out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if ct_out is None:
+            ct_out = torch.empty((self.info.n_outputs, self.ct_words), dtype=torch.int32, device="cuda")
+        assert ct_in.shape[0] >= self.info.n_inputs and ct_out.shape[0] >= self.info.n_outputs
+        ws = self.workspace()
+        S.sfft_execute(self.handle, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(), ws.numel() * 4,
+                       _stream_ptr(stream))
+        return ct_out
+
+    def close(self):
+        if self.handle:
+            S.sfft_plan_destroy(self.handle)
+            self.handle = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def size_params(dims, length, F, f, is_complex, n_lwe) -> S.sfft_params:
+    return S.sfft_size_params(S.shape(dims, length, F, f, is_complex), n_lwe)
+
+
+def signal_words(sig) -> np.ndarray:
+    """Quantised input words in ciphertext order: point-major, Re then Im."""
+    re = quantize(np.asarray(sig.re).ravel(), sig.F, sig.f)
+    if sig.im is None:
+        return re
+    im = quantize(np.asarray(sig.im).ravel(), sig.F, sig.f)
+    return np.stack([re, im], 1).ravel()

@@ -1,0 +1,493 @@
+// C ABI of libsfft: keys, encryption, plans, execution, decryption, gates.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sfft.h"
+#include "device.hpp"
+#include "netlist.hpp"
+#include "schedule.hpp"
+
+using namespace sfft;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    return fail(SFFT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool params_ok(const sfft_params* p, std::string* why)
+{
+    if (!p) { *why = "null params"; return false; }
+    if (p->n_lwe < 1 || p->n_lwe > 64) { *why = "n_lwe must be in [1, 64]"; return false; }
+    if (p->k <= 0 || p->k % 32 || p->k > 8192) { *why = "k must be a multiple of 32 in [32, 8192]"; return false; }
+    if (p->m != (p->n_lwe + 1) * p->k) { *why = "m must equal (n_lwe+1)*k"; return false; }
+    return true;
+}
+
+Geo geo_of(const sfft_params* p)
+{
+    Geo g;
+    g.k = p->k;
+    g.kw = p->k / 32;
+    g.n1 = p->n_lwe + 1;
+    g.nct = g.n1 * p->k;
+    g.W = g.n1 * g.kw;
+    return g;
+}
+
+int64_t ct_words(const Geo& g) { return (int64_t)g.nct * g.W; }
+
+bool shape_ok(const sfft_shape* s, std::string* why)
+{
+    if (!s) { *why = "null shape"; return false; }
+    if (s->dims != 1 && s->dims != 2) { *why = "dims must be 1 or 2"; return false; }
+    if (s->len < 2 || s->len > 4096 || (s->len & (s->len - 1))) { *why = "len must be a power of two in [2, 4096]"; return false; }
+    if (s->F < 1 || s->F > 32 || s->f < 0 || s->f > s->F) { *why = "need 1 <= F <= 32 and 0 <= f <= F"; return false; }
+    if (s->is_complex != 0 && s->is_complex != 1) { *why = "is_complex must be 0 or 1"; return false; }
+    return true;
+}
+
+Shape to_shape(const sfft_shape* s) { return Shape{s->dims, s->len, s->F, s->f, s->is_complex != 0}; }
+
+// ---- host SplitMix64 (domains: 1 t, 2 B, 3 e, 4 encryption masks) ----------
+uint64_t mix64(uint64_t z)
+{
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+uint64_t word64(uint64_t seed, uint64_t dom, uint64_t i) { return mix64(mix64(seed + dom * kGamma) + (i + 1) * kGamma); }
+
+// uniform element of Z_{2^k}: ceil(k/64) words, little-endian, top word masked
+void zq_element(uint64_t seed, uint64_t dom, uint64_t e, int k, uint32_t* out)
+{
+    const int L = (k + 63) / 64, kw = k / 32;
+    for (int w = 0; w < L; w++) {
+        uint64_t v = word64(seed, dom, e * (uint64_t)L + (uint64_t)w);
+        const int bits = (w == L - 1) ? k - 64 * (L - 1) : 64;
+        if (bits < 64) v &= (1ull << bits) - 1;
+        if (2 * w < kw) out[2 * w] = (uint32_t)v;
+        if (2 * w + 1 < kw) out[2 * w + 1] = (uint32_t)(v >> 32);
+    }
+}
+
+int ternary(uint64_t seed, uint64_t j)
+{
+    const uint64_t wd = word64(seed, 3, (2 * j) / 64);
+    const int s = (int)((2 * j) % 64);
+    return (int)((wd >> s) & 1) - (int)((wd >> (s + 1)) & 1);
+}
+
+// r = a * b mod 2^(32 kw)
+void mul_mod(const uint32_t* a, const uint32_t* b, int kw, uint32_t* r)
+{
+    std::vector<uint32_t> t(kw, 0);
+    for (int i = 0; i < kw; i++) {
+        uint64_t carry = 0;
+        for (int j = 0; i + j < kw; j++) {
+            const uint64_t v = (uint64_t)t[i + j] + (uint64_t)a[i] * b[j] + carry;
+            t[i + j] = (uint32_t)v;
+            carry = v >> 32;
+        }
+    }
+    std::memcpy(r, t.data(), sizeof(uint32_t) * kw);
+}
+
+// r += a mod 2^(32 kw)
+void add_mod(uint32_t* r, const uint32_t* a, int kw)
+{
+    uint64_t carry = 0;
+    for (int i = 0; i < kw; i++) {
+        const uint64_t v = (uint64_t)r[i] + a[i] + carry;
+        r[i] = (uint32_t)v;
+        carry = v >> 32;
+    }
+}
+
+// r = -a mod 2^(32 kw)
+void neg_mod(const uint32_t* a, int kw, uint32_t* r)
+{
+    uint64_t carry = 1;
+    for (int i = 0; i < kw; i++) {
+        const uint64_t v = (uint64_t)(~a[i]) + carry;
+        r[i] = (uint32_t)v;
+        carry = v >> 32;
+    }
+}
+
+// decrypted bit of one ciphertext's row k-1 (n1 elements of kw limbs)
+int decrypt_row(const uint32_t* row, const uint32_t* sk, int n1, int kw, int k)
+{
+    std::vector<uint32_t> x(kw, 0), t(kw);
+    for (int b = 0; b < n1; b++) {
+        mul_mod(row + b * kw, sk + b * kw, kw, t.data());
+        add_mod(x.data(), t.data(), kw);
+    }
+    // add q/4 = 2^(k-2) and take bit k-1
+    std::vector<uint32_t> quarter(kw, 0);
+    quarter[(k - 2) / 32] = 1u << ((k - 2) % 32);
+    add_mod(x.data(), quarter.data(), kw);
+    return (int)((x[(k - 1) / 32] >> ((k - 1) % 32)) & 1u);
+}
+
+}  // namespace
+
+struct sfft_plan {
+    sfft_shape shape;
+    sfft_params params;
+    Geo geo;
+    ProdCfg cfg;
+    Schedule sched;
+    ProdItem* d_prods = nullptr;
+    LinItem* d_lins = nullptr;
+    LinItem* d_final = nullptr;
+    sfft_plan_info info;
+};
+
+extern "C" {
+
+const char* sfft_last_error(void) { return g_err.c_str(); }
+
+int sfft_size_params(const sfft_shape* shape, int32_t n_lwe, sfft_params* out)
+{
+    std::string why;
+    if (!shape_ok(shape, &why)) return fail(SFFT_EINVAL, why);
+    if (!out || n_lwe < 1 || n_lwe > 64) return fail(SFFT_EINVAL, "n_lwe must be in [1, 64]");
+    try {
+        const Compact c = compact(build_fft_netlist(to_shape(shape)));
+        const int k = choose_k(c, n_lwe);
+        if (k < 0) return fail(SFFT_ENOISE, "no k <= 8192 satisfies the noise rule");
+        out->n_lwe = n_lwe;
+        out->k = k;
+        out->m = (n_lwe + 1) * k;
+        out->eta = 1;
+        return SFFT_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SFFT_ENOMEM, "out of host memory building the netlist");
+    } catch (const std::exception& e) {
+        return fail(SFFT_EINVAL, e.what());
+    }
+}
+
+int64_t sfft_ct_bytes(const sfft_params* params)
+{
+    std::string why;
+    if (!params_ok(params, &why)) return fail(SFFT_EINVAL, why);
+    const int64_t nct = (int64_t)(params->n_lwe + 1) * params->k;
+    return nct * nct / 8;
+}
+
+int sfft_keygen(const sfft_params* p, uint64_t seed, uint32_t* pk_host, uint32_t* sk_host)
+{
+    std::string why;
+    if (!params_ok(p, &why)) return fail(SFFT_EINVAL, why);
+    if (p->eta != 1) return fail(SFFT_EUNSUPPORTED, "only eta = 1 is implemented");
+    if (!pk_host || !sk_host) return fail(SFFT_EINVAL, "null key buffer");
+    const Geo g = geo_of(p);
+    const int n = p->n_lwe, kw = g.kw, k = p->k, m = p->m;
+    std::vector<uint32_t> t((size_t)n * kw);
+    for (int i = 0; i < n; i++) zq_element(seed, 1, (uint64_t)i, k, &t[(size_t)i * kw]);
+    // s = (1, -t)
+    std::memset(sk_host, 0, sizeof(uint32_t) * (size_t)g.n1 * kw);
+    sk_host[0] = 1;
+    for (int i = 0; i < n; i++) neg_mod(&t[(size_t)i * kw], kw, sk_host + (size_t)(i + 1) * kw);
+    // A = [B t + e | B], row-major m x (n+1)
+    std::vector<uint32_t> prod(kw), minus1(kw, 0xFFFFFFFFu), one(kw, 0);
+    one[0] = 1;
+    for (int j = 0; j < m; j++) {
+        uint32_t* row = pk_host + (size_t)j * g.n1 * kw;
+        std::memset(row, 0, sizeof(uint32_t) * kw);
+        for (int i = 0; i < n; i++) {
+            uint32_t* Bji = row + (size_t)(i + 1) * kw;
+            zq_element(seed, 2, (uint64_t)j * n + i, k, Bji);
+            mul_mod(Bji, &t[(size_t)i * kw], kw, prod.data());
+            add_mod(row, prod.data(), kw);
+        }
+        const int e = ternary(seed, (uint64_t)j);
+        if (e == 1) add_mod(row, one.data(), kw);
+        if (e == -1) add_mod(row, minus1.data(), kw);
+    }
+    return SFFT_OK;
+}
+
+int sfft_encrypt(const sfft_params* p, const uint32_t* pk_dev, const int32_t* fixed_host, int64_t n_values,
+                 int32_t F, uint64_t seed, uint64_t first_ct_id, uint32_t* ct_dev, void* hip_stream)
+{
+    std::string why;
+    if (!params_ok(p, &why)) return fail(SFFT_EINVAL, why);
+    if (p->eta != 1) return fail(SFFT_EUNSUPPORTED, "only eta = 1 is implemented");
+    if (F < 1 || F > 32 || n_values < 0) return fail(SFFT_EINVAL, "bad F or n_values");
+    if (n_values > 0 && (!pk_dev || !fixed_host || !ct_dev)) return fail(SFFT_EINVAL, "null buffer");
+    const Geo g = geo_of(p);
+    ProdCfg cfg;
+    if (!product_config(g, &cfg)) return fail(SFFT_EUNSUPPORTED, "no kernel configuration for this geometry");
+    const int64_t n_ct = n_values * F;
+    std::vector<uint32_t> bits(kMaxEncPerLaunch / 32);
+    Bufs b{nullptr, nullptr, nullptr, const_cast<uint32_t*>(pk_dev), ct_words(g)};
+    for (int64_t c0 = 0; c0 < n_ct; c0 += kMaxEncPerLaunch) {
+        const int64_t cnt = std::min<int64_t>(kMaxEncPerLaunch, n_ct - c0);
+        std::fill(bits.begin(), bits.end(), 0u);
+        for (int64_t i = 0; i < cnt; i++) {
+            const int64_t c = c0 + i;
+            const uint32_t u = (uint32_t)fixed_host[c / F];
+            if ((u >> (c % F)) & 1u) bits[i / 32] |= 1u << (i % 32);
+        }
+        b.out = ct_dev + c0 * ct_words(g);
+        hipError_t e = launch_encrypt(b, g, cfg, bits.data(), (int)cnt, seed, first_ct_id + (uint64_t)c0,
+                                      (hipStream_t)hip_stream);
+        if (e != hipSuccess) return hip_fail(e, "encrypt launch");
+    }
+    return SFFT_OK;
+}
+
+namespace {
+// Compile the circuit of a shape for params: netlist, noise check, sharing,
+// lowering.  Host only.
+int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* sched, sfft_plan_info* info)
+{
+    std::string why;
+    if (!shape_ok(shape, &why)) return fail(SFFT_EINVAL, why);
+    if (!params_ok(params, &why)) return fail(SFFT_EINVAL, why);
+    if (params->eta != 1) return fail(SFFT_EUNSUPPORTED, "only eta = 1 is implemented");
+    try {
+        const Geo geo = geo_of(params);
+        const Compact c = compact(build_fft_netlist(to_shape(shape)));
+        const int need = noise_bits(c, (int64_t)geo.nct);
+        if (need > params->k)
+            return fail(SFFT_ENOISE, "k = " + std::to_string(params->k) +
+                                         " is below the circuit's noise bound (needs " + std::to_string(need) +
+                                         " bits at this Nct)");
+        const NetStats st = netlist_stats(c);
+        *sched = lower(share(c));
+        sfft_plan_info& in = *info;
+        std::memset(&in, 0, sizeof(in));
+        in.nodes = st.nodes;
+        in.gates = st.gates;
+        in.products = st.products;
+        in.exec_products = sched->n_products;
+        in.levels = (int64_t)sched->levels.size() - 1;
+        in.max_level_products = sched->max_level_products;
+        in.n_inputs = c.n_inputs;
+        in.n_outputs = (int64_t)c.outputs.size();
+        in.ws_cts = sched->n_slots;
+        in.k_required = choose_k(c, params->n_lwe);
+        const std::string h = netlist_hash(c);
+        std::memcpy(in.netlist_sha256, h.c_str(), 64);
+        in.netlist_sha256[64] = 0;
+        return SFFT_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SFFT_ENOMEM, "out of host memory compiling the plan");
+    } catch (const std::exception& e) {
+        return fail(SFFT_EINVAL, e.what());
+    }
+}
+}  // namespace
+
+int sfft_analyze(const sfft_shape* shape, const sfft_params* params, sfft_plan_info* info)
+{
+    if (!info) return fail(SFFT_EINVAL, "null info");
+    Schedule sched;
+    return compile_plan(shape, params, &sched, info);
+}
+
+int sfft_plan_create(const sfft_shape* shape, const sfft_params* params, sfft_plan** out)
+{
+    if (!out) return fail(SFFT_EINVAL, "null plan pointer");
+    *out = nullptr;
+    sfft_plan* pl = new (std::nothrow) sfft_plan();
+    if (!pl) return fail(SFFT_ENOMEM, "out of host memory");
+    int rc = compile_plan(shape, params, &pl->sched, &pl->info);
+    if (rc != SFFT_OK) {
+        delete pl;
+        return rc;
+    }
+    pl->shape = *shape;
+    pl->params = *params;
+    pl->geo = geo_of(params);
+    if (!product_config(pl->geo, &pl->cfg)) {
+        delete pl;
+        return fail(SFFT_EUNSUPPORTED, "no kernel configuration for this geometry");
+    }
+    auto upload = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
+        *dst = nullptr;
+        if (!bytes) return hipSuccess;
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = upload(pl->sched.prods.data(), pl->sched.prods.size() * sizeof(ProdItem), (void**)&pl->d_prods);
+    if (e == hipSuccess) e = upload(pl->sched.lins.data(), pl->sched.lins.size() * sizeof(LinItem), (void**)&pl->d_lins);
+    if (e == hipSuccess)
+        e = upload(pl->sched.final_lins.data(), pl->sched.final_lins.size() * sizeof(LinItem), (void**)&pl->d_final);
+    if (e != hipSuccess) {
+        sfft_plan_destroy(pl);
+        return hip_fail(e, "plan upload");
+    }
+    *out = pl;
+    return SFFT_OK;
+}
+
+int sfft_plan_info_get(const sfft_plan* plan, sfft_plan_info* info)
+{
+    if (!plan || !info) return fail(SFFT_EINVAL, "null argument");
+    *info = plan->info;
+    return SFFT_OK;
+}
+
+int sfft_plan_workspace_bytes(const sfft_plan* plan, int64_t* bytes)
+{
+    if (!plan || !bytes) return fail(SFFT_EINVAL, "null argument");
+    *bytes = plan->sched.n_slots * ct_words(plan->geo) * 4;
+    return SFFT_OK;
+}
+
+void sfft_plan_destroy(sfft_plan* plan)
+{
+    if (!plan) return;
+    if (plan->d_prods) (void)hipFree(plan->d_prods);
+    if (plan->d_lins) (void)hipFree(plan->d_lins);
+    if (plan->d_final) (void)hipFree(plan->d_final);
+    delete plan;
+}
+
+int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                 int64_t ws_bytes, void* hip_stream)
+{
+    if (!plan) return fail(SFFT_EINVAL, "null plan");
+    int64_t need = 0;
+    sfft_plan_workspace_bytes(plan, &need);
+    if (ws_bytes < need) return fail(SFFT_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (!ct_out_dev || (plan->info.n_inputs > 0 && !ct_in_dev) || (need > 0 && !ws_dev))
+        return fail(SFFT_EINVAL, "null buffer");
+    const Geo& g = plan->geo;
+    Bufs b{const_cast<uint32_t*>(ct_in_dev), ct_out_dev, (uint32_t*)ws_dev, nullptr, ct_words(g)};
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Schedule& S = plan->sched;
+    for (size_t L = 0; L < S.levels.size(); L++) {
+        const LevelWork& lw = S.levels[L];
+        if (lw.prod_count) {
+            hipError_t e = launch_products(b, g, plan->cfg, plan->d_prods + lw.prod_begin, lw.prod_count, s);
+            if (e != hipSuccess) return hip_fail(e, "product launch");
+        }
+        for (const auto& pass : lw.lin) {
+            hipError_t e = launch_linear(b, g, plan->d_lins + pass.first, pass.second, s);
+            if (e != hipSuccess) return hip_fail(e, "linear launch");
+        }
+    }
+    if (!S.final_lins.empty()) {
+        hipError_t e = launch_linear(b, g, plan->d_final, (int64_t)S.final_lins.size(), s);
+        if (e != hipSuccess) return hip_fail(e, "output launch");
+    }
+    return SFFT_OK;
+}
+
+int sfft_decrypt_bits(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_ct,
+                      int ct_on_device, int32_t* bits_out)
+{
+    std::string why;
+    if (!params_ok(p, &why)) return fail(SFFT_EINVAL, why);
+    if (n_ct < 0 || (n_ct > 0 && (!sk_host || !ct || !bits_out))) return fail(SFFT_EINVAL, "bad buffers");
+    const Geo g = geo_of(p);
+    const int64_t cw = ct_words(g);
+    const size_t row_off = (size_t)(p->k - 1) * g.W;
+    std::vector<uint32_t> rows;
+    const uint32_t* src = ct;
+    int64_t stride = cw;
+    if (ct_on_device && n_ct > 0) {
+        rows.resize((size_t)n_ct * g.W);
+        hipError_t e = hipMemcpy2D(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
+                                   sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "decrypt copy");
+        src = rows.data();
+        stride = g.W;
+    } else {
+        src = ct + row_off;
+    }
+    for (int64_t i = 0; i < n_ct; i++) bits_out[i] = decrypt_row(src + i * stride, sk_host, g.n1, g.kw, p->k);
+    return SFFT_OK;
+}
+
+int sfft_decrypt(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_values, int32_t F,
+                 int ct_on_device, int32_t* fixed_out)
+{
+    if (F < 1 || F > 32 || n_values < 0) return fail(SFFT_EINVAL, "bad F or n_values");
+    if (n_values > 0 && !fixed_out) return fail(SFFT_EINVAL, "null output");
+    std::vector<int32_t> bits((size_t)(n_values * F));
+    const int rc = sfft_decrypt_bits(p, sk_host, ct, n_values * F, ct_on_device, bits.data());
+    if (rc != SFFT_OK) return rc;
+    for (int64_t v = 0; v < n_values; v++) {
+        uint32_t u = 0;
+        for (int i = 0; i < F; i++) u |= (uint32_t)(bits[(size_t)(v * F + i)] & 1) << i;
+        if (F < 32 && (u >> (F - 1)) & 1u) u |= ~0u << F;  // sign-extend
+        fixed_out[v] = (int32_t)u;
+    }
+    return SFFT_OK;
+}
+
+int sfft_gate(const sfft_params* p, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev, uint32_t* out_dev,
+              void* hip_stream)
+{
+    std::string why;
+    if (!params_ok(p, &why)) return fail(SFFT_EINVAL, why);
+    if (!x_dev || !out_dev || (gate != 3 && !y_dev)) return fail(SFFT_EINVAL, "null buffer");
+    if (gate < 3 || gate > 9) return fail(SFFT_EINVAL, "gate must be 3..9");
+    const Geo g = geo_of(p);
+    Bufs b{const_cast<uint32_t*>(x_dev), out_dev, nullptr, const_cast<uint32_t*>(y_dev), ct_words(g)};
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e;
+    if (gate == 3 || gate == 7) {
+        LinItem li{};
+        li.dst = ct_ref(B_OUT, 0);
+        li.X = ct_ref(B_IN, 0);
+        if (gate == 3) {
+            li.Y = -1;
+            li.cX = -1;
+            li.cG = 1;
+        } else {
+            li.Y = ct_ref(B_AUX, 0);
+            li.cX = 1;
+            li.cY = 1;
+        }
+        e = launch_linear_one(b, g, li, s);
+    } else {
+        ProdCfg cfg;
+        if (!product_config(g, &cfg)) return fail(SFFT_EUNSUPPORTED, "no kernel configuration for this geometry");
+        ProdItem it{};
+        it.L = ct_ref(B_IN, 0);
+        it.R = ct_ref(B_AUX, 0);
+        it.nout = 1;
+        it.dst[0] = ct_ref(B_OUT, 0);
+        it.E[0] = -1;
+        for (int i = 1; i < kMaxOut; i++) it.dst[i] = it.E[i] = -1;
+        switch (gate) {
+        case 4: case 9: it.cP[0] = 1; break;
+        case 5: it.cL[0] = 1; it.cR[0] = 1; it.cP[0] = -2; break;
+        case 6: it.cL[0] = 1; it.cR[0] = 1; it.cP[0] = -1; break;
+        case 8: it.cP[0] = -1; it.cG[0] = 1; break;
+        }
+        e = launch_product_one(b, g, cfg, it, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gate launch");
+    return SFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Host-side declarations of the gfx950 kernels' launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "schedule.hpp"
+
+namespace sfft {
+
+// Device buffers a ciphertext reference can point into.
+struct Bufs {
+    uint32_t* in;
+    uint32_t* out;
+    uint32_t* ws;
+    uint32_t* aux;
+    int64_t ct_words;  // uint32 words per ciphertext = Nct * (n+1) * k/32
+};
+
+// Ciphertext geometry: Nct rows of n1 = n+1 elements of kw = k/32 limbs.
+struct Geo {
+    int32_t nct, n1, kw, W, k;
+};
+
+// Per-launch choice of the product kernel's register tiling.
+struct ProdCfg {
+    int wpl;   // words of a row held per lane
+    int rpl;   // rows per lane
+    int rpw;   // rows per wave
+    int tr;    // rows per workgroup
+    int lds_bytes;
+};
+
+bool product_config(const Geo& g, ProdCfg* cfg);
+
+// One launch over `count` product items read from device memory.
+hipError_t launch_products(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items,
+                           int64_t count, hipStream_t s);
+// One product item passed by value (single gates).
+hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item,
+                              hipStream_t s);
+hipError_t launch_linear(const Bufs& b, const Geo& g, const LinItem* d_items, int64_t count, hipStream_t s);
+hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s);
+
+// Encryption of n_ct bits: out[i] = mu_i G + R_i A with R_i drawn from
+// SplitMix64 domain 4 (ciphertext id first_id + i).  bits: one bit per
+// ciphertext, packed LSB first, at most kMaxEncPerLaunch per call.
+constexpr int kMaxEncPerLaunch = 16384;
+hipError_t launch_encrypt(const Bufs& b, const Geo& g, const ProdCfg& cfg, const uint32_t* bits, int n_ct,
+                          uint64_t seed, uint64_t first_id, hipStream_t s);
+
+}  // namespace sfft

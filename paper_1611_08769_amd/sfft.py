@@ -1,0 +1,159 @@
+"""ctypes binding of libsfft (include/sfft.h): same names, argument
+marshalling only.  Every computation runs in the library; if the library is
+not built this module raises on import."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfft.so")
+
+SFFT_OK = 0
+SFFT_EINVAL = -1
+SFFT_ENOMEM = -2
+SFFT_EDEVICE = -3
+SFFT_ENOISE = -4
+SFFT_EBUSY = -5
+SFFT_EUNSUPPORTED = -6
+
+GATE_NOT, GATE_AND, GATE_XOR, GATE_OR, GATE_XADD, GATE_NAND, GATE_PRODUCT = 3, 4, 5, 6, 7, 8, 9
+
+
+class sfft_params(ctypes.Structure):
+    _fields_ = [("n_lwe", ctypes.c_int32), ("k", ctypes.c_int32), ("m", ctypes.c_int32), ("eta", ctypes.c_int32)]
+
+
+class sfft_shape(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("len", ctypes.c_int32), ("F", ctypes.c_int32), ("f", ctypes.c_int32),
+                ("is_complex", ctypes.c_int32)]
+
+
+class sfft_plan_info(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_int64), ("gates", ctypes.c_int64), ("products", ctypes.c_int64),
+                ("exec_products", ctypes.c_int64), ("levels", ctypes.c_int64),
+                ("max_level_products", ctypes.c_int64), ("n_inputs", ctypes.c_int64),
+                ("n_outputs", ctypes.c_int64), ("ws_cts", ctypes.c_int64), ("k_required", ctypes.c_int32),
+                ("netlist_sha256", ctypes.c_char * 65)]
+
+
+class SfftError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("sfft error %d: %s" % (code, msg))
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libsfft.so is not built (run paper_1611_08769_amd.build.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER
+
+_SIGS = {
+    "sfft_last_error": (ctypes.c_char_p, []),
+    "sfft_size_params": (ctypes.c_int, [_P(sfft_shape), ctypes.c_int32, _P(sfft_params)]),
+    "sfft_ct_bytes": (ctypes.c_int64, [_P(sfft_params)]),
+    "sfft_keygen": (ctypes.c_int, [_P(sfft_params), ctypes.c_uint64, _vp, _vp]),
+    "sfft_encrypt": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                    ctypes.c_uint64, _vp, _vp]),
+    "sfft_plan_create": (ctypes.c_int, [_P(sfft_shape), _P(sfft_params), _P(_vp)]),
+    "sfft_plan_info_get": (ctypes.c_int, [_vp, _P(sfft_plan_info)]),
+    "sfft_analyze": (ctypes.c_int, [_P(sfft_shape), _P(sfft_params), _P(sfft_plan_info)]),
+    "sfft_plan_workspace_bytes": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+    "sfft_plan_destroy": (None, [_vp]),
+    "sfft_execute": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "sfft_decrypt": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, _vp]),
+    "sfft_decrypt_bits": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
+    "sfft_gate": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _vp, _vp, _vp, _vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def last_error() -> str:
+    return _lib.sfft_last_error().decode()
+
+
+def _check(rc):
+    if rc != SFFT_OK:
+        raise SfftError(rc, last_error())
+
+
+def params(n_lwe: int, k: int) -> sfft_params:
+    return sfft_params(n_lwe, k, (n_lwe + 1) * k, 1)
+
+
+def shape(dims: int, length: int, F: int, f: int, is_complex: bool) -> sfft_shape:
+    return sfft_shape(dims, length, F, f, int(bool(is_complex)))
+
+
+def sfft_size_params(shp: sfft_shape, n_lwe: int) -> sfft_params:
+    out = sfft_params()
+    _check(_lib.sfft_size_params(ctypes.byref(shp), n_lwe, ctypes.byref(out)))
+    return out
+
+
+def sfft_ct_bytes(p: sfft_params) -> int:
+    v = _lib.sfft_ct_bytes(ctypes.byref(p))
+    if v < 0:
+        raise SfftError(v, last_error())
+    return v
+
+
+def sfft_keygen(p: sfft_params, seed: int, pk_host_ptr: int, sk_host_ptr: int) -> None:
+    _check(_lib.sfft_keygen(ctypes.byref(p), seed, pk_host_ptr, sk_host_ptr))
+
+
+def sfft_encrypt(p, pk_dev_ptr, fixed_host_ptr, n_values, F, seed, first_ct_id, ct_dev_ptr, stream) -> None:
+    _check(_lib.sfft_encrypt(ctypes.byref(p), pk_dev_ptr, fixed_host_ptr, n_values, F, seed, first_ct_id,
+                             ct_dev_ptr, stream))
+
+
+def sfft_plan_create(shp: sfft_shape, p: sfft_params) -> int:
+    h = _vp()
+    _check(_lib.sfft_plan_create(ctypes.byref(shp), ctypes.byref(p), ctypes.byref(h)))
+    return h.value
+
+
+def sfft_plan_info_get(plan: int) -> sfft_plan_info:
+    info = sfft_plan_info()
+    _check(_lib.sfft_plan_info_get(plan, ctypes.byref(info)))
+    return info
+
+
+def sfft_analyze(shp: sfft_shape, p: sfft_params) -> sfft_plan_info:
+    info = sfft_plan_info()
+    _check(_lib.sfft_analyze(ctypes.byref(shp), ctypes.byref(p), ctypes.byref(info)))
+    return info
+
+
+def sfft_plan_workspace_bytes(plan: int) -> int:
+    v = ctypes.c_int64()
+    _check(_lib.sfft_plan_workspace_bytes(plan, ctypes.byref(v)))
+    return v.value
+
+
+def sfft_plan_destroy(plan: int) -> None:
+    _lib.sfft_plan_destroy(plan)
+
+
+def sfft_execute(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_execute(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_decrypt(p, sk_host_ptr, ct_ptr, n_values, F, on_device, out_ptr) -> None:
+    _check(_lib.sfft_decrypt(ctypes.byref(p), sk_host_ptr, ct_ptr, n_values, F, int(on_device), out_ptr))
+
+
+def sfft_decrypt_bits(p, sk_host_ptr, ct_ptr, n_ct, on_device, out_ptr) -> None:
+    _check(_lib.sfft_decrypt_bits(ctypes.byref(p), sk_host_ptr, ct_ptr, n_ct, int(on_device), out_ptr))
+
+
+def sfft_gate(p, gate, x_ptr, y_ptr, out_ptr, stream) -> None:
+    _check(_lib.sfft_gate(ctypes.byref(p), gate, x_ptr, y_ptr, out_ptr, stream))
+
+
+EXPORTED = sorted(_SIGS)
