@@ -1,0 +1,184 @@
+"""Benchmark: encrypted FFT throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one encrypted FFT of one request (every product level of the
+compiled circuit, inputs already encrypted and resident in HBM).  Prints one
+JSON line: canonical-netlist Boolean gates per second (AND+XOR+OR+XADD), FFT
+points per second, per-step latency percentiles, the gate-product kernel's
+roofline (algorithmic bit-MACs per second from HIP events recorded around
+every product launch on the launch stream) and the CPU oracle's rate on a
+bounded sample of the same products.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# gate-product kernel ceiling: every 4 bits of an L row select one LDS table
+# word per 32-bit limb, added with v_add_co_u32 + v_addc_co_u32, i.e. 128
+# bit-MACs per 2 VALU lane-ops; 256 CUs x 64 lanes/clk x 2.4 GHz.
+LANE_OPS = 256 * 64 * 2.4e9
+PEAK_LOOKUP = LANE_OPS * 64.0          # 2.52e15 bit-MAC/s
+PEAK_POPCOUNT = LANE_OPS * 16.0        # 6.3e14 bit-MAC/s (v_and_b32 + v_bcnt_u32_b32 per 32 bits)
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
+    """Time the oracle's product (the whole of its per-gate cost) on operands
+    of the workload's geometry until `budget_s` has passed."""
+    from oracle import gsw
+    p = gsw.Params(n1 - 1, 32 * kw)
+    rng = np.random.default_rng(0)
+    L = rng.integers(0, 2**32, p.dims(), dtype=np.uint64).astype(np.uint32)
+    R = rng.integers(0, 2**32, p.dims(), dtype=np.uint64).astype(np.uint32)
+    gsw.product(p, L, R)  # warm the library and page in
+    n, t0 = 0, time.perf_counter()
+    while True:
+        gsw.product(p, L, R)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s and n >= 2:
+            break
+    per_product = dt / n
+    fft_s = per_product * canon_products
+    return {
+        "value": gates / fft_s,
+        "unit": "gates/s",
+        "cores": int(gsw.lib().or_threads()),
+        "kind": "oracle",
+        "sample": "%d oracle products at Nct=%d (n+1=%d, k=%d), %.2f s each; one FFT = %d canonical products "
+                  "-> %.0f s per FFT" % (n, nct, n1, 32 * kw, per_product, canon_products, fft_s),
+        "bitmac_per_s": nct ** 3 / per_product,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fft1d_n64_cplx_q16.8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(requests and levels would shard across GPUs as described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1611_08769_amd import api
+    from paper_1611_08769_amd import workloads as WL
+
+    sig, n_lwe, seed = WL.workload(args.workload)
+    cplx = sig.is_complex
+    params = api.size_params(sig.dims, sig.length, sig.F, sig.f, cplx, n_lwe)
+    keys = api.keygen(params, seed)
+    words = api.signal_words(sig)
+    ct_in = api.encrypt_words(keys, words, sig.F, seed=seed)
+    plan = api.Plan(sig.dims, sig.length, sig.F, sig.f, cplx, params)
+    info = plan.info
+    ct_out = torch.empty((info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
+    nct = (params.n_lwe + 1) * params.k
+    step_prods = plan.step_products()
+    nsteps = len(step_prods)
+    print("[bench] workload=%s k=%d Nct=%d products=%d exec=%d levels=%d ws=%.1f GB" % (
+        args.workload, params.k, nct, info.products, info.exec_products, info.levels, plan.ws_bytes / 1e9),
+        file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        plan.execute(ct_in, ct_out)
+        torch.cuda.synchronize()
+        print("[bench] warmup %d done" % w, file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    kern_ms = 0.0
+    n_launch = 0
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ts = time.perf_counter()
+        evs = []
+        for st in range(nsteps):
+            if step_prods[st]:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                plan.execute_steps(st, 1, ct_in, ct_out)
+                b.record(stream)
+                evs.append((a, b))
+            else:
+                plan.execute_steps(st, 1, ct_in, ct_out)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        kern_ms += sum(a.elapsed_time(b) for a, b in evs)
+        n_launch += len(evs)
+        print("[bench] step %d: %.3f s" % (s, lat[-1]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+
+    step_s = total / args.steps
+    bitmac_step = float(info.exec_products) * nct ** 3
+    achieved = bitmac_step * args.steps / (kern_ms / 1e3)
+    npts = sig.points
+    out = {
+        "metric": "encrypted gates/s (1 GPU)",
+        "value": info.gates / step_s,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "dims": sig.dims, "len": sig.length, "F": sig.F, "f": sig.f, "complex": cplx,
+            "n_lwe": params.n_lwe, "k": params.k, "nct": nct,
+            "canonical_gates": int(info.gates), "canonical_products": int(info.products),
+            "exec_products": int(info.exec_products), "levels": int(info.levels),
+        },
+        "fft_points_per_s": npts / step_s,
+        "products_per_s": info.exec_products / step_s,
+        "latency_p50_s": pct(lat, 50),
+        "latency_p99_s": pct(lat, 99),
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LOOKUP / 1e12,
+            "unit": "Tbitmac/s",
+            "frac": achieved / PEAK_LOOKUP,
+            "traffic": None,
+            "kernel": "k_product",
+            "launches": n_launch,
+            "avg_launch_ms": kern_ms / max(1, n_launch),
+            "frac_vs_popcount_ceiling": achieved / PEAK_POPCOUNT,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(nct, params.n_lwe + 1, params.k // 32, info.gates, info.products,
+                                           args.cpu_budget)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,7 @@ typedef struct {
     int64_t max_level_products;
     int64_t n_inputs, n_outputs;  /* ciphertexts */
     int64_t ws_cts;               /* workspace ciphertext slots */
+    int64_t exec_steps;           /* steps of sfft_execute_steps: levels + 2 */
     int32_t k_required;           /* least multiple of 32 meeting the noise rule */
     char netlist_sha256[65];      /* hex SHA-256 of the canonical netlist */
 } sfft_plan_info;
@@ -118,6 +119,17 @@ void sfft_plan_destroy(sfft_plan* plan);
  * sfft_plan_workspace_bytes.  Enqueues only. */
 int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
                  int64_t ws_bytes, void* hip_stream);
+
+/* The same work split into exec_steps ordered steps: step 0 prepares inputs
+ * (linear gates on inputs), step L in [1, levels] runs product level L and
+ * the linear gates that follow it, the last step writes outputs that are
+ * constants, inputs or repeated.  Running every step in order equals
+ * sfft_execute; between steps the caller may enqueue other work (other
+ * requests' steps, timing events) on the same or other streams. */
+int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, const uint32_t* ct_in_dev,
+                       uint32_t* ct_out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream);
+/* Product items per step (counts has exec_steps entries). */
+int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n);
 
 /* Decryption (workflow step 6, Lemma "decryption"): n_values words of F
  * ciphertexts each (LSB first) -> signed values sign-extended from F bits.

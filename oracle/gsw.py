@@ -55,6 +55,8 @@ def lib():
         i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
         i8p = np.ctypeslib.ndpointer(dtype=np.int8, flags="C_CONTIGUOUS")
         u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+        L.or_threads.restype = ctypes.c_int
+        L.or_threads.argtypes = []
         L.or_word.restype = ctypes.c_uint64
         L.or_word.argtypes = [ctypes.c_uint64] * 3
         L.or_words.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, u64p]

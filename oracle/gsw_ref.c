@@ -28,7 +28,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <omp.h>
+
 #define GAMMA 0x9E3779B97F4A7C15ULL
+
+/* OpenMP threads the oracle's parallel loops use. */
+int or_threads(void) { return omp_get_max_threads(); }
 
 /* SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014). */
 static uint64_t sm_mix(uint64_t z)

@@ -113,6 +113,14 @@ class Plan:
                        _stream_ptr(stream))
         return ct_out
 
+    def execute_steps(self, first: int, count: int, ct_in: torch.Tensor, ct_out: torch.Tensor, stream=None):
+        ws = self.workspace()
+        S.sfft_execute_steps(self.handle, first, count, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(),
+                             ws.numel() * 4, _stream_ptr(stream))
+
+    def step_products(self):
+        return S.sfft_plan_step_products(self.handle, self.info.exec_steps)
+
     def close(self):
         if self.handle:
             S.sfft_plan_destroy(self.handle)

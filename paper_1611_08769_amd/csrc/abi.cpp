@@ -289,6 +289,7 @@ int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* s
         in.n_inputs = c.n_inputs;
         in.n_outputs = (int64_t)c.outputs.size();
         in.ws_cts = sched->n_slots;
+        in.exec_steps = (int64_t)sched->levels.size() + 1;
         in.k_required = choose_k(c, params->n_lwe);
         const std::string h = netlist_hash(c);
         std::memcpy(in.netlist_sha256, h.c_str(), 64);
@@ -369,10 +370,13 @@ void sfft_plan_destroy(sfft_plan* plan)
     delete plan;
 }
 
-int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
-                 int64_t ws_bytes, void* hip_stream)
+int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, const uint32_t* ct_in_dev,
+                       uint32_t* ct_out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream)
 {
     if (!plan) return fail(SFFT_EINVAL, "null plan");
+    const Schedule& S = plan->sched;
+    const int32_t nsteps = (int32_t)S.levels.size() + 1;
+    if (first < 0 || count < 0 || first + count > nsteps) return fail(SFFT_EINVAL, "step range out of bounds");
     int64_t need = 0;
     sfft_plan_workspace_bytes(plan, &need);
     if (ws_bytes < need) return fail(SFFT_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -381,22 +385,40 @@ int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
     const Geo& g = plan->geo;
     Bufs b{const_cast<uint32_t*>(ct_in_dev), ct_out_dev, (uint32_t*)ws_dev, nullptr, ct_words(g)};
     hipStream_t s = (hipStream_t)hip_stream;
+    for (int32_t st = first; st < first + count; st++) {
+        if (st < (int32_t)S.levels.size()) {
+            const LevelWork& lw = S.levels[st];
+            if (lw.prod_count) {
+                hipError_t e = launch_products(b, g, plan->cfg, plan->d_prods + lw.prod_begin, lw.prod_count, s);
+                if (e != hipSuccess) return hip_fail(e, "product launch");
+            }
+            for (const auto& pass : lw.lin) {
+                hipError_t e = launch_linear(b, g, plan->d_lins + pass.first, pass.second, s);
+                if (e != hipSuccess) return hip_fail(e, "linear launch");
+            }
+        } else if (!S.final_lins.empty()) {
+            hipError_t e = launch_linear(b, g, plan->d_final, (int64_t)S.final_lins.size(), s);
+            if (e != hipSuccess) return hip_fail(e, "output launch");
+        }
+    }
+    return SFFT_OK;
+}
+
+int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                 int64_t ws_bytes, void* hip_stream)
+{
+    if (!plan) return fail(SFFT_EINVAL, "null plan");
+    return sfft_execute_steps(plan, 0, (int32_t)plan->sched.levels.size() + 1, ct_in_dev, ct_out_dev, ws_dev,
+                              ws_bytes, hip_stream);
+}
+
+int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n)
+{
+    if (!plan || (n > 0 && !counts)) return fail(SFFT_EINVAL, "null argument");
     const Schedule& S = plan->sched;
-    for (size_t L = 0; L < S.levels.size(); L++) {
-        const LevelWork& lw = S.levels[L];
-        if (lw.prod_count) {
-            hipError_t e = launch_products(b, g, plan->cfg, plan->d_prods + lw.prod_begin, lw.prod_count, s);
-            if (e != hipSuccess) return hip_fail(e, "product launch");
-        }
-        for (const auto& pass : lw.lin) {
-            hipError_t e = launch_linear(b, g, plan->d_lins + pass.first, pass.second, s);
-            if (e != hipSuccess) return hip_fail(e, "linear launch");
-        }
-    }
-    if (!S.final_lins.empty()) {
-        hipError_t e = launch_linear(b, g, plan->d_final, (int64_t)S.final_lins.size(), s);
-        if (e != hipSuccess) return hip_fail(e, "output launch");
-    }
+    const int32_t nsteps = (int32_t)S.levels.size() + 1;
+    if (n != nsteps) return fail(SFFT_EINVAL, "need exactly exec_steps entries");
+    for (int32_t st = 0; st < nsteps; st++) counts[st] = st < (int32_t)S.levels.size() ? S.levels[st].prod_count : 0;
     return SFFT_OK;
 }
 

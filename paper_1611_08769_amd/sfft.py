@@ -33,7 +33,8 @@ class sfft_plan_info(ctypes.Structure):
     _fields_ = [("nodes", ctypes.c_int64), ("gates", ctypes.c_int64), ("products", ctypes.c_int64),
                 ("exec_products", ctypes.c_int64), ("levels", ctypes.c_int64),
                 ("max_level_products", ctypes.c_int64), ("n_inputs", ctypes.c_int64),
-                ("n_outputs", ctypes.c_int64), ("ws_cts", ctypes.c_int64), ("k_required", ctypes.c_int32),
+                ("n_outputs", ctypes.c_int64), ("ws_cts", ctypes.c_int64), ("exec_steps", ctypes.c_int64),
+                ("k_required", ctypes.c_int32),
                 ("netlist_sha256", ctypes.c_char * 65)]
 
 
@@ -63,6 +64,8 @@ _SIGS = {
     "sfft_plan_workspace_bytes": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "sfft_plan_destroy": (None, [_vp]),
     "sfft_execute": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "sfft_execute_steps": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "sfft_plan_step_products": (ctypes.c_int, [_vp, _P(ctypes.c_int64), ctypes.c_int32]),
     "sfft_decrypt": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, _vp]),
     "sfft_decrypt_bits": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
     "sfft_gate": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _vp, _vp, _vp, _vp]),
@@ -142,6 +145,16 @@ def sfft_plan_destroy(plan: int) -> None:
 
 def sfft_execute(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
     _check(_lib.sfft_execute(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_plan_step_products(plan, n):
+    arr = (ctypes.c_int64 * n)()
+    _check(_lib.sfft_plan_step_products(plan, arr, n))
+    return list(arr)
 
 
 def sfft_decrypt(p, sk_host_ptr, ct_ptr, n_values, F, on_device, out_ptr) -> None:
