@@ -22,13 +22,22 @@ struct Geo {
     int32_t nct, n1, kw, W, k;
 };
 
-// Per-launch choice of the product kernel's register tiling.
+// Per-geometry choice of the product kernel's tiling.
 struct ProdCfg {
-    int wpl;   // words of a row held per lane
-    int rpl;   // rows per lane
-    int rpw;   // rows per wave
+    int nd;    // 30-bit digits per element (ceil(k/30))
+    int wd;    // digits per row (n1 * nd)
+    int lpr;   // lanes per output row (16 or 32)
+    int dpl;   // digit slots per lane
+    int st;    // digit slots per row (lpr * dpl >= wd)
+    int rpw;   // rows per wave per row-iteration (64 / lpr)
+    int rpl;   // row-iterations per lane
     int tr;    // rows per workgroup
     int lds_bytes;
+};
+
+// The same numbers as passed to the kernel.
+struct KCfg {
+    int32_t nd, wd, st, rpl, tr;
 };
 
 bool product_config(const Geo& g, ProdCfg* cfg);

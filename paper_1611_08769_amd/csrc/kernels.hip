@@ -8,15 +8,18 @@
 //
 // Method: four bits of a row of L select one of the 16 subset sums of four
 // consecutive rows of R (the method of Arlazarov, Dinic, Kronrod and Faradzev,
-// 1970).  A workgroup builds those subset-sum tables for 32 consecutive rows
-// of R in LDS (8 tables x 16 entries, carried mod 2^k per element), then every
-// lane adds one table entry per 4 bits of its L rows into 32-bit limb
-// accumulators with separate carry counters.  Integer VALU only: per table
-// word one LDS read, one add with carry-out and one add of the carry.
+// 1970).  Per chunk of 32 rows of R, a workgroup re-encodes the rows into
+// 30-bit digits (a sum of four digits fits 32 bits, so the tables need no
+// carries) and builds 8 tables x 16 subset sums in LDS, while the next
+// chunk's rows of R and words of L are already in flight into registers.
+// Each half-wave owns one output row and reads 32 consecutive digits of one
+// table entry per lookup (no LDS bank conflicts); every lane adds the digit
+// into a 64-bit accumulator (one v_lshl_add_u64, no carry flag).  Integer
+// VALU and LDS only.
 //
-// Epilogue (fused): the limb sums and carry counters of each (row, element)
-// are resolved into P mod 2^k and combined, still limb by limb, into up to
-// four outputs a L + b R + c P + g G + e E (AND, XOR, OR, NOT, XADD forms).
+// Epilogue (fused): per (row, element) the exact digit sums are carried into
+// P mod 2^k limb by limb and combined into up to four outputs
+// a L + b R + c P + g G + e E (AND, XOR, OR, NOT, NAND, XADD forms).
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -27,7 +30,13 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kGroups = 8;  // 4-bit groups per 32-row chunk of R
+constexpr int kGroups = 8;          // 4-bit groups per 32-row chunk of R
+constexpr int kDigitBits = 30;      // 4 * (2^30 - 1) < 2^32
+constexpr uint32_t kDigitMask = (1u << kDigitBits) - 1u;
+constexpr int kRPrefetch = 16;      // raw words of the next R chunk per thread (32 W <= 4096)
+constexpr int kBuildTasks = 4;      // (group, digit slot) table tasks per thread (8 wd <= 1024)
+constexpr int kPassIters = 8;       // row-iterations per epilogue pass
+constexpr int kLRows = 2;           // rows of L staged per thread per chunk (TR <= 512)
 
 __device__ __forceinline__ uint32_t* ctp(const Bufs& b, int32_t ref)
 {
@@ -52,35 +61,31 @@ struct MuBits {
     uint32_t w[kMaxEncPerLaunch / 32];
 };
 
-// Output row `row`, element e: resolve P from limb sums (acc, cnt pairs in
-// `sums`) and write every output of the item.
-__device__ void epilogue_element(const Bufs& bufs, const Geo& g, const ProdItem& it, const uint32_t* sums,
-                                 const uint32_t* Lp, const uint32_t* Rp, int row, int e, uint64_t dst_shift)
+// Output row `row`, element e: carry the exact digit sums A[0..nd) (digit d
+// weighs 2^(30 d)) into the limbs of P mod 2^k and write every output of the
+// item, limb by limb with signed carries.
+__device__ void finish_element(const Bufs& bufs, const Geo& g, const ProdItem& it, const uint64_t* A, int nd,
+                               const uint32_t* Lp, const uint32_t* Rp, int row, int e, uint64_t dst_shift)
 {
     const int br = row / g.k, tr = row % g.k;
-    const size_t rowoff = (size_t)row * g.W;
-    uint64_t cp = 0;
+    const size_t base = (size_t)row * g.W + (size_t)e * g.kw;
     int64_t carry[kMaxOut];
     uint32_t* dst[kMaxOut];
     const uint32_t* Ep[kMaxOut];
+    bool needL = false, needR = false;
 #pragma unroll
     for (int o = 0; o < kMaxOut; o++) {
         carry[o] = 0;
         dst[o] = o < it.nout ? ctp(bufs, it.dst[o]) + dst_shift : nullptr;
         Ep[o] = (o < it.nout && it.E[o] >= 0) ? ctp(bufs, it.E[o]) : nullptr;
+        if (o < it.nout) {
+            needL |= it.cL[o] != 0;
+            needR |= it.cR[o] != 0;
+        }
     }
-    bool needL = false, needR = false;
-    for (int o = 0; o < it.nout; o++) {
-        needL |= it.cL[o] != 0;
-        needR |= it.cR[o] != 0;
-    }
-    for (int l = 0; l < g.kw; l++) {
-        const int w = e * g.kw + l;
-        const uint64_t t = (uint64_t)sums[2 * w] + cp;
-        const uint32_t P = (uint32_t)t;
-        cp = (t >> 32) + sums[2 * w + 1];
+    auto emit = [&](int l, uint32_t P) {
+        const size_t off = base + l;
         const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
-        const size_t off = rowoff + w;
         const uint32_t Lv = needL ? Lp[off] : 0u;
         const uint32_t Rv = needR ? Rp[off] : 0u;
 #pragma unroll
@@ -92,24 +97,39 @@ __device__ void epilogue_element(const Bufs& bufs, const Geo& g, const ProdItem&
             dst[o][off] = (uint32_t)s;
             carry[o] = s >> 32;
         }
+    };
+    unsigned __int128 V = 0;  // pending bits from position `pos` up
+    int pos = 0, l = 0;
+    for (int d = 0; d < nd; d++) {
+        V += (unsigned __int128)A[d] << (kDigitBits * d - pos);
+        while (l < g.kw && pos + 32 <= kDigitBits * (d + 1)) {
+            emit(l++, (uint32_t)V);
+            V >>= 32;
+            pos += 32;
+        }
+    }
+    while (l < g.kw) {
+        emit(l++, (uint32_t)V);
+        V >>= 32;
     }
 }
 
-template <int WPL, int RPLMAX, bool ENC>
+// LPR lanes per output row (a half-wave or a quarter-wave), DPL digit slots
+// per lane (slot = lane % LPR + LPR * u), up to RPLMAX rows per lane.
+template <int LPR, int DPL, int RPLMAX, bool ENC>
 __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const ProdItem* __restrict__ items,
-                                                      ProdItem one, int rpl, uint64_t seed, uint64_t first_id,
+                                                      ProdItem one, KCfg kc, uint64_t seed, uint64_t first_id,
                                                       MuBits mu)
 {
+    constexpr int RPW = 64 / LPR;  // rows per wave per row-iteration
+    constexpr int st = LPR * DPL;  // digit slots per table entry
+    constexpr int plane = kGroups * 16 * LPR;  // table words per slot plane u (slot = lane + LPR u)
     extern __shared__ uint32_t lds[];
     ProdItem it = items ? items[blockIdx.y] : one;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int W = g.W;
-    const int LPR = W / WPL;
-    const int RPW = 64 / LPR;
-    const bool active = lane < RPW * LPR;
-    const int sub = lane % LPR, rloc = lane / LPR;
-    const int w0 = sub * WPL;
-    const int TR = kWaves * RPW * rpl;
+    const int rsub = lane / LPR, slot0 = lane % LPR;
+    const int W = g.W, kw = g.kw, nd = kc.nd, wd = kc.wd;
+    const int rpl = kc.rpl, TR = kc.tr;
     const int row_base = blockIdx.x * TR;
 
     uint64_t dst_shift = 0, ct_id = 0;
@@ -123,83 +143,153 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
     const uint64_t M64 = (uint64_t)(g.nct + 63) / 64;
     const uint64_t enc_base = sm_mix(seed + 4ull * 0x9E3779B97F4A7C15ull);
 
-    uint32_t acc[RPLMAX][WPL], cnt[RPLMAX][WPL];
+    uint32_t* Rs = lds;            // 32 x W raw words of the chunk's rows of R
+    uint32_t* Ls = Rs + 32 * W;    // TR words of L (this chunk's 32 bits of each row)
+    uint32_t* T = Ls + TR;         // [u][group][subset][lane]: DPL planes of 8 x 16 x LPR digits
+    for (int q = tid; q < kGroups * 16 * st; q += kThreads) T[q] = 0;  // empty subsets, padding slots
+
+    // table tasks of this thread: (group, digit slot) -> word offset and shift
+    int bt_off[kBuildTasks], bt_sh[kBuildTasks], bt_dst[kBuildTasks];
+    bool bt_ok[kBuildTasks], bt_hi[kBuildTasks];
+#pragma unroll
+    for (int q = 0; q < kBuildTasks; q++) {
+        const int task = tid + q * kThreads;
+        bt_ok[q] = task < kGroups * wd;
+        const int slot = bt_ok[q] ? task % wd : 0, grp = bt_ok[q] ? task / wd : 0;
+        const int e = slot / nd, d = slot % nd, o = kDigitBits * d;
+        bt_off[q] = grp * 4 * W + e * kw + (o >> 5);
+        bt_sh[q] = o & 31;
+        bt_hi[q] = (o >> 5) + 1 < kw;
+        bt_dst[q] = (slot / LPR) * plane + grp * 16 * LPR + slot % LPR;
+    }
+
+    uint64_t acc[RPLMAX][DPL];
 #pragma unroll
     for (int i = 0; i < RPLMAX; i++)
 #pragma unroll
-        for (int u = 0; u < WPL; u++) acc[i][u] = cnt[i][u] = 0;
+        for (int u = 0; u < DPL; u++) acc[i][u] = 0;
 
-    uint32_t* T = lds;
     const int nchunks = g.nct / 32;
-    const int ntask = kGroups * 16 * g.n1;
-    for (int c = 0; c < nchunks; c++) {
-        __syncthreads();
-        for (int task = tid; task < ntask; task += kThreads) {
-            const int e = task % g.n1;
-            const int v = (task / g.n1) & 15;
-            const int grp = task / (16 * g.n1);
-            const uint32_t* r0 = Rp + (size_t)(c * 32 + grp * 4) * W + e * g.kw;
-            uint32_t* dst = T + (grp * 16 + v) * W + e * g.kw;
-            uint64_t carry = 0;
-            for (int l = 0; l < g.kw; l++) {
-                uint64_t s = carry;
-                if (v & 1) s += r0[l];
-                if (v & 2) s += r0[W + l];
-                if (v & 4) s += r0[2 * W + l];
-                if (v & 8) s += r0[3 * W + l];
-                dst[l] = (uint32_t)s;
-                carry = s >> 32;
+    const int chunk_words = 32 * W;
+    uint32_t rpf[kRPrefetch];
+    uint32_t lpf[kLRows];
+    auto load_R = [&](int c) {
+        const uint32_t* src = Rp + (size_t)c * chunk_words;
+#pragma unroll
+        for (int q = 0; q < kRPrefetch; q++) {
+            const int idx = tid + q * kThreads;
+            rpf[q] = idx < chunk_words ? src[idx] : 0u;
+        }
+    };
+    auto load_L = [&](int c) {
+#pragma unroll
+        for (int q = 0; q < kLRows; q++) {
+            const int lr = tid + q * kThreads;
+            const int row = row_base + lr;
+            uint32_t v = 0;
+            if (lr < TR && row < g.nct) {
+                if (ENC) {
+                    const uint64_t widx = ct_id * (uint64_t)g.nct * M64 + (uint64_t)row * M64 + (uint64_t)(c >> 1);
+                    const uint64_t wd64 = sm_mix(enc_base + (widx + 1) * 0x9E3779B97F4A7C15ull);
+                    v = (uint32_t)(wd64 >> (32 * (c & 1)));
+                } else {
+                    v = Lp[(size_t)row * W + c];
+                }
             }
+            lpf[q] = v;
+        }
+    };
+
+    load_R(0);
+    load_L(0);
+    for (int c = 0; c < nchunks; c++) {
+        // stage this chunk; start loading the next one
+#pragma unroll
+        for (int q = 0; q < kRPrefetch; q++) {
+            const int idx = tid + q * kThreads;
+            if (idx < chunk_words) Rs[idx] = rpf[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kLRows; q++)
+            if (tid + q * kThreads < TR) Ls[tid + q * kThreads] = lpf[q];
+        if (c + 1 < nchunks) {
+            load_R(c + 1);
+            load_L(c + 1);
+        }
+        __syncthreads();
+        // digits of 4 rows at one slot -> the 15 non-empty subset sums
+#pragma unroll
+        for (int q = 0; q < kBuildTasks; q++) {
+            if (!bt_ok[q]) continue;
+            const uint32_t* r = Rs + bt_off[q];
+            uint32_t d[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t lo = r[j * W];
+                const uint32_t hi = bt_hi[q] ? r[j * W + 1] : 0u;
+                d[j] = __builtin_amdgcn_alignbit(hi, lo, bt_sh[q]) & kDigitMask;
+            }
+            uint32_t* tb = T + bt_dst[q];
+            const uint32_t s01 = d[0] + d[1], s02 = d[0] + d[2], s12 = d[1] + d[2], s012 = s01 + d[2];
+            tb[1 * LPR] = d[0];
+            tb[2 * LPR] = d[1];
+            tb[3 * LPR] = s01;
+            tb[4 * LPR] = d[2];
+            tb[5 * LPR] = s02;
+            tb[6 * LPR] = s12;
+            tb[7 * LPR] = s012;
+            tb[8 * LPR] = d[3];
+            tb[9 * LPR] = d[0] + d[3];
+            tb[10 * LPR] = d[1] + d[3];
+            tb[11 * LPR] = s01 + d[3];
+            tb[12 * LPR] = d[2] + d[3];
+            tb[13 * LPR] = s02 + d[3];
+            tb[14 * LPR] = s12 + d[3];
+            tb[15 * LPR] = s012 + d[3];
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < RPLMAX; i++) {
-            if (i >= rpl) break;
-            const int row = row_base + (wave * rpl + i) * RPW + rloc;
-            uint32_t Lw = 0;
-            if (active && row < g.nct) {
-                if (ENC) {
-                    const uint64_t widx = ct_id * (uint64_t)g.nct * M64 + (uint64_t)row * M64 + (uint64_t)(c >> 1);
-                    const uint64_t wd = sm_mix(enc_base + (widx + 1) * 0x9E3779B97F4A7C15ull);
-                    Lw = (uint32_t)(wd >> (32 * (c & 1)));
-                } else {
-                    Lw = Lp[(size_t)row * W + c];
-                }
-            }
+            if (i < rpl) {
+                const uint32_t Lw = Ls[(wave * rpl + i) * RPW + rsub];
 #pragma unroll
-            for (int grp = 0; grp < kGroups; grp++) {
-                const uint32_t idx = (Lw >> (4 * grp)) & 15u;
-                const uint32_t* t = T + (grp * 16 + idx) * W + w0;
+                for (int grp = 0; grp < kGroups; grp++) {
+                    const uint32_t idx = __builtin_amdgcn_ubfe(Lw, 4 * grp, 4);
+                    const uint32_t* t = T + grp * 16 * LPR + idx * LPR + slot0;
 #pragma unroll
-                for (int u = 0; u < WPL; u++) {
-                    const uint32_t x = t[u];
-                    const uint64_t s = (uint64_t)acc[i][u] + x;
-                    acc[i][u] = (uint32_t)s;
-                    cnt[i][u] += (uint32_t)(s >> 32);
+                    for (int u = 0; u < DPL; u++) acc[i][u] += (uint64_t)t[u * plane];
                 }
             }
         }
     }
 
-    // epilogue: stage one row-iteration of limb sums per wave in LDS, then
-    // one lane per (row, element) resolves carries and writes the outputs
-    __syncthreads();
-    uint32_t* E = lds + wave * (RPW * W * 2);
-    for (int i = 0; i < rpl; i++) {
-        if (active) {
+    // epilogue in passes of kPassIters row-iterations: stage the digit sums
+    // in LDS, then one thread per (row, element) finishes it
+    constexpr int kPassRows = kWaves * RPW * kPassIters;
+    uint64_t* E = reinterpret_cast<uint64_t*>(lds);
 #pragma unroll
-            for (int u = 0; u < WPL; u++) {
-                E[(rloc * W + w0 + u) * 2] = acc[i][u];
-                E[(rloc * W + w0 + u) * 2 + 1] = cnt[i][u];
+    for (int p = 0; p < RPLMAX / kPassIters; p++) {
+        if (p * kPassIters >= rpl) continue;  // uniform across the workgroup
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < kPassIters; ii++) {
+            const int i = p * kPassIters + ii;
+            if (i < rpl) {
+                const int pr = (wave * kPassIters + ii) * RPW + rsub;
+#pragma unroll
+                for (int u = 0; u < DPL; u++) E[pr * st + slot0 + u * LPR] = acc[i][u];
             }
         }
         __syncthreads();
-        for (int task = lane; task < RPW * g.n1; task += 64) {
-            const int rl = task / g.n1, e = task % g.n1;
-            const int row = row_base + (wave * rpl + i) * RPW + rl;
-            if (row < g.nct) epilogue_element(bufs, g, it, E + rl * W * 2, Lp, Rp, row, e, dst_shift);
+        for (int task = tid; task < kPassRows * g.n1; task += kThreads) {
+            const int pr = task / g.n1, e = task % g.n1;
+            const int wv = pr / (kPassIters * RPW), ii = (pr / RPW) % kPassIters, rs = pr % RPW;
+            const int i = p * kPassIters + ii;
+            if (i >= rpl) continue;
+            const int row = row_base + (wv * rpl + i) * RPW + rs;
+            if (row >= g.nct) continue;
+            finish_element(bufs, g, it, E + pr * st + e * nd, nd, Lp, Rp, row, e, dst_shift);
         }
-        __syncthreads();
     }
 }
 
@@ -225,24 +315,25 @@ __global__ void __launch_bounds__(kThreads) k_linear(Bufs bufs, Geo g, const Lin
     }
 }
 
-template <int WPL, int RPLMAX, bool ENC>
+template <int LPR, int DPL, int RPLMAX, bool ENC>
 hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, const ProdItem& one,
                     int64_t count, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
     static int attr_bytes = 64 * 1024;
     if (cfg.lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_product<WPL, RPLMAX, ENC>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_product<LPR, DPL, RPLMAX, ENC>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, cfg.lds_bytes);
         if (e != hipSuccess) return e;
         attr_bytes = cfg.lds_bytes;
     }
     const int tiles = (g.nct + cfg.tr - 1) / cfg.tr;
+    const KCfg kc{cfg.nd, cfg.wd, cfg.st, cfg.rpl, cfg.tr};
     MuBits none{};
     for (int64_t b0 = 0; b0 < count; b0 += 65535) {
         const int64_t n = count - b0 < 65535 ? count - b0 : 65535;
         dim3 grid(tiles, (unsigned)n);
-        hipLaunchKernelGGL((k_product<WPL, RPLMAX, ENC>), grid, dim3(kThreads), cfg.lds_bytes, s, b, g,
-                           d_items ? d_items + b0 : nullptr, one, cfg.rpl, seed, first_id + (uint64_t)b0,
+        hipLaunchKernelGGL((k_product<LPR, DPL, RPLMAX, ENC>), grid, dim3(kThreads), cfg.lds_bytes, s, b, g,
+                           d_items ? d_items + b0 : nullptr, one, kc, seed, first_id + (uint64_t)b0,
                            mu ? *mu : none);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -250,53 +341,54 @@ hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdI
     return hipSuccess;
 }
 
+constexpr int rplmax_for(int dpl) { return dpl <= 2 ? 32 : dpl == 3 ? 24 : 16; }
+
 template <bool ENC>
 hipError_t dispatch(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, const ProdItem& one,
                     int64_t count, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
-    switch (cfg.wpl) {
-#define CASE(WPL, RPLMAX) \
-    case WPL: return launch_t<WPL, RPLMAX, ENC>(b, g, cfg, d_items, one, count, seed, first_id, mu, s);
-        CASE(1, 8)
-        CASE(2, 8)
-        CASE(3, 8)
-        CASE(4, 8)
-        CASE(6, 8)
-        CASE(8, 8)
-        CASE(11, 8)
-        CASE(13, 7)
+#define CASE(LPR, DPL)                                                                                         \
+    if (cfg.lpr == LPR && cfg.dpl == DPL)                                                                      \
+        return launch_t<LPR, DPL, rplmax_for(DPL), ENC>(b, g, cfg, d_items, one, count, seed, first_id, mu, s);
+    CASE(16, 1)
+    CASE(32, 1)
+    CASE(32, 2)
+    CASE(32, 3)
+    CASE(32, 4)
 #undef CASE
-    default: return hipErrorInvalidValue;
-    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int rplmax_for(int wpl) { return wpl == 13 ? 7 : 8; }
-
 bool product_config(const Geo& g, ProdCfg* cfg)
 {
-    static const int cands[] = {13, 11, 8, 6, 4, 3, 2, 1};
-    if (g.nct % 32 != 0 || g.W * 32 != g.nct) return false;
-    for (int wpl : cands) {
-        if (g.W % wpl) continue;
-        const int lpr = g.W / wpl;
-        if (lpr > 64) continue;
-        const int rpw = 64 / lpr;
-        // rows per lane: enough rows per workgroup to amortise the tables,
-        // not more than the product has
-        int rpl = rplmax_for(wpl);
-        while (rpl > 1 && kWaves * rpw * (rpl - 1) >= g.nct) rpl--;
-        cfg->wpl = wpl;
-        cfg->rpl = rpl;
-        cfg->rpw = rpw;
-        cfg->tr = kWaves * rpw * rpl;
-        const int tbl = kGroups * 16 * g.W;
-        const int epi = kWaves * rpw * g.W * 2;
-        cfg->lds_bytes = 4 * (tbl > epi ? tbl : epi);
-        return cfg->lds_bytes <= 160 * 1024;
+    if (g.nct % 32 != 0 || g.W * 32 != g.nct || 32 * g.W > kRPrefetch * kThreads) return false;
+    const int nd = (g.k + kDigitBits - 1) / kDigitBits;
+    const int wd = g.n1 * nd;
+    if (wd > 128 || kGroups * wd > kBuildTasks * kThreads) return false;
+    cfg->nd = nd;
+    cfg->wd = wd;
+    if (wd <= 16) {
+        cfg->lpr = 16;
+        cfg->dpl = 1;
+    } else {
+        cfg->lpr = 32;
+        cfg->dpl = (wd + 31) / 32;
     }
-    return false;
+    cfg->st = cfg->lpr * cfg->dpl;
+    cfg->rpw = 64 / cfg->lpr;
+    const int per_iter = kWaves * cfg->rpw;
+    const int rplmax = rplmax_for(cfg->dpl);
+    int rpl = (g.nct + per_iter - 1) / per_iter;
+    if (rpl > rplmax) rpl = rplmax;
+    cfg->rpl = rpl;
+    cfg->tr = per_iter * rpl;
+    if (cfg->tr > kLRows * kThreads) return false;
+    const int main_words = 32 * g.W + cfg->tr + kGroups * 16 * cfg->st;
+    const int epi_words = 2 * kWaves * cfg->rpw * kPassIters * cfg->st;
+    cfg->lds_bytes = 4 * (main_words > epi_words ? main_words : epi_words);
+    return cfg->lds_bytes <= 160 * 1024;
 }
 
 hipError_t launch_products(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, int64_t count,
