@@ -23,12 +23,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# gate-product kernel ceiling: every 4 bits of an L row select one LDS table
-# word per 32-bit limb, added with v_add_co_u32 + v_addc_co_u32, i.e. 128
-# bit-MACs per 2 VALU lane-ops; 256 CUs x 64 lanes/clk x 2.4 GHz.
-LANE_OPS = 256 * 64 * 2.4e9
-PEAK_LOOKUP = LANE_OPS * 64.0          # 2.52e15 bit-MAC/s
-PEAK_POPCOUNT = LANE_OPS * 16.0        # 6.3e14 bit-MAC/s (v_and_b32 + v_bcnt_u32_b32 per 32 bits)
+# Gate-product kernel ceiling.  Any 4-bit table-lookup formulation reads one
+# 4-byte table word per 4 L bits x 32 R bits = 128 bit-MACs, i.e. 32 bit-MAC
+# per LDS byte; gfx950 LDS returns 64 banks x 4 B = 256 B/clk/CU (measured
+# 204 B/clk/CU with ds_read_b128).  256 CUs at 2.4 GHz.
+LDS_BYTES_PER_S = 256 * 256 * 2.4e9
+PEAK_LOOKUP = LDS_BYTES_PER_S * 32.0   # 5.03e15 bit-MAC/s
+# For reference, the AND + popcount formulation on the integer VALU
+# (128 lanes/clk/CU, v_and_b32 + v_bcnt_u32_b32 per 32 bit-MACs).
+PEAK_POPCOUNT = 256 * 128 * 2.4e9 * 16.0   # 1.26e15 bit-MAC/s
 
 
 def pct(xs, q):
@@ -58,8 +61,8 @@ def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
         "unit": "gates/s",
         "cores": int(gsw.lib().or_threads()),
         "kind": "oracle",
-        "sample": "%d oracle products at Nct=%d (n+1=%d, k=%d), %.2f s each; one FFT = %d canonical products "
-                  "-> %.0f s per FFT" % (n, nct, n1, 32 * kw, per_product, canon_products, fft_s),
+        "sample": "%d oracle products at Nct=%d (n+1=%d, k=%d), %.2f ms each; one FFT = %d canonical products "
+                  "-> %.0f s per FFT" % (n, nct, n1, 32 * kw, per_product * 1e3, canon_products, fft_s),
         "bitmac_per_s": nct ** 3 / per_product,
     }
 

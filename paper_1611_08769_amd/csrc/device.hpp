@@ -38,6 +38,9 @@ struct ProdCfg {
 // The same numbers as passed to the kernel.
 struct KCfg {
     int32_t nd, wd, st, rpl, tr;
+    // always 1: a run-time multiplier makes acc = digit * one + acc compile to
+    // v_mad_u64_u32, which takes the 32-bit digit as is (no zero-extended pair)
+    uint32_t one;
 };
 
 bool product_config(const Geo& g, ProdCfg* cfg);

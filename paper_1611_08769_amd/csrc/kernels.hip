@@ -14,7 +14,7 @@
 // chunk's rows of R and words of L are already in flight into registers.
 // Each half-wave owns one output row and reads 32 consecutive digits of one
 // table entry per lookup (no LDS bank conflicts); every lane adds the digit
-// into a 64-bit accumulator (one v_lshl_add_u64, no carry flag).  Integer
+// into a 64-bit accumulator (one v_mad_u64_u32, no carry flag).  Integer
 // VALU and LDS only.
 //
 // Epilogue (fused): per (row, element) the exact digit sums are carried into
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
                     const uint32_t idx = __builtin_amdgcn_ubfe(Lw, 4 * grp, 4);
                     const uint32_t* t = T + grp * 16 * LPR + idx * LPR + slot0;
 #pragma unroll
-                    for (int u = 0; u < DPL; u++) acc[i][u] += (uint64_t)t[u * plane];
+                    for (int u = 0; u < DPL; u++) acc[i][u] = (uint64_t)t[u * plane] * kc.one + acc[i][u];
                 }
             }
         }
@@ -327,7 +327,7 @@ hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdI
         attr_bytes = cfg.lds_bytes;
     }
     const int tiles = (g.nct + cfg.tr - 1) / cfg.tr;
-    const KCfg kc{cfg.nd, cfg.wd, cfg.st, cfg.rpl, cfg.tr};
+    const KCfg kc{cfg.nd, cfg.wd, cfg.st, cfg.rpl, cfg.tr, 1u};
     MuBits none{};
     for (int64_t b0 = 0; b0 < count; b0 += 65535) {
         const int64_t n = count - b0 < 65535 ? count - b0 : 65535;
