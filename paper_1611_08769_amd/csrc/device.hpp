@@ -24,6 +24,7 @@ struct Geo {
 
 // Per-geometry choice of the product kernel's tiling.
 struct ProdCfg {
+    int tiling;  // index into the kernel's tiling table
     int nd;    // 30-bit digits per element (ceil(k/30))
     int wd;    // digits per row (n1 * nd)
     int lpr;   // lanes per output row (16 or 32)

@@ -33,10 +33,9 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kGroups = 8;          // 4-bit groups per 32-row chunk of R
 constexpr int kDigitBits = 30;      // 4 * (2^30 - 1) < 2^32
 constexpr uint32_t kDigitMask = (1u << kDigitBits) - 1u;
-constexpr int kRPrefetch = 16;      // raw words of the next R chunk per thread (32 W <= 4096)
-constexpr int kBuildTasks = 4;      // (group, digit slot) table tasks per thread (8 wd <= 1024)
-constexpr int kPassIters = 8;       // row-iterations per epilogue pass
-constexpr int kLRows = 2;           // rows of L staged per thread per chunk (TR <= 512)
+constexpr int kMaxChunkWords = 4096;  // 32 rows of R, W <= 128 words per row
+constexpr int kMaxDigitSlots = 128;   // digits per row incl. padding
+constexpr int kPassMinRows = 64;      // rows staged per epilogue pass (at least)
 
 __device__ __forceinline__ uint32_t* ctp(const Bufs& b, int32_t ref)
 {
@@ -114,20 +113,30 @@ __device__ void finish_element(const Bufs& bufs, const Geo& g, const ProdItem& i
     }
 }
 
-// LPR lanes per output row (a half-wave or a quarter-wave), DPL digit slots
-// per lane (slot = lane % LPR + LPR * u), up to RPLMAX rows per lane.
-template <int LPR, int DPL, int RPLMAX, bool ENC>
-__global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const ProdItem* __restrict__ items,
-                                                      ProdItem one, KCfg kc, uint64_t seed, uint64_t first_id,
-                                                      MuBits mu)
+// THREADS threads per workgroup, LPR lanes per output row, DPL digit slots
+// per lane held as DPL/4 groups of 4 consecutive digits (lane slot group
+// q covers digits 4 (lane % LPR + LPR q) .. +3, read with one ds_read_b128),
+// up to RPLMAX rows per lane.
+template <int THREADS, int LPR, int DPL, int RPLMAX, bool ENC>
+__global__ void __launch_bounds__(THREADS) k_product(Bufs bufs, Geo g, const ProdItem* __restrict__ items,
+                                                     ProdItem one, KCfg kc, uint64_t seed, uint64_t first_id,
+                                                     MuBits mu)
 {
-    constexpr int RPW = 64 / LPR;  // rows per wave per row-iteration
-    constexpr int st = LPR * DPL;  // digit slots per table entry
-    constexpr int plane = kGroups * 16 * LPR;  // table words per slot plane u (slot = lane + LPR u)
+    constexpr int NW = THREADS / 64;
+    constexpr int RPW = 64 / LPR;      // rows per wave per row-iteration
+    constexpr int NQ = DPL / 4;        // 16-byte table reads per lookup
+    constexpr int st = LPR * DPL;      // digit slots per table entry
+    constexpr int RPF = (kMaxChunkWords + THREADS - 1) / THREADS;
+    constexpr int BT = (kGroups * kMaxDigitSlots + THREADS - 1) / THREADS;
+    constexpr int LR = (NW * RPW * RPLMAX + THREADS - 1) / THREADS;
+    constexpr int PI = (kPassMinRows + NW * RPW - 1) / (NW * RPW);  // row-iterations per epilogue pass
+    constexpr int PASS_ROWS = NW * RPW * PI;
+    static_assert(DPL % 4 == 0, "digit slots come in groups of 4");
+
     extern __shared__ uint32_t lds[];
     ProdItem it = items ? items[blockIdx.y] : one;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rsub = lane / LPR, slot0 = lane % LPR;
+    const int rsub = lane / LPR, lq = lane % LPR;
     const int W = g.W, kw = g.kw, nd = kc.nd, wd = kc.wd;
     const int rpl = kc.rpl, TR = kc.tr;
     const int row_base = blockIdx.x * TR;
@@ -144,23 +153,23 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
     const uint64_t enc_base = sm_mix(seed + 4ull * 0x9E3779B97F4A7C15ull);
 
     uint32_t* Rs = lds;            // 32 x W raw words of the chunk's rows of R
-    uint32_t* Ls = Rs + 32 * W;    // TR words of L (this chunk's 32 bits of each row)
-    uint32_t* T = Ls + TR;         // [u][group][subset][lane]: DPL planes of 8 x 16 x LPR digits
-    for (int q = tid; q < kGroups * 16 * st; q += kThreads) T[q] = 0;  // empty subsets, padding slots
+    uint32_t* Ls = Rs + 32 * W;    // TR words of L (this chunk's 32 bits of each row); TR % 4 == 0
+    uint32_t* T = Ls + TR;         // 8 groups x 16 subset sums x st digit slots, 16-byte aligned
+    for (int q = tid; q < kGroups * 16 * st; q += THREADS) T[q] = 0;  // empty subsets, padding slots
 
     // table tasks of this thread: (group, digit slot) -> word offset and shift
-    int bt_off[kBuildTasks], bt_sh[kBuildTasks], bt_dst[kBuildTasks];
-    bool bt_ok[kBuildTasks], bt_hi[kBuildTasks];
+    int bt_off[BT], bt_sh[BT], bt_dst[BT];
+    bool bt_ok[BT], bt_hi[BT];
 #pragma unroll
-    for (int q = 0; q < kBuildTasks; q++) {
-        const int task = tid + q * kThreads;
+    for (int q = 0; q < BT; q++) {
+        const int task = tid + q * THREADS;
         bt_ok[q] = task < kGroups * wd;
         const int slot = bt_ok[q] ? task % wd : 0, grp = bt_ok[q] ? task / wd : 0;
         const int e = slot / nd, d = slot % nd, o = kDigitBits * d;
         bt_off[q] = grp * 4 * W + e * kw + (o >> 5);
         bt_sh[q] = o & 31;
         bt_hi[q] = (o >> 5) + 1 < kw;
-        bt_dst[q] = (slot / LPR) * plane + grp * 16 * LPR + slot % LPR;
+        bt_dst[q] = grp * 16 * st + slot;
     }
 
     uint64_t acc[RPLMAX][DPL];
@@ -171,20 +180,20 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
 
     const int nchunks = g.nct / 32;
     const int chunk_words = 32 * W;
-    uint32_t rpf[kRPrefetch];
-    uint32_t lpf[kLRows];
+    uint32_t rpf[RPF];
+    uint32_t lpf[LR];
     auto load_R = [&](int c) {
         const uint32_t* src = Rp + (size_t)c * chunk_words;
 #pragma unroll
-        for (int q = 0; q < kRPrefetch; q++) {
-            const int idx = tid + q * kThreads;
+        for (int q = 0; q < RPF; q++) {
+            const int idx = tid + q * THREADS;
             rpf[q] = idx < chunk_words ? src[idx] : 0u;
         }
     };
     auto load_L = [&](int c) {
 #pragma unroll
-        for (int q = 0; q < kLRows; q++) {
-            const int lr = tid + q * kThreads;
+        for (int q = 0; q < LR; q++) {
+            const int lr = tid + q * THREADS;
             const int row = row_base + lr;
             uint32_t v = 0;
             if (lr < TR && row < g.nct) {
@@ -205,13 +214,13 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
     for (int c = 0; c < nchunks; c++) {
         // stage this chunk; start loading the next one
 #pragma unroll
-        for (int q = 0; q < kRPrefetch; q++) {
-            const int idx = tid + q * kThreads;
+        for (int q = 0; q < RPF; q++) {
+            const int idx = tid + q * THREADS;
             if (idx < chunk_words) Rs[idx] = rpf[q];
         }
 #pragma unroll
-        for (int q = 0; q < kLRows; q++)
-            if (tid + q * kThreads < TR) Ls[tid + q * kThreads] = lpf[q];
+        for (int q = 0; q < LR; q++)
+            if (tid + q * THREADS < TR) Ls[tid + q * THREADS] = lpf[q];
         if (c + 1 < nchunks) {
             load_R(c + 1);
             load_L(c + 1);
@@ -219,7 +228,7 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
         __syncthreads();
         // digits of 4 rows at one slot -> the 15 non-empty subset sums
 #pragma unroll
-        for (int q = 0; q < kBuildTasks; q++) {
+        for (int q = 0; q < BT; q++) {
             if (!bt_ok[q]) continue;
             const uint32_t* r = Rs + bt_off[q];
             uint32_t d[4];
@@ -231,21 +240,21 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
             }
             uint32_t* tb = T + bt_dst[q];
             const uint32_t s01 = d[0] + d[1], s02 = d[0] + d[2], s12 = d[1] + d[2], s012 = s01 + d[2];
-            tb[1 * LPR] = d[0];
-            tb[2 * LPR] = d[1];
-            tb[3 * LPR] = s01;
-            tb[4 * LPR] = d[2];
-            tb[5 * LPR] = s02;
-            tb[6 * LPR] = s12;
-            tb[7 * LPR] = s012;
-            tb[8 * LPR] = d[3];
-            tb[9 * LPR] = d[0] + d[3];
-            tb[10 * LPR] = d[1] + d[3];
-            tb[11 * LPR] = s01 + d[3];
-            tb[12 * LPR] = d[2] + d[3];
-            tb[13 * LPR] = s02 + d[3];
-            tb[14 * LPR] = s12 + d[3];
-            tb[15 * LPR] = s012 + d[3];
+            tb[1 * st] = d[0];
+            tb[2 * st] = d[1];
+            tb[3 * st] = s01;
+            tb[4 * st] = d[2];
+            tb[5 * st] = s02;
+            tb[6 * st] = s12;
+            tb[7 * st] = s012;
+            tb[8 * st] = d[3];
+            tb[9 * st] = d[0] + d[3];
+            tb[10 * st] = d[1] + d[3];
+            tb[11 * st] = s01 + d[3];
+            tb[12 * st] = d[2] + d[3];
+            tb[13 * st] = s02 + d[3];
+            tb[14 * st] = s12 + d[3];
+            tb[15 * st] = s012 + d[3];
         }
         __syncthreads();
 #pragma unroll
@@ -255,36 +264,43 @@ __global__ void __launch_bounds__(kThreads) k_product(Bufs bufs, Geo g, const Pr
 #pragma unroll
                 for (int grp = 0; grp < kGroups; grp++) {
                     const uint32_t idx = __builtin_amdgcn_ubfe(Lw, 4 * grp, 4);
-                    const uint32_t* t = T + grp * 16 * LPR + idx * LPR + slot0;
+                    const uint4* t = reinterpret_cast<const uint4*>(T + (grp * 16 + idx) * st) + lq;
 #pragma unroll
-                    for (int u = 0; u < DPL; u++) acc[i][u] = (uint64_t)t[u * plane] * kc.one + acc[i][u];
+                    for (int q = 0; q < NQ; q++) {
+                        const uint4 x = t[q * LPR];
+                        acc[i][4 * q + 0] = (uint64_t)x.x * kc.one + acc[i][4 * q + 0];
+                        acc[i][4 * q + 1] = (uint64_t)x.y * kc.one + acc[i][4 * q + 1];
+                        acc[i][4 * q + 2] = (uint64_t)x.z * kc.one + acc[i][4 * q + 2];
+                        acc[i][4 * q + 3] = (uint64_t)x.w * kc.one + acc[i][4 * q + 3];
+                    }
                 }
             }
         }
     }
 
-    // epilogue in passes of kPassIters row-iterations: stage the digit sums
-    // in LDS, then one thread per (row, element) finishes it
-    constexpr int kPassRows = kWaves * RPW * kPassIters;
+    // epilogue in passes of PI row-iterations: stage the digit sums in LDS,
+    // then one thread per (row, element) finishes it
     uint64_t* E = reinterpret_cast<uint64_t*>(lds);
 #pragma unroll
-    for (int p = 0; p < RPLMAX / kPassIters; p++) {
-        if (p * kPassIters >= rpl) continue;  // uniform across the workgroup
+    for (int p = 0; p < (RPLMAX + PI - 1) / PI; p++) {
+        if (p * PI >= rpl) continue;  // uniform across the workgroup
         __syncthreads();
 #pragma unroll
-        for (int ii = 0; ii < kPassIters; ii++) {
-            const int i = p * kPassIters + ii;
-            if (i < rpl) {
-                const int pr = (wave * kPassIters + ii) * RPW + rsub;
+        for (int ii = 0; ii < PI; ii++) {
+            const int i = p * PI + ii;
+            if (i < RPLMAX && i < rpl) {
+                const int pr = (wave * PI + ii) * RPW + rsub;
 #pragma unroll
-                for (int u = 0; u < DPL; u++) E[pr * st + slot0 + u * LPR] = acc[i][u];
+                for (int q = 0; q < NQ; q++)
+#pragma unroll
+                    for (int c4 = 0; c4 < 4; c4++) E[pr * st + 4 * (lq + LPR * q) + c4] = acc[i][4 * q + c4];
             }
         }
         __syncthreads();
-        for (int task = tid; task < kPassRows * g.n1; task += kThreads) {
+        for (int task = tid; task < PASS_ROWS * g.n1; task += THREADS) {
             const int pr = task / g.n1, e = task % g.n1;
-            const int wv = pr / (kPassIters * RPW), ii = (pr / RPW) % kPassIters, rs = pr % RPW;
-            const int i = p * kPassIters + ii;
+            const int wv = pr / (PI * RPW), ii = (pr / RPW) % PI, rs = pr % RPW;
+            const int i = p * PI + ii;
             if (i >= rpl) continue;
             const int row = row_base + (wv * rpl + i) * RPW + rs;
             if (row >= g.nct) continue;
@@ -315,13 +331,13 @@ __global__ void __launch_bounds__(kThreads) k_linear(Bufs bufs, Geo g, const Lin
     }
 }
 
-template <int LPR, int DPL, int RPLMAX, bool ENC>
+template <int THREADS, int LPR, int DPL, int RPLMAX, bool ENC>
 hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, const ProdItem& one,
                     int64_t count, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
     static int attr_bytes = 64 * 1024;
     if (cfg.lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_product<LPR, DPL, RPLMAX, ENC>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_product<THREADS, LPR, DPL, RPLMAX, ENC>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, cfg.lds_bytes);
         if (e != hipSuccess) return e;
         attr_bytes = cfg.lds_bytes;
@@ -332,7 +348,7 @@ hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdI
     for (int64_t b0 = 0; b0 < count; b0 += 65535) {
         const int64_t n = count - b0 < 65535 ? count - b0 : 65535;
         dim3 grid(tiles, (unsigned)n);
-        hipLaunchKernelGGL((k_product<LPR, DPL, RPLMAX, ENC>), grid, dim3(kThreads), cfg.lds_bytes, s, b, g,
+        hipLaunchKernelGGL((k_product<THREADS, LPR, DPL, RPLMAX, ENC>), grid, dim3(THREADS), cfg.lds_bytes, s, b, g,
                            d_items ? d_items + b0 : nullptr, one, kc, seed, first_id + (uint64_t)b0,
                            mu ? *mu : none);
         hipError_t e = hipGetLastError();
@@ -341,20 +357,31 @@ hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdI
     return hipSuccess;
 }
 
-constexpr int rplmax_for(int dpl) { return dpl <= 2 ? 32 : dpl == 3 ? 24 : 16; }
+// Tilings: (threads, lanes per row, digit slots per lane, rows per lane).
+struct Tiling {
+    int threads, lpr, dpl, rplmax;
+};
+constexpr Tiling kTilings[] = {
+    {256, 4, 4, 8},    // rows of <= 16 digits
+    {256, 8, 4, 16},   // <= 32
+    {256, 8, 8, 8},    // <= 64
+    {256, 8, 12, 5},   // <= 96
+    {256, 8, 16, 4},   // <= 128
+};
 
 template <bool ENC>
 hipError_t dispatch(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, const ProdItem& one,
                     int64_t count, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
-#define CASE(LPR, DPL)                                                                                         \
-    if (cfg.lpr == LPR && cfg.dpl == DPL)                                                                      \
-        return launch_t<LPR, DPL, rplmax_for(DPL), ENC>(b, g, cfg, d_items, one, count, seed, first_id, mu, s);
-    CASE(16, 1)
-    CASE(32, 1)
-    CASE(32, 2)
-    CASE(32, 3)
-    CASE(32, 4)
+#define CASE(I)                                                                                              \
+    if (cfg.tiling == I)                                                                                     \
+        return launch_t<kTilings[I].threads, kTilings[I].lpr, kTilings[I].dpl, kTilings[I].rplmax, ENC>(     \
+            b, g, cfg, d_items, one, count, seed, first_id, mu, s);
+    CASE(0)
+    CASE(1)
+    CASE(2)
+    CASE(3)
+    CASE(4)
 #undef CASE
     return hipErrorInvalidValue;
 }
@@ -363,30 +390,32 @@ hipError_t dispatch(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdI
 
 bool product_config(const Geo& g, ProdCfg* cfg)
 {
-    if (g.nct % 32 != 0 || g.W * 32 != g.nct || 32 * g.W > kRPrefetch * kThreads) return false;
+    if (g.nct % 32 != 0 || g.W * 32 != g.nct || 32 * g.W > kMaxChunkWords) return false;
     const int nd = (g.k + kDigitBits - 1) / kDigitBits;
     const int wd = g.n1 * nd;
-    if (wd > 128 || kGroups * wd > kBuildTasks * kThreads) return false;
+    int ti = -1;
+    for (int i = 0; i < (int)(sizeof(kTilings) / sizeof(kTilings[0])); i++)
+        if (kTilings[i].lpr * kTilings[i].dpl >= wd) {
+            ti = i;
+            break;
+        }
+    if (ti < 0) return false;
+    const Tiling& t = kTilings[ti];
+    cfg->tiling = ti;
     cfg->nd = nd;
     cfg->wd = wd;
-    if (wd <= 16) {
-        cfg->lpr = 16;
-        cfg->dpl = 1;
-    } else {
-        cfg->lpr = 32;
-        cfg->dpl = (wd + 31) / 32;
-    }
-    cfg->st = cfg->lpr * cfg->dpl;
-    cfg->rpw = 64 / cfg->lpr;
-    const int per_iter = kWaves * cfg->rpw;
-    const int rplmax = rplmax_for(cfg->dpl);
+    cfg->lpr = t.lpr;
+    cfg->dpl = t.dpl;
+    cfg->st = t.lpr * t.dpl;
+    cfg->rpw = 64 / t.lpr;
+    const int per_iter = (t.threads / 64) * cfg->rpw;
     int rpl = (g.nct + per_iter - 1) / per_iter;
-    if (rpl > rplmax) rpl = rplmax;
+    if (rpl > t.rplmax) rpl = t.rplmax;
     cfg->rpl = rpl;
     cfg->tr = per_iter * rpl;
-    if (cfg->tr > kLRows * kThreads) return false;
+    const int pi = (kPassMinRows + per_iter - 1) / per_iter;
     const int main_words = 32 * g.W + cfg->tr + kGroups * 16 * cfg->st;
-    const int epi_words = 2 * kWaves * cfg->rpw * kPassIters * cfg->st;
+    const int epi_words = 2 * per_iter * pi * cfg->st;
     cfg->lds_bytes = 4 * (main_words > epi_words ? main_words : epi_words);
     return cfg->lds_bytes <= 160 * 1024;
 }
