@@ -110,6 +110,8 @@ int sfft_plan_info_get(const sfft_plan* plan, sfft_plan_info* info);
 int sfft_analyze(const sfft_shape* shape, const sfft_params* params, sfft_plan_info* info);
 /* Device workspace the caller must pass to sfft_execute. */
 int sfft_plan_workspace_bytes(const sfft_plan* plan, int64_t* bytes);
+/* Waits for all device work (work enqueued with the plan reads its tables),
+ * then frees the plan. */
 void sfft_plan_destroy(sfft_plan* plan);
 
 /* Encrypted FFT (workflow step 4).  ct_in_dev: the shape's input ciphertexts,
@@ -148,6 +150,52 @@ int sfft_decrypt_bits(const sfft_params* params, const uint32_t* sk_host, const 
  * (= AND).  x, y, out: one ciphertext each, device; out must not alias. */
 int sfft_gate(const sfft_params* params, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev,
               uint32_t* out_dev, void* hip_stream);
+
+/* ---- continuous batching / serving -------------------------------------
+ * A server runs many encrypted FFTs of different shapes and parameter sets
+ * at once.  Requests are admitted in arrival order when their plan's
+ * workspace fits the device memory budget (and fewer than max_active run);
+ * each global step advances every admitted request by one of its plan's
+ * steps, with the products of all requests of the same ciphertext geometry
+ * in one launch.  Each request's ciphertexts are bit-identical to running
+ * its plan alone.  Requests are independent FFTs (the paper's workflow,
+ * section "Introduction", repeated per client signal). */
+#define SFFT_SERVER_DRYRUN 1  /* no device work: admission/scheduling only, modelled time */
+
+typedef struct {
+    int64_t mem_budget_bytes;  /* device memory for request workspaces (allocated at create) */
+    int32_t max_active;        /* requests in flight at once; 0 = no limit */
+    int32_t flags;             /* SFFT_SERVER_DRYRUN */
+    double dry_bitmac_per_s;   /* modelled product rate in dry-run mode (0 = 1e15) */
+} sfft_server_cfg;
+
+typedef struct {
+    int64_t submitted, admitted, completed, queued, active;
+    int64_t steps, launches, products, gates, fft_points;
+    int64_t max_active, peak_ws_bytes;
+    double clock_s; /* current time: host seconds, or modelled seconds in dry-run */
+} sfft_server_stats;
+
+typedef struct sfft_server sfft_server;
+
+int sfft_server_create(const sfft_server_cfg* cfg, sfft_server** out);
+/* Queue a request: the shape's input ciphertexts (layout of sfft_execute) in
+ * ct_in_dev, outputs written to ct_out_dev; both caller-owned and untouched
+ * by the caller until the request completes.  Compiles (or reuses) the plan
+ * on the host.  SFFT_ENOMEM if the plan's workspace exceeds the budget. */
+int sfft_server_submit(sfft_server* srv, const sfft_shape* shape, const sfft_params* params,
+                       const uint32_t* ct_in_dev, uint32_t* ct_out_dev, uint64_t* ticket);
+/* Admit what fits, run one global step on hip_stream and wait for it;
+ * *pending = requests still queued or running. */
+int sfft_server_step(sfft_server* srv, void* hip_stream, int32_t* pending);
+/* done = 1 once the request's outputs are complete; latency = completion
+ * minus submission (seconds; modelled in dry-run). */
+int sfft_server_poll(sfft_server* srv, uint64_t ticket, int32_t* done, double* latency_s);
+/* Step until every submitted request is complete. */
+int sfft_server_drain(sfft_server* srv, void* hip_stream);
+int sfft_server_stats_get(const sfft_server* srv, sfft_server_stats* out);
+/* Waits for all device work, then frees the server and its memory budget. */
+void sfft_server_destroy(sfft_server* srv);
 
 #ifdef __cplusplus
 }

@@ -145,3 +145,46 @@ def signal_words(sig) -> np.ndarray:
         return re
     im = quantize(np.asarray(sig.im).ravel(), sig.F, sig.f)
     return np.stack([re, im], 1).ravel()
+
+
+class Server:
+    """Continuous-batching request loop over libsfft's sfft_server_*."""
+
+    def __init__(self, mem_budget_bytes: int, max_active: int = 0, dry_run: bool = False,
+                 dry_bitmac_per_s: float = 0.0):
+        cfg = S.sfft_server_cfg(int(mem_budget_bytes), int(max_active), S.SFFT_SERVER_DRYRUN if dry_run else 0,
+                                float(dry_bitmac_per_s))
+        self.dry = dry_run
+        self.handle = S.sfft_server_create(cfg)
+        self._keep = {}
+
+    def submit(self, dims, length, F, f, is_complex, params, ct_in=None, ct_out=None) -> int:
+        shp = S.shape(dims, length, F, f, is_complex)
+        t = S.sfft_server_submit(self.handle, shp, params, ct_in.data_ptr() if ct_in is not None else None,
+                                 ct_out.data_ptr() if ct_out is not None else None)
+        self._keep[t] = (ct_in, ct_out)  # the buffers must outlive the request
+        return t
+
+    def step(self, stream=None) -> int:
+        return S.sfft_server_step(self.handle, None if self.dry else _stream_ptr(stream))
+
+    def drain(self, stream=None) -> None:
+        S.sfft_server_drain(self.handle, None if self.dry else _stream_ptr(stream))
+
+    def poll(self, ticket):
+        return S.sfft_server_poll(self.handle, ticket)
+
+    def stats(self):
+        return S.sfft_server_stats_get(self.handle)
+
+    def close(self):
+        if self.handle:
+            S.sfft_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,6 +11,7 @@
 #include "../../include/sfft.h"
 #include "device.hpp"
 #include "netlist.hpp"
+#include "plan_internal.hpp"
 #include "schedule.hpp"
 
 using namespace sfft;
@@ -29,6 +30,13 @@ int hip_fail(hipError_t e, const char* where)
 {
     return fail(SFFT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
+
+}  // namespace
+
+int sfft_fail(int code, const std::string& msg) { return fail(code, msg); }
+int sfft_hip_fail(hipError_t e, const char* where) { return hip_fail(e, where); }
+
+namespace {
 
 bool params_ok(const sfft_params* p, std::string* why)
 {
@@ -151,17 +159,89 @@ int decrypt_row(const uint32_t* row, const uint32_t* sk, int n1, int kw, int k)
 
 }  // namespace
 
-struct sfft_plan {
-    sfft_shape shape;
-    sfft_params params;
-    Geo geo;
-    ProdCfg cfg;
-    Schedule sched;
-    ProdItem* d_prods = nullptr;
-    LinItem* d_lins = nullptr;
-    LinItem* d_final = nullptr;
-    sfft_plan_info info;
-};
+struct sfft_plan : PlanCore {};
+
+namespace {
+// Compile the circuit of a shape for params: netlist, noise check, sharing,
+// lowering.  Host only.
+int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* sched, sfft_plan_info* info)
+{
+    std::string why;
+    if (!shape_ok(shape, &why)) return fail(SFFT_EINVAL, why);
+    if (!params_ok(params, &why)) return fail(SFFT_EINVAL, why);
+    if (params->eta != 1) return fail(SFFT_EUNSUPPORTED, "only eta = 1 is implemented");
+    try {
+        const Geo geo = geo_of(params);
+        const Compact c = compact(build_fft_netlist(to_shape(shape)));
+        const int need = noise_bits(c, (int64_t)geo.nct);
+        if (need > params->k)
+            return fail(SFFT_ENOISE, "k = " + std::to_string(params->k) +
+                                         " is below the circuit's noise bound (needs " + std::to_string(need) +
+                                         " bits at this Nct)");
+        const NetStats st = netlist_stats(c);
+        *sched = lower(share(c));
+        sfft_plan_info& in = *info;
+        std::memset(&in, 0, sizeof(in));
+        in.nodes = st.nodes;
+        in.gates = st.gates;
+        in.products = st.products;
+        in.exec_products = sched->n_products;
+        in.levels = (int64_t)sched->levels.size() - 1;
+        in.max_level_products = sched->max_level_products;
+        in.n_inputs = c.n_inputs;
+        in.n_outputs = (int64_t)c.outputs.size();
+        in.ws_cts = sched->n_slots;
+        in.exec_steps = (int64_t)sched->levels.size() + 1;
+        in.k_required = choose_k(c, params->n_lwe);
+        const std::string h = netlist_hash(c);
+        std::memcpy(in.netlist_sha256, h.c_str(), 64);
+        in.netlist_sha256[64] = 0;
+        return SFFT_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SFFT_ENOMEM, "out of host memory compiling the plan");
+    } catch (const std::exception& e) {
+        return fail(SFFT_EINVAL, e.what());
+    }
+}
+}  // namespace
+
+namespace sfft {
+
+PlanCore::~PlanCore()
+{
+    // work enqueued with this plan may still read its tables
+    if (d_prods || d_lins || d_final) (void)hipDeviceSynchronize();
+    if (d_prods) (void)hipFree(d_prods);
+    if (d_lins) (void)hipFree(d_lins);
+    if (d_final) (void)hipFree(d_final);
+}
+
+int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upload, PlanCore* pl)
+{
+    const int rc = compile_plan(shape, params, &pl->sched, &pl->info);
+    if (rc != SFFT_OK) return rc;
+    pl->shape = *shape;
+    pl->params = *params;
+    pl->geo = geo_of(params);
+    pl->points = shape->dims == 1 ? shape->len : (int64_t)shape->len * shape->len;
+    if (!product_config(pl->geo, &pl->cfg)) return fail(SFFT_EUNSUPPORTED, "no kernel configuration for this geometry");
+    if (!upload) return SFFT_OK;
+    auto put = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
+        *dst = nullptr;
+        if (!bytes) return hipSuccess;
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = put(pl->sched.prods.data(), pl->sched.prods.size() * sizeof(ProdItem), (void**)&pl->d_prods);
+    if (e == hipSuccess) e = put(pl->sched.lins.data(), pl->sched.lins.size() * sizeof(LinItem), (void**)&pl->d_lins);
+    if (e == hipSuccess)
+        e = put(pl->sched.final_lins.data(), pl->sched.final_lins.size() * sizeof(LinItem), (void**)&pl->d_final);
+    if (e != hipSuccess) return hip_fail(e, "plan upload");
+    return SFFT_OK;
+}
+
+}  // namespace sfft
 
 extern "C" {
 
@@ -259,49 +339,6 @@ int sfft_encrypt(const sfft_params* p, const uint32_t* pk_dev, const int32_t* fi
     return SFFT_OK;
 }
 
-namespace {
-// Compile the circuit of a shape for params: netlist, noise check, sharing,
-// lowering.  Host only.
-int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* sched, sfft_plan_info* info)
-{
-    std::string why;
-    if (!shape_ok(shape, &why)) return fail(SFFT_EINVAL, why);
-    if (!params_ok(params, &why)) return fail(SFFT_EINVAL, why);
-    if (params->eta != 1) return fail(SFFT_EUNSUPPORTED, "only eta = 1 is implemented");
-    try {
-        const Geo geo = geo_of(params);
-        const Compact c = compact(build_fft_netlist(to_shape(shape)));
-        const int need = noise_bits(c, (int64_t)geo.nct);
-        if (need > params->k)
-            return fail(SFFT_ENOISE, "k = " + std::to_string(params->k) +
-                                         " is below the circuit's noise bound (needs " + std::to_string(need) +
-                                         " bits at this Nct)");
-        const NetStats st = netlist_stats(c);
-        *sched = lower(share(c));
-        sfft_plan_info& in = *info;
-        std::memset(&in, 0, sizeof(in));
-        in.nodes = st.nodes;
-        in.gates = st.gates;
-        in.products = st.products;
-        in.exec_products = sched->n_products;
-        in.levels = (int64_t)sched->levels.size() - 1;
-        in.max_level_products = sched->max_level_products;
-        in.n_inputs = c.n_inputs;
-        in.n_outputs = (int64_t)c.outputs.size();
-        in.ws_cts = sched->n_slots;
-        in.exec_steps = (int64_t)sched->levels.size() + 1;
-        in.k_required = choose_k(c, params->n_lwe);
-        const std::string h = netlist_hash(c);
-        std::memcpy(in.netlist_sha256, h.c_str(), 64);
-        in.netlist_sha256[64] = 0;
-        return SFFT_OK;
-    } catch (const std::bad_alloc&) {
-        return fail(SFFT_ENOMEM, "out of host memory compiling the plan");
-    } catch (const std::exception& e) {
-        return fail(SFFT_EINVAL, e.what());
-    }
-}
-}  // namespace
 
 int sfft_analyze(const sfft_shape* shape, const sfft_params* params, sfft_plan_info* info)
 {
@@ -316,32 +353,10 @@ int sfft_plan_create(const sfft_shape* shape, const sfft_params* params, sfft_pl
     *out = nullptr;
     sfft_plan* pl = new (std::nothrow) sfft_plan();
     if (!pl) return fail(SFFT_ENOMEM, "out of host memory");
-    int rc = compile_plan(shape, params, &pl->sched, &pl->info);
+    const int rc = plan_core_build(shape, params, true, pl);
     if (rc != SFFT_OK) {
         delete pl;
         return rc;
-    }
-    pl->shape = *shape;
-    pl->params = *params;
-    pl->geo = geo_of(params);
-    if (!product_config(pl->geo, &pl->cfg)) {
-        delete pl;
-        return fail(SFFT_EUNSUPPORTED, "no kernel configuration for this geometry");
-    }
-    auto upload = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
-        *dst = nullptr;
-        if (!bytes) return hipSuccess;
-        hipError_t e = hipMalloc(dst, bytes);
-        if (e != hipSuccess) return e;
-        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-    };
-    hipError_t e = upload(pl->sched.prods.data(), pl->sched.prods.size() * sizeof(ProdItem), (void**)&pl->d_prods);
-    if (e == hipSuccess) e = upload(pl->sched.lins.data(), pl->sched.lins.size() * sizeof(LinItem), (void**)&pl->d_lins);
-    if (e == hipSuccess)
-        e = upload(pl->sched.final_lins.data(), pl->sched.final_lins.size() * sizeof(LinItem), (void**)&pl->d_final);
-    if (e != hipSuccess) {
-        sfft_plan_destroy(pl);
-        return hip_fail(e, "plan upload");
     }
     *out = pl;
     return SFFT_OK;
@@ -361,14 +376,7 @@ int sfft_plan_workspace_bytes(const sfft_plan* plan, int64_t* bytes)
     return SFFT_OK;
 }
 
-void sfft_plan_destroy(sfft_plan* plan)
-{
-    if (!plan) return;
-    if (plan->d_prods) (void)hipFree(plan->d_prods);
-    if (plan->d_lins) (void)hipFree(plan->d_lins);
-    if (plan->d_final) (void)hipFree(plan->d_final);
-    delete plan;
-}
+void sfft_plan_destroy(sfft_plan* plan) { delete plan; }
 
 int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, const uint32_t* ct_in_dev,
                        uint32_t* ct_out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream)
@@ -389,15 +397,18 @@ int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, cons
         if (st < (int32_t)S.levels.size()) {
             const LevelWork& lw = S.levels[st];
             if (lw.prod_count) {
-                hipError_t e = launch_products(b, g, plan->cfg, plan->d_prods + lw.prod_begin, lw.prod_count, s);
+                const ProdSeg seg{plan->d_prods + lw.prod_begin, b, 0, 0};
+                hipError_t e = launch_products(g, plan->cfg, nullptr, 1, seg, lw.prod_count, s);
                 if (e != hipSuccess) return hip_fail(e, "product launch");
             }
             for (const auto& pass : lw.lin) {
-                hipError_t e = launch_linear(b, g, plan->d_lins + pass.first, pass.second, s);
+                const LinSeg seg{plan->d_lins + pass.first, b, 0, 0};
+                hipError_t e = launch_linear(g, nullptr, 1, seg, pass.second, s);
                 if (e != hipSuccess) return hip_fail(e, "linear launch");
             }
         } else if (!S.final_lins.empty()) {
-            hipError_t e = launch_linear(b, g, plan->d_final, (int64_t)S.final_lins.size(), s);
+            const LinSeg seg{plan->d_final, b, 0, 0};
+            hipError_t e = launch_linear(g, nullptr, 1, seg, (int64_t)S.final_lins.size(), s);
             if (e != hipSuccess) return hip_fail(e, "output launch");
         }
     }

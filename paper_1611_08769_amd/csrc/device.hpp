@@ -46,13 +46,31 @@ struct KCfg {
 
 bool product_config(const Geo& g, ProdCfg* cfg);
 
-// One launch over `count` product items read from device memory.
-hipError_t launch_products(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items,
-                           int64_t count, hipStream_t s);
+// A run of work items sharing one set of buffers (one request).  A launch
+// covers the concatenation of its segments; `first` is the global index of
+// the segment's first item within the launch.
+struct ProdSeg {
+    const ProdItem* items;
+    Bufs bufs;
+    uint32_t first;
+    uint32_t pad;
+};
+struct LinSeg {
+    const LinItem* items;
+    Bufs bufs;
+    uint32_t first;
+    uint32_t pad;
+};
+
+// One launch over `total` product items in nseg segments: d_segs in device
+// memory when nseg > 1, else seg0 (by value).
+hipError_t launch_products(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                           int64_t total, hipStream_t s);
 // One product item passed by value (single gates).
 hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item,
                               hipStream_t s);
-hipError_t launch_linear(const Bufs& b, const Geo& g, const LinItem* d_items, int64_t count, hipStream_t s);
+hipError_t launch_linear(const Geo& g, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
+                         hipStream_t s);
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s);
 
 // Encryption of n_ct bits: out[i] = mu_i G + R_i A with R_i drawn from

@@ -118,9 +118,9 @@ __device__ void finish_element(const Bufs& bufs, const Geo& g, const ProdItem& i
 // q covers digits 4 (lane % LPR + LPR q) .. +3, read with one ds_read_b128),
 // up to RPLMAX rows per lane.
 template <int THREADS, int LPR, int DPL, int RPLMAX, bool ENC>
-__global__ void __launch_bounds__(THREADS) k_product(Bufs bufs, Geo g, const ProdItem* __restrict__ items,
-                                                     ProdItem one, KCfg kc, uint64_t seed, uint64_t first_id,
-                                                     MuBits mu)
+__global__ void __launch_bounds__(THREADS) k_product(Geo g, KCfg kc, const ProdSeg* __restrict__ segs, int nseg,
+                                                     ProdSeg seg0, ProdItem one, uint32_t ybase, uint64_t seed,
+                                                     uint64_t first_id, MuBits mu)
 {
     constexpr int NW = THREADS / 64;
     constexpr int RPW = 64 / LPR;      // rows per wave per row-iteration
@@ -134,7 +134,21 @@ __global__ void __launch_bounds__(THREADS) k_product(Bufs bufs, Geo g, const Pro
     static_assert(DPL % 4 == 0, "digit slots come in groups of 4");
 
     extern __shared__ uint32_t lds[];
-    ProdItem it = items ? items[blockIdx.y] : one;
+    // work item of this workgroup: segment (a request's buffers and items) by
+    // binary search over the segments' first global item index
+    const uint32_t y = blockIdx.y + ybase;
+    ProdSeg sg = seg0;
+    if (nseg > 1) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].first <= y) lo = mid;
+            else hi = mid - 1;
+        }
+        sg = segs[lo];
+    }
+    const Bufs bufs = sg.bufs;
+    ProdItem it = sg.items ? sg.items[y - sg.first] : one;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rsub = lane / LPR, lq = lane % LPR;
     const int W = g.W, kw = g.kw, nd = kc.nd, wd = kc.wd;
@@ -143,18 +157,20 @@ __global__ void __launch_bounds__(THREADS) k_product(Bufs bufs, Geo g, const Pro
 
     uint64_t dst_shift = 0, ct_id = 0;
     if (ENC) {
-        ct_id = first_id + blockIdx.y;
-        dst_shift = (uint64_t)blockIdx.y * (uint64_t)bufs.ct_words;
-        it.cG[0] = (int8_t)((mu.w[blockIdx.y >> 5] >> (blockIdx.y & 31)) & 1u);
+        ct_id = first_id + y;
+        dst_shift = (uint64_t)y * (uint64_t)bufs.ct_words;
+        it.cG[0] = (int8_t)((mu.w[y >> 5] >> (y & 31)) & 1u);
     }
     const uint32_t* Lp = ENC ? nullptr : ctp(bufs, it.L);
     const uint32_t* Rp = ctp(bufs, it.R);
     const uint64_t M64 = (uint64_t)(g.nct + 63) / 64;
     const uint64_t enc_base = sm_mix(seed + 4ull * 0x9E3779B97F4A7C15ull);
 
+    // Ls is double-buffered by chunk parity: a wave still looking up chunk c
+    // reads its half while faster waves stage chunk c+1 into the other.
     uint32_t* Rs = lds;            // 32 x W raw words of the chunk's rows of R
-    uint32_t* Ls = Rs + 32 * W;    // TR words of L (this chunk's 32 bits of each row); TR % 4 == 0
-    uint32_t* T = Ls + TR;         // 8 groups x 16 subset sums x st digit slots, 16-byte aligned
+    uint32_t* Ls = Rs + 32 * W;    // 2 x TR words of L (a chunk's 32 bits of each row); TR % 4 == 0
+    uint32_t* T = Ls + 2 * TR;     // 8 groups x 16 subset sums x st digit slots, 16-byte aligned
     for (int q = tid; q < kGroups * 16 * st; q += THREADS) T[q] = 0;  // empty subsets, padding slots
 
     // table tasks of this thread: (group, digit slot) -> word offset and shift
@@ -218,9 +234,10 @@ __global__ void __launch_bounds__(THREADS) k_product(Bufs bufs, Geo g, const Pro
             const int idx = tid + q * THREADS;
             if (idx < chunk_words) Rs[idx] = rpf[q];
         }
+        uint32_t* Lc = Ls + (c & 1) * TR;
 #pragma unroll
         for (int q = 0; q < LR; q++)
-            if (tid + q * THREADS < TR) Ls[tid + q * THREADS] = lpf[q];
+            if (tid + q * THREADS < TR) Lc[tid + q * THREADS] = lpf[q];
         if (c + 1 < nchunks) {
             load_R(c + 1);
             load_L(c + 1);
@@ -260,7 +277,7 @@ __global__ void __launch_bounds__(THREADS) k_product(Bufs bufs, Geo g, const Pro
 #pragma unroll
         for (int i = 0; i < RPLMAX; i++) {
             if (i < rpl) {
-                const uint32_t Lw = Ls[(wave * rpl + i) * RPW + rsub];
+                const uint32_t Lw = Lc[(wave * rpl + i) * RPW + rsub];
 #pragma unroll
                 for (int grp = 0; grp < kGroups; grp++) {
                     const uint32_t idx = __builtin_amdgcn_ubfe(Lw, 4 * grp, 4);
@@ -309,9 +326,22 @@ __global__ void __launch_bounds__(THREADS) k_product(Bufs bufs, Geo g, const Pro
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_linear(Bufs bufs, Geo g, const LinItem* __restrict__ items, LinItem one)
+__global__ void __launch_bounds__(kThreads) k_linear(Geo g, const LinSeg* __restrict__ segs, int nseg, LinSeg seg0,
+                                                     LinItem one, uint32_t ybase)
 {
-    const LinItem it = items ? items[blockIdx.y] : one;
+    const uint32_t y = blockIdx.y + ybase;
+    LinSeg sg = seg0;
+    if (nseg > 1) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].first <= y) lo = mid;
+            else hi = mid - 1;
+        }
+        sg = segs[lo];
+    }
+    const Bufs bufs = sg.bufs;
+    const LinItem it = sg.items ? sg.items[y - sg.first] : one;
     const int task = blockIdx.x * kThreads + threadIdx.x;
     if (task >= g.nct * g.n1) return;
     const int row = task / g.n1, e = task % g.n1;
@@ -332,8 +362,9 @@ __global__ void __launch_bounds__(kThreads) k_linear(Bufs bufs, Geo g, const Lin
 }
 
 template <int THREADS, int LPR, int DPL, int RPLMAX, bool ENC>
-hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, const ProdItem& one,
-                    int64_t count, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
+hipError_t launch_t(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                    const ProdItem& one, int64_t total, uint64_t seed, uint64_t first_id, const MuBits* mu,
+                    hipStream_t s)
 {
     static int attr_bytes = 64 * 1024;
     if (cfg.lds_bytes > attr_bytes) {
@@ -345,12 +376,11 @@ hipError_t launch_t(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdI
     const int tiles = (g.nct + cfg.tr - 1) / cfg.tr;
     const KCfg kc{cfg.nd, cfg.wd, cfg.st, cfg.rpl, cfg.tr, 1u};
     MuBits none{};
-    for (int64_t b0 = 0; b0 < count; b0 += 65535) {
-        const int64_t n = count - b0 < 65535 ? count - b0 : 65535;
+    for (int64_t b0 = 0; b0 < total; b0 += 65535) {
+        const int64_t n = total - b0 < 65535 ? total - b0 : 65535;
         dim3 grid(tiles, (unsigned)n);
-        hipLaunchKernelGGL((k_product<THREADS, LPR, DPL, RPLMAX, ENC>), grid, dim3(THREADS), cfg.lds_bytes, s, b, g,
-                           d_items ? d_items + b0 : nullptr, one, kc, seed, first_id + (uint64_t)b0,
-                           mu ? *mu : none);
+        hipLaunchKernelGGL((k_product<THREADS, LPR, DPL, RPLMAX, ENC>), grid, dim3(THREADS), cfg.lds_bytes, s, g, kc,
+                           d_segs, nseg, seg0, one, (uint32_t)b0, seed, first_id, mu ? *mu : none);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -370,13 +400,14 @@ constexpr Tiling kTilings[] = {
 };
 
 template <bool ENC>
-hipError_t dispatch(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, const ProdItem& one,
-                    int64_t count, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
+hipError_t dispatch(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                    const ProdItem& one, int64_t total, uint64_t seed, uint64_t first_id, const MuBits* mu,
+                    hipStream_t s)
 {
 #define CASE(I)                                                                                              \
     if (cfg.tiling == I)                                                                                     \
         return launch_t<kTilings[I].threads, kTilings[I].lpr, kTilings[I].dpl, kTilings[I].rplmax, ENC>(     \
-            b, g, cfg, d_items, one, count, seed, first_id, mu, s);
+            g, cfg, d_segs, nseg, seg0, one, total, seed, first_id, mu, s);
     CASE(0)
     CASE(1)
     CASE(2)
@@ -414,32 +445,35 @@ bool product_config(const Geo& g, ProdCfg* cfg)
     cfg->rpl = rpl;
     cfg->tr = per_iter * rpl;
     const int pi = (kPassMinRows + per_iter - 1) / per_iter;
-    const int main_words = 32 * g.W + cfg->tr + kGroups * 16 * cfg->st;
+    const int main_words = 32 * g.W + 2 * cfg->tr + kGroups * 16 * cfg->st;
     const int epi_words = 2 * per_iter * pi * cfg->st;
     cfg->lds_bytes = 4 * (main_words > epi_words ? main_words : epi_words);
     return cfg->lds_bytes <= 160 * 1024;
 }
 
-hipError_t launch_products(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem* d_items, int64_t count,
-                           hipStream_t s)
+hipError_t launch_products(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg,
+                           const ProdSeg& seg0, int64_t total, hipStream_t s)
 {
-    if (count <= 0) return hipSuccess;
+    if (total <= 0) return hipSuccess;
     ProdItem none{};
-    return dispatch<false>(b, g, cfg, d_items, none, count, 0, 0, nullptr, s);
+    return dispatch<false>(g, cfg, d_segs, nseg, seg0, none, total, 0, 0, nullptr, s);
 }
 
 hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, hipStream_t s)
 {
-    return dispatch<false>(b, g, cfg, nullptr, item, 1, 0, 0, nullptr, s);
+    const ProdSeg seg0{nullptr, b, 0, 0};
+    return dispatch<false>(g, cfg, nullptr, 1, seg0, item, 1, 0, 0, nullptr, s);
 }
 
-hipError_t launch_linear(const Bufs& b, const Geo& g, const LinItem* d_items, int64_t count, hipStream_t s)
+hipError_t launch_linear(const Geo& g, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
+                         hipStream_t s)
 {
     LinItem none{};
     const int blocks = (g.nct * g.n1 + kThreads - 1) / kThreads;
-    for (int64_t b0 = 0; b0 < count; b0 += 65535) {
-        const int64_t n = count - b0 < 65535 ? count - b0 : 65535;
-        hipLaunchKernelGGL(k_linear, dim3(blocks, (unsigned)n), dim3(kThreads), 0, s, b, g, d_items + b0, none);
+    for (int64_t b0 = 0; b0 < total; b0 += 65535) {
+        const int64_t n = total - b0 < 65535 ? total - b0 : 65535;
+        hipLaunchKernelGGL(k_linear, dim3(blocks, (unsigned)n), dim3(kThreads), 0, s, g, d_segs, nseg, seg0, none,
+                           (uint32_t)b0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -449,7 +483,9 @@ hipError_t launch_linear(const Bufs& b, const Geo& g, const LinItem* d_items, in
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s)
 {
     const int blocks = (g.nct * g.n1 + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_linear, dim3(blocks, 1), dim3(kThreads), 0, s, b, g, (const LinItem*)nullptr, item);
+    const LinSeg seg0{nullptr, b, 0, 0};
+    hipLaunchKernelGGL(k_linear, dim3(blocks, 1), dim3(kThreads), 0, s, g, (const LinSeg*)nullptr, 1, seg0, item,
+                       0u);
     return hipGetLastError();
 }
 
@@ -468,7 +504,8 @@ hipError_t launch_encrypt(const Bufs& b, const Geo& g, const ProdCfg& cfg, const
     one.E[0] = -1;
     one.cP[0] = 1;
     for (int i = 1; i < kMaxOut; i++) one.dst[i] = one.E[i] = -1;
-    return dispatch<true>(b, g, cfg, nullptr, one, n_ct, seed, first_id, &mu, s);
+    const ProdSeg seg0{nullptr, b, 0, 0};
+    return dispatch<true>(g, cfg, nullptr, 1, seg0, one, n_ct, seed, first_id, &mu, s);
 }
 
 }  // namespace sfft

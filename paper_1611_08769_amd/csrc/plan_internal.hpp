@@ -1,0 +1,40 @@
+// A compiled encrypted-FFT plan as shared by the plan ABI and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/sfft.h"
+#include "device.hpp"
+#include "schedule.hpp"
+
+namespace sfft {
+
+struct PlanCore {
+    sfft_shape shape{};
+    sfft_params params{};
+    Geo geo{};
+    ProdCfg cfg{};
+    Schedule sched;
+    sfft_plan_info info{};
+    int64_t points = 0;  // FFT points (len or len^2)
+    ProdItem* d_prods = nullptr;
+    LinItem* d_lins = nullptr;
+    LinItem* d_final = nullptr;
+
+    int64_t ct_words() const { return (int64_t)geo.nct * geo.W; }
+    int64_t ws_bytes() const { return sched.n_slots * ct_words() * 4; }
+    PlanCore() = default;
+    PlanCore(const PlanCore&) = delete;
+    PlanCore& operator=(const PlanCore&) = delete;
+    ~PlanCore();
+};
+
+// Compile (and, with upload, copy the work tables to the device).
+int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upload, PlanCore* out);
+
+}  // namespace sfft
+
+// status helpers shared by the ABI translation units (set sfft_last_error)
+int sfft_fail(int code, const std::string& msg);
+int sfft_hip_fail(hipError_t e, const char* where);

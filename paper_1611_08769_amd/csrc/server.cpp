@@ -1,0 +1,408 @@
+// Request loop: continuous batching of encrypted FFTs of different shapes.
+//
+// Every request runs its own compiled plan (a sequence of steps: product
+// levels and the linear passes after them).  A global step advances every
+// admitted request by one of its own steps; the product items of all
+// requests with the same ciphertext geometry go into one launch (one
+// segment per request), then their linear passes.  Requests are admitted in
+// arrival order while a workspace for their plan fits the device memory
+// budget and the number of requests in flight is below the limit, so
+// requests that arrive while others run join at their step 0 and overlap
+// with them on the device.  The paper's FFT evaluates butterflies
+// independently within each stage (section "FFT in FHE"); requests are
+// independent altogether, which is what makes the interleaving exact: each
+// request's ciphertexts are bit-identical alone and in the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sfft.h"
+#include "device.hpp"
+#include "netlist.hpp"
+#include "plan_internal.hpp"
+#include "schedule.hpp"
+
+using namespace sfft;
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over one device arena (offsets in bytes, 256-aligned).
+class Arena {
+public:
+    void reset(int64_t size)
+    {
+        size_ = size;
+        free_.clear();
+        if (size > 0) free_[0] = size;
+        used_ = peak_ = 0;
+    }
+    int64_t alloc(int64_t bytes)
+    {
+        bytes = (bytes + 255) / 256 * 256;
+        if (bytes == 0) bytes = 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                sizes_[off] = bytes;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off)
+    {
+        auto s = sizes_.find(off);
+        if (s == sizes_.end()) return;
+        int64_t bytes = s->second;
+        sizes_.erase(s);
+        used_ -= bytes;
+        int64_t start = off;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && next->first == off + bytes) {
+            bytes += next->second;
+            free_.erase(next);
+        }
+        auto prev = free_.lower_bound(off);
+        if (prev != free_.begin()) {
+            --prev;
+            if (prev->first + prev->second == off) {
+                start = prev->first;
+                bytes += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = bytes;
+    }
+    int64_t size() const { return size_; }
+    int64_t peak() const { return peak_; }
+
+private:
+    int64_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<int64_t, int64_t> free_, sizes_;
+};
+
+struct Request {
+    uint64_t ticket;
+    std::shared_ptr<PlanCore> plan;
+    const uint32_t* in;
+    uint32_t* out;
+    int64_t ws_off = -1;
+    int32_t step = 0;
+    double arrival = 0, done_at = -1;
+};
+
+}  // namespace
+
+struct sfft_server {
+    sfft_server_cfg cfg;
+    bool dry = false;
+    double vclock = 0;  // modelled time (dry-run)
+    uint8_t* arena_dev = nullptr;
+    Arena arena;
+    std::map<std::string, std::shared_ptr<PlanCore>> plans;
+    std::deque<std::unique_ptr<Request>> queue;
+    std::vector<std::unique_ptr<Request>> active;
+    std::map<uint64_t, std::unique_ptr<Request>> done;
+    uint64_t next_ticket = 1;
+    // segment staging (host pinned + device), reused every step
+    void* seg_host = nullptr;
+    void* seg_dev = nullptr;
+    size_t seg_cap = 0;
+    sfft_server_stats st{};
+};
+
+static std::string plan_key(const sfft_shape* s, const sfft_params* p)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d|%d/%d/%d/%d", s->dims, s->len, s->F, s->f, s->is_complex, p->n_lwe,
+                  p->k, p->m, p->eta);
+    return buf;
+}
+
+static double now_of(const sfft_server* sv) { return sv->dry ? sv->vclock : now_s(); }
+
+extern "C" {
+
+int sfft_server_create(const sfft_server_cfg* cfg, sfft_server** out)
+{
+    if (!cfg || !out) return sfft_fail(SFFT_EINVAL, "null argument");
+    *out = nullptr;
+    if (cfg->mem_budget_bytes <= 0 || cfg->max_active < 0) return sfft_fail(SFFT_EINVAL, "bad server configuration");
+    auto* sv = new (std::nothrow) sfft_server();
+    if (!sv) return sfft_fail(SFFT_ENOMEM, "out of host memory");
+    sv->cfg = *cfg;
+    sv->dry = (cfg->flags & SFFT_SERVER_DRYRUN) != 0;
+    sv->arena.reset(cfg->mem_budget_bytes);
+    if (!sv->dry) {
+        hipError_t e = hipMalloc((void**)&sv->arena_dev, (size_t)cfg->mem_budget_bytes);
+        if (e != hipSuccess) {
+            delete sv;
+            return sfft_fail(SFFT_ENOMEM, "cannot allocate the server's device memory budget");
+        }
+        sv->seg_cap = 1 << 20;  // bytes of segment lists per step
+        e = hipHostMalloc(&sv->seg_host, sv->seg_cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&sv->seg_dev, sv->seg_cap);
+        if (e != hipSuccess) {
+            sfft_server_destroy(sv);
+            return sfft_fail(SFFT_ENOMEM, "cannot allocate segment staging");
+        }
+    }
+    *out = sv;
+    return SFFT_OK;
+}
+
+int sfft_server_submit(sfft_server* sv, const sfft_shape* shape, const sfft_params* params,
+                       const uint32_t* ct_in_dev, uint32_t* ct_out_dev, uint64_t* ticket)
+{
+    if (!sv || !shape || !params || !ticket) return sfft_fail(SFFT_EINVAL, "null argument");
+    if (!sv->dry && (!ct_in_dev || !ct_out_dev)) return sfft_fail(SFFT_EINVAL, "null ciphertext buffer");
+    const std::string key = plan_key(shape, params);
+    std::shared_ptr<PlanCore> pc;
+    auto it = sv->plans.find(key);
+    if (it != sv->plans.end()) {
+        pc = it->second;
+    } else {
+        pc = std::make_shared<PlanCore>();
+        const int rc = plan_core_build(shape, params, !sv->dry, pc.get());
+        if (rc != SFFT_OK) return rc;
+        sv->plans[key] = pc;
+    }
+    if (pc->ws_bytes() > sv->arena.size())
+        return sfft_fail(SFFT_ENOMEM, "request workspace exceeds the server's memory budget");
+    auto r = std::make_unique<Request>();
+    r->ticket = sv->next_ticket++;
+    r->plan = pc;
+    r->in = ct_in_dev;
+    r->out = ct_out_dev;
+    r->arrival = now_of(sv);
+    *ticket = r->ticket;
+    sv->queue.push_back(std::move(r));
+    sv->st.submitted++;
+    return SFFT_OK;
+}
+
+int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
+{
+    if (!sv) return sfft_fail(SFFT_EINVAL, "null server");
+    hipStream_t s = (hipStream_t)hip_stream;
+    // admission: arrival order, by workspace footprint and slot limit
+    while (!sv->queue.empty()) {
+        if (sv->cfg.max_active > 0 && (int)sv->active.size() >= sv->cfg.max_active) break;
+        Request* r = sv->queue.front().get();
+        const int64_t off = sv->arena.alloc(std::max<int64_t>(r->plan->ws_bytes(), 1));
+        if (off < 0) break;
+        r->ws_off = off;
+        sv->active.push_back(std::move(sv->queue.front()));
+        sv->queue.pop_front();
+        sv->st.admitted++;
+    }
+    sv->st.max_active = std::max<int64_t>(sv->st.max_active, (int64_t)sv->active.size());
+    sv->st.peak_ws_bytes = std::max<int64_t>(sv->st.peak_ws_bytes, sv->arena.peak());
+    if (sv->active.empty()) {
+        if (pending) *pending = (int32_t)sv->queue.size();
+        return SFFT_OK;
+    }
+
+    // group this step's work by ciphertext geometry (k, n1)
+    struct Group {
+        const PlanCore* proto;
+        std::vector<ProdSeg> prods;
+        int64_t nprod = 0;
+        std::vector<std::vector<LinSeg>> lins;  // per linear sub-pass
+        std::vector<int64_t> nlin;
+    };
+    std::map<std::pair<int, int>, Group> groups;
+    double model_s = 0;
+    for (auto& rp : sv->active) {
+        Request* r = rp.get();
+        const PlanCore& pc = *r->plan;
+        const Schedule& S = pc.sched;
+        Group& G = groups[{pc.geo.k, pc.geo.n1}];
+        G.proto = &pc;
+        Bufs b{const_cast<uint32_t*>(r->in), r->out,
+               sv->dry ? nullptr : (uint32_t*)(sv->arena_dev + r->ws_off), nullptr, pc.ct_words()};
+        const int32_t st = r->step;
+        if (st < (int32_t)S.levels.size()) {
+            const LevelWork& lw = S.levels[st];
+            if (lw.prod_count) {
+                G.prods.push_back(ProdSeg{pc.d_prods + lw.prod_begin, b, (uint32_t)G.nprod, 0});
+                G.nprod += lw.prod_count;
+                sv->st.products += lw.prod_count;
+                model_s += (double)lw.prod_count * (double)pc.geo.nct * pc.geo.nct * pc.geo.nct;
+            }
+            for (size_t q = 0; q < lw.lin.size(); q++) {
+                if (G.lins.size() <= q) {
+                    G.lins.resize(q + 1);
+                    G.nlin.resize(q + 1, 0);
+                }
+                G.lins[q].push_back(LinSeg{pc.d_lins + lw.lin[q].first, b, (uint32_t)G.nlin[q], 0});
+                G.nlin[q] += lw.lin[q].second;
+            }
+        } else if (!S.final_lins.empty()) {
+            if (G.lins.empty()) {
+                G.lins.resize(1);
+                G.nlin.resize(1, 0);
+            }
+            G.lins[0].push_back(LinSeg{pc.d_final, b, (uint32_t)G.nlin[0], 0});
+            G.nlin[0] += (int64_t)S.final_lins.size();
+        }
+    }
+
+    if (!sv->dry) {
+        // stage every segment list in one host->device copy
+        size_t off = 0;
+        std::vector<std::pair<const void*, size_t>> places;
+        auto place = [&](const void* src, size_t bytes) -> size_t {
+            off = (off + 63) / 64 * 64;
+            const size_t at = off;
+            if (at + bytes > sv->seg_cap) return (size_t)-1;
+            std::memcpy((uint8_t*)sv->seg_host + at, src, bytes);
+            off += bytes;
+            return at;
+        };
+        struct Launch {
+            const Group* g;
+            int lin_pass;  // -1 = products
+            size_t at;
+        };
+        std::vector<Launch> launches;
+        for (auto& kv : groups) {
+            Group& G = kv.second;
+            if (G.nprod) {
+                const size_t at = place(G.prods.data(), G.prods.size() * sizeof(ProdSeg));
+                if (at == (size_t)-1) return sfft_fail(SFFT_ENOMEM, "segment staging full");
+                launches.push_back({&G, -1, at});
+            }
+            for (size_t q = 0; q < G.lins.size(); q++) {
+                if (!G.nlin[q]) continue;
+                const size_t at = place(G.lins[q].data(), G.lins[q].size() * sizeof(LinSeg));
+                if (at == (size_t)-1) return sfft_fail(SFFT_ENOMEM, "segment staging full");
+                launches.push_back({&G, (int)q, at});
+            }
+        }
+        hipError_t e = hipMemcpyAsync(sv->seg_dev, sv->seg_host, off, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return sfft_hip_fail(e, "segment upload");
+        // products of every group first, then linear passes in order
+        for (const Launch& L : launches) {
+            if (L.lin_pass >= 0) continue;
+            const Group& G = *L.g;
+            const PlanCore& pc = *G.proto;
+            e = launch_products(pc.geo, pc.cfg, (const ProdSeg*)((uint8_t*)sv->seg_dev + L.at), (int)G.prods.size(),
+                                G.prods[0], G.nprod, s);
+            if (e != hipSuccess) return sfft_hip_fail(e, "server product launch");
+            sv->st.launches++;
+        }
+        int max_pass = 0;
+        for (const Launch& L : launches) max_pass = std::max(max_pass, L.lin_pass + 1);
+        for (int q = 0; q < max_pass; q++) {
+            for (const Launch& L : launches) {
+                if (L.lin_pass != q) continue;
+                const Group& G = *L.g;
+                const PlanCore& pc = *G.proto;
+                e = launch_linear(pc.geo, (const LinSeg*)((uint8_t*)sv->seg_dev + L.at), (int)G.lins[q].size(),
+                                  G.lins[q][0], G.nlin[q], s);
+                if (e != hipSuccess) return sfft_hip_fail(e, "server linear launch");
+                sv->st.launches++;
+            }
+        }
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return sfft_hip_fail(e, "server step");
+    } else {
+        const double rate = sv->cfg.dry_bitmac_per_s > 0 ? sv->cfg.dry_bitmac_per_s : 1e15;
+        sv->vclock += model_s / rate + 1e-5;
+    }
+    sv->st.steps++;
+
+    // advance; retire finished requests
+    const double t = now_of(sv);
+    std::vector<std::unique_ptr<Request>> still;
+    for (auto& rp : sv->active) {
+        rp->step++;
+        if (rp->step >= (int32_t)rp->plan->sched.levels.size() + 1) {
+            rp->done_at = t;
+            sv->arena.release(rp->ws_off);
+            rp->ws_off = -1;
+            sv->st.completed++;
+            sv->st.gates += rp->plan->info.gates;
+            sv->st.fft_points += rp->plan->points;
+            sv->done[rp->ticket] = std::move(rp);
+        } else {
+            still.push_back(std::move(rp));
+        }
+    }
+    sv->active.swap(still);
+    if (pending) *pending = (int32_t)(sv->active.size() + sv->queue.size());
+    return SFFT_OK;
+}
+
+int sfft_server_poll(sfft_server* sv, uint64_t ticket, int32_t* done, double* latency_s)
+{
+    if (!sv || !done) return sfft_fail(SFFT_EINVAL, "null argument");
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) {
+        *done = 0;
+        if (latency_s) *latency_s = -1;
+        for (auto& r : sv->active)
+            if (r->ticket == ticket) return SFFT_OK;
+        for (auto& r : sv->queue)
+            if (r->ticket == ticket) return SFFT_OK;
+        return sfft_fail(SFFT_EINVAL, "unknown ticket");
+    }
+    *done = 1;
+    if (latency_s) *latency_s = it->second->done_at - it->second->arrival;
+    return SFFT_OK;
+}
+
+int sfft_server_drain(sfft_server* sv, void* hip_stream)
+{
+    if (!sv) return sfft_fail(SFFT_EINVAL, "null server");
+    int32_t pending = 1;
+    while (pending > 0) {
+        const size_t before = sv->active.size() + sv->queue.size();
+        const int rc = sfft_server_step(sv, hip_stream, &pending);
+        if (rc != SFFT_OK) return rc;
+        if (sv->active.empty() && pending > 0 && before == (size_t)pending)
+            return sfft_fail(SFFT_ENOMEM, "queued request cannot be admitted");
+    }
+    return SFFT_OK;
+}
+
+int sfft_server_stats_get(const sfft_server* sv, sfft_server_stats* out)
+{
+    if (!sv || !out) return sfft_fail(SFFT_EINVAL, "null argument");
+    *out = sv->st;
+    out->queued = (int64_t)sv->queue.size();
+    out->active = (int64_t)sv->active.size();
+    out->clock_s = sv->dry ? sv->vclock : now_s();
+    return SFFT_OK;
+}
+
+void sfft_server_destroy(sfft_server* sv)
+{
+    if (!sv) return;
+    if (sv->arena_dev) (void)hipDeviceSynchronize();  // enqueued steps may still use the arena
+    if (sv->arena_dev) (void)hipFree(sv->arena_dev);
+    if (sv->seg_dev) (void)hipFree(sv->seg_dev);
+    if (sv->seg_host) (void)hipHostFree(sv->seg_host);
+    delete sv;
+}
+
+}  // extern "C"

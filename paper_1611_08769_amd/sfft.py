@@ -38,6 +38,20 @@ class sfft_plan_info(ctypes.Structure):
                 ("netlist_sha256", ctypes.c_char * 65)]
 
 
+SFFT_SERVER_DRYRUN = 1
+
+
+class sfft_server_cfg(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("dry_bitmac_per_s", ctypes.c_double)]
+
+
+class sfft_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "admitted", "completed", "queued", "active", "steps",
+                                              "launches", "products", "gates", "fft_points", "max_active",
+                                              "peak_ws_bytes")] + [("clock_s", ctypes.c_double)]
+
+
 class SfftError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("sfft error %d: %s" % (code, msg))
@@ -69,6 +83,13 @@ _SIGS = {
     "sfft_decrypt": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, _vp]),
     "sfft_decrypt_bits": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
     "sfft_gate": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    "sfft_server_create": (ctypes.c_int, [_P(sfft_server_cfg), _P(_vp)]),
+    "sfft_server_submit": (ctypes.c_int, [_vp, _P(sfft_shape), _P(sfft_params), _vp, _vp, _P(ctypes.c_uint64)]),
+    "sfft_server_step": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
+    "sfft_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(ctypes.c_int32), _P(ctypes.c_double)]),
+    "sfft_server_drain": (ctypes.c_int, [_vp, _vp]),
+    "sfft_server_stats_get": (ctypes.c_int, [_vp, _P(sfft_server_stats)]),
+    "sfft_server_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -167,6 +188,44 @@ def sfft_decrypt_bits(p, sk_host_ptr, ct_ptr, n_ct, on_device, out_ptr) -> None:
 
 def sfft_gate(p, gate, x_ptr, y_ptr, out_ptr, stream) -> None:
     _check(_lib.sfft_gate(ctypes.byref(p), gate, x_ptr, y_ptr, out_ptr, stream))
+
+
+def sfft_server_create(cfg: sfft_server_cfg) -> int:
+    h = _vp()
+    _check(_lib.sfft_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def sfft_server_submit(srv, shp, p, ct_in_ptr, ct_out_ptr) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.sfft_server_submit(srv, ctypes.byref(shp), ctypes.byref(p), ct_in_ptr, ct_out_ptr, ctypes.byref(t)))
+    return t.value
+
+
+def sfft_server_step(srv, stream) -> int:
+    pend = ctypes.c_int32()
+    _check(_lib.sfft_server_step(srv, stream, ctypes.byref(pend)))
+    return pend.value
+
+
+def sfft_server_poll(srv, ticket):
+    done, lat = ctypes.c_int32(), ctypes.c_double()
+    _check(_lib.sfft_server_poll(srv, ticket, ctypes.byref(done), ctypes.byref(lat)))
+    return bool(done.value), lat.value
+
+
+def sfft_server_drain(srv, stream) -> None:
+    _check(_lib.sfft_server_drain(srv, stream))
+
+
+def sfft_server_stats_get(srv) -> sfft_server_stats:
+    st = sfft_server_stats()
+    _check(_lib.sfft_server_stats_get(srv, ctypes.byref(st)))
+    return st
+
+
+def sfft_server_destroy(srv) -> None:
+    _lib.sfft_server_destroy(srv)
 
 
 EXPORTED = sorted(_SIGS)

@@ -110,6 +110,9 @@ def _fft_case(dims, L, F, f, cplx, n, seed, sig=None):
 
 @pytest.mark.parametrize("dims,L,F,f,cplx", [
     (1, 2, 6, 3, True), (1, 4, 8, 4, True), (1, 8, 8, 4, False), (2, 4, 6, 3, False), (1, 8, 6, 3, True),
+    # k = 288: 20 digits per row (8 lanes per row, 512-row tiles, two tiles, ragged tail); this is the shape
+    # that exposed a race on the staged L words between waves at a chunk boundary
+    (1, 16, 8, 4, True),
 ])
 def test_fft_bit_exact_small(dims, L, F, f, cplx):
     """Whole encrypted FFTs: every output ciphertext equals the oracle's,
