@@ -67,8 +67,89 @@ def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
     }
 
 
+def run_batch(args):
+    """Independent 1D requests (length, word width and modulus differ per
+    request): all through the request loop at once vs one at a time."""
+    import torch
+    from paper_1611_08769_amd import api
+    from paper_1611_08769_amd import workloads as WL
+
+    sigs = WL.batch_requests(seed=4, count=args.requests)
+    reqs, plans = [], {}
+    for i, sig in enumerate(sigs):
+        p = api.size_params(1, sig.length, sig.F, sig.f, True, 1)
+        keys = api.keygen(p, 1000 + i)
+        ct_in = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=1000 + i)
+        key = (sig.length, sig.F, p.k)
+        if key not in plans:
+            plans[key] = api.Plan(1, sig.length, sig.F, sig.f, True, p)
+        plan = plans[key]
+        ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
+        reqs.append((sig, p, plan, ct_in, ct_out))
+    torch.cuda.synchronize()
+    gates = sum(r[2].info.gates for r in reqs)
+    points = sum(r[0].points for r in reqs)
+    bitmacs = sum(float(r[2].info.exec_products) * ((r[1].n_lwe + 1) * r[1].k) ** 3 for r in reqs)
+    print("[bench] batch of %d requests: %d gates, %.2e bit-MACs, %d distinct plans" % (
+        len(reqs), gates, bitmacs, len(plans)), file=sys.stderr, flush=True)
+
+    # one request at a time (same plans, same buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sig, p, plan, ct_in, ct_out in reqs:
+        plan.execute(ct_in, ct_out)
+        torch.cuda.synchronize()
+        plan._ws = None  # keep at most one plan workspace alive (stream-ordered reuse)
+    t_alone = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    alone_out = [r[4].clone() for r in reqs]
+    print("[bench] one at a time: %.2f s" % t_alone, file=sys.stderr, flush=True)
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(free * 0.7, args.budget_gb * 1e9))
+    srv = api.Server(budget, max_active=args.max_active)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [srv.submit(1, r[0].length, r[0].F, r[0].f, True, r[1], r[3], r[4]) for r in reqs]
+    srv.drain()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    st = srv.stats()
+    lat = [srv.poll(t)[1] for t in tickets]
+    same = all(torch.equal(a, r[4]) for a, r in zip(alone_out, reqs))
+    srv.close()
+    print("[bench] batched: %.2f s (%d steps, %d launches, max %d in flight); outputs identical to alone: %s" % (
+        t_batch, st.steps, st.launches, st.max_active, same), file=sys.stderr, flush=True)
+    return {
+        "metric": "encrypted gates/s (1 GPU, batched)",
+        "value": gates / t_batch,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "batch_1d_mixed", "requests": len(reqs), "lengths": "8..128", "F": "12/16/24",
+                   "n_lwe": 1, "distinct_plans": len(plans), "budget_gb": round(budget / 1e9, 1)},
+        "one_at_a_time_gates_per_s": gates / t_alone,
+        "speedup_vs_one_at_a_time": t_alone / t_batch,
+        "fft_points_per_s": points / t_batch,
+        "bitmac_per_s": bitmacs / t_batch,
+        "latency_p50_s": pct(lat, 50),
+        "latency_p99_s": pct(lat, 99),
+        "outputs_identical_to_alone": same,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=64, help="batch mode: number of requests")
+    ap.add_argument("--max-active", type=int, default=0, help="batch mode: requests in flight (0 = no limit)")
+    ap.add_argument("--budget-gb", type=float, default=120.0, help="batch mode: workspace memory budget")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
@@ -86,6 +167,9 @@ def main():
     from paper_1611_08769_amd import api
     from paper_1611_08769_amd import workloads as WL
 
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
     sig, n_lwe, seed = WL.workload(args.workload)
     cplx = sig.is_complex
     params = api.size_params(sig.dims, sig.length, sig.F, sig.f, cplx, n_lwe)
@@ -176,6 +260,17 @@ def main():
         },
         "cpu_baseline": None,
     }
+    # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+    # command, valid only for the kernel source they were taken with
+    tpath = os.path.join(ROOT, "profiles", "traffic_k_product_%s.json" % args.workload)
+    if os.path.exists(tpath):
+        import hashlib
+        tr = json.load(open(tpath))
+        src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "kernels.hip")
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() == tr.get("kernels_hip_sha256"):
+            out["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
+            alg = 3.0 * nct * nct / 8 * info.exec_products / max(1, info.levels)
+            out["roofline"]["traffic_vs_algorithmic_bytes"] = tr["traffic_bytes_per_launch"] / alg
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nct, params.n_lwe + 1, params.k // 32, info.gates, info.products,
                                            args.cpu_budget)
