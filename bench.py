@@ -145,6 +145,70 @@ def run_batch(args):
     }
 
 
+def copy_probe():
+    """A plain device copy of 1 GiB, three times: the reference against which
+    the HBM counters FETCH_SIZE and WRITE_SIZE are scaled."""
+    import torch
+    n = 256 * 1024 * 1024  # int32 elements = 1 GiB
+    x = torch.ones(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("[bench] copied 1 GiB three times", flush=True)
+
+
+def _counter_rows(path, kernel_prefix):
+    import csv
+    vals = []
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Kernel_Name"].startswith(kernel_prefix):
+                vals.append(float(row["Counter_Value"]))
+    return vals
+
+
+def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """HBM bytes per k_product launch (encryption launches excluded) from the
+    rocprofv3 counter CSVs of one bench step, each counter scaled by what it
+    reads for the 1 GiB copy; written next to the kernel trace summaries."""
+    import hashlib
+    prod = "void sfft::(anonymous namespace)::k_product<"
+    fetch = [v for v, n in zip(_counter_rows(fetch_csv, prod), _kernel_names(fetch_csv, prod)) if "false>" in n]
+    write = [v for v, n in zip(_counter_rows(write_csv, prod), _kernel_names(write_csv, prod)) if "false>" in n]
+    cf = max(_counter_rows(copy_fetch_csv, "__amd_rocclr_copyBuffer"))
+    cw = max(_counter_rows(copy_write_csv, "__amd_rocclr_copyBuffer"))
+    gib = float(1 << 30)
+    fetch_scale, write_scale = gib / (cf * 1024), gib / (cw * 1024)
+    fk, wk = sum(fetch) / len(fetch), sum(write) / len(write)
+    src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "kernels.hip")
+    out = {
+        "workload": workload,
+        "kernel": "k_product",
+        "kernels_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "launches": len(fetch),
+        "fetch_kib_per_launch": fk,
+        "write_kib_per_launch": wk,
+        "fetch_scale": fetch_scale,
+        "write_scale": write_scale,
+        "traffic_bytes_per_launch": (fk * fetch_scale + wk * write_scale) * 1024,
+        "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py "
+                   "--workload %s --steps 1 --warmup 0 --no-cpu-baseline; the same for python3 bench.py "
+                   "--copy-probe; python3 bench.py --traffic-summary on the four CSVs" % workload,
+    }
+    path = os.path.join(ROOT, "profiles", "traffic_k_product_%s.json" % workload)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def _kernel_names(path, kernel_prefix):
+    import csv
+    with open(path) as f:
+        return [r["Kernel_Name"] for r in csv.DictReader(f) if r["Kernel_Name"].startswith(kernel_prefix)]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=64, help="batch mode: number of requests")
@@ -156,13 +220,22 @@ def main():
     ap.add_argument("--workload", default="fft1d_n64_cplx_q16.8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB three times (counter reference)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/traffic_k_product_<workload>.json from rocprofv3 counter CSVs")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args.workload, *args.traffic_summary)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(requests and levels would shard across GPUs as described in the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe:
+        copy_probe()
+        return
     import torch
     from paper_1611_08769_amd import api
     from paper_1611_08769_amd import workloads as WL

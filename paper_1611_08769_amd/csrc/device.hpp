@@ -25,9 +25,11 @@ struct Geo {
 // Per-geometry choice of the product kernel's tiling.
 struct ProdCfg {
     int tiling;  // index into the kernel's tiling table
+    int threads; // threads per workgroup
+    int cg;      // 4-bit groups (4 rows of R each) per chunk
     int nd;    // 30-bit digits per element (ceil(k/30))
     int wd;    // digits per row (n1 * nd)
-    int lpr;   // lanes per output row (16 or 32)
+    int lpr;   // lanes per output row
     int dpl;   // digit slots per lane
     int st;    // digit slots per row (lpr * dpl >= wd)
     int rpw;   // rows per wave per row-iteration (64 / lpr)

@@ -8,18 +8,18 @@
 //
 // Method: four bits of a row of L select one of the 16 subset sums of four
 // consecutive rows of R (the method of Arlazarov, Dinic, Kronrod and Faradzev,
-// 1970).  Per chunk of 32 rows of R, a workgroup re-encodes the rows into
-// 30-bit digits (a sum of four digits fits 32 bits, so the tables need no
-// carries) and builds 8 tables x 16 subset sums in LDS, while the next
-// chunk's rows of R and words of L are already in flight into registers.
-// Each half-wave owns one output row and reads 32 consecutive digits of one
-// table entry per lookup (no LDS bank conflicts); every lane adds the digit
-// into a 64-bit accumulator (one v_mad_u64_u32, no carry flag).  Integer
-// VALU and LDS only.
+// 1970).  A workgroup owns a tile of output rows and walks R in chunks of 16
+// or 32 rows.  Per chunk it re-encodes the rows into 30-bit digits (a sum of
+// four digits fits 32 bits, so the tables need no carries) and builds the
+// chunk's tables of subset sums in LDS, one table set ahead of the lookups,
+// with one barrier per chunk.  Lanes of a row each read 4 consecutive digits
+// of the selected entry with one ds_read_b128 and add them into 64-bit
+// accumulators (v_mad_u64_u32 with a multiplier of one: no carry flags, no
+// zero-extended register pairs).  Integer VALU and LDS only.
 //
-// Epilogue (fused): per (row, element) the exact digit sums are carried into
-// P mod 2^k limb by limb and combined into up to four outputs
-// a L + b R + c P + g G + e E (AND, XOR, OR, NOT, NAND, XADD forms).
+// Epilogue (fused): per (row, element) the exact digit sums become 32-bit
+// column sums that feed, limb by limb, up to four outputs
+// a L + b R + c P + g G + e E (AND, XOR, OR, NOT, NAND, XADD forms) mod 2^k.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -30,20 +30,36 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kGroups = 8;          // 4-bit groups per 32-row chunk of R
 constexpr int kDigitBits = 30;      // 4 * (2^30 - 1) < 2^32
 constexpr uint32_t kDigitMask = (1u << kDigitBits) - 1u;
-constexpr int kMaxChunkWords = 4096;  // 32 rows of R, W <= 128 words per row
+constexpr int kMaxRowWords = 128;     // words per ciphertext row (W)
 constexpr int kMaxDigitSlots = 128;   // digits per row incl. padding
-constexpr int kPassMinRows = 64;      // rows staged per epilogue pass (at least)
 
-__device__ __forceinline__ uint32_t* ctp(const Bufs& b, int32_t ref)
+// Ciphertext words in the global address space: loads and stores through
+// these pointers compile to global (not flat) instructions, which the LDS
+// wait counter does not track, so an LDS wait never waits for them.
+typedef __attribute__((address_space(1))) uint32_t gword;
+
+__device__ __forceinline__ gword* ctp(const Bufs& b, int32_t ref)
 {
     const uint32_t u = (uint32_t)ref;
     const uint32_t buf = u >> 29;
     const uint64_t idx = u & 0x1FFFFFFFu;
     uint32_t* base = buf == B_IN ? b.in : buf == B_OUT ? b.out : buf == B_WS ? b.ws : b.aux;
-    return base + idx * (uint64_t)b.ct_words;
+    return (gword*)(base + idx * (uint64_t)b.ct_words);
+}
+
+// A work item read word by word through the global address space.
+template <class T>
+__device__ __forceinline__ T load_global(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "work items are whole words");
+    T v;
+    const gword* src = (const gword*)p;
+    uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); i++) w[i] = src[i];
+    return v;
 }
 
 __device__ __forceinline__ uint64_t sm_mix(uint64_t z)
@@ -60,78 +76,135 @@ struct MuBits {
     uint32_t w[kMaxEncPerLaunch / 32];
 };
 
-// Output row `row`, element e: carry the exact digit sums A[0..nd) (digit d
-// weighs 2^(30 d)) into the limbs of P mod 2^k and write every output of the
-// item, limb by limb with signed carries.
+// Row-iterations per epilogue pass: as many as the workgroup's share of LDS
+// (160 KB for 512 threads, 80 KB for 256, so that two of those fit a CU)
+// holds as 64-bit digit sums, so that few accumulators stay live across the
+// passes.
+constexpr int pass_iters(int threads, int rpw, int st, int rpl)
+{
+    const int cap = 160 * 1024 * threads / 512;
+    const int per = (threads / 64) * rpw * st * 8;
+    const int pi = cap / per;
+    return pi < 1 ? 1 : pi > rpl ? rpl : pi;
+}
+
+// Output row `row`, element e.  The exact digit sums A[0..nd) (digit d
+// weighs 2^(30 d)) are split into 32-bit column sums, 16 digits onto 15 limbs
+// (480 bits) at a time; every output a L + b R + c P + g G + e E of the item
+// is formed from the column sums limb by limb with one signed carry chain per
+// output, so that P is never carried on its own.  The words of L and R (and
+// of each output's E) for up to 8 limbs are loaded before the arithmetic that
+// uses them, so that their latencies overlap.
 __device__ void finish_element(const Bufs& bufs, const Geo& g, const ProdItem& it, const uint64_t* A, int nd,
-                               const uint32_t* Lp, const uint32_t* Rp, int row, int e, uint64_t dst_shift)
+                               const gword* Lp, const gword* Rp, int row, int e, uint64_t dst_shift)
 {
     const int br = row / g.k, tr = row % g.k;
     const size_t base = (size_t)row * g.W + (size_t)e * g.kw;
     int64_t carry[kMaxOut];
-    uint32_t* dst[kMaxOut];
-    const uint32_t* Ep[kMaxOut];
     bool needL = false, needR = false;
 #pragma unroll
     for (int o = 0; o < kMaxOut; o++) {
         carry[o] = 0;
-        dst[o] = o < it.nout ? ctp(bufs, it.dst[o]) + dst_shift : nullptr;
-        Ep[o] = (o < it.nout && it.E[o] >= 0) ? ctp(bufs, it.E[o]) : nullptr;
         if (o < it.nout) {
             needL |= it.cL[o] != 0;
             needR |= it.cR[o] != 0;
         }
     }
-    auto emit = [&](int l, uint32_t P) {
-        const size_t off = base + l;
-        const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
-        const uint32_t Lv = needL ? Lp[off] : 0u;
-        const uint32_t Rv = needR ? Rp[off] : 0u;
+    uint64_t next0 = 0, next1 = 0;  // column sums that reach the next group's limbs 0 and 1
+    for (int l0 = 0, d0 = 0; l0 < g.kw; l0 += 15, d0 += 16) {
+        uint64_t col[17];
+        col[0] = next0;
+        col[1] = next1;
 #pragma unroll
-        for (int o = 0; o < kMaxOut; o++) {
-            if (o >= it.nout) break;
-            int64_t s = carry[o] + (int64_t)it.cL[o] * Lv + (int64_t)it.cR[o] * Rv + (int64_t)it.cP[o] * P +
-                        (int64_t)it.cG[o] * Gv;
-            if (Ep[o]) s += (int64_t)it.cE[o] * Ep[o][off];
-            dst[o][off] = (uint32_t)s;
-            carry[o] = s >> 32;
+        for (int j = 2; j < 17; j++) col[j] = 0;
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            // digit d0 + t starts at bit 30 t of the group: limb j0, bit sh
+            const uint64_t a = d0 + t < nd ? A[d0 + t] : 0;
+            const int j0 = (30 * t) >> 5, sh = (30 * t) & 31;
+            const uint64_t hi = sh ? a >> (32 - sh) : a >> 32;  // bits 32 and up of a 2^sh
+            col[j0] += (uint32_t)(a << sh);
+            col[j0 + 1] += (uint32_t)hi;
+            col[j0 + 2] += hi >> 32;
         }
-    };
-    unsigned __int128 V = 0;  // pending bits from position `pos` up
-    int pos = 0, l = 0;
-    for (int d = 0; d < nd; d++) {
-        V += (unsigned __int128)A[d] << (kDigitBits * d - pos);
-        while (l < g.kw && pos + 32 <= kDigitBits * (d + 1)) {
-            emit(l++, (uint32_t)V);
-            V >>= 32;
-            pos += 32;
+        next0 = col[15];
+        next1 = col[16];
+        // the group's limbs in two halves of at most 8
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j1 = 8 * h, nh = h ? 7 : 8;
+            const int lh = l0 + j1;
+            const int nl = g.kw - lh < nh ? g.kw - lh : nh;
+            if (nl <= 0) break;
+            const size_t off = base + lh;
+            uint32_t Lv[8], Rv[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                Lv[j] = (needL && j < nl) ? Lp[off + j] : 0u;
+                Rv[j] = (needR && j < nl) ? Rp[off + j] : 0u;
+            }
+#pragma unroll
+            for (int o = 0; o < kMaxOut; o++) {
+                if (o < it.nout) {
+                    gword* dst = ctp(bufs, it.dst[o]) + dst_shift + off;
+                    const gword* Ep = it.E[o] >= 0 ? ctp(bufs, it.E[o]) + off : nullptr;
+                    uint32_t Ev[8];
+#pragma unroll
+                    for (int j = 0; j < 8; j++) Ev[j] = (Ep && j < nl) ? Ep[j] : 0u;
+#pragma unroll
+                    for (int j = 0; j < 8; j++) {
+                        if (j < nl) {
+                            const int l = lh + j;
+                            const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
+                            const int64_t s = carry[o] + (int64_t)it.cL[o] * Lv[j] + (int64_t)it.cR[o] * Rv[j] +
+                                              (int64_t)it.cP[o] * (int64_t)col[j1 + j] + (int64_t)it.cG[o] * Gv +
+                                              (int64_t)it.cE[o] * Ev[j];
+                            dst[j] = (uint32_t)s;
+                            carry[o] = s >> 32;
+                        }
+                    }
+                }
+            }
         }
-    }
-    while (l < g.kw) {
-        emit(l++, (uint32_t)V);
-        V >>= 32;
     }
 }
 
-// THREADS threads per workgroup, LPR lanes per output row, DPL digit slots
-// per lane held as DPL/4 groups of 4 consecutive digits (lane slot group
-// q covers digits 4 (lane % LPR + LPR q) .. +3, read with one ds_read_b128),
-// up to RPLMAX rows per lane.
-template <int THREADS, int LPR, int DPL, int RPLMAX, bool ENC>
+// THREADS threads per workgroup; LPR lanes per output row; DPL digit slots
+// per lane, held as DPL/4 quads of consecutive digits (quad q of a lane covers
+// slots 4 (lane % LPR + LPR q) .. +3 and is read with one ds_read_b128); RPL
+// rows per lane, so that a workgroup covers TR = (THREADS/64)(64/LPR) RPL rows
+// of the product; CG 4-bit groups (4 CG rows of R) per chunk.
+//
+// Chunks are pipelined with one barrier per chunk: while the waves look up
+// chunk c in one table set, they build chunk c+1's tables in the other from
+// rows of R staged in LDS the chunk before, stage chunk c+2's rows of R and
+// bits of L, and load chunk c+3's from memory into registers.  Within a chunk
+// the lookups of consecutive (row, group) steps form a software pipeline PD
+// steps deep: the table reads of step s + PD are issued before the additions
+// of step s.
+template <int THREADS, int LPR, int DPL, int RPL, int PD, int CG, bool ENC>
 __global__ void __launch_bounds__(THREADS) k_product(Geo g, KCfg kc, const ProdSeg* __restrict__ segs, int nseg,
                                                      ProdSeg seg0, ProdItem one, uint32_t ybase, uint64_t seed,
                                                      uint64_t first_id, MuBits mu)
 {
     constexpr int NW = THREADS / 64;
-    constexpr int RPW = 64 / LPR;      // rows per wave per row-iteration
-    constexpr int NQ = DPL / 4;        // 16-byte table reads per lookup
-    constexpr int st = LPR * DPL;      // digit slots per table entry
-    constexpr int RPF = (kMaxChunkWords + THREADS - 1) / THREADS;
-    constexpr int BT = (kGroups * kMaxDigitSlots + THREADS - 1) / THREADS;
-    constexpr int LR = (NW * RPW * RPLMAX + THREADS - 1) / THREADS;
-    constexpr int PI = (kPassMinRows + NW * RPW - 1) / (NW * RPW);  // row-iterations per epilogue pass
+    constexpr int RPW = 64 / LPR;          // rows per wave per row-iteration
+    constexpr int NQ = DPL / 4;            // 16-byte table reads per lookup
+    constexpr int st = LPR * DPL;          // digit slots per table entry
+    constexpr int SQ = st / 4;             // slot quads per table entry
+    constexpr int TR = NW * RPW * RPL;     // rows per workgroup
+    constexpr int CR = 4 * CG;             // rows of R per chunk
+    constexpr int TSZ = CG * 16 * st;      // words per table set
+    constexpr int NSTEP = RPL * CG;        // lookup steps per chunk
+    constexpr int NTASK = CG * SQ;         // table-build tasks per chunk
+    constexpr int RPF = (CR * kMaxRowWords + THREADS - 1) / THREADS;
+    constexpr int LR = (TR + THREADS - 1) / THREADS;
+    constexpr int PI = pass_iters(THREADS, RPW, st, RPL);  // row-iterations per epilogue pass
     constexpr int PASS_ROWS = NW * RPW * PI;
-    static_assert(DPL % 4 == 0, "digit slots come in groups of 4");
+    static_assert(DPL % 4 == 0, "digit slots come in quads");
+    static_assert(NTASK <= THREADS, "one table-build task per thread");
+    static_assert(CG == 4 || CG == 8, "chunks of 16 or 32 rows of R");
+    static_assert(PD >= 1 && PD < NSTEP, "pipeline depth");
 
     extern __shared__ uint32_t lds[];
     // work item of this workgroup: segment (a request's buffers and items) by
@@ -148,11 +221,10 @@ __global__ void __launch_bounds__(THREADS) k_product(Geo g, KCfg kc, const ProdS
         sg = segs[lo];
     }
     const Bufs bufs = sg.bufs;
-    ProdItem it = sg.items ? sg.items[y - sg.first] : one;
+    ProdItem it = sg.items ? load_global(sg.items + (y - sg.first)) : one;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rsub = lane / LPR, lq = lane % LPR;
     const int W = g.W, kw = g.kw, nd = kc.nd, wd = kc.wd;
-    const int rpl = kc.rpl, TR = kc.tr;
     const int row_base = blockIdx.x * TR;
 
     uint64_t dst_shift = 0, ct_id = 0;
@@ -161,165 +233,237 @@ __global__ void __launch_bounds__(THREADS) k_product(Geo g, KCfg kc, const ProdS
         dst_shift = (uint64_t)y * (uint64_t)bufs.ct_words;
         it.cG[0] = (int8_t)((mu.w[y >> 5] >> (y & 31)) & 1u);
     }
-    const uint32_t* Lp = ENC ? nullptr : ctp(bufs, it.L);
-    const uint32_t* Rp = ctp(bufs, it.R);
+    const gword* Lp = ENC ? nullptr : ctp(bufs, it.L);
+    const gword* Rp = ctp(bufs, it.R);
     const uint64_t M64 = (uint64_t)(g.nct + 63) / 64;
     const uint64_t enc_base = sm_mix(seed + 4ull * 0x9E3779B97F4A7C15ull);
 
-    // Ls is double-buffered by chunk parity: a wave still looking up chunk c
-    // reads its half while faster waves stage chunk c+1 into the other.
-    uint32_t* Rs = lds;            // 32 x W raw words of the chunk's rows of R
-    uint32_t* Ls = Rs + 32 * W;    // 2 x TR words of L (a chunk's 32 bits of each row); TR % 4 == 0
-    uint32_t* T = Ls + 2 * TR;     // 8 groups x 16 subset sums x st digit slots, 16-byte aligned
-    for (int q = tid; q < kGroups * 16 * st; q += THREADS) T[q] = 0;  // empty subsets, padding slots
-
-    // table tasks of this thread: (group, digit slot) -> word offset and shift
-    int bt_off[BT], bt_sh[BT], bt_dst[BT];
-    bool bt_ok[BT], bt_hi[BT];
-#pragma unroll
-    for (int q = 0; q < BT; q++) {
-        const int task = tid + q * THREADS;
-        bt_ok[q] = task < kGroups * wd;
-        const int slot = bt_ok[q] ? task % wd : 0, grp = bt_ok[q] ? task / wd : 0;
-        const int e = slot / nd, d = slot % nd, o = kDigitBits * d;
-        bt_off[q] = grp * 4 * W + e * kw + (o >> 5);
-        bt_sh[q] = o & 31;
-        bt_hi[q] = (o >> 5) + 1 < kw;
-        bt_dst[q] = grp * 16 * st + slot;
+    const int chunk_words = CR * W;
+    uint32_t* Rs = lds;                    // 2 x CR rows of R (raw words), by chunk parity
+    uint32_t* Ls = Rs + 2 * chunk_words;   // 3 x TR: a chunk's CR bits of each row of L, by chunk mod 3
+    uint32_t* T = Ls + 3 * TR;             // 2 table sets (CG groups x 16 subset sums x st slots), by chunk parity
+    // entry 0 of every group is the empty subset; the build never writes it
+    for (int q = tid; q < 2 * CG * st; q += THREADS) {
+        const int grp = q / st;  // over both table sets
+        T[grp * 16 * st + q % st] = 0;
     }
 
-    uint64_t acc[RPLMAX][DPL];
+    // table-build task of this thread: group `grp`, slot quad `sq` (slots
+    // 4 sq .. 4 sq + 3).  Tasks fill whole waves, so that the build costs as
+    // few wave instructions as possible.  A digit's mask keeps its bits below
+    // k (the top digit of an element ends early; its high word is then the
+    // next element's and is masked away); padding slots beyond wd get mask 0.
+    const bool bt_task = tid < NTASK;
+    const int bt_grp = bt_task ? tid / SQ : 0, bt_sq = bt_task ? tid % SQ : 0;
+    int bt_off[4], bt_sh[4];
+    uint32_t bt_mask[4];
 #pragma unroll
-    for (int i = 0; i < RPLMAX; i++)
+    for (int u = 0; u < 4; u++) {
+        const int slot = 4 * bt_sq + u;
+        const bool ok = bt_task && slot < wd;
+        const int e = ok ? slot / nd : 0, d = ok ? slot % nd : 0, o = kDigitBits * d;
+        bt_off[u] = bt_grp * 4 * W + e * kw + (o >> 5);
+        bt_sh[u] = o & 31;
+        const int bits = g.k - o < kDigitBits ? g.k - o : kDigitBits;
+        bt_mask[u] = ok ? (uint32_t)((1ull << bits) - 1) : 0u;
+    }
+    const int bt_dst = bt_grp * 16 * st + 4 * bt_sq;
+
+    uint64_t acc[RPL][DPL];
+#pragma unroll
+    for (int i = 0; i < RPL; i++)
 #pragma unroll
         for (int u = 0; u < DPL; u++) acc[i][u] = 0;
 
-    const int nchunks = g.nct / 32;
-    const int chunk_words = 32 * W;
+    const int nchunks = g.nct / CR;
     uint32_t rpf[RPF];
     uint32_t lpf[LR];
+    bool l_ok[LR];  // staged row of L lies in the product
+#pragma unroll
+    for (int q = 0; q < LR; q++) l_ok[q] = tid + q * THREADS < TR && row_base + tid + q * THREADS < g.nct;
     auto load_R = [&](int c) {
-        const uint32_t* src = Rp + (size_t)c * chunk_words;
+        const gword* src = Rp + (size_t)c * chunk_words;
 #pragma unroll
         for (int q = 0; q < RPF; q++) {
             const int idx = tid + q * THREADS;
-            rpf[q] = idx < chunk_words ? src[idx] : 0u;
+            rpf[q] = src[idx < chunk_words ? idx : chunk_words - 1];  // words past the chunk are not staged
         }
     };
+    auto stage_R = [&](int c) {
+        uint32_t* dst = Rs + (c & 1) * chunk_words;
+#pragma unroll
+        for (int q = 0; q < RPF; q++) {
+            const int idx = tid + q * THREADS;
+            if (idx < chunk_words) dst[idx] = rpf[q];
+        }
+    };
+    // bits [CR c, CR c + CR) of each row of L, in the low CR bits
     auto load_L = [&](int c) {
+        const int b = CR * c;
 #pragma unroll
         for (int q = 0; q < LR; q++) {
-            const int lr = tid + q * THREADS;
-            const int row = row_base + lr;
-            uint32_t v = 0;
-            if (lr < TR && row < g.nct) {
-                if (ENC) {
-                    const uint64_t widx = ct_id * (uint64_t)g.nct * M64 + (uint64_t)row * M64 + (uint64_t)(c >> 1);
-                    const uint64_t wd64 = sm_mix(enc_base + (widx + 1) * 0x9E3779B97F4A7C15ull);
-                    v = (uint32_t)(wd64 >> (32 * (c & 1)));
-                } else {
-                    v = Lp[(size_t)row * W + c];
-                }
+            // rows past the product read row 0 and are staged as zero
+            const int rowc = l_ok[q] ? row_base + tid + q * THREADS : 0;
+            if (ENC) {
+                const uint64_t widx = ct_id * (uint64_t)g.nct * M64 + (uint64_t)rowc * M64 + (uint64_t)(b >> 6);
+                const uint64_t w64 = sm_mix(enc_base + (widx + 1) * 0x9E3779B97F4A7C15ull);
+                lpf[q] = (uint32_t)(w64 >> (b & 63));
+            } else {
+                lpf[q] = Lp[(size_t)rowc * W + (b >> 5)] >> (b & 31);
             }
-            lpf[q] = v;
+        }
+    };
+    // (the mask is applied here, not at the load, so that nothing waits for
+    // the load before the chunk after it)
+    auto stage_L = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < LR; q++)
+            if (tid + q * THREADS < TR) Ls[slot * TR + tid + q * THREADS] = l_ok[q] ? lpf[q] : 0u;
+    };
+    // Table build for chunk c in two halves: build_read issues the LDS reads
+    // of the digits' words (4 rows x 4 slots, low and high word), build_write
+    // (after the chunk's staging work, which hides the reads' latency) cuts the
+    // digits and stores the 15 non-empty subset sums, one 16-byte store per
+    // entry.
+    uint32_t b_lo[4][4], b_hi[4][4];
+    auto build_read = [&](int c) {
+        const uint32_t* Rb = Rs + (c & 1) * chunk_words;
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                b_lo[j][u] = Rb[bt_off[u] + j * W];
+                b_hi[j][u] = Rb[bt_off[u] + j * W + 1];
+            }
+    };
+    auto build_write = [&](int c) {
+        uint32_t d[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                d[j][u] = __builtin_amdgcn_alignbit(b_hi[j][u], b_lo[j][u], bt_sh[u]) & bt_mask[u];
+            }
+        uint4* tb = reinterpret_cast<uint4*>(T + (c & 1) * TSZ + bt_dst);
+        // sums over subsets of rows {0, 1}, then entries v and v + 8 (v < 8)
+        // written as soon as they are formed
+        uint32_t a[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            a[0][u] = 0;
+            a[1][u] = d[0][u];
+            a[2][u] = d[1][u];
+            a[3][u] = d[0][u] + d[1][u];
+        }
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            uint32_t sv[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) sv[u] = v < 4 ? a[v][u] : a[v - 4][u] + d[2][u];
+            if (v > 0) tb[v * SQ] = make_uint4(sv[0], sv[1], sv[2], sv[3]);
+            tb[(v + 8) * SQ] = make_uint4(sv[0] + d[3][0], sv[1] + d[3][1], sv[2] + d[3][2], sv[3] + d[3][3]);
         }
     };
 
+    // prologue: chunks 0 and 1 staged, chunk 2 in registers, tables of chunk 0
     load_R(0);
     load_L(0);
+    stage_R(0);
+    stage_L(0);
+    if (1 < nchunks) {
+        load_R(1);
+        load_L(1);
+        stage_R(1);
+        stage_L(1);
+    }
+    if (2 < nchunks) {
+        load_R(2);
+        load_L(2);
+    }
+    __syncthreads();
+    if (bt_task) {
+        build_read(0);
+        build_write(0);
+    }
+    __syncthreads();
+
+    int ls_c = 0, ls_c2 = 2;  // c mod 3, (c + 2) mod 3
     for (int c = 0; c < nchunks; c++) {
-        // stage this chunk; start loading the next one
-#pragma unroll
-        for (int q = 0; q < RPF; q++) {
-            const int idx = tid + q * THREADS;
-            if (idx < chunk_words) Rs[idx] = rpf[q];
+        const bool do_build = bt_task && c + 1 < nchunks;
+        if (do_build) build_read(c + 1);
+        if (c + 2 < nchunks) {
+            stage_R(c + 2);
+            stage_L(ls_c2);
         }
-        uint32_t* Lc = Ls + (c & 1) * TR;
-#pragma unroll
-        for (int q = 0; q < LR; q++)
-            if (tid + q * THREADS < TR) Lc[tid + q * THREADS] = lpf[q];
-        if (c + 1 < nchunks) {
-            load_R(c + 1);
-            load_L(c + 1);
+        if (c + 3 < nchunks) {
+            load_R(c + 3);
+            load_L(c + 3);
         }
-        __syncthreads();
-        // digits of 4 rows at one slot -> the 15 non-empty subset sums
+        if (do_build) build_write(c + 1);
+        // lookups: step s = (row-iteration s / CG, group s % CG)
+        const uint32_t* Lc = Ls + ls_c * TR;
+        const uint32_t* Tc = T + (c & 1) * TSZ;
+        uint32_t Lw[RPL];
 #pragma unroll
-        for (int q = 0; q < BT; q++) {
-            if (!bt_ok[q]) continue;
-            const uint32_t* r = Rs + bt_off[q];
-            uint32_t d[4];
+        for (int i = 0; i < RPL; i++) Lw[i] = Lc[(wave * RPL + i) * RPW + rsub];
+        uint4 buf[PD + 1][NQ];
+        auto issue = [&](int s, uint4* b) {
+            const int i = s / CG, grp = s % CG;
+            const uint32_t idx = __builtin_amdgcn_ubfe(Lw[i], 4 * grp, 4);
+            const uint4* t = reinterpret_cast<const uint4*>(Tc + (grp * 16 + idx) * st) + lq;
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const uint32_t lo = r[j * W];
-                const uint32_t hi = bt_hi[q] ? r[j * W + 1] : 0u;
-                d[j] = __builtin_amdgcn_alignbit(hi, lo, bt_sh[q]) & kDigitMask;
-            }
-            uint32_t* tb = T + bt_dst[q];
-            const uint32_t s01 = d[0] + d[1], s02 = d[0] + d[2], s12 = d[1] + d[2], s012 = s01 + d[2];
-            tb[1 * st] = d[0];
-            tb[2 * st] = d[1];
-            tb[3 * st] = s01;
-            tb[4 * st] = d[2];
-            tb[5 * st] = s02;
-            tb[6 * st] = s12;
-            tb[7 * st] = s012;
-            tb[8 * st] = d[3];
-            tb[9 * st] = d[0] + d[3];
-            tb[10 * st] = d[1] + d[3];
-            tb[11 * st] = s01 + d[3];
-            tb[12 * st] = d[2] + d[3];
-            tb[13 * st] = s02 + d[3];
-            tb[14 * st] = s12 + d[3];
-            tb[15 * st] = s012 + d[3];
-        }
-        __syncthreads();
+            for (int q = 0; q < NQ; q++) b[q] = t[q * LPR];
+        };
 #pragma unroll
-        for (int i = 0; i < RPLMAX; i++) {
-            if (i < rpl) {
-                const uint32_t Lw = Lc[(wave * rpl + i) * RPW + rsub];
+        for (int s = 0; s < PD; s++) issue(s, buf[s]);
 #pragma unroll
-                for (int grp = 0; grp < kGroups; grp++) {
-                    const uint32_t idx = __builtin_amdgcn_ubfe(Lw, 4 * grp, 4);
-                    const uint4* t = reinterpret_cast<const uint4*>(T + (grp * 16 + idx) * st) + lq;
+        for (int s = 0; s < NSTEP; s++) {
+            if (s + PD < NSTEP) issue(s + PD, buf[(s + PD) % (PD + 1)]);
+            const int i = s / CG;
+            const uint4* b = buf[s % (PD + 1)];
 #pragma unroll
-                    for (int q = 0; q < NQ; q++) {
-                        const uint4 x = t[q * LPR];
-                        acc[i][4 * q + 0] = (uint64_t)x.x * kc.one + acc[i][4 * q + 0];
-                        acc[i][4 * q + 1] = (uint64_t)x.y * kc.one + acc[i][4 * q + 1];
-                        acc[i][4 * q + 2] = (uint64_t)x.z * kc.one + acc[i][4 * q + 2];
-                        acc[i][4 * q + 3] = (uint64_t)x.w * kc.one + acc[i][4 * q + 3];
-                    }
-                }
+            for (int q = 0; q < NQ; q++) {
+                acc[i][4 * q + 0] = (uint64_t)b[q].x * kc.one + acc[i][4 * q + 0];
+                acc[i][4 * q + 1] = (uint64_t)b[q].y * kc.one + acc[i][4 * q + 1];
+                acc[i][4 * q + 2] = (uint64_t)b[q].z * kc.one + acc[i][4 * q + 2];
+                acc[i][4 * q + 3] = (uint64_t)b[q].w * kc.one + acc[i][4 * q + 3];
             }
         }
+        ls_c = ls_c == 2 ? 0 : ls_c + 1;
+        ls_c2 = ls_c2 == 2 ? 0 : ls_c2 + 1;
+        __syncthreads();
     }
 
     // epilogue in passes of PI row-iterations: stage the digit sums in LDS,
     // then one thread per (row, element) finishes it
+    // (the pass loop stays rolled; the accumulators, which need compile-time
+    // indices, are staged under a uniform branch per pass)
     uint64_t* E = reinterpret_cast<uint64_t*>(lds);
+    constexpr int NPASS = (RPL + PI - 1) / PI;
+    for (int p = 0; p < NPASS; p++) {
+        if (p > 0) __syncthreads();
 #pragma unroll
-    for (int p = 0; p < (RPLMAX + PI - 1) / PI; p++) {
-        if (p * PI >= rpl) continue;  // uniform across the workgroup
-        __syncthreads();
+        for (int pp = 0; pp < NPASS; pp++) {
+            if (pp != p) continue;
 #pragma unroll
-        for (int ii = 0; ii < PI; ii++) {
-            const int i = p * PI + ii;
-            if (i < RPLMAX && i < rpl) {
-                const int pr = (wave * PI + ii) * RPW + rsub;
+            for (int ii = 0; ii < PI; ii++) {
+                const int i = pp * PI + ii;
+                if (i < RPL) {
+                    const int pr = (wave * PI + ii) * RPW + rsub;
 #pragma unroll
-                for (int q = 0; q < NQ; q++)
+                    for (int q = 0; q < NQ; q++)
 #pragma unroll
-                    for (int c4 = 0; c4 < 4; c4++) E[pr * st + 4 * (lq + LPR * q) + c4] = acc[i][4 * q + c4];
+                        for (int c4 = 0; c4 < 4; c4++) E[pr * st + 4 * (lq + LPR * q) + c4] = acc[i][4 * q + c4];
+                }
             }
         }
         __syncthreads();
-        for (int task = tid; task < PASS_ROWS * g.n1; task += THREADS) {
-            const int pr = task / g.n1, e = task % g.n1;
+        for (int tk = tid; tk < PASS_ROWS * g.n1; tk += THREADS) {
+            const int pr = tk / g.n1, e = tk % g.n1;
             const int wv = pr / (PI * RPW), ii = (pr / RPW) % PI, rs = pr % RPW;
             const int i = p * PI + ii;
-            if (i >= rpl) continue;
-            const int row = row_base + (wv * rpl + i) * RPW + rs;
+            if (i >= RPL) continue;
+            const int row = row_base + (wv * RPL + i) * RPW + rs;
             if (row >= g.nct) continue;
             finish_element(bufs, g, it, E + pr * st + e * nd, nd, Lp, Rp, row, e, dst_shift);
         }
@@ -341,14 +485,14 @@ __global__ void __launch_bounds__(kThreads) k_linear(Geo g, const LinSeg* __rest
         sg = segs[lo];
     }
     const Bufs bufs = sg.bufs;
-    const LinItem it = sg.items ? sg.items[y - sg.first] : one;
+    const LinItem it = sg.items ? load_global(sg.items + (y - sg.first)) : one;
     const int task = blockIdx.x * kThreads + threadIdx.x;
     if (task >= g.nct * g.n1) return;
     const int row = task / g.n1, e = task % g.n1;
     const int br = row / g.k, tr = row % g.k;
-    uint32_t* dst = ctp(bufs, it.dst);
-    const uint32_t* X = it.X >= 0 ? ctp(bufs, it.X) : nullptr;
-    const uint32_t* Y = it.Y >= 0 ? ctp(bufs, it.Y) : nullptr;
+    gword* dst = ctp(bufs, it.dst);
+    const gword* X = it.X >= 0 ? ctp(bufs, it.X) : nullptr;
+    const gword* Y = it.Y >= 0 ? ctp(bufs, it.Y) : nullptr;
     int64_t carry = 0;
     for (int l = 0; l < g.kw; l++) {
         const size_t off = (size_t)row * g.W + e * g.kw + l;
@@ -361,14 +505,14 @@ __global__ void __launch_bounds__(kThreads) k_linear(Geo g, const LinSeg* __rest
     }
 }
 
-template <int THREADS, int LPR, int DPL, int RPLMAX, bool ENC>
+template <int THREADS, int LPR, int DPL, int RPL, int PD, int CG, bool ENC>
 hipError_t launch_t(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
                     const ProdItem& one, int64_t total, uint64_t seed, uint64_t first_id, const MuBits* mu,
                     hipStream_t s)
 {
     static int attr_bytes = 64 * 1024;
     if (cfg.lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_product<THREADS, LPR, DPL, RPLMAX, ENC>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_product<THREADS, LPR, DPL, RPL, PD, CG, ENC>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, cfg.lds_bytes);
         if (e != hipSuccess) return e;
         attr_bytes = cfg.lds_bytes;
@@ -379,7 +523,7 @@ hipError_t launch_t(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int
     for (int64_t b0 = 0; b0 < total; b0 += 65535) {
         const int64_t n = total - b0 < 65535 ? total - b0 : 65535;
         dim3 grid(tiles, (unsigned)n);
-        hipLaunchKernelGGL((k_product<THREADS, LPR, DPL, RPLMAX, ENC>), grid, dim3(THREADS), cfg.lds_bytes, s, g, kc,
+        hipLaunchKernelGGL((k_product<THREADS, LPR, DPL, RPL, PD, CG, ENC>), grid, dim3(THREADS), cfg.lds_bytes, s, g, kc,
                            d_segs, nseg, seg0, one, (uint32_t)b0, seed, first_id, mu ? *mu : none);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -387,16 +531,17 @@ hipError_t launch_t(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int
     return hipSuccess;
 }
 
-// Tilings: (threads, lanes per row, digit slots per lane, rows per lane).
+// Tilings: (threads, lanes per row, digit slots per lane, rows per lane,
+// lookup pipeline depth, 4-bit groups per chunk).
 struct Tiling {
-    int threads, lpr, dpl, rplmax;
+    int threads, lpr, dpl, rpl, pd, cg;
 };
 constexpr Tiling kTilings[] = {
-    {256, 4, 4, 8},    // rows of <= 16 digits
-    {256, 8, 4, 16},   // <= 32
-    {256, 8, 8, 8},    // <= 64
-    {256, 8, 12, 5},   // <= 96
-    {256, 8, 16, 4},   // <= 128
+    {256, 4, 4, 8, 2, 8},    // rows of <= 16 digits
+    {256, 8, 4, 12, 1, 8},   // <= 32
+    {256, 8, 8, 7, 2, 8},    // <= 64
+    {512, 8, 12, 5, 2, 8},   // <= 96
+    {512, 8, 16, 4, 1, 4},   // <= 128
 };
 
 template <bool ENC>
@@ -406,7 +551,8 @@ hipError_t dispatch(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int
 {
 #define CASE(I)                                                                                              \
     if (cfg.tiling == I)                                                                                     \
-        return launch_t<kTilings[I].threads, kTilings[I].lpr, kTilings[I].dpl, kTilings[I].rplmax, ENC>(     \
+        return launch_t<kTilings[I].threads, kTilings[I].lpr, kTilings[I].dpl, kTilings[I].rpl, kTilings[I].pd, \
+                        kTilings[I].cg, ENC>(                                                         \
             g, cfg, d_segs, nseg, seg0, one, total, seed, first_id, mu, s);
     CASE(0)
     CASE(1)
@@ -421,7 +567,7 @@ hipError_t dispatch(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int
 
 bool product_config(const Geo& g, ProdCfg* cfg)
 {
-    if (g.nct % 32 != 0 || g.W * 32 != g.nct || 32 * g.W > kMaxChunkWords) return false;
+    if (g.nct % 32 != 0 || g.W * 32 != g.nct || g.W > kMaxRowWords) return false;
     const int nd = (g.k + kDigitBits - 1) / kDigitBits;
     const int wd = g.n1 * nd;
     int ti = -1;
@@ -433,6 +579,8 @@ bool product_config(const Geo& g, ProdCfg* cfg)
     if (ti < 0) return false;
     const Tiling& t = kTilings[ti];
     cfg->tiling = ti;
+    cfg->threads = t.threads;
+    cfg->cg = t.cg;
     cfg->nd = nd;
     cfg->wd = wd;
     cfg->lpr = t.lpr;
@@ -440,12 +588,12 @@ bool product_config(const Geo& g, ProdCfg* cfg)
     cfg->st = t.lpr * t.dpl;
     cfg->rpw = 64 / t.lpr;
     const int per_iter = (t.threads / 64) * cfg->rpw;
-    int rpl = (g.nct + per_iter - 1) / per_iter;
-    if (rpl > t.rplmax) rpl = t.rplmax;
-    cfg->rpl = rpl;
-    cfg->tr = per_iter * rpl;
-    const int pi = (kPassMinRows + per_iter - 1) / per_iter;
-    const int main_words = 32 * g.W + 2 * cfg->tr + kGroups * 16 * cfg->st;
+    cfg->rpl = t.rpl;
+    cfg->tr = per_iter * t.rpl;
+    // LDS: two chunks of rows of R, three chunks of bits of L, two table
+    // sets; the epilogue reuses it for one pass of 64-bit digit sums
+    const int pi = pass_iters(t.threads, cfg->rpw, cfg->st, t.rpl);
+    const int main_words = 2 * 4 * t.cg * g.W + 3 * cfg->tr + 2 * t.cg * 16 * cfg->st;
     const int epi_words = 2 * per_iter * pi * cfg->st;
     cfg->lds_bytes = 4 * (main_words > epi_words ? main_words : epi_words);
     return cfg->lds_bytes <= 160 * 1024;
