@@ -61,6 +61,15 @@ class SfftError(RuntimeError):
 if not os.path.exists(LIB_PATH):
     raise ImportError("libsfft.so is not built (run paper_1611_08769_amd.build.build())")
 
+# One HIP runtime per process: torch ships its own copy of the HIP and HSA
+# runtimes under the same sonames as ROCm's.  Loading torch first makes the
+# library bind to the copy already in the process; loading the library
+# first would bring in a second pair of runtimes, and the one initialised
+# second finds no device.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 _vp = ctypes.c_void_p
 _P = ctypes.POINTER
