@@ -74,7 +74,8 @@ def run_batch(args):
     from paper_1611_08769_amd import api
     from paper_1611_08769_amd import workloads as WL
 
-    sigs = WL.batch_requests(seed=4, count=args.requests)
+    lengths = tuple(n for n in (8, 16, 32, 64, 128) if n <= args.max_len)
+    sigs = WL.batch_requests(seed=4, count=args.requests, lengths=lengths)
     reqs, plans = [], {}
     for i, sig in enumerate(sigs):
         p = api.size_params(1, sig.length, sig.F, sig.f, True, 1)
@@ -110,7 +111,7 @@ def run_batch(args):
     srv = api.Server(budget, max_active=args.max_active)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tickets = [srv.submit(1, r[0].length, r[0].F, r[0].f, True, r[1], r[3], r[4]) for r in reqs]
+    tickets = [srv.submit_plan(r[2], r[3], r[4]) for r in reqs]  # the plans compiled above, shared
     srv.drain()
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
@@ -133,7 +134,8 @@ def run_batch(args):
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "batch_1d_mixed", "requests": len(reqs), "lengths": "8..128", "F": "12/16/24",
+        "config": {"workload": "batch_1d_mixed", "requests": len(reqs), "lengths": "%d..%d" % (lengths[0], lengths[-1]),
+                   "F": "12/16/24",
                    "n_lwe": 1, "distinct_plans": len(plans), "budget_gb": round(budget / 1e9, 1)},
         "one_at_a_time_gates_per_s": gates / t_alone,
         "speedup_vs_one_at_a_time": t_alone / t_batch,
@@ -214,6 +216,7 @@ def main():
     ap.add_argument("--requests", type=int, default=64, help="batch mode: number of requests")
     ap.add_argument("--max-active", type=int, default=0, help="batch mode: requests in flight (0 = no limit)")
     ap.add_argument("--budget-gb", type=float, default=120.0, help="batch mode: workspace memory budget")
+    ap.add_argument("--max-len", type=int, default=128, help="batch mode: longest request length (8..128)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)

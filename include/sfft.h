@@ -156,8 +156,8 @@ int sfft_gate(const sfft_params* params, int32_t gate, const uint32_t* x_dev, co
  * at once.  Requests are admitted in arrival order when their plan's
  * workspace fits the device memory budget (and fewer than max_active run);
  * each global step advances every admitted request by one of its plan's
- * steps, with the products of all requests of the same ciphertext geometry
- * in one launch.  Each request's ciphertexts are bit-identical to running
+ * steps, with the products of all requests that share a kernel tiling (and
+ * LDS occupancy) in one launch, whatever their k and n.  Each request's ciphertexts are bit-identical to running
  * its plan alone.  Requests are independent FFTs (the paper's workflow,
  * section "Introduction", repeated per client signal). */
 #define SFFT_SERVER_DRYRUN 1  /* no device work: admission/scheduling only, modelled time */
@@ -185,6 +185,11 @@ int sfft_server_create(const sfft_server_cfg* cfg, sfft_server** out);
  * on the host.  SFFT_ENOMEM if the plan's workspace exceeds the budget. */
 int sfft_server_submit(sfft_server* srv, const sfft_shape* shape, const sfft_params* params,
                        const uint32_t* ct_in_dev, uint32_t* ct_out_dev, uint64_t* ticket);
+/* The same with a plan the caller already compiled (sfft_plan_create): no
+ * host compilation on submit.  The plan is shared, not copied, and must
+ * outlive the request. */
+int sfft_server_submit_plan(sfft_server* srv, const struct sfft_plan* plan, const uint32_t* ct_in_dev,
+                            uint32_t* ct_out_dev, uint64_t* ticket);
 /* Admit what fits, run one global step on hip_stream and wait for it;
  * *pending = requests still queued or running. */
 int sfft_server_step(sfft_server* srv, void* hip_stream, int32_t* pending);

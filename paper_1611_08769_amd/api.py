@@ -165,6 +165,13 @@ class Server:
         self._keep[t] = (ct_in, ct_out)  # the buffers must outlive the request
         return t
 
+    def submit_plan(self, plan: "Plan", ct_in: torch.Tensor, ct_out: torch.Tensor) -> int:
+        """Queue a request on a plan compiled beforehand (shared; keep it open
+        until the request completes)."""
+        t = S.sfft_server_submit_plan(self.handle, plan.handle, ct_in.data_ptr(), ct_out.data_ptr())
+        self._keep[t] = (ct_in, ct_out, plan)
+        return t
+
     def step(self, stream=None) -> int:
         return S.sfft_server_step(self.handle, None if self.dry else _stream_ptr(stream))
 

@@ -161,6 +161,8 @@ int decrypt_row(const uint32_t* row, const uint32_t* sk, int n1, int kw, int k)
 
 struct sfft_plan : PlanCore {};
 
+const PlanCore* plan_core_of(const sfft_plan* plan) { return plan; }
+
 namespace {
 // Compile the circuit of a shape for params: netlist, noise check, sharing,
 // lowering.  Host only.
@@ -397,18 +399,19 @@ int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, cons
         if (st < (int32_t)S.levels.size()) {
             const LevelWork& lw = S.levels[st];
             if (lw.prod_count) {
-                const ProdSeg seg{plan->d_prods + lw.prod_begin, b, 0, 0};
-                hipError_t e = launch_products(g, plan->cfg, nullptr, 1, seg, lw.prod_count, s);
+                const ProdSeg seg{plan->d_prods + lw.prod_begin, b, g, plan->cfg.nd, plan->cfg.wd, 0, 0};
+                hipError_t e = launch_products(plan->cfg, nullptr, 1, seg,
+                                               (int64_t)lw.prod_count * product_tiles(g, plan->cfg), s);
                 if (e != hipSuccess) return hip_fail(e, "product launch");
             }
             for (const auto& pass : lw.lin) {
-                const LinSeg seg{plan->d_lins + pass.first, b, 0, 0};
-                hipError_t e = launch_linear(g, nullptr, 1, seg, pass.second, s);
+                const LinSeg seg{plan->d_lins + pass.first, b, g, 0, 0};
+                hipError_t e = launch_linear((int64_t)g.nct * g.n1, nullptr, 1, seg, pass.second, s);
                 if (e != hipSuccess) return hip_fail(e, "linear launch");
             }
         } else if (!S.final_lins.empty()) {
-            const LinSeg seg{plan->d_final, b, 0, 0};
-            hipError_t e = launch_linear(g, nullptr, 1, seg, (int64_t)S.final_lins.size(), s);
+            const LinSeg seg{plan->d_final, b, g, 0, 0};
+            hipError_t e = launch_linear((int64_t)g.nct * g.n1, nullptr, 1, seg, (int64_t)S.final_lins.size(), s);
             if (e != hipSuccess) return hip_fail(e, "output launch");
         }
     }

@@ -38,9 +38,8 @@ struct ProdCfg {
     int lds_bytes;
 };
 
-// The same numbers as passed to the kernel.
+// Passed to the kernel by value.
 struct KCfg {
-    int32_t nd, wd, st, rpl, tr;
     // always 1: a run-time multiplier makes acc = digit * one + acc compile to
     // v_mad_u64_u32, which takes the 32-bit digit as is (no zero-extended pair)
     uint32_t one;
@@ -48,30 +47,43 @@ struct KCfg {
 
 bool product_config(const Geo& g, ProdCfg* cfg);
 
-// A run of work items sharing one set of buffers (one request).  A launch
-// covers the concatenation of its segments; `first` is the global index of
-// the segment's first item within the launch.
+// A run of work items sharing one set of buffers and one ciphertext
+// geometry (one request).  A launch covers the concatenation of its
+// segments; `first` is the index of the segment's first item within the
+// launch.  Segments of one product launch may differ in geometry but share
+// the kernel tiling (ProdCfg::tiling); nd and wd are the segment's digits per
+// element and per row.  A product item takes product_tiles() workgroups (row
+// tiles); first_block is the segment's first workgroup within the launch.
 struct ProdSeg {
     const ProdItem* items;
     Bufs bufs;
+    Geo geo;
+    int32_t nd, wd;
     uint32_t first;
-    uint32_t pad;
+    uint32_t first_block;
 };
 struct LinSeg {
     const LinItem* items;
     Bufs bufs;
+    Geo geo;
     uint32_t first;
     uint32_t pad;
 };
 
-// One launch over `total` product items in nseg segments: d_segs in device
-// memory when nseg > 1, else seg0 (by value).
-hipError_t launch_products(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                           int64_t total, hipStream_t s);
+// Workgroups (row tiles) per product item of geometry g.
+inline int product_tiles(const Geo& g, const ProdCfg& cfg) { return (g.nct + cfg.tr - 1) / cfg.tr; }
+
+// One launch over `blocks` workgroups (the sum over the segments of items x
+// product_tiles) in nseg segments: d_segs in device memory when nseg > 1,
+// else seg0 (by value).  cfg is the tiling shared by the segments with
+// lds_bytes the largest any of them needs.
+hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                           int64_t blocks, hipStream_t s);
 // One product item passed by value (single gates).
 hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item,
                               hipStream_t s);
-hipError_t launch_linear(const Geo& g, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
+// Linear items; max_elems = the largest Nct * (n+1) among the segments.
+hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
                          hipStream_t s);
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s);
 

@@ -49,6 +49,38 @@ __device__ __forceinline__ gword* ctp(const Bufs& b, int32_t ref)
     return (gword*)(base + idx * (uint64_t)b.ct_words);
 }
 
+// Index of the last segment whose key (first item or first workgroup) is
+// <= y (the keys ascend), found by the whole wave at once: lane i tests segment base + i and
+// the highest lane that passes is the answer.  One round of loads per 64
+// segments instead of a chain of dependent loads.
+template <class Seg, class Key>
+__device__ __forceinline__ int find_segment(const Seg* segs, int nseg, uint32_t y, Key key)
+{
+    const int lane = threadIdx.x & 63;
+    int found = 0;
+    for (int base = 0; base < nseg; base += 64) {
+        const int i = base + lane;
+        const bool le = i < nseg && key(segs[i]) <= y;
+        const uint64_t m = __ballot(le);
+        if (m) found = base + 63 - __clzll(m);
+        if (m != ~0ull) break;
+    }
+    // the same on every lane: keep it (and the segment) in scalar registers
+    return __builtin_amdgcn_readfirstlane(found);
+}
+
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8).
+// Renumber them so that each XCD works through one contiguous range of the
+// launch's (item, row tile) order: the row tiles of one product, which all
+// read its whole right operand, then share one XCD's L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t n)
+{
+    const uint32_t x = b % kXcds, k = b / kXcds;
+    const uint32_t per = n / kXcds, rem = n % kXcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 // A work item read word by word through the global address space.
 template <class T>
 __device__ __forceinline__ T load_global(const T* p)
@@ -183,9 +215,9 @@ __device__ void finish_element(const Bufs& bufs, const Geo& g, const ProdItem& i
 // steps deep: the table reads of step s + PD are issued before the additions
 // of step s.
 template <int THREADS, int LPR, int DPL, int RPL, int PD, int CG, bool ENC>
-__global__ void __launch_bounds__(THREADS) k_product(Geo g, KCfg kc, const ProdSeg* __restrict__ segs, int nseg,
-                                                     ProdSeg seg0, ProdItem one, uint32_t ybase, uint64_t seed,
-                                                     uint64_t first_id, MuBits mu)
+__global__ void __launch_bounds__(THREADS) k_product(KCfg kc, const ProdSeg* __restrict__ segs, int nseg,
+                                                     ProdSeg seg0, ProdItem one, uint64_t seed, uint64_t first_id,
+                                                     MuBits mu)
 {
     constexpr int NW = THREADS / 64;
     constexpr int RPW = 64 / LPR;          // rows per wave per row-iteration
@@ -207,25 +239,23 @@ __global__ void __launch_bounds__(THREADS) k_product(Geo g, KCfg kc, const ProdS
     static_assert(PD >= 1 && PD < NSTEP, "pipeline depth");
 
     extern __shared__ uint32_t lds[];
-    // work item of this workgroup: segment (a request's buffers and items) by
-    // binary search over the segments' first global item index
-    const uint32_t y = blockIdx.y + ybase;
-    ProdSeg sg = seg0;
-    if (nseg > 1) {
-        int lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (segs[mid].first <= y) lo = mid;
-            else hi = mid - 1;
-        }
-        sg = segs[lo];
-    }
+    // work of this workgroup: virtual index v (XCD-grouped), its segment (a
+    // request's buffers, geometry and items: the last whose first workgroup
+    // is <= v), then item and row tile within the segment
+    const uint32_t v = xcd_order(blockIdx.x, gridDim.x);
+    ProdSeg sg = seg0;  // (a select between the two structs would copy both into vector registers)
+    if (nseg > 1) sg = segs[find_segment(segs, nseg, v, [](const ProdSeg& q) { return q.first_block; })];
+    const Geo g = sg.geo;
+    const uint32_t tiles = ((uint32_t)g.nct + TR - 1) / TR;
+    const uint32_t local = v - sg.first_block;
+    const uint32_t yl = local / tiles;
+    const uint32_t y = sg.first + yl;  // item index within the launch (numbers encryptions)
+    const int row_base = (int)(local % tiles) * TR;
     const Bufs bufs = sg.bufs;
-    ProdItem it = sg.items ? load_global(sg.items + (y - sg.first)) : one;
+    ProdItem it = sg.items ? load_global(sg.items + yl) : one;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rsub = lane / LPR, lq = lane % LPR;
-    const int W = g.W, kw = g.kw, nd = kc.nd, wd = kc.wd;
-    const int row_base = blockIdx.x * TR;
+    const int W = g.W, kw = g.kw, nd = sg.nd, wd = sg.wd;
 
     uint64_t dst_shift = 0, ct_id = 0;
     if (ENC) {
@@ -470,24 +500,17 @@ __global__ void __launch_bounds__(THREADS) k_product(Geo g, KCfg kc, const ProdS
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_linear(Geo g, const LinSeg* __restrict__ segs, int nseg, LinSeg seg0,
+__global__ void __launch_bounds__(kThreads) k_linear(const LinSeg* __restrict__ segs, int nseg, LinSeg seg0,
                                                      LinItem one, uint32_t ybase)
 {
     const uint32_t y = blockIdx.y + ybase;
     LinSeg sg = seg0;
-    if (nseg > 1) {
-        int lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (segs[mid].first <= y) lo = mid;
-            else hi = mid - 1;
-        }
-        sg = segs[lo];
-    }
-    const Bufs bufs = sg.bufs;
-    const LinItem it = sg.items ? load_global(sg.items + (y - sg.first)) : one;
+    if (nseg > 1) sg = segs[find_segment(segs, nseg, y, [](const LinSeg& q) { return q.first; })];
+    const Geo g = sg.geo;
     const int task = blockIdx.x * kThreads + threadIdx.x;
     if (task >= g.nct * g.n1) return;
+    const Bufs bufs = sg.bufs;
+    const LinItem it = sg.items ? load_global(sg.items + (y - sg.first)) : one;
     const int row = task / g.n1, e = task % g.n1;
     const int br = row / g.k, tr = row % g.k;
     gword* dst = ctp(bufs, it.dst);
@@ -506,9 +529,8 @@ __global__ void __launch_bounds__(kThreads) k_linear(Geo g, const LinSeg* __rest
 }
 
 template <int THREADS, int LPR, int DPL, int RPL, int PD, int CG, bool ENC>
-hipError_t launch_t(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                    const ProdItem& one, int64_t total, uint64_t seed, uint64_t first_id, const MuBits* mu,
-                    hipStream_t s)
+hipError_t launch_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0, const ProdItem& one,
+                    int64_t blocks, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
     static int attr_bytes = 64 * 1024;
     if (cfg.lds_bytes > attr_bytes) {
@@ -517,18 +539,13 @@ hipError_t launch_t(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int
         if (e != hipSuccess) return e;
         attr_bytes = cfg.lds_bytes;
     }
-    const int tiles = (g.nct + cfg.tr - 1) / cfg.tr;
-    const KCfg kc{cfg.nd, cfg.wd, cfg.st, cfg.rpl, cfg.tr, 1u};
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const KCfg kc{1u};
     MuBits none{};
-    for (int64_t b0 = 0; b0 < total; b0 += 65535) {
-        const int64_t n = total - b0 < 65535 ? total - b0 : 65535;
-        dim3 grid(tiles, (unsigned)n);
-        hipLaunchKernelGGL((k_product<THREADS, LPR, DPL, RPL, PD, CG, ENC>), grid, dim3(THREADS), cfg.lds_bytes, s, g, kc,
-                           d_segs, nseg, seg0, one, (uint32_t)b0, seed, first_id, mu ? *mu : none);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipLaunchKernelGGL((k_product<THREADS, LPR, DPL, RPL, PD, CG, ENC>), dim3((unsigned)blocks), dim3(THREADS),
+                       cfg.lds_bytes, s, kc, d_segs, nseg, seg0, one, seed, first_id, mu ? *mu : none);
+    return hipGetLastError();
 }
 
 // Tilings: (threads, lanes per row, digit slots per lane, rows per lane,
@@ -545,15 +562,13 @@ constexpr Tiling kTilings[] = {
 };
 
 template <bool ENC>
-hipError_t dispatch(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                    const ProdItem& one, int64_t total, uint64_t seed, uint64_t first_id, const MuBits* mu,
-                    hipStream_t s)
+hipError_t dispatch(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0, const ProdItem& one,
+                    int64_t blocks, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
 #define CASE(I)                                                                                              \
     if (cfg.tiling == I)                                                                                     \
         return launch_t<kTilings[I].threads, kTilings[I].lpr, kTilings[I].dpl, kTilings[I].rpl, kTilings[I].pd, \
-                        kTilings[I].cg, ENC>(                                                         \
-            g, cfg, d_segs, nseg, seg0, one, total, seed, first_id, mu, s);
+                        kTilings[I].cg, ENC>(cfg, d_segs, nseg, seg0, one, blocks, seed, first_id, mu, s);
     CASE(0)
     CASE(1)
     CASE(2)
@@ -561,6 +576,16 @@ hipError_t dispatch(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int
     CASE(4)
 #undef CASE
     return hipErrorInvalidValue;
+}
+
+ProdSeg single_segment(const Bufs& b, const Geo& g, const ProdCfg& cfg)
+{
+    ProdSeg sg{};
+    sg.bufs = b;
+    sg.geo = g;
+    sg.nd = cfg.nd;
+    sg.wd = cfg.wd;
+    return sg;
 }
 
 }  // namespace
@@ -599,28 +624,26 @@ bool product_config(const Geo& g, ProdCfg* cfg)
     return cfg->lds_bytes <= 160 * 1024;
 }
 
-hipError_t launch_products(const Geo& g, const ProdCfg& cfg, const ProdSeg* d_segs, int nseg,
-                           const ProdSeg& seg0, int64_t total, hipStream_t s)
+hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                           int64_t blocks, hipStream_t s)
 {
-    if (total <= 0) return hipSuccess;
     ProdItem none{};
-    return dispatch<false>(g, cfg, d_segs, nseg, seg0, none, total, 0, 0, nullptr, s);
+    return dispatch<false>(cfg, d_segs, nseg, seg0, none, blocks, 0, 0, nullptr, s);
 }
 
 hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, hipStream_t s)
 {
-    const ProdSeg seg0{nullptr, b, 0, 0};
-    return dispatch<false>(g, cfg, nullptr, 1, seg0, item, 1, 0, 0, nullptr, s);
+    return dispatch<false>(cfg, nullptr, 1, single_segment(b, g, cfg), item, product_tiles(g, cfg), 0, 0, nullptr, s);
 }
 
-hipError_t launch_linear(const Geo& g, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
+hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
                          hipStream_t s)
 {
     LinItem none{};
-    const int blocks = (g.nct * g.n1 + kThreads - 1) / kThreads;
+    const int blocks = (int)((max_elems + kThreads - 1) / kThreads);
     for (int64_t b0 = 0; b0 < total; b0 += 65535) {
         const int64_t n = total - b0 < 65535 ? total - b0 : 65535;
-        hipLaunchKernelGGL(k_linear, dim3(blocks, (unsigned)n), dim3(kThreads), 0, s, g, d_segs, nseg, seg0, none,
+        hipLaunchKernelGGL(k_linear, dim3(blocks, (unsigned)n), dim3(kThreads), 0, s, d_segs, nseg, seg0, none,
                            (uint32_t)b0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -631,9 +654,10 @@ hipError_t launch_linear(const Geo& g, const LinSeg* d_segs, int nseg, const Lin
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s)
 {
     const int blocks = (g.nct * g.n1 + kThreads - 1) / kThreads;
-    const LinSeg seg0{nullptr, b, 0, 0};
-    hipLaunchKernelGGL(k_linear, dim3(blocks, 1), dim3(kThreads), 0, s, g, (const LinSeg*)nullptr, 1, seg0, item,
-                       0u);
+    LinSeg seg0{};
+    seg0.bufs = b;
+    seg0.geo = g;
+    hipLaunchKernelGGL(k_linear, dim3(blocks, 1), dim3(kThreads), 0, s, (const LinSeg*)nullptr, 1, seg0, item, 0u);
     return hipGetLastError();
 }
 
@@ -652,8 +676,8 @@ hipError_t launch_encrypt(const Bufs& b, const Geo& g, const ProdCfg& cfg, const
     one.E[0] = -1;
     one.cP[0] = 1;
     for (int i = 1; i < kMaxOut; i++) one.dst[i] = one.E[i] = -1;
-    const ProdSeg seg0{nullptr, b, 0, 0};
-    return dispatch<true>(g, cfg, nullptr, 1, seg0, one, n_ct, seed, first_id, &mu, s);
+    return dispatch<true>(cfg, nullptr, 1, single_segment(b, g, cfg), one, (int64_t)n_ct * product_tiles(g, cfg), seed,
+                          first_id, &mu, s);
 }
 
 }  // namespace sfft

@@ -35,6 +35,9 @@ int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upl
 
 }  // namespace sfft
 
+// The compiled core of a public plan handle (defined with the ABI).
+const sfft::PlanCore* plan_core_of(const struct sfft_plan* plan);
+
 // status helpers shared by the ABI translation units (set sfft_last_error)
 int sfft_fail(int code, const std::string& msg);
 int sfft_hip_fail(hipError_t e, const char* where);

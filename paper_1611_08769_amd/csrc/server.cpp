@@ -3,8 +3,8 @@
 // Every request runs its own compiled plan (a sequence of steps: product
 // levels and the linear passes after them).  A global step advances every
 // admitted request by one of its own steps; the product items of all
-// requests with the same ciphertext geometry go into one launch (one
-// segment per request), then their linear passes.  Requests are admitted in
+// requests whose kernel tiling matches go into one launch (one segment per
+// request, each with its own ciphertext geometry), then the linear passes.  Requests are admitted in
 // arrival order while a workspace for their plan fits the device memory
 // budget and the number of requests in flight is below the limit, so
 // requests that arrive while others run join at their step 0 and overlap
@@ -199,6 +199,28 @@ int sfft_server_submit(sfft_server* sv, const sfft_shape* shape, const sfft_para
     return SFFT_OK;
 }
 
+int sfft_server_submit_plan(sfft_server* sv, const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev,
+                            uint64_t* ticket)
+{
+    if (!sv || !plan || !ticket) return sfft_fail(SFFT_EINVAL, "null argument");
+    if (sv->dry) return sfft_fail(SFFT_EINVAL, "a dry-run server compiles its own plans (sfft_server_submit)");
+    if (!ct_in_dev || !ct_out_dev) return sfft_fail(SFFT_EINVAL, "null ciphertext buffer");
+    // shared with the caller, who keeps it alive: no-op deleter
+    std::shared_ptr<PlanCore> pc(const_cast<PlanCore*>(plan_core_of(plan)), [](PlanCore*) {});
+    if (pc->ws_bytes() > sv->arena.size())
+        return sfft_fail(SFFT_ENOMEM, "request workspace exceeds the server's memory budget");
+    auto r = std::make_unique<Request>();
+    r->ticket = sv->next_ticket++;
+    r->plan = pc;
+    r->in = ct_in_dev;
+    r->out = ct_out_dev;
+    r->arrival = now_of(sv);
+    *ticket = r->ticket;
+    sv->queue.push_back(std::move(r));
+    sv->st.submitted++;
+    return SFFT_OK;
+}
+
 int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
 {
     if (!sv) return sfft_fail(SFFT_EINVAL, "null server");
@@ -221,55 +243,74 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         return SFFT_OK;
     }
 
-    // group this step's work by ciphertext geometry (k, n1)
-    struct Group {
-        const PlanCore* proto;
-        std::vector<ProdSeg> prods;
-        int64_t nprod = 0;
-        std::vector<std::vector<LinSeg>> lins;  // per linear sub-pass
-        std::vector<int64_t> nlin;
+    // This step's work: the product items of every request whose kernel
+    // tiling matches go into one launch (segments may differ in k and n+1),
+    // split further by how many workgroups of the launch fit a CU's 160 KB
+    // of LDS (the launch allocates its largest member's LDS for every
+    // workgroup, so one large member must not halve the others' occupancy);
+    // the linear passes of all requests go by sub-pass index.
+    struct ProdGroup {
+        ProdCfg cfg;  // the shared tiling; lds_bytes = the largest any member needs
+        std::vector<ProdSeg> segs;
+        int64_t n = 0, blocks = 0;
     };
-    std::map<std::pair<int, int>, Group> groups;
+    struct LinGroup {
+        std::vector<LinSeg> segs;
+        int64_t n = 0, max_elems = 0;
+    };
+    std::map<std::pair<int, int>, ProdGroup> pgroups;  // (tiling, workgroups per CU by LDS)
+    std::vector<LinGroup> lgroups;
     double model_s = 0;
+    auto add_lin = [&](size_t q, const LinItem* items, const Bufs& b, const Geo& g, int64_t count) {
+        if (lgroups.size() <= q) lgroups.resize(q + 1);
+        LinGroup& G = lgroups[q];
+        G.segs.push_back(LinSeg{items, b, g, (uint32_t)G.n, 0});
+        G.n += count;
+        G.max_elems = std::max<int64_t>(G.max_elems, (int64_t)g.nct * g.n1);
+    };
     for (auto& rp : sv->active) {
         Request* r = rp.get();
         const PlanCore& pc = *r->plan;
         const Schedule& S = pc.sched;
-        Group& G = groups[{pc.geo.k, pc.geo.n1}];
-        G.proto = &pc;
         Bufs b{const_cast<uint32_t*>(r->in), r->out,
                sv->dry ? nullptr : (uint32_t*)(sv->arena_dev + r->ws_off), nullptr, pc.ct_words()};
         const int32_t st = r->step;
         if (st < (int32_t)S.levels.size()) {
             const LevelWork& lw = S.levels[st];
             if (lw.prod_count) {
-                G.prods.push_back(ProdSeg{pc.d_prods + lw.prod_begin, b, (uint32_t)G.nprod, 0});
-                G.nprod += lw.prod_count;
+                ProdGroup& G = pgroups[{pc.cfg.tiling, 160 * 1024 / std::max(pc.cfg.lds_bytes, 1)}];
+                if (G.segs.empty()) G.cfg = pc.cfg;
+                G.cfg.lds_bytes = std::max(G.cfg.lds_bytes, pc.cfg.lds_bytes);
+                G.segs.push_back(ProdSeg{pc.d_prods + lw.prod_begin, b, pc.geo, pc.cfg.nd, pc.cfg.wd,
+                                         (uint32_t)lw.prod_count, (uint32_t)product_tiles(pc.geo, pc.cfg)});
                 sv->st.products += lw.prod_count;
                 model_s += (double)lw.prod_count * (double)pc.geo.nct * pc.geo.nct * pc.geo.nct;
             }
-            for (size_t q = 0; q < lw.lin.size(); q++) {
-                if (G.lins.size() <= q) {
-                    G.lins.resize(q + 1);
-                    G.nlin.resize(q + 1, 0);
-                }
-                G.lins[q].push_back(LinSeg{pc.d_lins + lw.lin[q].first, b, (uint32_t)G.nlin[q], 0});
-                G.nlin[q] += lw.lin[q].second;
-            }
+            for (size_t q = 0; q < lw.lin.size(); q++) add_lin(q, pc.d_lins + lw.lin[q].first, b, pc.geo, lw.lin[q].second);
         } else if (!S.final_lins.empty()) {
-            if (G.lins.empty()) {
-                G.lins.resize(1);
-                G.nlin.resize(1, 0);
-            }
-            G.lins[0].push_back(LinSeg{pc.d_final, b, (uint32_t)G.nlin[0], 0});
-            G.nlin[0] += (int64_t)S.final_lins.size();
+            add_lin(0, pc.d_final, b, pc.geo, (int64_t)S.final_lins.size());
+        }
+    }
+
+    // Within a launch, workgroups of larger Nct walk more chunks of R and run
+    // longer: dispatch them first, so that the launch ends on short ones.
+    // (first / first_block hold the item and tile counts until here.)
+    for (auto& kv : pgroups) {
+        ProdGroup& G = kv.second;
+        std::stable_sort(G.segs.begin(), G.segs.end(),
+                         [](const ProdSeg& a, const ProdSeg& b) { return a.geo.nct > b.geo.nct; });
+        for (ProdSeg& q : G.segs) {
+            const int64_t items = q.first, tiles = q.first_block;
+            q.first = (uint32_t)G.n;
+            q.first_block = (uint32_t)G.blocks;
+            G.n += items;
+            G.blocks += items * tiles;
         }
     }
 
     if (!sv->dry) {
         // stage every segment list in one host->device copy
         size_t off = 0;
-        std::vector<std::pair<const void*, size_t>> places;
         auto place = [&](const void* src, size_t bytes) -> size_t {
             off = (off + 63) / 64 * 64;
             const size_t at = off;
@@ -278,50 +319,33 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
             off += bytes;
             return at;
         };
-        struct Launch {
-            const Group* g;
-            int lin_pass;  // -1 = products
-            size_t at;
-        };
-        std::vector<Launch> launches;
-        for (auto& kv : groups) {
-            Group& G = kv.second;
-            if (G.nprod) {
-                const size_t at = place(G.prods.data(), G.prods.size() * sizeof(ProdSeg));
-                if (at == (size_t)-1) return sfft_fail(SFFT_ENOMEM, "segment staging full");
-                launches.push_back({&G, -1, at});
-            }
-            for (size_t q = 0; q < G.lins.size(); q++) {
-                if (!G.nlin[q]) continue;
-                const size_t at = place(G.lins[q].data(), G.lins[q].size() * sizeof(LinSeg));
-                if (at == (size_t)-1) return sfft_fail(SFFT_ENOMEM, "segment staging full");
-                launches.push_back({&G, (int)q, at});
-            }
+        std::vector<size_t> p_at, l_at;
+        for (auto& kv : pgroups) {
+            p_at.push_back(place(kv.second.segs.data(), kv.second.segs.size() * sizeof(ProdSeg)));
+            if (p_at.back() == (size_t)-1) return sfft_fail(SFFT_ENOMEM, "segment staging full");
+        }
+        for (auto& G : lgroups) {
+            l_at.push_back(place(G.segs.data(), G.segs.size() * sizeof(LinSeg)));
+            if (l_at.back() == (size_t)-1) return sfft_fail(SFFT_ENOMEM, "segment staging full");
         }
         hipError_t e = hipMemcpyAsync(sv->seg_dev, sv->seg_host, off, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return sfft_hip_fail(e, "segment upload");
-        // products of every group first, then linear passes in order
-        for (const Launch& L : launches) {
-            if (L.lin_pass >= 0) continue;
-            const Group& G = *L.g;
-            const PlanCore& pc = *G.proto;
-            e = launch_products(pc.geo, pc.cfg, (const ProdSeg*)((uint8_t*)sv->seg_dev + L.at), (int)G.prods.size(),
-                                G.prods[0], G.nprod, s);
+        // products first (one launch per tiling), then the linear passes in order
+        size_t gi = 0;
+        for (auto& kv : pgroups) {
+            const ProdGroup& G = kv.second;
+            e = launch_products(G.cfg, (const ProdSeg*)((uint8_t*)sv->seg_dev + p_at[gi++]), (int)G.segs.size(),
+                                G.segs[0], G.blocks, s);
             if (e != hipSuccess) return sfft_hip_fail(e, "server product launch");
             sv->st.launches++;
         }
-        int max_pass = 0;
-        for (const Launch& L : launches) max_pass = std::max(max_pass, L.lin_pass + 1);
-        for (int q = 0; q < max_pass; q++) {
-            for (const Launch& L : launches) {
-                if (L.lin_pass != q) continue;
-                const Group& G = *L.g;
-                const PlanCore& pc = *G.proto;
-                e = launch_linear(pc.geo, (const LinSeg*)((uint8_t*)sv->seg_dev + L.at), (int)G.lins[q].size(),
-                                  G.lins[q][0], G.nlin[q], s);
-                if (e != hipSuccess) return sfft_hip_fail(e, "server linear launch");
-                sv->st.launches++;
-            }
+        for (size_t q = 0; q < lgroups.size(); q++) {
+            const LinGroup& G = lgroups[q];
+            if (!G.n) continue;
+            e = launch_linear(G.max_elems, (const LinSeg*)((uint8_t*)sv->seg_dev + l_at[q]), (int)G.segs.size(),
+                              G.segs[0], G.n, s);
+            if (e != hipSuccess) return sfft_hip_fail(e, "server linear launch");
+            sv->st.launches++;
         }
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return sfft_hip_fail(e, "server step");

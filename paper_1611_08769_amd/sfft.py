@@ -94,6 +94,7 @@ _SIGS = {
     "sfft_gate": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "sfft_server_create": (ctypes.c_int, [_P(sfft_server_cfg), _P(_vp)]),
     "sfft_server_submit": (ctypes.c_int, [_vp, _P(sfft_shape), _P(sfft_params), _vp, _vp, _P(ctypes.c_uint64)]),
+    "sfft_server_submit_plan": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint64)]),
     "sfft_server_step": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
     "sfft_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(ctypes.c_int32), _P(ctypes.c_double)]),
     "sfft_server_drain": (ctypes.c_int, [_vp, _vp]),
@@ -208,6 +209,12 @@ def sfft_server_create(cfg: sfft_server_cfg) -> int:
 def sfft_server_submit(srv, shp, p, ct_in_ptr, ct_out_ptr) -> int:
     t = ctypes.c_uint64()
     _check(_lib.sfft_server_submit(srv, ctypes.byref(shp), ctypes.byref(p), ct_in_ptr, ct_out_ptr, ctypes.byref(t)))
+    return t.value
+
+
+def sfft_server_submit_plan(srv, plan, ct_in_ptr, ct_out_ptr) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.sfft_server_submit_plan(srv, plan, ct_in_ptr, ct_out_ptr, ctypes.byref(t)))
     return t.value
 
 

@@ -119,14 +119,15 @@ def workload(name: str):
     raise KeyError(name)
 
 
-def batch_requests(seed: int = 4, count: int = 256):
-    """Independent 1D requests: length uniform in {8..128}, F uniform in
-    {12, 16, 24} with f = F/2, complex inputs uniform in [-1, 1)."""
+def batch_requests(seed: int = 4, count: int = 256, lengths=(8, 16, 32, 64, 128)):
+    """Independent 1D requests: length uniform in `lengths` (default
+    {8..128}), F uniform in {12, 16, 24} with f = F/2, complex inputs uniform
+    in [-1, 1)."""
     u = Uniforms(seed)
     reqs = []
     for _ in range(count):
         a, b = u.next(2)
-        n = (8, 16, 32, 64, 128)[min(int(a * 5), 4)]
+        n = lengths[min(int(a * len(lengths)), len(lengths) - 1)]
         F = (12, 16, 24)[min(int(b * 3), 2)]
         reqs.append(uniform_pm1(seed, n, F, F // 2, True, stream=u))
     return reqs

@@ -53,11 +53,14 @@ def test_batched_equals_alone(staggered):
     reqs = [_request(i, sh) for i, sh in enumerate(MIX)]
     outs_mix, outs_alone, tickets = [], [], []
     srv = api.Server(8 << 30)
+    plans = []
     for i, (sh, (sig, p, keys, words, ct_in)) in enumerate(zip(MIX, reqs)):
         plan = api.Plan(*sh, p)
+        plans.append(plan)
         out = torch.zeros((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
         outs_mix.append(out)
-        tickets.append(srv.submit(*sh, p, ct_in, out))
+        # odd requests share the caller's compiled plan, even ones let the server compile
+        tickets.append(srv.submit_plan(plan, ct_in, out) if i % 2 else srv.submit(*sh, p, ct_in, out))
         outs_alone.append(plan.execute(ct_in))
         if staggered and i == 2:
             for _ in range(3):
@@ -83,3 +86,5 @@ def test_batched_equals_alone(staggered):
     got = outs_mix[0].cpu().numpy().view(np.uint32)
     assert np.array_equal(got, want.reshape(want.shape[0], -1))
     srv.close()
+    for plan in plans:
+        plan.close()
