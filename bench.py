@@ -1,6 +1,8 @@
 """Benchmark: encrypted FFT throughput on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py --workload batch [--requests 64] [--max-len 128]
+    python bench.py --workload serve [--requests 40] [--load 0.7] [--max-active 0]
 
 A step is one encrypted FFT of one request (every product level of the
 compiled circuit, inputs already encrypted and resident in HBM).  Prints one
@@ -107,8 +109,8 @@ def run_batch(args):
     print("[bench] one at a time: %.2f s" % t_alone, file=sys.stderr, flush=True)
 
     free, _ = torch.cuda.mem_get_info()
-    budget = int(min(free * 0.7, args.budget_gb * 1e9))
-    srv = api.Server(budget, max_active=args.max_active)
+    budget = int(min(free * 0.7, (args.budget_gb or 120.0) * 1e9))
+    srv = api.Server(budget, max_active=args.max_active, fill_blocks=max(0, args.fill_blocks))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tickets = [srv.submit_plan(r[2], r[3], r[4]) for r in reqs]  # the plans compiled above, shared
@@ -211,12 +213,123 @@ def _kernel_names(path, kernel_prefix):
         return [r["Kernel_Name"] for r in csv.DictReader(f) if r["Kernel_Name"].startswith(kernel_prefix)]
 
 
+def run_serve(args):
+    """Served traffic: requests (1D and 2D, Q(16,8), n_lwe=1, their own k)
+    arrive as a Poisson process; each is encrypted on arrival, queued into
+    the request loop, and its buffers freed when it completes.  Plans are
+    compiled before the clock starts (a server keeps its plans).  Requests
+    wait on the client side while the ciphertexts of those in flight would
+    exceed --io-gb; latency runs from arrival to completion."""
+    import collections
+    import torch
+    from paper_1611_08769_amd import api
+    from paper_1611_08769_amd import workloads as WL
+
+    sigs = WL.served_requests(seed=5, count=args.requests)
+    plans = {}
+    for sig in sigs:
+        key = (sig.dims, sig.length)
+        if key not in plans:
+            p = api.size_params(sig.dims, sig.length, sig.F, sig.f, sig.is_complex, 1)
+            plans[key] = (p, api.Plan(sig.dims, sig.length, sig.F, sig.f, sig.is_complex, p))
+            print("[bench] plan %s: k=%d exec products %d ws %.1f GB" % (
+                key, p.k, plans[key][1].info.exec_products, plans[key][1].ws_bytes / 1e9), file=sys.stderr, flush=True)
+    def work(sig):
+        p, plan = plans[(sig.dims, sig.length)]
+        return float(plan.info.exec_products) * ((p.n_lwe + 1) * p.k) ** 3
+    mean_work = sum(work(s) for s in sigs) / len(sigs)
+    rate = args.rate if args.rate > 0 else args.load * args.rate_bitmac / mean_work
+    arrivals = WL.poisson_arrivals(6, len(sigs), rate)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(free * 0.65, (args.budget_gb or 180.0) * 1e9))
+    fill = 2048 if args.fill_blocks < 0 else args.fill_blocks
+    srv = api.Server(budget, max_active=args.max_active, fill_blocks=fill)
+    print("[bench] serve: %d requests, rate %.4f /s (load %.2f of %.2e bit-MAC/s), budget %.0f GB" % (
+        len(sigs), rate, args.load, args.rate_bitmac, budget / 1e9), file=sys.stderr, flush=True)
+
+    waiting = collections.deque(range(len(sigs)))
+    client_q = collections.deque()
+    live = {}
+    io_used, io_cap = 0, args.io_gb * 1e9
+    lat, t_done = [None] * len(sigs), [None] * len(sigs)
+    t0 = time.perf_counter()
+    while waiting or client_q or live:
+        now = time.perf_counter() - t0
+        while waiting and arrivals[waiting[0]] <= now:
+            client_q.append(waiting.popleft())
+        while client_q:
+            i = client_q[0]
+            sig = sigs[i]
+            p, plan = plans[(sig.dims, sig.length)]
+            io = (plan.info.n_inputs + plan.info.n_outputs) * plan.ct_words * 4
+            if live and io_used + io > io_cap:
+                break
+            keys = api.keygen(p, 5000 + i)
+            ct_in = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=5000 + i)
+            ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
+            live[srv.submit_plan(plan, ct_in, ct_out)] = (i, io)
+            io_used += io
+            client_q.popleft()
+        if live:
+            srv.step()
+            now = time.perf_counter() - t0
+            for t in list(live):
+                if srv.poll(t)[0]:
+                    i, io = live.pop(t)
+                    io_used -= io
+                    lat[i], t_done[i] = now - arrivals[i], now
+                    print("[bench] request %d (%s %d) done: latency %.2f s" % (
+                        i, "2D" if sigs[i].dims == 2 else "1D", sigs[i].length, lat[i]), file=sys.stderr, flush=True)
+        elif waiting:
+            time.sleep(max(0.0, min(0.05, arrivals[waiting[0]] - now)))
+    torch.cuda.synchronize()
+    wall = max(t_done) - float(arrivals[0])
+    st = srv.stats()
+    srv.close()
+    gates = sum(plans[(s.dims, s.length)][1].info.gates for s in sigs)
+    points = sum(s.points for s in sigs)
+    bitmacs = sum(work(s) for s in sigs)
+    return {
+        "metric": "encrypted gates/s (1 GPU, served)",
+        "value": gates / wall,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "served_poisson", "requests": len(sigs), "mix": "1D 16..256 complex / 2D 8..32 real",
+                   "F": 16, "f": 8, "n_lwe": 1, "rate_per_s": rate, "load": args.load,
+                   "max_active": args.max_active, "fill_blocks": fill, "budget_gb": round(budget / 1e9, 1),
+                   "io_gb": args.io_gb},
+        "fft_points_per_s": points / wall,
+        "bitmac_per_s": bitmacs / wall,
+        "latency_p50_s": pct(lat, 50),
+        "latency_p99_s": pct(lat, 99),
+        "latency_mean_s": float(np.mean(lat)),
+        "steps_run": int(st.steps),
+        "max_in_flight": int(st.max_active),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=64, help="batch mode: number of requests")
     ap.add_argument("--max-active", type=int, default=0, help="batch mode: requests in flight (0 = no limit)")
-    ap.add_argument("--budget-gb", type=float, default=120.0, help="batch mode: workspace memory budget")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="batch/serve: workspace memory budget (default 120 GB batch, 180 GB serve)")
     ap.add_argument("--max-len", type=int, default=128, help="batch mode: longest request length (8..128)")
+    ap.add_argument("--rate", type=float, default=0.0, help="serve mode: arrivals per second (0 = from --load)")
+    ap.add_argument("--load", type=float, default=0.7, help="serve mode: offered load as a fraction of capacity")
+    ap.add_argument("--rate-bitmac", type=float, default=1.3e15, help="serve mode: capacity in bit-MAC/s")
+    ap.add_argument("--io-gb", type=float, default=60.0, help="serve mode: ciphertexts of requests in flight")
+    ap.add_argument("--fill-blocks", type=int, default=-1,
+                    help="batch/serve: request-loop fill target in workgroups, 0 = lockstep "
+                         "(default: 0 batch, 2048 serve)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
@@ -245,6 +358,9 @@ def main():
 
     if args.workload == "batch":
         print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
         return
     sig, n_lwe, seed = WL.workload(args.workload)
     cplx = sig.is_complex

@@ -167,6 +167,14 @@ typedef struct {
     int32_t max_active;        /* requests in flight at once; 0 = no limit */
     int32_t flags;             /* SFFT_SERVER_DRYRUN */
     double dry_bitmac_per_s;   /* modelled product rate in dry-run mode (0 = 1e15) */
+    /* 0: every step advances every admitted request (lockstep).  > 0: a step
+     * advances admitted requests in order of least remaining work: the first
+     * always, others while the step's product workgroups are below
+     * fill_blocks, skipping any whose level alone exceeds fill_blocks.  The
+     * others wait, so small requests are not held to the pace of a large
+     * one's levels (which may starve a large request under a steady stream
+     * of small ones). */
+    int64_t fill_blocks;
 } sfft_server_cfg;
 
 typedef struct {

@@ -151,9 +151,9 @@ class Server:
     """Continuous-batching request loop over libsfft's sfft_server_*."""
 
     def __init__(self, mem_budget_bytes: int, max_active: int = 0, dry_run: bool = False,
-                 dry_bitmac_per_s: float = 0.0):
+                 dry_bitmac_per_s: float = 0.0, fill_blocks: int = 0):
         cfg = S.sfft_server_cfg(int(mem_budget_bytes), int(max_active), S.SFFT_SERVER_DRYRUN if dry_run else 0,
-                                float(dry_bitmac_per_s))
+                                float(dry_bitmac_per_s), int(fill_blocks))
         self.dry = dry_run
         self.handle = S.sfft_server_create(cfg)
         self._keep = {}
@@ -179,7 +179,12 @@ class Server:
         S.sfft_server_drain(self.handle, None if self.dry else _stream_ptr(stream))
 
     def poll(self, ticket):
-        return S.sfft_server_poll(self.handle, ticket)
+        """(done, latency_s); once done, the request's buffers are no longer
+        held by the server object."""
+        done, lat = S.sfft_server_poll(self.handle, ticket)
+        if done:
+            self._keep.pop(ticket, None)
+        return done, lat
 
     def stats(self):
         return S.sfft_server_stats_get(self.handle)

@@ -227,6 +227,15 @@ int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upl
     pl->geo = geo_of(params);
     pl->points = shape->dims == 1 ? shape->len : (int64_t)shape->len * shape->len;
     if (!product_config(pl->geo, &pl->cfg)) return fail(SFFT_EUNSUPPORTED, "no kernel configuration for this geometry");
+    const size_t nsteps = pl->sched.levels.size() + 1;
+    pl->step_blocks.assign(nsteps, 0);
+    pl->work_from.assign(nsteps + 1, 0.0);
+    const double per_product = (double)pl->geo.nct * pl->geo.nct * pl->geo.nct;
+    for (size_t st = nsteps; st-- > 0;) {
+        const int64_t prods = st < pl->sched.levels.size() ? pl->sched.levels[st].prod_count : 0;
+        pl->step_blocks[st] = prods * product_tiles(pl->geo, pl->cfg);
+        pl->work_from[st] = pl->work_from[st + 1] + (double)prods * per_product;
+    }
     if (!upload) return SFFT_OK;
     auto put = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
         *dst = nullptr;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/sfft.h"
 #include "device.hpp"
@@ -21,6 +22,10 @@ struct PlanCore {
     ProdItem* d_prods = nullptr;
     LinItem* d_lins = nullptr;
     LinItem* d_final = nullptr;
+    // per step s (levels, then the output pass): the step's workgroups and the
+    // bit-MACs (products x Nct^3) of steps s.. to the end
+    std::vector<int64_t> step_blocks;
+    std::vector<double> work_from;
 
     int64_t ct_words() const { return (int64_t)geo.nct * geo.W; }
     int64_t ws_bytes() const { return sched.n_slots * ct_words() * 4; }

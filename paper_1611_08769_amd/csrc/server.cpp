@@ -261,6 +261,27 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
     std::map<std::pair<int, int>, ProdGroup> pgroups;  // (tiling, workgroups per CU by LDS)
     std::vector<LinGroup> lgroups;
     double model_s = 0;
+    // which requests advance this step (all, or least remaining work first
+    // up to fill_blocks workgroups)
+    std::vector<Request*> run;
+    for (auto& rp : sv->active) run.push_back(rp.get());
+    if (sv->cfg.fill_blocks > 0) {
+        std::stable_sort(run.begin(), run.end(), [](const Request* a, const Request* b) {
+            return a->plan->work_from[a->step] < b->plan->work_from[b->step];
+        });
+        // the first request always runs; others join while the step is below
+        // the target, except one whose level alone exceeds the target (it
+        // would set the step's pace for all the small ones: it waits)
+        std::vector<Request*> pick;
+        int64_t blocks = 0;
+        for (Request* q : run) {
+            const int64_t qb = q->plan->step_blocks[q->step];
+            if (!pick.empty() && (blocks >= sv->cfg.fill_blocks || qb > sv->cfg.fill_blocks)) continue;
+            pick.push_back(q);
+            blocks += qb;
+        }
+        run.swap(pick);
+    }
     auto add_lin = [&](size_t q, const LinItem* items, const Bufs& b, const Geo& g, int64_t count) {
         if (lgroups.size() <= q) lgroups.resize(q + 1);
         LinGroup& G = lgroups[q];
@@ -268,8 +289,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         G.n += count;
         G.max_elems = std::max<int64_t>(G.max_elems, (int64_t)g.nct * g.n1);
     };
-    for (auto& rp : sv->active) {
-        Request* r = rp.get();
+    for (Request* r : run) {
         const PlanCore& pc = *r->plan;
         const Schedule& S = pc.sched;
         Bufs b{const_cast<uint32_t*>(r->in), r->out,
@@ -355,11 +375,11 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
     }
     sv->st.steps++;
 
-    // advance; retire finished requests
+    // advance the requests that ran; retire finished ones
+    for (Request* r : run) r->step++;
     const double t = now_of(sv);
     std::vector<std::unique_ptr<Request>> still;
     for (auto& rp : sv->active) {
-        rp->step++;
         if (rp->step >= (int32_t)rp->plan->sched.levels.size() + 1) {
             rp->done_at = t;
             sv->arena.release(rp->ws_off);

@@ -43,7 +43,7 @@ SFFT_SERVER_DRYRUN = 1
 
 class sfft_server_cfg(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("dry_bitmac_per_s", ctypes.c_double)]
+                ("dry_bitmac_per_s", ctypes.c_double), ("fill_blocks", ctypes.c_int64)]
 
 
 class sfft_server_stats(ctypes.Structure):

@@ -131,3 +131,28 @@ def batch_requests(seed: int = 4, count: int = 256, lengths=(8, 16, 32, 64, 128)
         F = (12, 16, 24)[min(int(b * 3), 2)]
         reqs.append(uniform_pm1(seed, n, F, F // 2, True, stream=u))
     return reqs
+
+
+def served_requests(seed: int = 5, count: int = 40):
+    """Mixed serving traffic: half 1D requests (length uniform in
+    {16, 32, 64, 128, 256}, complex inputs uniform in [-1, 1)), half 2D
+    images (side uniform in {8, 16, 32}, pixels as in image()), all Q(16,8)."""
+    u = Uniforms(seed)
+    reqs = []
+    for _ in range(count):
+        a, b = u.next(2)
+        if a < 0.5:
+            n = (16, 32, 64, 128, 256)[min(int(b * 5), 4)]
+            reqs.append(uniform_pm1(seed, n, 16, 8, True, stream=u))
+        else:
+            side = (8, 16, 32)[min(int(b * 3), 2)]
+            reqs.append(image(seed, side, 16, 8, stream=u))
+    return reqs
+
+
+def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate:
+    exponential gaps -ln(1 - u) / rate from domain-5 uniforms of seed."""
+    u = Uniforms(seed).next(count)
+    return np.cumsum(-np.log1p(-u) / rate)
+

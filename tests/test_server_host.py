@@ -99,3 +99,44 @@ def test_unknown_ticket():
     srv = api.Server(1 << 20, dry_run=True)
     with pytest.raises(S.SfftError):
         srv.poll(12345)
+
+
+def test_fill_policy_runs_least_remaining_work_first():
+    """With fill_blocks set, a small request submitted behind a large one is
+    not held to the large one's pace: it completes first, every request
+    still completes and the products add up."""
+    big, small = (1, 32, 12, 6, True), (1, 8, 8, 4, False)
+    pb, ib = _plan_info(big)
+    ps, is_ = _plan_info(small)
+    lock = api.Server(1 << 34, dry_run=True)
+    fill = api.Server(1 << 34, dry_run=True, fill_blocks=1)
+    res = {}
+    for name, srv in (("lock", lock), ("fill", fill)):
+        tb = srv.submit(*big, pb)
+        ts = srv.submit(*small, ps)
+        srv.drain()
+        st = srv.stats()
+        assert st.completed == 2 and st.products == ib.exec_products + is_.exec_products
+        res[name] = (srv.poll(tb)[1], srv.poll(ts)[1], st.steps)
+    # lockstep: both advance every step; fill (one request per step): the
+    # small one runs alone from the start and finishes sooner
+    assert res["fill"][1] < res["lock"][1]
+    assert res["fill"][1] < res["fill"][0]
+    # one request per step here: about as many steps as the two plans have together
+    assert res["fill"][2] >= ib.levels + is_.levels
+
+
+def test_fill_policy_keeps_large_levels_out_of_small_steps():
+    """A large request's level (more workgroups than fill_blocks) does not join
+    a step that small requests started: small requests run on their own and
+    all finish before the large one, which then completes too."""
+    big, small = (1, 32, 12, 6, True), (1, 8, 8, 4, False)
+    pb, _ = _plan_info(big)
+    ps, _ = _plan_info(small)
+    srv = api.Server(1 << 34, dry_run=True, fill_blocks=64)
+    tb = srv.submit(*big, pb)
+    ts = [srv.submit(*small, ps) for _ in range(3)]
+    srv.drain()
+    lb = srv.poll(tb)[1]
+    assert all(srv.poll(t)[0] for t in ts) and srv.poll(tb)[0]
+    assert max(srv.poll(t)[1] for t in ts) < lb
