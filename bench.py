@@ -257,19 +257,22 @@ def run_serve(args):
         now = time.perf_counter() - t0
         while waiting and arrivals[waiting[0]] <= now:
             client_q.append(waiting.popleft())
-        while client_q:
-            i = client_q[0]
+        # arrived requests enter in arrival order while their ciphertexts fit
+        # (with the fill policy, later ones that fit may pass one that does not)
+        for i in list(client_q):
             sig = sigs[i]
             p, plan = plans[(sig.dims, sig.length)]
             io = (plan.info.n_inputs + plan.info.n_outputs) * plan.ct_words * 4
             if live and io_used + io > io_cap:
+                if fill > 0:
+                    continue
                 break
             keys = api.keygen(p, 5000 + i)
             ct_in = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=5000 + i)
             ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
             live[srv.submit_plan(plan, ct_in, ct_out)] = (i, io)
             io_used += io
-            client_q.popleft()
+            client_q.remove(i)
         if live:
             srv.step()
             now = time.perf_counter() - t0

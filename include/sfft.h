@@ -172,8 +172,9 @@ typedef struct {
      * always, others while the step's product workgroups are below
      * fill_blocks, skipping any whose level alone exceeds fill_blocks.  The
      * others wait, so small requests are not held to the pace of a large
-     * one's levels (which may starve a large request under a steady stream
-     * of small ones). */
+     * one's levels.  Admission then also lets a later request whose
+     * workspace fits pass one that does not yet.  (Both may starve a large
+     * request under a steady stream of small ones.) */
     int64_t fill_blocks;
 } sfft_server_cfg;
 

@@ -225,15 +225,23 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
 {
     if (!sv) return sfft_fail(SFFT_EINVAL, "null server");
     hipStream_t s = (hipStream_t)hip_stream;
-    // admission: arrival order, by workspace footprint and slot limit
-    while (!sv->queue.empty()) {
+    // admission by workspace footprint and slot limit, in arrival order; with
+    // the fill policy a request whose workspace does not fit yet lets later
+    // ones that fit pass (no head-of-line blocking), lockstep keeps strict order
+    for (auto it = sv->queue.begin(); it != sv->queue.end();) {
         if (sv->cfg.max_active > 0 && (int)sv->active.size() >= sv->cfg.max_active) break;
-        Request* r = sv->queue.front().get();
+        Request* r = it->get();
         const int64_t off = sv->arena.alloc(std::max<int64_t>(r->plan->ws_bytes(), 1));
-        if (off < 0) break;
+        if (off < 0) {
+            if (sv->cfg.fill_blocks > 0) {
+                ++it;
+                continue;
+            }
+            break;
+        }
         r->ws_off = off;
-        sv->active.push_back(std::move(sv->queue.front()));
-        sv->queue.pop_front();
+        sv->active.push_back(std::move(*it));
+        it = sv->queue.erase(it);
         sv->st.admitted++;
     }
     sv->st.max_active = std::max<int64_t>(sv->st.max_active, (int64_t)sv->active.size());

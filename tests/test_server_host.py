@@ -140,3 +140,23 @@ def test_fill_policy_keeps_large_levels_out_of_small_steps():
     lb = srv.poll(tb)[1]
     assert all(srv.poll(t)[0] for t in ts) and srv.poll(tb)[0]
     assert max(srv.poll(t)[1] for t in ts) < lb
+
+
+def test_fill_policy_admission_skips_a_blocked_head():
+    """Under the fill policy a small request queued behind one whose workspace
+    does not fit yet is admitted at once; lockstep keeps strict arrival order."""
+    big, small = (1, 32, 12, 6, True), (1, 8, 8, 4, False)
+    pb, ib = _plan_info(big)
+    ps, is_ = _plan_info(small)
+    wb, ws = _ws_bytes(ib, pb), _ws_bytes(is_, ps)
+    budget = wb + 2 * ws + 4096  # one big at a time, with room left for small ones
+    for fill, expect_small_first in ((1, True), (0, False)):
+        srv = api.Server(budget, dry_run=True, fill_blocks=fill)
+        t1 = srv.submit(*big, pb)
+        t2 = srv.submit(*big, pb)   # cannot be admitted while t1 runs
+        t3 = srv.submit(*small, ps)
+        srv.step()
+        st = srv.stats()
+        assert st.admitted == (2 if expect_small_first else 1)
+        srv.drain()
+        assert all(srv.poll(t)[0] for t in (t1, t2, t3))
