@@ -338,6 +338,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fft1d_n64_cplx_q16.8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the default tiling instead of tuning it first")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB three times (counter reference)")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -357,6 +358,7 @@ def main():
         return
     import torch
     from paper_1611_08769_amd import api
+    from paper_1611_08769_amd import sfft as S
     from paper_1611_08769_amd import workloads as WL
 
     if args.workload == "batch":
@@ -368,12 +370,19 @@ def main():
     sig, n_lwe, seed = WL.workload(args.workload)
     cplx = sig.is_complex
     params = api.size_params(sig.dims, sig.length, sig.F, sig.f, cplx, n_lwe)
+    tuned = None
     keys = api.keygen(params, seed)
     words = api.signal_words(sig)
     ct_in = api.encrypt_words(keys, words, sig.F, seed=seed)
     plan = api.Plan(sig.dims, sig.length, sig.F, sig.f, cplx, params)
+    ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
+    if not args.no_tune:
+        # tiling chosen on the plan's own widest level, before the clock starts
+        best, rates = plan.tune(ct_in, ct_out)
+        tuned = {"tiling": best, "candidates": {str(k): round(v / 1e12, 1) for k, v in rates.items()}}
+        print("[bench] tuner: tiling %d; Tbit-MAC/s per candidate %s" % (best, tuned["candidates"]),
+              file=sys.stderr, flush=True)
     info = plan.info
-    ct_out = torch.empty((info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
     nct = (params.n_lwe + 1) * params.k
     step_prods = plan.step_products()
     nsteps = len(step_prods)
@@ -436,7 +445,9 @@ def main():
             "n_lwe": params.n_lwe, "k": params.k, "nct": nct,
             "canonical_gates": int(info.gates), "canonical_products": int(info.products),
             "exec_products": int(info.exec_products), "levels": int(info.levels),
+            "tiling": list(S.sfft_tiling_describe(info.tiling)),
         },
+        "tuner": tuned,
         "fft_points_per_s": npts / step_s,
         "products_per_s": info.exec_products / step_s,
         "latency_p50_s": pct(lat, 50),

@@ -73,6 +73,7 @@ typedef struct {
     int64_t exec_steps;           /* steps of sfft_execute_steps: levels + 2 */
     int32_t k_required;           /* least multiple of 32 meeting the noise rule */
     char netlist_sha256[65];      /* hex SHA-256 of the canonical netlist */
+    int32_t tiling;               /* product-kernel tiling the plan launches (sfft_tiling_describe) */
 } sfft_plan_info;
 
 const char* sfft_last_error(void);
@@ -150,6 +151,36 @@ int sfft_decrypt_bits(const sfft_params* params, const uint32_t* sk_host, const 
  * (= AND).  x, y, out: one ciphertext each, device; out must not alias. */
 int sfft_gate(const sfft_params* params, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev,
               uint32_t* out_dev, void* hip_stream);
+
+/* ---- product-kernel tilings and the autotuner ---------------------------
+ * The product kernel exists in several tilings (threads per workgroup, lanes
+ * per output row, digit slots per lane, rows per lane, lookup pipeline
+ * depth, 4-bit groups per chunk of R).  Plans use, per ciphertext geometry
+ * (k, n_lwe), the tiling recorded for it (by sfft_tune or sfft_set_tiling,
+ * process-wide), else a default by digits per row.  Plans keep the tiling
+ * they were created with. */
+int sfft_tiling_count(void);
+/* fields[6] = threads, lanes per row, digit slots per lane, rows per lane,
+ * pipeline depth, groups per chunk.  SFFT_EINVAL for an unknown tiling. */
+int sfft_tiling_describe(int32_t tiling, int32_t* fields);
+/* Record a tiling for params' geometry (-1: back to the default).
+ * SFFT_EINVAL if the tiling cannot serve the geometry. */
+int sfft_set_tiling(const sfft_params* params, int32_t tiling);
+/* Time every tiling that can serve params' geometry on a synthetic level of
+ * products (random operands, two outputs each; reps timed launches after a
+ * warm-up, on hip_stream), record the fastest and return it in
+ * *best_tiling.  rates (optional, sfft_tiling_count() entries) receives
+ * bit-MAC/s per tiling, 0 where a tiling cannot serve.  Allocates and frees
+ * its own device buffers (a few GB at most); synchronous. */
+int sfft_tune(const sfft_params* params, int32_t reps, int32_t* best_tiling, double* rates, void* hip_stream);
+/* Tune on a plan's own work: run the plan's steps up to its widest product
+ * level (ct_in_dev, ct_out_dev and the workspace as for sfft_execute), time
+ * that level under every tiling that can serve the plan, switch the plan to
+ * the fastest and record it for its geometry.  Re-running a level rewrites
+ * the same outputs, so the buffers hold a valid partial run afterwards;
+ * sfft_execute from the start gives the usual result.  Synchronous. */
+int sfft_plan_tune(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                   int64_t ws_bytes, int32_t reps, int32_t* best_tiling, double* rates, void* hip_stream);
 
 /* ---- continuous batching / serving -------------------------------------
  * A server runs many encrypted FFTs of different shapes and parameter sets

@@ -118,6 +118,17 @@ class Plan:
         S.sfft_execute_steps(self.handle, first, count, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(),
                              ws.numel() * 4, _stream_ptr(stream))
 
+    def tune(self, ct_in: torch.Tensor, ct_out: torch.Tensor | None = None, reps: int = 3, stream=None):
+        """Time the plan's widest level under every tiling that can serve it
+        and switch the plan to the fastest: (tiling, {tiling: bit-MAC/s})."""
+        if ct_out is None:
+            ct_out = torch.empty((self.info.n_outputs, self.ct_words), dtype=torch.int32, device=ct_in.device)
+        ws = self.workspace()
+        best, rates = S.sfft_plan_tune(self.handle, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(),
+                                       ws.numel() * 4, reps, _stream_ptr(stream))
+        self.info = S.sfft_plan_info_get(self.handle)
+        return best, {i: r for i, r in enumerate(rates) if r > 0}
+
     def step_products(self):
         return S.sfft_plan_step_products(self.handle, self.info.exec_steps)
 
@@ -132,6 +143,19 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def tune(params: S.sfft_params, reps: int = 3, stream=None):
+    """Time every product-kernel tiling for params' geometry on the GPU and
+    record the fastest for plans created afterwards: (tiling, {tiling:
+    bit-MAC/s})."""
+    best, rates = S.sfft_tune(params, reps, _stream_ptr(stream))
+    return best, {i: r for i, r in enumerate(rates) if r > 0}
+
+
+def set_tiling(params: S.sfft_params, tiling: int) -> None:
+    """Record a tiling for params' geometry (-1: back to the default)."""
+    S.sfft_set_tiling(params, tiling)
 
 
 def size_params(dims, length, F, f, is_complex, n_lwe) -> S.sfft_params:

@@ -377,6 +377,7 @@ int sfft_plan_info_get(const sfft_plan* plan, sfft_plan_info* info)
 {
     if (!plan || !info) return fail(SFFT_EINVAL, "null argument");
     *info = plan->info;
+    info->tiling = plan->cfg.tiling;
     return SFFT_OK;
 }
 

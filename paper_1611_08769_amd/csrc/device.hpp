@@ -45,7 +45,18 @@ struct KCfg {
     uint32_t one;
 };
 
+// The kernel's tilings: how many, and (threads, lanes per row, digit slots
+// per lane, rows per lane, pipeline depth, groups per chunk) of one.
+int tiling_count();
+void tiling_fields(int ti, int* fields6);
+// cfg for tiling ti on geometry g; false if ti cannot serve g (too few digit
+// slots per row, or more LDS than a CU has).
+bool tiling_config(const Geo& g, int ti, ProdCfg* cfg);
+// The tiling a plan of geometry g uses: the one recorded for g by the tuner
+// (set_tuned_tiling, process-wide; ti < 0 clears), else the default of g's
+// width class.
 bool product_config(const Geo& g, ProdCfg* cfg);
+void set_tuned_tiling(const Geo& g, int ti);
 
 // A run of work items sharing one set of buffers and one ciphertext
 // geometry (one request).  A launch covers the concatenation of its

@@ -22,6 +22,9 @@
 // a L + b R + c P + g G + e E (AND, XOR, OR, NOT, NAND, XADD forms) mod 2^k.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "device.hpp"
 
 namespace sfft {
@@ -549,7 +552,9 @@ hipError_t launch_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const P
 }
 
 // Tilings: (threads, lanes per row, digit slots per lane, rows per lane,
-// lookup pipeline depth, 4-bit groups per chunk).
+// lookup pipeline depth, 4-bit groups per chunk).  The first kDefaultTilings
+// are the defaults, one per width class; the rest are alternatives the tuner
+// may pick for a geometry.
 struct Tiling {
     int threads, lpr, dpl, rpl, pd, cg;
 };
@@ -559,7 +564,17 @@ constexpr Tiling kTilings[] = {
     {256, 8, 8, 7, 2, 8},    // <= 64
     {512, 8, 12, 5, 2, 8},   // <= 96
     {512, 8, 16, 4, 1, 4},   // <= 128
+    // alternatives
+    {512, 8, 4, 12, 1, 8},   // <= 32, 8 waves
+    {512, 8, 8, 7, 2, 8},    // <= 64, 8 waves
+    {256, 8, 8, 8, 2, 4},    // <= 64, 16-row chunks
+    {512, 8, 12, 5, 1, 8},   // <= 96, pipeline depth 1
+    {256, 8, 12, 5, 2, 4},   // <= 96, 4 waves, 16-row chunks
+    {256, 4, 12, 4, 2, 8},   // <= 48, 4 lanes per row
+    {512, 4, 20, 2, 1, 8},   // <= 80, 4 lanes per row
 };
+constexpr int kNumTilings = (int)(sizeof(kTilings) / sizeof(kTilings[0]));
+constexpr int kDefaultTilings = 5;
 
 template <bool ENC>
 hipError_t dispatch(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0, const ProdItem& one,
@@ -574,7 +589,15 @@ hipError_t dispatch(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const P
     CASE(2)
     CASE(3)
     CASE(4)
+    CASE(5)
+    CASE(6)
+    CASE(7)
+    CASE(8)
+    CASE(9)
+    CASE(10)
+    CASE(11)
 #undef CASE
+    static_assert(kNumTilings == 12, "one CASE per tiling");
     return hipErrorInvalidValue;
 }
 
@@ -590,19 +613,22 @@ ProdSeg single_segment(const Bufs& b, const Geo& g, const ProdCfg& cfg)
 
 }  // namespace
 
-bool product_config(const Geo& g, ProdCfg* cfg)
+int tiling_count() { return kNumTilings; }
+
+void tiling_fields(int ti, int* f)
 {
+    const Tiling& t = kTilings[ti];
+    f[0] = t.threads, f[1] = t.lpr, f[2] = t.dpl, f[3] = t.rpl, f[4] = t.pd, f[5] = t.cg;
+}
+
+bool tiling_config(const Geo& g, int ti, ProdCfg* cfg)
+{
+    if (ti < 0 || ti >= kNumTilings) return false;
     if (g.nct % 32 != 0 || g.W * 32 != g.nct || g.W > kMaxRowWords) return false;
+    const Tiling& t = kTilings[ti];
     const int nd = (g.k + kDigitBits - 1) / kDigitBits;
     const int wd = g.n1 * nd;
-    int ti = -1;
-    for (int i = 0; i < (int)(sizeof(kTilings) / sizeof(kTilings[0])); i++)
-        if (kTilings[i].lpr * kTilings[i].dpl >= wd) {
-            ti = i;
-            break;
-        }
-    if (ti < 0) return false;
-    const Tiling& t = kTilings[ti];
+    if (t.lpr * t.dpl < wd) return false;
     cfg->tiling = ti;
     cfg->threads = t.threads;
     cfg->cg = t.cg;
@@ -622,6 +648,30 @@ bool product_config(const Geo& g, ProdCfg* cfg)
     const int epi_words = 2 * per_iter * pi * cfg->st;
     cfg->lds_bytes = 4 * (main_words > epi_words ? main_words : epi_words);
     return cfg->lds_bytes <= 160 * 1024;
+}
+
+namespace {
+std::mutex g_tuned_mu;
+std::map<std::pair<int, int>, int> g_tuned;  // (k, n+1) -> tiling
+}  // namespace
+
+void set_tuned_tiling(const Geo& g, int ti)
+{
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    if (ti < 0) g_tuned.erase({g.k, g.n1});
+    else g_tuned[{g.k, g.n1}] = ti;
+}
+
+bool product_config(const Geo& g, ProdCfg* cfg)
+{
+    {
+        std::lock_guard<std::mutex> lock(g_tuned_mu);
+        auto it = g_tuned.find({g.k, g.n1});
+        if (it != g_tuned.end() && tiling_config(g, it->second, cfg)) return true;
+    }
+    for (int i = 0; i < kDefaultTilings; i++)
+        if (tiling_config(g, i, cfg)) return true;
+    return false;
 }
 
 hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,

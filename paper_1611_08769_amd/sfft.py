@@ -35,7 +35,7 @@ class sfft_plan_info(ctypes.Structure):
                 ("max_level_products", ctypes.c_int64), ("n_inputs", ctypes.c_int64),
                 ("n_outputs", ctypes.c_int64), ("ws_cts", ctypes.c_int64), ("exec_steps", ctypes.c_int64),
                 ("k_required", ctypes.c_int32),
-                ("netlist_sha256", ctypes.c_char * 65)]
+                ("netlist_sha256", ctypes.c_char * 65), ("tiling", ctypes.c_int32)]
 
 
 SFFT_SERVER_DRYRUN = 1
@@ -95,6 +95,12 @@ _SIGS = {
     "sfft_server_create": (ctypes.c_int, [_P(sfft_server_cfg), _P(_vp)]),
     "sfft_server_submit": (ctypes.c_int, [_vp, _P(sfft_shape), _P(sfft_params), _vp, _vp, _P(ctypes.c_uint64)]),
     "sfft_server_submit_plan": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint64)]),
+    "sfft_tiling_count": (ctypes.c_int, []),
+    "sfft_tiling_describe": (ctypes.c_int, [ctypes.c_int32, _P(ctypes.c_int32)]),
+    "sfft_set_tiling": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32]),
+    "sfft_tune": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_double), _vp]),
+    "sfft_plan_tune": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_int32),
+                                      _P(ctypes.c_double), _vp]),
     "sfft_server_step": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
     "sfft_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(ctypes.c_int32), _P(ctypes.c_double)]),
     "sfft_server_drain": (ctypes.c_int, [_vp, _vp]),
@@ -216,6 +222,34 @@ def sfft_server_submit_plan(srv, plan, ct_in_ptr, ct_out_ptr) -> int:
     t = ctypes.c_uint64()
     _check(_lib.sfft_server_submit_plan(srv, plan, ct_in_ptr, ct_out_ptr, ctypes.byref(t)))
     return t.value
+
+
+def sfft_tiling_count() -> int:
+    return _lib.sfft_tiling_count()
+
+
+def sfft_tiling_describe(tiling: int):
+    f = (ctypes.c_int32 * 6)()
+    _check(_lib.sfft_tiling_describe(tiling, f))
+    return tuple(f)
+
+
+def sfft_set_tiling(p, tiling: int) -> None:
+    _check(_lib.sfft_set_tiling(ctypes.byref(p), tiling))
+
+
+def sfft_tune(p, reps, stream):
+    best = ctypes.c_int32()
+    rates = (ctypes.c_double * sfft_tiling_count())()
+    _check(_lib.sfft_tune(ctypes.byref(p), reps, ctypes.byref(best), rates, stream))
+    return best.value, list(rates)
+
+
+def sfft_plan_tune(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, reps, stream):
+    best = ctypes.c_int32()
+    rates = (ctypes.c_double * sfft_tiling_count())()
+    _check(_lib.sfft_plan_tune(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, reps, ctypes.byref(best), rates, stream))
+    return best.value, list(rates)
 
 
 def sfft_server_step(srv, stream) -> int:
