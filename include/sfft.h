@@ -131,6 +131,13 @@ int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
  * requests' steps, timing events) on the same or other streams. */
 int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, const uint32_t* ct_in_dev,
                        uint32_t* ct_out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream);
+/* sfft_execute through a HIP graph: the first call (or one with other
+ * buffers than the last) captures the plan's launch sequence on hip_stream
+ * (which must not be the null stream) and instantiates it; later calls with
+ * the same buffers replay it with one graph launch.  One captured graph per
+ * plan; the graph holds no memset nodes.  Same results as sfft_execute. */
+int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                       int64_t ws_bytes, void* hip_stream);
 /* Product items per step (counts has exec_steps entries). */
 int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n);
 

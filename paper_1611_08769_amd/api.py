@@ -118,6 +118,17 @@ class Plan:
         S.sfft_execute_steps(self.handle, first, count, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(),
                              ws.numel() * 4, _stream_ptr(stream))
 
+    def execute_graph(self, ct_in: torch.Tensor, ct_out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """execute() through a HIP graph captured on first use for these
+        buffers and replayed afterwards (stream: a torch stream other than
+        the null stream; the current stream by default)."""
+        if ct_out is None:
+            ct_out = torch.empty((self.info.n_outputs, self.ct_words), dtype=torch.int32, device=ct_in.device)
+        ws = self.workspace()
+        S.sfft_execute_graph(self.handle, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(), ws.numel() * 4,
+                             _stream_ptr(stream))
+        return ct_out
+
     def tune(self, ct_in: torch.Tensor, ct_out: torch.Tensor | None = None, reps: int = 3, stream=None):
         """Time the plan's widest level under every tiling that can serve it
         and switch the plan to the fastest: (tiling, {tiling: bit-MAC/s})."""

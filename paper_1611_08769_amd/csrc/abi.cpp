@@ -213,6 +213,8 @@ PlanCore::~PlanCore()
 {
     // work enqueued with this plan may still read its tables
     if (d_prods || d_lins || d_final) (void)hipDeviceSynchronize();
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (d_prods) (void)hipFree(d_prods);
     if (d_lins) (void)hipFree(d_lins);
     if (d_final) (void)hipFree(d_final);
@@ -434,6 +436,47 @@ int sfft_execute(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
     if (!plan) return fail(SFFT_EINVAL, "null plan");
     return sfft_execute_steps(plan, 0, (int32_t)plan->sched.levels.size() + 1, ct_in_dev, ct_out_dev, ws_dev,
                               ws_bytes, hip_stream);
+}
+
+int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                       int64_t ws_bytes, void* hip_stream)
+{
+    if (!plan) return fail(SFFT_EINVAL, "null plan");
+    if (!hip_stream) return fail(SFFT_EINVAL, "graph capture needs a stream other than the null stream");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!plan->graph_exec || plan->graph_in != ct_in_dev || plan->graph_out != ct_out_dev || plan->graph_ws != ws_dev) {
+        if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+        if (plan->graph) (void)hipGraphDestroy(plan->graph);
+        plan->graph_exec = nullptr;
+        plan->graph = nullptr;
+        // set the kernel's LDS attribute outside the capture (a launch of
+        // no workgroups does only that)
+        const ProdSeg none{nullptr, Bufs{}, plan->geo, plan->cfg.nd, plan->cfg.wd, 0, 0};
+        hipError_t e = launch_products(plan->cfg, nullptr, 1, none, 0, s);
+        if (e != hipSuccess) return hip_fail(e, "graph preparation");
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "graph capture");
+        const int rc = sfft_execute(plan, ct_in_dev, ct_out_dev, ws_dev, ws_bytes, hip_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (rc != SFFT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture");
+        e = hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "graph instantiation");
+        }
+        plan->graph = g;
+        plan->graph_in = ct_in_dev;
+        plan->graph_out = ct_out_dev;
+        plan->graph_ws = ws_dev;
+    }
+    hipError_t e = hipGraphLaunch(plan->graph_exec, s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SFFT_OK;
 }
 
 int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n)

@@ -26,6 +26,12 @@ struct PlanCore {
     // bit-MACs (products x Nct^3) of steps s.. to the end
     std::vector<int64_t> step_blocks;
     std::vector<double> work_from;
+    // the plan's launch sequence captured for one set of buffers (sfft_execute_graph)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void* graph_in = nullptr;
+    const void* graph_out = nullptr;
+    const void* graph_ws = nullptr;
 
     int64_t ct_words() const { return (int64_t)geo.nct * geo.W; }
     int64_t ws_bytes() const { return sched.n_slots * ct_words() * 4; }

@@ -95,6 +95,7 @@ _SIGS = {
     "sfft_server_create": (ctypes.c_int, [_P(sfft_server_cfg), _P(_vp)]),
     "sfft_server_submit": (ctypes.c_int, [_vp, _P(sfft_shape), _P(sfft_params), _vp, _vp, _P(ctypes.c_uint64)]),
     "sfft_server_submit_plan": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint64)]),
+    "sfft_execute_graph": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "sfft_tiling_count": (ctypes.c_int, []),
     "sfft_tiling_describe": (ctypes.c_int, [ctypes.c_int32, _P(ctypes.c_int32)]),
     "sfft_set_tiling": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32]),
@@ -250,6 +251,10 @@ def sfft_plan_tune(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, reps, stream):
     rates = (ctypes.c_double * sfft_tiling_count())()
     _check(_lib.sfft_plan_tune(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, reps, ctypes.byref(best), rates, stream))
     return best.value, list(rates)
+
+
+def sfft_execute_graph(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_execute_graph(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
 
 
 def sfft_server_step(srv, stream) -> int:
