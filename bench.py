@@ -3,6 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
     python bench.py --workload batch [--requests 64] [--max-len 128]
     python bench.py --workload serve [--requests 40] [--load 0.7] [--max-active 0]
+    python bench.py --workload accuracy [--signals 4]
 
 A step is one encrypted FFT of one request (every product level of the
 compiled circuit, inputs already encrypted and resident in HBM).  Prints one
@@ -319,6 +320,64 @@ def run_serve(args):
     }
 
 
+def run_accuracy(args):
+    """The paper's accuracy experiment in its own format, on the encrypted
+    path: random complex signals in [0, 1), Q(32,16), N = 8..128.  Each
+    signal is encrypted, transformed and decrypted on the GPU; the error is
+    |decrypted - float64 FFT| per real component (2N values per signal),
+    summarised as the paper's Table 1 (total, mean, population variance and
+    standard deviation), printed beside the paper's rows."""
+    import torch
+    from paper_1611_08769_amd import api
+    from paper_1611_08769_amd import workloads as WL
+
+    paper = json.load(open(os.path.join(ROOT, "tests", "golden", "table1_errors.json")))["rows_1d"]
+    rows, gates, t_gpu = {}, 0, 0.0
+    for n in (8, 16, 32, 64, 128):
+        p = api.size_params(1, n, 32, 16, True, 1)
+        plan = api.Plan(1, n, 32, 16, True, p)
+        errs = []
+        u = WL.Uniforms(7000 + n)
+        for j in range(args.signals):
+            sig = WL.unit_complex(0, n, stream=u)
+            keys = api.keygen(p, 7000 + 100 * n + j)
+            ct_in = api.encrypt_words(keys, api.signal_words(sig), 32, seed=7000 + 100 * n + j)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ct_out = plan.execute(ct_in)
+            torch.cuda.synchronize()
+            t_gpu += time.perf_counter() - t0
+            gates += plan.info.gates
+            w = api.decrypt_words(keys, ct_out, 2 * n, 32).astype(np.float64) / 2.0 ** 16
+            exact = np.fft.fft(np.asarray(sig.re) + 1j * np.asarray(sig.im))
+            errs.append(np.abs(w[0::2] - exact.real))
+            errs.append(np.abs(w[1::2] - exact.imag))
+        e = np.concatenate(errs)
+        rows[str(n)] = {"signals": args.signals, "k": p.k, "total": float(e.sum()), "mean": float(e.mean()),
+                        "variance": float(e.var()), "sd": float(e.std()), "paper": paper[str(n)]}
+        print("[bench] N=%d k=%d: mean %.3e sd %.3e (paper %.3e, %.3e)" % (
+            n, p.k, e.mean(), e.std(), paper[str(n)][1], paper[str(n)][3]), file=sys.stderr, flush=True)
+        plan.close()
+    return {
+        "metric": "encrypted gates/s (1 GPU, paper accuracy format)",
+        "value": gates / t_gpu,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": t_gpu * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "accuracy_q32.16", "lengths": "8..128", "signals_per_length": args.signals,
+                   "inputs": "complex, real and imaginary parts uniform in [0,1)", "n_lwe": 1},
+        "table1": rows,
+        "table1_columns": ["total", "mean", "variance", "sd"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=64, help="batch mode: number of requests")
@@ -330,6 +389,7 @@ def main():
     ap.add_argument("--load", type=float, default=0.7, help="serve mode: offered load as a fraction of capacity")
     ap.add_argument("--rate-bitmac", type=float, default=1.3e15, help="serve mode: capacity in bit-MAC/s")
     ap.add_argument("--io-gb", type=float, default=60.0, help="serve mode: ciphertexts of requests in flight")
+    ap.add_argument("--signals", type=int, default=4, help="accuracy mode: signals per length")
     ap.add_argument("--fill-blocks", type=int, default=-1,
                     help="batch/serve: request-loop fill target in workgroups, 0 = lockstep "
                          "(default: 0 batch, 2048 serve)")
@@ -363,6 +423,9 @@ def main():
 
     if args.workload == "batch":
         print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.workload == "accuracy":
+        print(json.dumps(run_accuracy(args)), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps(run_serve(args)), flush=True)

@@ -156,3 +156,11 @@ def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
     u = Uniforms(seed).next(count)
     return np.cumsum(-np.log1p(-u) / rate)
 
+
+def unit_complex(seed: int, n: int, F: int = 32, f: int = 16, stream=None):
+    """Complex signal with real and imaginary parts uniform in [0, 1): the
+    inputs of the paper's one-dimensional accuracy experiment (section
+    "Experimental Results"), in its 32-bit format with 16 fractional bits."""
+    u = stream or Uniforms(seed)
+    return Signal(1, n, F, f, u.next(n), u.next(n))
+
