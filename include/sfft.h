@@ -53,9 +53,13 @@ typedef struct {
 /* Transform shape: dims 1 (len points) or 2 (len x len image, rows then
  * columns); len a power of two in [2, 4096]; F-bit two's-complement words
  * with f fractional bits (1 <= F <= 32, 0 <= f <= F); is_complex 0 for real
- * input (imaginary parts are plaintext zero and not encrypted). */
+ * input (imaginary parts are plaintext zero and not encrypted).  nand_only 1
+ * builds the paper's literal circuit, every gate a NAND (Lemma "binary
+ * gates"; full adders as two half adders and an OR, Lemma "full adder"),
+ * instead of the arithmetic gate forms (0, the default). */
 typedef struct {
     int32_t dims, len, F, f, is_complex;
+    int32_t nand_only;
 } sfft_shape;
 
 typedef struct sfft_plan sfft_plan;

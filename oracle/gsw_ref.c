@@ -14,7 +14,8 @@
  * G[r][b] = 2^(r mod k) when b = r div k, else 0; the bits of C' are exactly C.
  *
  *   product       P   = BitDecomp(C'_L) * C'_R mod q  (packed Flatten(C_L*C_R))
- *   AND = P,  XOR = L + R - 2P,  OR = L + R - P,  NOT = G - C',  XADD = X + Y
+ *   AND = P,  XOR = L + R - 2P,  OR = L + R - P,  NOT = G - C',  XADD = X + Y,
+ *   NAND = G - P
  *   Enc(mu)       C'  = mu*G + Rbits*A mod q
  *
  * Layout (the library's interchange format): row-major, Nct rows, each row
@@ -158,7 +159,7 @@ void or_gate(int nct, int n1, int kw, int type, const uint32_t *X, const uint32_
 {
     const size_t n = (size_t)nct * n1 * kw;
     uint32_t *P = NULL;
-    if (type == 4 || type == 5 || type == 6) {
+    if (type == 4 || type == 5 || type == 6 || type == 8) {
         P = (uint32_t *)malloc(sizeof(uint32_t) * n);
         or_product(nct, n1, kw, X, Y, P);
     }
@@ -168,13 +169,14 @@ void or_gate(int nct, int n1, int kw, int type, const uint32_t *X, const uint32_
     case 5: lincomb(nct, n1, kw, out, 1, X, 1, Y, -2, P, 0); break;        /* XOR  */
     case 6: lincomb(nct, n1, kw, out, 1, X, 1, Y, -1, P, 0); break;        /* OR   */
     case 7: lincomb(nct, n1, kw, out, 1, X, 1, Y, 0, NULL, 0); break;      /* XADD */
+    case 8: lincomb(nct, n1, kw, out, 0, NULL, 0, NULL, -1, P, 1); break;  /* NAND */
     default: break;
     }
     free(P);
 }
 
 /* Evaluate a netlist (node arrays in construction order; type codes
- * IN=0 CONST0=1 CONST1=2 NOT=3 AND=4 XOR=5 OR=6 XADD=7; node 0/1 are the
+ * IN=0 CONST0=1 CONST1=2 NOT=3 AND=4 XOR=5 OR=6 XADD=7 NAND=8; node 0/1 are the
  * constants) on input ciphertexts and write one ciphertext per output.
  * Constant outputs are the noiseless 0 and G.  Each node's ciphertext is
  * freed after its last use; the product of an (l, r) pair is kept while the
@@ -210,7 +212,7 @@ int or_eval(int nct, int n1, int kw, int n_nodes, const int8_t *type, const int3
         if (!dst) { rc = -1; break; }
         const uint32_t *X = buf[na[v]];
         const uint32_t *Y = (t >= 4) ? buf[nb[v]] : NULL;
-        if (t >= 4 && t <= 6 && !(pl == na[v] && pr == nb[v])) {
+        if (((t >= 4 && t <= 6) || t == 8) && !(pl == na[v] && pr == nb[v])) {
             or_product(nct, n1, kw, X, Y, P);
             pl = na[v];
             pr = nb[v];
@@ -221,6 +223,7 @@ int or_eval(int nct, int n1, int kw, int n_nodes, const int8_t *type, const int3
         case 5: lincomb(nct, n1, kw, dst, 1, X, 1, Y, -2, P, 0); break;
         case 6: lincomb(nct, n1, kw, dst, 1, X, 1, Y, -1, P, 0); break;
         case 7: lincomb(nct, n1, kw, dst, 1, X, 1, Y, 0, NULL, 0); break;
+        case 8: lincomb(nct, n1, kw, dst, 0, NULL, 0, NULL, -1, P, 1); break;
         }
         buf[v] = dst;
         /* release operands whose last use was this node */

@@ -29,8 +29,10 @@ import math
 import struct
 
 # node types (serialised in the netlist hash with these codes)
-IN, CONST0, CONST1, NOT, AND, XOR, OR, XADD = range(8)
-TYPE_NAMES = ["IN", "CONST0", "CONST1", "NOT", "AND", "XOR", "OR", "XADD"]
+IN, CONST0, CONST1, NOT, AND, XOR, OR, XADD, NAND = range(9)
+TYPE_NAMES = ["IN", "CONST0", "CONST1", "NOT", "AND", "XOR", "OR", "XADD", "NAND"]
+BINARY = (AND, XOR, OR, XADD, NAND)   # node types with two operands
+PRODUCT = (AND, XOR, OR, NAND)        # node types evaluated through the product of their operands
 ZERO, ONE = 0, 1
 RIPPLE, CSA = 0, 1
 
@@ -42,9 +44,16 @@ def is_const(v: int) -> bool:
 class Netlist:
     """Gate graph in construction order.  Every gate call creates a new node
     (no structural sharing), so the graph mirrors the circuit as drawn: each
-    adder and each Wallace tree owns its gates."""
+    adder and each Wallace tree owns its gates.
 
-    def __init__(self):
+    With nand_only the circuit is the paper's literal one (Lemma "binary
+    gates": every gate a NAND; Lemma "full adder": two half adders and an
+    OR): NOT x = NAND(x, x), AND = NOT NAND, OR(l, r) = NAND(NOT l, NOT r),
+    XOR(l, r) = NAND(NAND(l, t), NAND(r, t)) with t = NAND(l, r), and a full
+    adder's carry is OR of the two half-adder carries."""
+
+    def __init__(self, nand_only: bool = False):
+        self.nand_only = nand_only
         self.t = [CONST0, CONST1]
         self.a = [-1, -1]
         self.b = [-1, -1]
@@ -69,11 +78,24 @@ class Netlist:
         return i
 
     # -- gates with constant folding ------------------------------------
+    def NAND(self, l, r):
+        if l == ZERO or r == ZERO:
+            return ONE
+        if l == ONE and r == ONE:
+            return ZERO
+        if l == ONE:
+            return self.NOT(r)
+        if r == ONE:
+            return self.NOT(l)
+        return self._node(NAND, l, r)
+
     def NOT(self, x):
         if x == ZERO:
             return ONE
         if x == ONE:
             return ZERO
+        if self.nand_only:
+            return self._node(NAND, x, x)
         return self._node(NOT, x)
 
     def AND(self, l, r):
@@ -83,6 +105,9 @@ class Netlist:
             return r
         if r == ONE:
             return l
+        if self.nand_only:
+            t = self._node(NAND, l, r)
+            return self._node(NAND, t, t)
         return self._node(AND, l, r)
 
     def XOR(self, l, r):
@@ -94,6 +119,9 @@ class Netlist:
             return self.NOT(r)
         if r == ONE:
             return self.NOT(l)
+        if self.nand_only:
+            t = self._node(NAND, l, r)
+            return self._node(NAND, self._node(NAND, l, t), self._node(NAND, r, t))
         return self._node(XOR, l, r)
 
     def OR(self, l, r):
@@ -103,6 +131,8 @@ class Netlist:
             return r
         if r == ZERO:
             return l
+        if self.nand_only:
+            return self._node(NAND, self._node(NAND, l, l), self._node(NAND, r, r))
         return self._node(OR, l, r)
 
     def XADD(self, x, y):
@@ -149,6 +179,8 @@ class Netlist:
         else:
             P = self.AND(X, c)
             S = self.XOR(X, c)
+        if self.nand_only:
+            return S, self.OR(A, P)
         return S, self.XADD(A, P)
 
     # -- fixed-point words (lists of bit node ids, LSB first) -----------------
@@ -267,14 +299,15 @@ def twiddle(j: int, m: int, f: int):
 # ---------------------------------------------------------------------------
 # whole-transform netlists
 # ---------------------------------------------------------------------------
-def build_fft_netlist(dims: int, length: int, F: int, f: int, is_complex: bool):
+def build_fft_netlist(dims: int, length: int, F: int, f: int, is_complex: bool, nand_only: bool = False):
     """Canonical netlist of a 1D (dims=1, `length` points) or 2D (dims=2,
     length x length image, rows then columns) forward FFT.
 
     Input ciphertext index = (v*C + comp)*F + bit (v = point index, row-major
     for images; C = 2 for complex input, 1 for real; comp 0 = Re, 1 = Im).
-    Output index = (v*2 + comp)*F + bit in natural order."""
-    nl = Netlist()
+    Output index = (v*2 + comp)*F + bit in natural order.  nand_only builds
+    every gate from NANDs (see Netlist)."""
+    nl = Netlist(nand_only)
     npts = length if dims == 1 else length * length
     C = 2 if is_complex else 1
     words = []
@@ -323,7 +356,7 @@ class Compact:
             t = nl.t[v]
             if t in (NOT,):
                 stack.append(nl.a[v])
-            elif t in (AND, XOR, OR, XADD):
+            elif t in BINARY:
                 stack.append(nl.a[v])
                 stack.append(nl.b[v])
         # inputs are kept even when unused so that input indices stay valid
@@ -344,7 +377,7 @@ class Compact:
             elif t == NOT:
                 self.a.append(remap[nl.a[v]])
                 self.b.append(-1)
-            elif t in (AND, XOR, OR, XADD):
+            elif t in BINARY:
                 self.a.append(remap[nl.a[v]])
                 self.b.append(remap[nl.b[v]])
             else:
@@ -357,18 +390,18 @@ class Compact:
         return len(self.t)
 
     def products(self):
-        """Distinct ordered operand pairs of AND/XOR/OR nodes, in order of
-        first appearance."""
+        """Distinct ordered operand pairs of AND/XOR/OR/NAND nodes, in order
+        of first appearance."""
         seen = {}
         for v, t in enumerate(self.t):
-            if t in (AND, XOR, OR):
+            if t in PRODUCT:
                 key = (self.a[v], self.b[v])
                 if key not in seen:
                     seen[key] = len(seen)
         return list(seen.keys())
 
     def stats(self):
-        cnt = [0] * 8
+        cnt = [0] * 9
         for t in self.t:
             cnt[t] += 1
         level = [0] * len(self.t)
@@ -377,7 +410,7 @@ class Compact:
                 level[v] = level[self.a[v]]
             elif t == XADD:
                 level[v] = max(level[self.a[v]], level[self.b[v]])
-            elif t in (AND, XOR, OR):
+            elif t in PRODUCT:
                 level[v] = 1 + max(level[self.a[v]], level[self.b[v]])
         prods = self.products()
         plev = [1 + max(level[a], level[b]) for a, b in prods]
@@ -388,7 +421,7 @@ class Compact:
         return dict(
             nodes=len(self.t),
             products=len(prods),
-            gates=cnt[AND] + cnt[XOR] + cnt[OR] + cnt[XADD],
+            gates=cnt[AND] + cnt[XOR] + cnt[OR] + cnt[XADD] + cnt[NAND],
             nots=cnt[NOT],
             depth=depth,
             max_width=max(width) if prods else 0,
@@ -437,6 +470,8 @@ def simulate(cn: Compact, inputs: list[int], nsamples: int) -> list[int]:
             if x & y:
                 raise AssertionError("XADD operands are both 1 for some sample")
             val[v] = x | y
+        elif t == NAND:
+            val[v] = (val[cn.a[v]] & val[cn.b[v]]) ^ mask
     return [val[o] for o in cn.outputs]
 
 
@@ -450,14 +485,15 @@ def noise_bounds(cn: Compact, nct: int) -> list[int]:
     e in {-1,0,1}: at most m.  For a gate of the form alpha*L + beta*R +
     gamma*P with P = BitDecomp(L')*R', the noise is
     (alpha + gamma*mu_R)*e_L + (beta*I + gamma*C_L)*e_R, whose row sums bound
-    AND (gamma=1), XOR (1,1,-2) and OR (1,1,-1) as below."""
+    AND (gamma=1), XOR (1,1,-2) and OR (1,1,-1) as below; NAND = G - P adds
+    no noise to P's."""
     B = [0] * len(cn.t)
     for v, t in enumerate(cn.t):
         if t == IN:
             B[v] = nct
         elif t == NOT:
             B[v] = B[cn.a[v]]
-        elif t == AND or t == OR:
+        elif t == AND or t == OR or t == NAND:
             B[v] = B[cn.a[v]] + nct * B[cn.b[v]]
         elif t == XOR:
             B[v] = B[cn.a[v]] + (2 * nct - 1) * B[cn.b[v]]

@@ -90,8 +90,9 @@ def gate(keys_or_params, g: int, x: torch.Tensor, y: torch.Tensor | None = None,
 class Plan:
     """A compiled encrypted FFT for one shape and parameter set."""
 
-    def __init__(self, dims: int, length: int, F: int, f: int, is_complex: bool, params: S.sfft_params):
-        self.shape = S.shape(dims, length, F, f, is_complex)
+    def __init__(self, dims: int, length: int, F: int, f: int, is_complex: bool, params: S.sfft_params,
+                 nand_only: bool = False):
+        self.shape = S.shape(dims, length, F, f, is_complex, nand_only)
         self.params = params
         self.handle = S.sfft_plan_create(self.shape, params)
         self.info = S.sfft_plan_info_get(self.handle)
@@ -169,8 +170,8 @@ def set_tiling(params: S.sfft_params, tiling: int) -> None:
     S.sfft_set_tiling(params, tiling)
 
 
-def size_params(dims, length, F, f, is_complex, n_lwe) -> S.sfft_params:
-    return S.sfft_size_params(S.shape(dims, length, F, f, is_complex), n_lwe)
+def size_params(dims, length, F, f, is_complex, n_lwe, nand_only: bool = False) -> S.sfft_params:
+    return S.sfft_size_params(S.shape(dims, length, F, f, is_complex, nand_only), n_lwe)
 
 
 def signal_words(sig) -> np.ndarray:
@@ -193,8 +194,8 @@ class Server:
         self.handle = S.sfft_server_create(cfg)
         self._keep = {}
 
-    def submit(self, dims, length, F, f, is_complex, params, ct_in=None, ct_out=None) -> int:
-        shp = S.shape(dims, length, F, f, is_complex)
+    def submit(self, dims, length, F, f, is_complex, params, ct_in=None, ct_out=None, nand_only=False) -> int:
+        shp = S.shape(dims, length, F, f, is_complex, nand_only)
         t = S.sfft_server_submit(self.handle, shp, params, ct_in.data_ptr() if ct_in is not None else None,
                                  ct_out.data_ptr() if ct_out is not None else None)
         self._keep[t] = (ct_in, ct_out)  # the buffers must outlive the request

@@ -67,10 +67,16 @@ bool shape_ok(const sfft_shape* s, std::string* why)
     if (s->len < 2 || s->len > 4096 || (s->len & (s->len - 1))) { *why = "len must be a power of two in [2, 4096]"; return false; }
     if (s->F < 1 || s->F > 32 || s->f < 0 || s->f > s->F) { *why = "need 1 <= F <= 32 and 0 <= f <= F"; return false; }
     if (s->is_complex != 0 && s->is_complex != 1) { *why = "is_complex must be 0 or 1"; return false; }
+    if (s->nand_only != 0 && s->nand_only != 1) { *why = "nand_only must be 0 or 1"; return false; }
     return true;
 }
 
-Shape to_shape(const sfft_shape* s) { return Shape{s->dims, s->len, s->F, s->f, s->is_complex != 0}; }
+Shape to_shape(const sfft_shape* s)
+{
+    Shape r{s->dims, s->len, s->F, s->f, s->is_complex != 0};
+    r.nand_only = s->nand_only != 0;
+    return r;
+}
 
 // ---- host SplitMix64 (domains: 1 t, 2 B, 3 e, 4 encryption masks) ----------
 uint64_t mix64(uint64_t z)

@@ -30,7 +30,7 @@ void twiddle(int j, int m, int f, int64_t* cr, int64_t* ci)
 // ---------------------------------------------------------------------------
 static inline bool is_const(int32_t v) { return v == kZero || v == kOne; }
 
-Netlist::Netlist()
+Netlist::Netlist(bool nand) : nand_only(nand)
 {
     t = {T_C0, T_C1};
     a = {-1, -1};
@@ -55,10 +55,20 @@ int32_t Netlist::input()
     return id;
 }
 
+int32_t Netlist::NAND(int32_t l, int32_t r)
+{
+    if (l == kZero || r == kZero) return kOne;
+    if (l == kOne && r == kOne) return kZero;
+    if (l == kOne) return NOT(r);
+    if (r == kOne) return NOT(l);
+    return node(T_NAND, l, r);
+}
+
 int32_t Netlist::NOT(int32_t x)
 {
     if (x == kZero) return kOne;
     if (x == kOne) return kZero;
+    if (nand_only) return node(T_NAND, x, x);
     return node(T_NOT, x, -1);
 }
 
@@ -67,6 +77,10 @@ int32_t Netlist::AND(int32_t l, int32_t r)
     if (l == kZero || r == kZero) return kZero;
     if (l == kOne) return r;
     if (r == kOne) return l;
+    if (nand_only) {
+        const int32_t n = node(T_NAND, l, r);
+        return node(T_NAND, n, n);
+    }
     return node(T_AND, l, r);
 }
 
@@ -76,6 +90,12 @@ int32_t Netlist::XOR(int32_t l, int32_t r)
     if (r == kZero) return l;
     if (l == kOne) return NOT(r);
     if (r == kOne) return NOT(l);
+    if (nand_only) {
+        const int32_t n = node(T_NAND, l, r);
+        const int32_t x = node(T_NAND, l, n);
+        const int32_t y = node(T_NAND, r, n);
+        return node(T_NAND, x, y);
+    }
     return node(T_XOR, l, r);
 }
 
@@ -84,6 +104,11 @@ int32_t Netlist::OR(int32_t l, int32_t r)
     if (l == kOne || r == kOne) return kOne;
     if (l == kZero) return r;
     if (r == kZero) return l;
+    if (nand_only) {
+        const int32_t x = node(T_NAND, l, l);
+        const int32_t y = node(T_NAND, r, r);
+        return node(T_NAND, x, y);
+    }
     return node(T_OR, l, r);
 }
 
@@ -139,7 +164,7 @@ std::pair<int32_t, int32_t> Netlist::FA(int32_t x, int32_t y, int32_t c, AdderMo
         P = AND(X, c);
         S = XOR(X, c);
     }
-    const int32_t cy = XADD(A, P);
+    const int32_t cy = nand_only ? OR(A, P) : XADD(A, P);
     return {S, cy};
 }
 
@@ -282,7 +307,7 @@ std::vector<Netlist::Cplx> Netlist::fft1d(const std::vector<Cplx>& xs, int f)
 
 Netlist build_fft_netlist(const Shape& s)
 {
-    Netlist nl;
+    Netlist nl(s.nand_only);
     const int npts = s.points();
     std::vector<Netlist::Cplx> words(npts);
     for (int v = 0; v < npts; v++) {
@@ -522,7 +547,7 @@ NetStats netlist_stats(const Compact& c)
         } else if (ty == T_XADD) {
             st.gates++;
             level[v] = std::max(level[c.a[v]], level[c.b[v]]);
-        } else if (ty == T_AND || ty == T_XOR || ty == T_OR) {
+        } else if (is_product_type(ty)) {
             st.gates++;
             level[v] = 1 + std::max(level[c.a[v]], level[c.b[v]]);
             const uint64_t key = (uint64_t)(uint32_t)c.a[v] << 32 | (uint32_t)c.b[v];
@@ -611,7 +636,8 @@ int noise_bits(const Compact& c, int64_t nct)
         } else if (ty == T_NOT) {
             ar.off[v] = ar.off[c.a[v]];
             ar.len[v] = ar.len[c.a[v]];
-        } else if (ty == T_AND || ty == T_OR || ty == T_XOR || ty == T_XADD) {
+        } else if (is_product_type(ty) || ty == T_XADD) {
+            // AND, OR, NAND: B(l) + Nct B(r); XOR: B(l) + (2 Nct - 1) B(r); XADD: B(l) + B(r)
             const uint64_t s = ty == T_XADD ? 1 : ty == T_XOR ? (uint64_t)(2 * nct - 1) : (uint64_t)nct;
             const int32_t l = c.a[v], r = c.b[v];
             // copy operands out first: the arena may reallocate on store

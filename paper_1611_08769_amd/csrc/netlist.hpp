@@ -18,7 +18,11 @@
 
 namespace sfft {
 
-enum NodeType : int8_t { T_IN = 0, T_C0 = 1, T_C1 = 2, T_NOT = 3, T_AND = 4, T_XOR = 5, T_OR = 6, T_XADD = 7 };
+enum NodeType : int8_t {
+    T_IN = 0, T_C0 = 1, T_C1 = 2, T_NOT = 3, T_AND = 4, T_XOR = 5, T_OR = 6, T_XADD = 7, T_NAND = 8
+};
+// node types evaluated through the product of their two operands
+inline bool is_product_type(int8_t t) { return t == T_AND || t == T_XOR || t == T_OR || t == T_NAND; }
 
 constexpr int32_t kZero = 0, kOne = 1;
 enum AdderMode { kRipple = 0, kCsa = 1 };
@@ -29,6 +33,7 @@ struct Shape {
     int F;     // word width
     int f;     // fractional bits
     bool is_complex;
+    bool nand_only = false;  // every gate a NAND (the paper's literal circuit)
     int points() const { return dims == 1 ? len : len * len; }
     int n_inputs() const { return points() * (is_complex ? 2 : 1) * F; }
     int n_outputs() const { return points() * 2 * F; }
@@ -44,8 +49,14 @@ public:
     std::vector<int32_t> outputs;
     int32_t n_inputs = 0;
 
-    Netlist();
+    // nand_only: NOT x = NAND(x, x), AND = NOT NAND, OR(l, r) = NAND(NOT l,
+    // NOT r), XOR(l, r) = NAND(NAND(l, t), NAND(r, t)) with t = NAND(l, r),
+    // and a full adder's carry is the OR of its two half-adder carries
+    // (paper, Lemmas "binary gates" and "full adder")
+    explicit Netlist(bool nand_only = false);
+    bool nand_only;
     int32_t input();
+    int32_t NAND(int32_t l, int32_t r);
     int32_t NOT(int32_t x);
     int32_t AND(int32_t l, int32_t r);
     int32_t XOR(int32_t l, int32_t r);

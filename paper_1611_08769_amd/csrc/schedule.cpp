@@ -96,13 +96,14 @@ Schedule lower(const Compact& c)
         case T_IN: f = term((int32_t)v); mat[v] = 1; break;
         case T_C0: break;
         case T_C1: f.cG = 1; break;
-        case T_AND: case T_XOR: case T_OR: {
+        case T_AND: case T_XOR: case T_OR: case T_NAND: {
             const int32_t l = c.a[v], r = c.b[v];
             f.prod = product_id(l, r);
             mat[l] = mat[r] = 1;
             if (ty == T_AND) { f.cP = 1; }
             else if (ty == T_XOR) { f.cL = 1; f.cR = 1; f.cP = -2; }
-            else { f.cL = 1; f.cR = 1; f.cP = -1; }
+            else if (ty == T_OR) { f.cL = 1; f.cR = 1; f.cP = -1; }
+            else { f.cP = -1; f.cG = 1; }  // NAND = G - P
             break;
         }
         case T_NOT: f = neg(form[c.a[v]]); f.cG += 1; break;

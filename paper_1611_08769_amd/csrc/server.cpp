@@ -132,7 +132,8 @@ struct sfft_server {
 static std::string plan_key(const sfft_shape* s, const sfft_params* p)
 {
     char buf[160];
-    std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d|%d/%d/%d/%d", s->dims, s->len, s->F, s->f, s->is_complex, p->n_lwe,
+    std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d/%d|%d/%d/%d/%d", s->dims, s->len, s->F, s->f, s->is_complex,
+                  s->nand_only, p->n_lwe,
                   p->k, p->m, p->eta);
     return buf;
 }

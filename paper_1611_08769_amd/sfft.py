@@ -26,7 +26,7 @@ class sfft_params(ctypes.Structure):
 
 class sfft_shape(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int32), ("len", ctypes.c_int32), ("F", ctypes.c_int32), ("f", ctypes.c_int32),
-                ("is_complex", ctypes.c_int32)]
+                ("is_complex", ctypes.c_int32), ("nand_only", ctypes.c_int32)]
 
 
 class sfft_plan_info(ctypes.Structure):
@@ -127,8 +127,8 @@ def params(n_lwe: int, k: int) -> sfft_params:
     return sfft_params(n_lwe, k, (n_lwe + 1) * k, 1)
 
 
-def shape(dims: int, length: int, F: int, f: int, is_complex: bool) -> sfft_shape:
-    return sfft_shape(dims, length, F, f, int(bool(is_complex)))
+def shape(dims: int, length: int, F: int, f: int, is_complex: bool, nand_only: bool = False) -> sfft_shape:
+    return sfft_shape(dims, length, F, f, int(bool(is_complex)), int(bool(nand_only)))
 
 
 def sfft_size_params(shp: sfft_shape, n_lwe: int) -> sfft_params:

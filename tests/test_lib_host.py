@@ -102,3 +102,20 @@ def test_error_statuses():
         S.sfft_analyze(shp, p)
     assert e.value.code == S.SFFT_EUNSUPPORTED
     assert "eta" in S.last_error()
+
+
+@pytest.mark.parametrize("dims,L,F,f,cplx", [(1, 8, 8, 4, False), (1, 4, 6, 3, True), (2, 4, 6, 3, False)])
+def test_nand_only_compiler_matches_oracle(dims, L, F, f, cplx):
+    """The paper-literal NAND-only circuit: both constructions agree on hash,
+    counts and modulus, and differ from the arithmetic-form circuit."""
+    cn = N.Compact(N.build_fft_netlist(dims, L, F, f, cplx, nand_only=True))
+    st = cn.stats()
+    k = N.choose_k(cn, 1)
+    shp = S.shape(dims, L, F, f, cplx, nand_only=True)
+    p = S.sfft_size_params(shp, 1)
+    assert p.k == k
+    info = S.sfft_analyze(shp, p)
+    assert info.netlist_sha256.decode() == cn.hash()
+    assert info.products == st["products"] and info.gates == st["gates"] and info.levels == st["depth"]
+    plain = S.sfft_analyze(S.shape(dims, L, F, f, cplx), S.sfft_size_params(S.shape(dims, L, F, f, cplx), 1))
+    assert plain.netlist_sha256 != info.netlist_sha256

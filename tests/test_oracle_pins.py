@@ -375,3 +375,73 @@ def test_encrypted_fft_cfg_small_end_to_end():
     B = N.noise_bounds(cn, p.nct)
     for i in range(0, len(out), 7):  # a spread of outputs (all rows each)
         assert gsw.max_noise(keys, out[i], dec[i]) <= B[cn.outputs[i]] < p.q // 8
+
+
+# ---------------------------------------------------------------------------
+# paper-literal NAND-only circuits (Lemma "binary gates", Lemma "full adder")
+# ---------------------------------------------------------------------------
+def test_nand_only_gates_adders_truth_tables():
+    """NOT/AND/OR/XOR built from NANDs, and full adders whose carry is the OR
+    of two half-adder carries, over every input and constant pattern; no
+    node of the NAND-only netlist is anything but an input or a NAND."""
+    for pattern in range(27):
+        kinds = [(pattern // 3 ** i) % 3 for i in range(3)]
+        nl = N.Netlist(nand_only=True)
+        wires = [nl.inp() if kd == 2 else kd for kd in kinds]
+        s, cy = nl.FA(*wires, N.RIPPLE)
+        x, y = wires[0], wires[1]
+        nl.outputs = [s, cy, nl.NOT(x), nl.AND(x, y), nl.OR(x, y), nl.XOR(x, y)]
+        cn = N.Compact(nl)
+        assert set(cn.t[2:]) <= {N.IN, N.NAND}
+        for v in range(1 << cn.n_inputs):
+            ins = [(v >> i) & 1 for i in range(cn.n_inputs)]
+            outs = N.simulate(cn, ins, 1)
+            it = iter(ins)
+            a, b, c = [next(it) if kd == 2 else kd for kd in kinds]
+            assert outs == [(a + b + c) & 1, (a + b + c) >> 1, 1 - a, a & b, a | b, a ^ b], (kinds, v)
+
+
+@pytest.mark.parametrize("op", ["add", "sub", "mul"])
+def test_nand_only_words_exhaustive_F6(op):
+    F = 6
+    lo, hi = -(1 << (F - 1)), 1 << (F - 1)
+    if op == "mul":
+        xs = np.arange(lo, hi)
+        for c in (-31, -17, 5, 22, 31):
+            nl = N.Netlist(nand_only=True)
+            x = [nl.inp() for _ in range(F)]
+            nl.outputs = nl.mul_const(x, c, 3)
+            cn = N.Compact(nl)
+            got = _words_from_sim(N.simulate(cn, _bits_of(xs, F), len(xs)), F, len(xs))
+            assert np.array_equal(got, fx.wrap(np.array([(int(v) * c) >> 3 for v in xs]), F)), c
+        return
+    nl = N.Netlist(nand_only=True)
+    x = [nl.inp() for _ in range(F)]
+    y = [nl.inp() for _ in range(F)]
+    nl.outputs = nl.add(x, y) if op == "add" else nl.sub(x, y)
+    cn = N.Compact(nl)
+    a = np.repeat(np.arange(lo, hi), hi - lo)
+    b = np.tile(np.arange(lo, hi), hi - lo)
+    got = _words_from_sim(N.simulate(cn, _bits_of(a, F) + _bits_of(b, F), len(a)), F, len(a))
+    assert np.array_equal(got, fx.wrap(a + b if op == "add" else a - b, F))
+
+
+def test_nand_only_fft_netlist_and_encrypted_run():
+    """The NAND-only FFT netlist simulates to the integer emulation, and an
+    encrypted N=4 transform through the packed-GSW oracle decrypts to it."""
+    dims, L, F, f, cplx = 1, 4, 6, 3, True
+    cn = N.Compact(N.build_fft_netlist(dims, L, F, f, cplx, nand_only=True))
+    assert N.Compact(N.build_fft_netlist(dims, L, F, f, cplx)).hash() != cn.hash()
+    rng = np.random.default_rng(9)
+    re = rng.integers(-32, 32, (1, L))
+    im = rng.integers(-32, 32, (1, L))
+    words = np.stack([re[0], im[0]], 1).ravel()
+    bits = fx.words_to_bits(words, F)
+    yr, yi = fx.fft_fixed(1, re, im, F, f)
+    want = np.stack([yr.ravel(), yi.ravel()], 1).ravel()
+    sim = N.simulate(cn, [int(b) for b in bits], 1)
+    assert fx.bits_to_words(np.array(sim), F).tolist() == want.tolist()
+    k = N.choose_k(cn, 1)
+    keys = gsw.keygen(gsw.Params(1, k), 4)
+    out = gsw.evaluate(keys.params, cn, gsw.encrypt(keys, bits, seed=4))
+    assert fx.bits_to_words(np.array(gsw.decrypt_many(keys, out)), F).tolist() == want.tolist()
