@@ -182,6 +182,10 @@ def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_c
     prod = "void sfft::(anonymous namespace)::k_product<"
     fetch = [v for v, n in zip(_counter_rows(fetch_csv, prod), _kernel_names(fetch_csv, prod)) if "false>" in n]
     write = [v for v, n in zip(_counter_rows(write_csv, prod), _kernel_names(write_csv, prod)) if "false>" in n]
+    # the run tunes the plan first: keep the product launches of the one
+    # timed FFT, which come last (one per level)
+    levels = _product_levels(workload)
+    fetch, write = fetch[-levels:], write[-levels:]
     cf = max(_counter_rows(copy_fetch_csv, "__amd_rocclr_copyBuffer"))
     cw = max(_counter_rows(copy_write_csv, "__amd_rocclr_copyBuffer"))
     gib = float(1 << 30)
@@ -200,12 +204,43 @@ def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_c
         "traffic_bytes_per_launch": (fk * fetch_scale + wk * write_scale) * 1024,
         "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py "
                    "--workload %s --steps 1 --warmup 0 --no-cpu-baseline; the same for python3 bench.py "
-                   "--copy-probe; python3 bench.py --traffic-summary on the four CSVs" % workload,
+                   "--copy-probe; python3 bench.py --traffic-summary on the four CSVs (the last FFT's "
+                   "product launches, after the plan tuner's)" % workload,
     }
     path = os.path.join(ROOT, "profiles", "traffic_k_product_%s.json" % workload)
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def _product_levels(workload):
+    from paper_1611_08769_amd import sfft as S
+    from paper_1611_08769_amd import workloads as WL
+    sig, n_lwe, _ = WL.workload(workload)
+    shp = S.shape(sig.dims, sig.length, sig.F, sig.f, sig.is_complex)
+    return int(S.sfft_analyze(shp, S.sfft_size_params(shp, n_lwe)).levels)
+
+
+def trace_summary(workload, db_path, steps):
+    """Per-kernel statistics of a rocprofv3 kernel trace (rocpd database) of
+    a bench run, and the average product launch over its `steps` timed FFTs
+    (the last steps x levels product launches), for comparison with the
+    bench's own HIP-event average."""
+    import sqlite3
+    cur = sqlite3.connect(db_path).cursor()
+    rows = list(cur.execute("select name, duration from kernels order by start"))
+    by = {}
+    for name, d in rows:
+        short = name.replace("sfft::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        by.setdefault(short, []).append(d)
+    print("| kernel | calls | total (ms) | average (ms) | min (ms) | max (ms) |")
+    print("|:--|--:|--:|--:|--:|--:|")
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        print("| %s | %d | %.1f | %.4f | %.4f | %.4f |" % (k, len(v), sum(v) / 1e6, sum(v) / len(v) / 1e6,
+                                                        min(v) / 1e6, max(v) / 1e6))
+    prods = [d for name, d in rows if "k_product<" in name and "false>" in name]
+    timed = prods[-steps * _product_levels(workload):]
+    print("\ntimed product launches: %d, average %.3f ms" % (len(timed), sum(timed) / len(timed) / 1e6))
 
 
 def _kernel_names(path, kernel_prefix):
@@ -403,9 +438,14 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB three times (counter reference)")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write profiles/traffic_k_product_<workload>.json from rocprofv3 counter CSVs")
+    ap.add_argument("--trace-summary", metavar="RESULTS_DB",
+                    help="summarise a rocprofv3 kernel trace of a bench run (its --steps timed FFTs)")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(args.workload, *args.traffic_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.workload, args.trace_summary, args.steps)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -538,7 +578,10 @@ def main():
         src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "kernels.hip")
         if hashlib.sha256(open(src, "rb").read()).hexdigest() == tr.get("kernels_hip_sha256"):
             out["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
-            alg = 3.0 * nct * nct / 8 * info.exec_products / max(1, info.levels)
+            # algorithmic bytes: each ciphertext a product item reads (L, R and
+            # extra operands) or writes, once
+            alg = (info.prod_ct_reads + info.prod_ct_writes) * nct * nct / 8 / max(1, info.levels)
+            out["roofline"]["algorithmic_bytes_per_launch"] = alg
             out["roofline"]["traffic_vs_algorithmic_bytes"] = tr["traffic_bytes_per_launch"] / alg
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nct, params.n_lwe + 1, params.k // 32, info.gates, info.products,

@@ -78,6 +78,8 @@ typedef struct {
     int32_t k_required;           /* least multiple of 32 meeting the noise rule */
     char netlist_sha256[65];      /* hex SHA-256 of the canonical netlist */
     int32_t tiling;               /* product-kernel tiling the plan launches (sfft_tiling_describe) */
+    int64_t prod_ct_reads;        /* ciphertexts the product items read: L, R and extra operands */
+    int64_t prod_ct_writes;       /* ciphertexts the product items write (their outputs) */
 } sfft_plan_info;
 
 const char* sfft_last_error(void);

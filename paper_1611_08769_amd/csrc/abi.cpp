@@ -201,6 +201,15 @@ int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* s
         in.ws_cts = sched->n_slots;
         in.exec_steps = (int64_t)sched->levels.size() + 1;
         in.k_required = choose_k(c, params->n_lwe);
+        for (const ProdItem& it : sched->prods) {
+            in.prod_ct_reads += 2;
+            for (int o = 0; o < it.nout; o++) {
+                in.prod_ct_writes += 1;
+                bool seen = it.E[o] < 0;
+                for (int q = 0; q < o && !seen; q++) seen = it.E[q] == it.E[o];
+                if (!seen) in.prod_ct_reads += 1;
+            }
+        }
         const std::string h = netlist_hash(c);
         std::memcpy(in.netlist_sha256, h.c_str(), 64);
         in.netlist_sha256[64] = 0;

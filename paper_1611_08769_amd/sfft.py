@@ -35,7 +35,8 @@ class sfft_plan_info(ctypes.Structure):
                 ("max_level_products", ctypes.c_int64), ("n_inputs", ctypes.c_int64),
                 ("n_outputs", ctypes.c_int64), ("ws_cts", ctypes.c_int64), ("exec_steps", ctypes.c_int64),
                 ("k_required", ctypes.c_int32),
-                ("netlist_sha256", ctypes.c_char * 65), ("tiling", ctypes.c_int32)]
+                ("netlist_sha256", ctypes.c_char * 65), ("tiling", ctypes.c_int32),
+                ("prod_ct_reads", ctypes.c_int64), ("prod_ct_writes", ctypes.c_int64)]
 
 
 SFFT_SERVER_DRYRUN = 1

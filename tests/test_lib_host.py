@@ -46,6 +46,10 @@ def test_library_compiler_matches_oracle(dims, L, F, f, cplx, n):
     assert info.levels == st["depth"] and info.k_required == k
     assert info.n_inputs == cn.n_inputs and info.n_outputs == len(cn.outputs)
     assert info.exec_products <= info.products
+    # every product item reads L and R (plus at most one extra operand per
+    # output) and writes one to four outputs
+    assert 2 * info.exec_products <= info.prod_ct_reads <= 6 * info.exec_products
+    assert info.exec_products <= info.prod_ct_writes <= 4 * info.exec_products
 
 
 def test_keygen_matches_oracle():
