@@ -166,15 +166,23 @@ int sfft_gate(const sfft_params* params, int32_t gate, const uint32_t* x_dev, co
               uint32_t* out_dev, void* hip_stream);
 
 /* ---- product-kernel tilings and the autotuner ---------------------------
- * The product kernel exists in several tilings (threads per workgroup, lanes
- * per output row, digit slots per lane, rows per lane, lookup pipeline
- * depth, 4-bit groups per chunk of R).  Plans use, per ciphertext geometry
- * (k, n_lwe), the tiling recorded for it (by sfft_tune or sfft_set_tiling,
- * process-wide), else a default by digits per row.  Plans keep the tiling
- * they were created with. */
+ * The gate product (section "Time/Space Complexities": a matrix-matrix
+ * product per gate) has two kernels, each in several tilings: a table-lookup
+ * kernel on the integer VALU (threads per workgroup, lanes per output row,
+ * digit slots per lane, rows per lane, lookup pipeline depth, 4-bit groups
+ * per chunk of R) and a matrix-core kernel that multiplies the bits of L by
+ * the bytes of R with int8 MFMA (threads, row groups, column groups, 32-byte
+ * column fragments per wave).  Plans use, per ciphertext geometry (k,
+ * n_lwe), the tiling recorded for it (by sfft_tune or sfft_set_tiling,
+ * process-wide), else the matrix-core default for the row width, else a
+ * lookup default by digits per row.  Plans keep the tiling they were created
+ * with.  Encryption always runs on the lookup kernel. */
 int sfft_tiling_count(void);
-/* fields[6] = threads, lanes per row, digit slots per lane, rows per lane,
- * pipeline depth, groups per chunk.  SFFT_EINVAL for an unknown tiling. */
+/* fields[7]: fields[6] = 0 for a lookup tiling, then fields[0..5] = threads,
+ * lanes per row, digit slots per lane, rows per lane, pipeline depth, groups
+ * per chunk; fields[6] = 1 for a matrix-core tiling, then fields[0..3] =
+ * threads, row groups, column groups, fragments per wave (fields[4..5] = 0).
+ * SFFT_EINVAL for an unknown tiling. */
 int sfft_tiling_describe(int32_t tiling, int32_t* fields);
 /* Record a tiling for params' geometry (-1: back to the default).
  * SFFT_EINVAL if the tiling cannot serve the geometry. */

@@ -36,6 +36,10 @@ struct ProdCfg {
     int rpl;   // row-iterations per lane
     int tr;    // rows per workgroup
     int lds_bytes;
+    // matrix-core tilings (mfma): row groups, column groups, 32-column
+    // fragments per wave
+    bool mfma;
+    int rg, cgw, cf;
 };
 
 // Passed to the kernel by value.
@@ -45,17 +49,22 @@ struct KCfg {
     uint32_t one;
 };
 
-// The kernel's tilings: how many, and (threads, lanes per row, digit slots
-// per lane, rows per lane, pipeline depth, groups per chunk) of one.
+// The kernels' tilings: how many, and the 7 fields of one: for the lookup
+// kernel (threads, lanes per row, digit slots per lane, rows per lane,
+// pipeline depth, groups per chunk, 0), for the matrix-core kernel (threads,
+// row groups, column groups, fragments per wave, 0, 0, 1).
 int tiling_count();
-void tiling_fields(int ti, int* fields6);
+void tiling_fields(int ti, int* fields7);
 // cfg for tiling ti on geometry g; false if ti cannot serve g (too few digit
-// slots per row, or more LDS than a CU has).
+// slots or fragments per row, or more LDS than a CU has).
 bool tiling_config(const Geo& g, int ti, ProdCfg* cfg);
 // The tiling a plan of geometry g uses: the one recorded for g by the tuner
-// (set_tuned_tiling, process-wide; ti < 0 clears), else the default of g's
-// width class.
+// (set_tuned_tiling, process-wide; ti < 0 clears), else the matrix-core
+// default for g's row width, else the lookup default of g's width class.
 bool product_config(const Geo& g, ProdCfg* cfg);
+// The lookup default of g's width class (encryption draws its bits of L
+// inside the lookup kernel, so it always runs there).
+bool lookup_config(const Geo& g, ProdCfg* cfg);
 void set_tuned_tiling(const Geo& g, int ti);
 
 // A run of work items sharing one set of buffers and one ciphertext

@@ -22,6 +22,7 @@
 // a L + b R + c P + g G + e E (AND, XOR, OR, NOT, NAND, XADD forms) mod 2^k.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -503,6 +504,348 @@ __global__ void __launch_bounds__(THREADS) k_product(KCfg kc, const ProdSeg* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// The product on the matrix cores.  P = BitDecomp(L) R is a dense integer
+// matrix product: an Nct x Nct matrix of bits times the Nct x N matrix of the
+// bytes of R (N = 4 W bytes per row), whose column sums S[r][b] (byte b of
+// row r) give P = sum_b S[r][b] 2^(8 b) per element.  v_mfma_i32_32x32x32_i8
+// multiplies signed bytes exactly into 32-bit sums; the bytes u of R enter as
+// u - 128 (u xor 0x80), and 128 popcount(row r of L) is added back in the
+// epilogue.  Column sums stay below Nct 255 < 2^31.
+//
+// Workgroup: RG x CG waves; a wave owns 64 rows (two 32-row fragments) of
+// the tile and CF 32-column fragments, so a tile is TM = 64 RG rows by up to
+// 32 CG CF byte columns.  R is walked in chunks of 64 rows: each chunk is
+// loaded as 4x4 byte blocks, transposed in registers (v_perm) and stored in
+// LDS column by column (64 bytes of a column contiguous, so that a lane's
+// 16 bytes of a B fragment are one ds_read_b128), double-buffered with one
+// barrier per chunk.  A lane's 16 bits of L for a fragment become 16 bytes of
+// 0/1 by a multiply that spreads 4 bits to the 4 bytes of a word.
+//
+// Epilogue: the accumulators go to LDS in slabs of 32 rows, and one thread
+// per (row, element) forms 32-bit limbs from 4 column sums at a time and
+// feeds up to four outputs a L + b R + c P + g G + e E, one signed carry
+// chain each, as in the lookup kernel.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x4 gu32x4;  // 16 bytes of a ciphertext, global
+
+constexpr int kMfmaChunk = 128;                 // rows of R per chunk
+constexpr int kMfmaPitch = kMfmaChunk;          // LDS bytes per staged column
+
+// A staged column n keeps its 8 units of 16 bytes (16 rows each) in the
+// order unit ^ swz(n): the 16 lanes of a ds_read_b128 phase (16 consecutive
+// columns) then hit 16 distinct 4-bank groups, and the dword stores of a
+// staging wave spread over all banks but one factor of two.
+__device__ __forceinline__ int mfma_swz(int n) { return ((n >> 1) + (n >> 4)) & 7; }
+
+// r[i] holds bytes (i, 0..3) of a 4x4 byte block; c[j] gets bytes (0..3, j)
+__device__ __forceinline__ void transpose4x4(const uint32_t r[4], uint32_t c[4])
+{
+    const uint32_t lo01 = __builtin_amdgcn_perm(r[1], r[0], 0x05010400u);
+    const uint32_t hi01 = __builtin_amdgcn_perm(r[1], r[0], 0x07030602u);
+    const uint32_t lo23 = __builtin_amdgcn_perm(r[3], r[2], 0x05010400u);
+    const uint32_t hi23 = __builtin_amdgcn_perm(r[3], r[2], 0x07030602u);
+    c[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+    c[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+    c[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+    c[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+}
+
+// 16 bits to 16 bytes of 0/1 (byte p = bit p): x * 0x204081 places bits
+// 0..3 of a nibble at bits 0, 8, 16, 24 without carries.
+__device__ __forceinline__ i32x4 spread_bits(uint32_t u)
+{
+    i32x4 a;
+    a[0] = (int32_t)(((u & 15u) * 0x204081u) & 0x01010101u);
+    a[1] = (int32_t)((((u >> 4) & 15u) * 0x204081u) & 0x01010101u);
+    a[2] = (int32_t)((((u >> 8) & 15u) * 0x204081u) & 0x01010101u);
+    a[3] = (int32_t)((((u >> 12) & 15u) * 0x204081u) & 0x01010101u);
+    return a;
+}
+
+// Output row `row`, element e, from its byte column sums S[0..4 kw) (LDS,
+// each missing 128 popcount) and the row's popcount pc.
+__device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it, const int32_t* S, int pc,
+                             const gword* Lp, const gword* Rp, int row, int e)
+{
+    const int br = row / g.k, tr = row % g.k;
+    const size_t base = (size_t)row * g.W + (size_t)e * g.kw;
+    const int64_t corr = 128ll * pc * 0x01010101ll;
+    int64_t carry[kMaxOut];
+    bool needL = false, needR = false;
+#pragma unroll
+    for (int o = 0; o < kMaxOut; o++) {
+        carry[o] = 0;
+        if (o < it.nout) {
+            needL |= it.cL[o] != 0;
+            needR |= it.cR[o] != 0;
+        }
+    }
+    for (int l0 = 0; l0 < g.kw; l0 += 8) {
+        const int nl = g.kw - l0 < 8 ? g.kw - l0 : 8;
+        const size_t off = base + l0;
+        uint32_t Lv[8], Rv[8];
+        int64_t P[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            Lv[j] = (needL && j < nl) ? Lp[off + j] : 0u;
+            Rv[j] = (needR && j < nl) ? Rp[off + j] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (j < nl) {
+                const i32x4 s4 = *reinterpret_cast<const i32x4*>(S + 4 * (l0 + j));
+                P[j] = (int64_t)s4[0] + (int64_t)s4[1] * 256 + (int64_t)s4[2] * 65536 + (int64_t)s4[3] * 16777216 +
+                       corr;
+            } else {
+                P[j] = 0;
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < kMaxOut; o++) {
+            if (o < it.nout) {
+                gword* dst = ctp(bufs, it.dst[o]) + off;
+                const gword* Ep = it.E[o] >= 0 ? ctp(bufs, it.E[o]) + off : nullptr;
+                uint32_t Ev[8];
+#pragma unroll
+                for (int j = 0; j < 8; j++) Ev[j] = (Ep && j < nl) ? Ep[j] : 0u;
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    if (j < nl) {
+                        const int l = l0 + j;
+                        const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
+                        const int64_t s = carry[o] + (int64_t)it.cL[o] * Lv[j] + (int64_t)it.cR[o] * Rv[j] +
+                                          (int64_t)it.cP[o] * P[j] + (int64_t)it.cG[o] * Gv +
+                                          (int64_t)it.cE[o] * Ev[j];
+                        dst[j] = (uint32_t)s;
+                        carry[o] = s >> 32;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int RG, int CG, int CF>
+__global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __restrict__ segs, int nseg,
+                                                               ProdSeg seg0, ProdItem one, int lds_bytes)
+{
+    constexpr int THREADS = RG * CG * 64;
+    constexpr int TM = 64 * RG;
+    constexpr int KC = kMfmaChunk;
+    constexpr int BP = kMfmaPitch;
+    constexpr int SPT = (KC / 4 * 2 * CG * CF + THREADS - 1) / THREADS;  // staged 4-row x 16-byte blocks per thread
+    constexpr int APT = (TM * (KC / 32) + THREADS - 1) / THREADS;        // staged words of L per thread
+
+    extern __shared__ uint32_t lds[];
+    const uint32_t v = xcd_order(blockIdx.x, gridDim.x);
+    ProdSeg sg = seg0;  // (a select between the two structs would copy both into vector registers)
+    if (nseg > 1) sg = segs[find_segment(segs, nseg, v, [](const ProdSeg& q) { return q.first_block; })];
+    const Geo g = sg.geo;
+    const uint32_t tiles = ((uint32_t)g.nct + TM - 1) / TM;
+    const uint32_t local = v - sg.first_block;
+    const uint32_t yl = local / tiles;
+    const int row_base = (int)(local % tiles) * TM;
+    const Bufs bufs = sg.bufs;
+    const ProdItem it = sg.items ? load_global(sg.items + yl) : one;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave % RG, wc = wave / RG;
+    const int half = lane >> 5;
+    const int W = g.W, nct = g.nct;
+    const int NF = (4 * W + 31) / 32;
+    const int bsz = NF * 32 * BP;  // bytes per staged chunk of R
+    const int nchunks = (nct + KC - 1) / KC;
+    const bool quads = (W & 3) == 0;  // rows are whole 16-byte units
+    const gword* Lp = ctp(bufs, it.L);
+    const gword* Rp = ctp(bufs, it.R);
+
+    const int SP = NF * 32 + 4;  // LDS words per row of column sums in the epilogue
+    // epilogue slabs of 32 rows per pass: as many as the launch's LDS holds
+    // beside the popcounts (segments of one launch may differ in width)
+    const int main_bytes = 2 * bsz + 2 * TM * (KC / 8);
+    int spp = 1;
+    while (spp < 2 * RG &&
+           (main_bytes > 2 * spp * 32 * SP * 4 ? main_bytes : 2 * spp * 32 * SP * 4) + TM * 4 <= lds_bytes)
+        spp *= 2;
+    const int s_bytes = 32 * spp * SP * 4;
+    uint8_t* Bs = reinterpret_cast<uint8_t*>(lds);                // 2 chunks of R, column by column
+    uint32_t* As = reinterpret_cast<uint32_t*>(Bs + 2 * bsz);     // 2 chunks of bits of L, KC/32 words per row
+    int32_t* Pc = reinterpret_cast<int32_t*>(Bs + (main_bytes > s_bytes ? main_bytes : s_bytes));  // popcount per row
+
+    // staging block i of this thread: rows 4 jq .. 4 jq + 3 of the chunk,
+    // words 4 wq .. 4 wq + 3 (one 16-byte load per row).  Within a wave 8
+    // consecutive wq (128 bytes of a row) times 8 consecutive jq.
+    uint32_t rs[SPT][4][4];
+    uint32_t as[APT];
+    auto block_of = [&](int i, int& jq, int& wq) {
+        const int t = tid + i * THREADS, r = t >> 6;
+        jq = ((t >> 3) & 7) + 8 * (r & 3);
+        wq = (t & 7) + 8 * (r >> 2);
+    };
+    auto load = [&](int c) {
+        const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
+        const gword* src = Rp + (size_t)(KC * c) * W;
+#pragma unroll
+        for (int i = 0; i < SPT; i++) {
+            int jq, wq;
+            block_of(i, jq, wq);
+            const bool ok = 4 * wq < W && 4 * jq < rows_c;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const gword* p = src + (size_t)(4 * jq + r) * W + 4 * wq;
+                if (ok && quads) {
+                    const u32x4 x = *reinterpret_cast<const gu32x4*>(p);
+                    rs[i][r][0] = x[0], rs[i][r][1] = x[1], rs[i][r][2] = x[2], rs[i][r][3] = x[3];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; u++) rs[i][r][u] = ok && 4 * wq + u < W ? p[u] : 0u;
+                }
+            }
+        }
+        // words of L: row a / (KC/32) of the tile, word a % (KC/32) of the chunk
+#pragma unroll
+        for (int i = 0; i < APT; i++) {
+            const int a = tid + i * THREADS, r = a / (KC / 32), wq = a % (KC / 32);
+            const bool ok = r < TM && row_base + r < nct && 32 * wq < rows_c;
+            as[i] = ok ? Lp[(size_t)(row_base + r) * W + (KC / 32) * c + wq] : 0u;
+        }
+    };
+    auto stage = [&](int c) {
+        const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
+        uint8_t* dst = Bs + (c & 1) * bsz;
+#pragma unroll
+        for (int i = 0; i < SPT; i++) {
+            int jq, wq;
+            block_of(i, jq, wq);
+            if (4 * wq < W && 4 * jq < rows_c) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t blk[4] = {rs[i][0][u], rs[i][1][u], rs[i][2][u], rs[i][3][u]};
+                    uint32_t col[4];
+                    transpose4x4(blk, col);
+#pragma unroll
+                    for (int cc = 0; cc < 4; cc++) {
+                        const int n = 16 * wq + 4 * u + cc;
+                        // columns past the row (a partial last unit) are never read
+                        *reinterpret_cast<uint32_t*>(dst + n * BP + 16 * ((jq >> 2) ^ mfma_swz(n)) + 4 * (jq & 3)) =
+                            col[cc] ^ 0x80808080u;
+                    }
+                }
+            }
+        }
+        uint32_t* ad = As + (c & 1) * TM * (KC / 32);
+#pragma unroll
+        for (int i = 0; i < APT; i++) {
+            const int a = tid + i * THREADS;
+            if (a < TM * (KC / 32)) ad[a] = as[i];
+        }
+    };
+
+    i32x16 acc[2][CF];
+#pragma unroll
+    for (int f = 0; f < 2; f++)
+#pragma unroll
+        for (int q = 0; q < CF; q++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[f][q][r] = 0;
+    uint32_t pc[2] = {0u, 0u};
+    // B fragments of this lane: column 32 fi + lane % 32 (fragments past the
+    // row read the last one; their sums are never used), units 2 s + half
+    int bcol[CF], bswz[CF];
+#pragma unroll
+    for (int q = 0; q < CF; q++) {
+        const int fi = wc * CF + q < NF ? wc * CF + q : NF - 1;
+        const int n = 32 * fi + (lane & 31);
+        bcol[q] = n * BP;
+        bswz[q] = mfma_swz(n);
+    }
+
+    load(0);
+    stage(0);
+    if (1 < nchunks) load(1);
+    __syncthreads();
+    for (int c = 0; c < nchunks; c++) {
+        const uint8_t* Bc = Bs + (c & 1) * bsz;
+        const uint32_t* Ac = As + (c & 1) * TM * (KC / 32);
+        const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
+        uint32_t aw[2][KC / 32];
+#pragma unroll
+        for (int f = 0; f < 2; f++) {
+            const uint4 q4 = *reinterpret_cast<const uint4*>(Ac + (64 * wr + 32 * f + (lane & 31)) * (KC / 32));
+            aw[f][0] = q4.x, aw[f][1] = q4.y, aw[f][2] = q4.z, aw[f][3] = q4.w;
+        }
+#pragma unroll
+        for (int s = 0; s < KC / 32; s++) {
+            if (32 * s < rows_c) {
+                i32x4 B[CF];
+#pragma unroll
+                for (int q = 0; q < CF; q++)
+                    B[q] = *reinterpret_cast<const i32x4*>(Bc + bcol[q] + 16 * ((2 * s + half) ^ bswz[q]));
+                i32x4 A[2];
+#pragma unroll
+                for (int f = 0; f < 2; f++) {
+                    const uint32_t u = (aw[f][s] >> (16 * half)) & 0xFFFFu;
+                    pc[f] += __builtin_popcount(u);
+                    A[f] = spread_bits(u);
+                }
+#pragma unroll
+                for (int q = 0; q < CF; q++) {
+                    acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[0], B[q], acc[0][q], 0, 0, 0);
+                    acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[1], B[q], acc[1][q], 0, 0, 0);
+                }
+            }
+        }
+        if (c + 1 < nchunks) stage(c + 1);
+        if (c + 2 < nchunks) load(c + 2);
+        __syncthreads();
+    }
+
+    // popcount of each row: the two half-waves hold bits 0..15 and 16..31 of
+    // every 32-bit step
+#pragma unroll
+    for (int f = 0; f < 2; f++) pc[f] += __shfl_xor(pc[f], 32);
+    if (wc == 0 && half == 0) {
+#pragma unroll
+        for (int f = 0; f < 2; f++) Pc[64 * wr + 32 * f + lane] = (int32_t)pc[f];
+    }
+
+    // epilogue in passes of spp slabs of 32 rows (slab 2 wr + f is fragment f
+    // of row group wr); the column sums of a pass reuse the chunk buffers
+    int32_t* S = reinterpret_cast<int32_t*>(lds);
+    for (int p0 = 0; p0 < 2 * RG; p0 += spp) {
+        if (p0 > 0) __syncthreads();
+#pragma unroll
+        for (int f = 0; f < 2; f++) {
+            const int slab = 2 * wr + f;
+            if (slab >= p0 && slab < p0 + spp) {
+#pragma unroll
+                for (int q = 0; q < CF; q++) {
+                    const int fi = wc * CF + q;
+                    if (fi < NF) {
+                        const int col = 32 * fi + (lane & 31);
+#pragma unroll
+                        for (int r = 0; r < 16; r++) {
+                            const int rl = 32 * (slab - p0) + 8 * (r >> 2) + 4 * half + (r & 3);
+                            S[rl * SP + col] = acc[f][q][r];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const int rows_p = 32 * spp;
+        for (int tk = tid; tk < rows_p * g.n1; tk += THREADS) {
+            const int rl = tk % rows_p, e = tk / rows_p;
+            const int trow = 32 * p0 + rl;
+            const int row = row_base + trow;
+            if (trow >= TM || row >= nct) continue;
+            finish_bytes(bufs, g, it, S + rl * SP + e * 4 * g.kw, Pc[trow], Lp, Rp, row, e);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_linear(const LinSeg* __restrict__ segs, int nseg, LinSeg seg0,
                                                      LinItem one, uint32_t ybase)
 {
@@ -551,6 +894,24 @@ hipError_t launch_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const P
     return hipGetLastError();
 }
 
+template <int RG, int CG, int CF>
+hipError_t launch_mfma_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                         const ProdItem& one, int64_t blocks, hipStream_t s)
+{
+    static int attr_bytes = 64 * 1024;
+    if (cfg.lds_bytes > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_product_mfma<RG, CG, CF>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, cfg.lds_bytes);
+        if (e != hipSuccess) return e;
+        attr_bytes = cfg.lds_bytes;
+    }
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_product_mfma<RG, CG, CF>), dim3((unsigned)blocks), dim3(RG * CG * 64), cfg.lds_bytes, s,
+                       d_segs, nseg, seg0, one, cfg.lds_bytes);
+    return hipGetLastError();
+}
+
 // Tilings: (threads, lanes per row, digit slots per lane, rows per lane,
 // lookup pipeline depth, 4-bit groups per chunk).  The first kDefaultTilings
 // are the defaults, one per width class; the rest are alternatives the tuner
@@ -573,13 +934,56 @@ constexpr Tiling kTilings[] = {
     {256, 4, 12, 4, 2, 8},   // <= 48, 4 lanes per row
     {512, 4, 20, 2, 1, 8},   // <= 80, 4 lanes per row
 };
-constexpr int kNumTilings = (int)(sizeof(kTilings) / sizeof(kTilings[0]));
+constexpr int kNumLookupTilings = (int)(sizeof(kTilings) / sizeof(kTilings[0]));
 constexpr int kDefaultTilings = 5;
+
+// Matrix-core tilings: (row groups, column groups, 32-column fragments per
+// wave).  They follow the lookup tilings in the tiling numbering; a tiling
+// serves a geometry whose NF = ceil(4 W / 32) fragments give each column
+// group CF of them (the last fewer).
+struct MfmaTiling {
+    int rg, cgw, cf;
+};
+constexpr MfmaTiling kMfmaTilings[] = {
+    {2, 4, 1}, {2, 4, 2}, {2, 4, 3},                        // 512 threads, 128-row tiles
+    {2, 2, 1}, {2, 2, 2}, {2, 2, 3}, {2, 2, 4}, {2, 2, 5}, {2, 2, 6},  // 256 threads, 128-row tiles
+    {4, 2, 3}, {4, 2, 4}, {4, 2, 6},                        // 512 threads, 256-row tiles
+};
+constexpr int kNumMfmaTilings = (int)(sizeof(kMfmaTilings) / sizeof(kMfmaTilings[0]));
+constexpr int kNumTilings = kNumLookupTilings + kNumMfmaTilings;
+
+hipError_t dispatch_mfma(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0, const ProdItem& one,
+                         int64_t blocks, hipStream_t s)
+{
+#define MCASE(I)                                                                                         \
+    if (cfg.tiling == kNumLookupTilings + I)                                                             \
+        return launch_mfma_t<kMfmaTilings[I].rg, kMfmaTilings[I].cgw, kMfmaTilings[I].cf>(cfg, d_segs, nseg, \
+                                                                                           seg0, one, blocks, s);
+    MCASE(0)
+    MCASE(1)
+    MCASE(2)
+    MCASE(3)
+    MCASE(4)
+    MCASE(5)
+    MCASE(6)
+    MCASE(7)
+    MCASE(8)
+    MCASE(9)
+    MCASE(10)
+    MCASE(11)
+#undef MCASE
+    static_assert(kNumMfmaTilings == 12, "one MCASE per matrix-core tiling");
+    return hipErrorInvalidValue;
+}
 
 template <bool ENC>
 hipError_t dispatch(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0, const ProdItem& one,
                     int64_t blocks, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
+    if (cfg.mfma) {
+        if (ENC) return hipErrorInvalidValue;  // encryption draws its bits of L inside the lookup kernel
+        return dispatch_mfma(cfg, d_segs, nseg, seg0, one, blocks, s);
+    }
 #define CASE(I)                                                                                              \
     if (cfg.tiling == I)                                                                                     \
         return launch_t<kTilings[I].threads, kTilings[I].lpr, kTilings[I].dpl, kTilings[I].rpl, kTilings[I].pd, \
@@ -597,7 +1001,7 @@ hipError_t dispatch(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const P
     CASE(10)
     CASE(11)
 #undef CASE
-    static_assert(kNumTilings == 12, "one CASE per tiling");
+    static_assert(kNumLookupTilings == 12, "one CASE per tiling");
     return hipErrorInvalidValue;
 }
 
@@ -617,18 +1021,60 @@ int tiling_count() { return kNumTilings; }
 
 void tiling_fields(int ti, int* f)
 {
+    if (ti >= kNumLookupTilings) {
+        const MfmaTiling& t = kMfmaTilings[ti - kNumLookupTilings];
+        f[0] = t.rg * t.cgw * 64, f[1] = t.rg, f[2] = t.cgw, f[3] = t.cf, f[4] = 0, f[5] = 0, f[6] = 1;
+        return;
+    }
     const Tiling& t = kTilings[ti];
-    f[0] = t.threads, f[1] = t.lpr, f[2] = t.dpl, f[3] = t.rpl, f[4] = t.pd, f[5] = t.cg;
+    f[0] = t.threads, f[1] = t.lpr, f[2] = t.dpl, f[3] = t.rpl, f[4] = t.pd, f[5] = t.cg, f[6] = 0;
 }
+
+namespace {
+bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
+{
+    const MfmaTiling& t = kMfmaTilings[ti - kNumLookupTilings];
+    const int nf = (4 * g.W + 31) / 32;
+    if ((nf + t.cgw - 1) / t.cgw != t.cf) return false;
+    // the staging blocks of a chunk (32 row quads x ceil(W/4) word quads,
+    // 8 x 8 per wave) fit the threads' blocks
+    const int threads = t.rg * t.cgw * 64;
+    const int spt = (kMfmaChunk / 4 * 2 * t.cgw * t.cf + threads - 1) / threads;
+    if (4 * ((g.W + 31) / 32) > spt * threads / 64) return false;
+    *cfg = ProdCfg{};
+    cfg->tiling = ti;
+    cfg->mfma = true;
+    cfg->threads = t.rg * t.cgw * 64;
+    cfg->rg = t.rg;
+    cfg->cgw = t.cgw;
+    cfg->cf = t.cf;
+    cfg->tr = 64 * t.rg;
+    cfg->nd = (g.k + kDigitBits - 1) / kDigitBits;
+    cfg->wd = g.n1 * cfg->nd;
+    // LDS: two chunks of R by columns, then per epilogue pass spp slabs of 32
+    // rows of column sums (as many as the workgroup's share allows: all of a
+    // CU for 512 threads, half for 256), and a popcount per tile row
+    const int cap = cfg->threads >= 512 ? 160 * 1024 : 80 * 1024;
+    const int chunks = 2 * nf * 32 * kMfmaPitch + 2 * cfg->tr * (kMfmaChunk / 8);
+    const int slab = 32 * (nf * 32 + 4) * 4;
+    const int tail = cfg->tr * 4;
+    int spp = 1;
+    while (spp < 2 * t.rg && std::max(chunks, 2 * spp * slab) + tail <= cap) spp *= 2;
+    cfg->lds_bytes = std::max(chunks, spp * slab) + tail;
+    return cfg->lds_bytes <= 160 * 1024;
+}
+}  // namespace
 
 bool tiling_config(const Geo& g, int ti, ProdCfg* cfg)
 {
     if (ti < 0 || ti >= kNumTilings) return false;
     if (g.nct % 32 != 0 || g.W * 32 != g.nct || g.W > kMaxRowWords) return false;
+    if (ti >= kNumLookupTilings) return mfma_config(g, ti, cfg);
     const Tiling& t = kTilings[ti];
     const int nd = (g.k + kDigitBits - 1) / kDigitBits;
     const int wd = g.n1 * nd;
     if (t.lpr * t.dpl < wd) return false;
+    *cfg = ProdCfg{};
     cfg->tiling = ti;
     cfg->threads = t.threads;
     cfg->cg = t.cg;
@@ -669,6 +1115,16 @@ bool product_config(const Geo& g, ProdCfg* cfg)
         auto it = g_tuned.find({g.k, g.n1});
         if (it != g_tuned.end() && tiling_config(g, it->second, cfg)) return true;
     }
+    // matrix cores first: two column groups while they have two fragments
+    // or fewer each, four after that
+    static const int order[] = {3, 4, 0, 1, 2};
+    for (int i : order)
+        if (tiling_config(g, kNumLookupTilings + i, cfg)) return true;
+    return lookup_config(g, cfg);
+}
+
+bool lookup_config(const Geo& g, ProdCfg* cfg)
+{
     for (int i = 0; i < kDefaultTilings; i++)
         if (tiling_config(g, i, cfg)) return true;
     return false;
@@ -716,6 +1172,8 @@ hipError_t launch_encrypt(const Bufs& b, const Geo& g, const ProdCfg& cfg, const
 {
     if (n_ct <= 0) return hipSuccess;
     if (n_ct > kMaxEncPerLaunch) return hipErrorInvalidValue;
+    ProdCfg lk = cfg;
+    if (cfg.mfma && !lookup_config(g, &lk)) return hipErrorInvalidValue;
     MuBits mu{};
     for (int i = 0; i < (n_ct + 31) / 32; i++) mu.w[i] = bits[i];
     ProdItem one{};
@@ -726,7 +1184,7 @@ hipError_t launch_encrypt(const Bufs& b, const Geo& g, const ProdCfg& cfg, const
     one.E[0] = -1;
     one.cP[0] = 1;
     for (int i = 1; i < kMaxOut; i++) one.dst[i] = one.E[i] = -1;
-    return dispatch<true>(cfg, nullptr, 1, single_segment(b, g, cfg), one, (int64_t)n_ct * product_tiles(g, cfg), seed,
+    return dispatch<true>(lk, nullptr, 1, single_segment(b, g, lk), one, (int64_t)n_ct * product_tiles(g, lk), seed,
                           first_id, &mu, s);
 }
 

@@ -58,9 +58,9 @@ int sfft_tiling_count(void) { return tiling_count(); }
 int sfft_tiling_describe(int32_t tiling, int32_t* fields)
 {
     if (tiling < 0 || tiling >= tiling_count() || !fields) return sfft_fail(SFFT_EINVAL, "no such tiling");
-    int f[6];
+    int f[7];
     tiling_fields(tiling, f);
-    for (int i = 0; i < 6; i++) fields[i] = f[i];
+    for (int i = 0; i < 7; i++) fields[i] = f[i];
     return SFFT_OK;
 }
 

@@ -231,7 +231,7 @@ def sfft_tiling_count() -> int:
 
 
 def sfft_tiling_describe(tiling: int):
-    f = (ctypes.c_int32 * 6)()
+    f = (ctypes.c_int32 * 7)()
     _check(_lib.sfft_tiling_describe(tiling, f))
     return tuple(f)
 

@@ -17,15 +17,29 @@ pytestmark = pytest.mark.gpu
 GEOS = {16: (1, 224), 32: (1, 480), 48: (1, 704), 64: (1, 960), 80: (1, 1184), 96: (1, 1440), 128: (3, 960)}
 
 
+def _mfma_geos(nf):
+    """Two geometries with nf 32-byte fragments per row: one filling them
+    (n=1, 4W = 32 nf bytes) and a ragged one (4W = 32 nf - 12 bytes, W odd,
+    so Nct = 32 W is an odd multiple of 32: a half chunk of R at the end and
+    a partial row tile)."""
+    w = 8 * nf - 3
+    n1 = next(d for d in range(3, w + 1) if w % d == 0)
+    return [(1, 128 * nf), (n1 - 1, 32 * (w // n1))]
+
+
 def _cases():
     out = []
     for ti in range(S.sfft_tiling_count()):
-        threads, lpr, dpl, rpl, pd, cg = S.sfft_tiling_describe(ti)
-        out.append((ti, GEOS[lpr * dpl]))
+        f = S.sfft_tiling_describe(ti)
+        if f[6] == 0:
+            out.append((ti, GEOS[f[1] * f[2]]))
+        else:
+            for geo in _mfma_geos(f[2] * f[3]):
+                out.append((ti, geo))
     return out
 
 
-@pytest.mark.parametrize("ti,geo", _cases())
+@pytest.mark.parametrize("ti,geo", _cases(), ids=lambda v: str(v))
 def test_tiling_matches_oracle(ti, geo):
     n, k = geo
     print("[gpu-case] tiling %d n=%d k=%d" % (ti, n, k), flush=True)
@@ -58,7 +72,7 @@ def test_tuner_records_a_tiling_plans_use():
     plan.close()
     api.set_tiling(p, -1)
     plan = api.Plan(1, 8, 8, 4, False, p)
-    assert plan.info.tiling == 0  # default of the 16-slot class
+    assert S.sfft_tiling_describe(plan.info.tiling)[6] == 1  # the matrix-core default
     plan.close()
 
 
