@@ -534,10 +534,12 @@ typedef __attribute__((address_space(1))) u32x4 gu32x4;  // 16 bytes of a cipher
 constexpr int kMfmaChunk = 128;                 // rows of R per chunk
 constexpr int kMfmaPitch = kMfmaChunk;          // LDS bytes per staged column
 
-// A staged column n keeps its 8 units of 16 bytes (16 rows each) in the
-// order unit ^ swz(n): the 16 lanes of a ds_read_b128 phase (16 consecutive
-// columns) then hit 16 distinct 4-bank groups, and the dword stores of a
-// staging wave spread over all banks but one factor of two.
+// A staged column n (or row of bits of L) keeps its 8 units of 16 bytes in
+// the order unit ^ swz(n).  swz takes distinct values on the even and on the
+// odd n of any 16 aligned consecutive n, so that the 16 lanes of a
+// ds_read_b128 phase (16 consecutive columns) hit distinct 4-bank groups of
+// the 64 banks, and distinct values on n = 16 w + k for w = 0..7, so that
+// the dword stores of a staging wave spread over all banks (two lanes each).
 __device__ __forceinline__ int mfma_swz(int n) { return ((n >> 1) + (n >> 4)) & 7; }
 
 // r[i] holds bytes (i, 0..3) of a 4x4 byte block; c[j] gets bytes (0..3, j)
@@ -566,63 +568,51 @@ __device__ __forceinline__ i32x4 spread_bits(uint32_t u)
 }
 
 // Output row `row`, element e, from its byte column sums S[0..4 kw) (LDS,
-// each missing 128 popcount) and the row's popcount pc.
-__device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it, const int32_t* S, int pc,
-                             const gword* Lp, const gword* Rp, int row, int e)
+// each missing 128 popcount), the row's popcount pc and its words of L and
+// R (LDS).  Output o's limb l replaces S[4 l + o] (the sums of limb l are
+// consumed first), for a coalesced write-out afterwards.
+__device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it, int32_t* S, int pc,
+                             const uint32_t* Lw, const uint32_t* Rw, int row, int e)
 {
     const int br = row / g.k, tr = row % g.k;
     const size_t base = (size_t)row * g.W + (size_t)e * g.kw;
     const int64_t corr = 128ll * pc * 0x01010101ll;
     int64_t carry[kMaxOut];
-    bool needL = false, needR = false;
+    const gword* Ep[kMaxOut];
 #pragma unroll
     for (int o = 0; o < kMaxOut; o++) {
         carry[o] = 0;
-        if (o < it.nout) {
-            needL |= it.cL[o] != 0;
-            needR |= it.cR[o] != 0;
-        }
+        Ep[o] = o < it.nout && it.E[o] >= 0 ? ctp(bufs, it.E[o]) + base : nullptr;
     }
-    for (int l0 = 0; l0 < g.kw; l0 += 8) {
-        const int nl = g.kw - l0 < 8 ? g.kw - l0 : 8;
-        const size_t off = base + l0;
-        uint32_t Lv[8], Rv[8];
-        int64_t P[8];
+    for (int l0 = 0; l0 < g.kw; l0 += 4) {
+        const int nl = g.kw - l0 < 4 ? g.kw - l0 : 4;
+        uint32_t Ev[kMaxOut][4];
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            Lv[j] = (needL && j < nl) ? Lp[off + j] : 0u;
-            Rv[j] = (needR && j < nl) ? Rp[off + j] : 0u;
-        }
+        for (int o = 0; o < kMaxOut; o++)
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
+            for (int j = 0; j < 4; j++) Ev[o][j] = (Ep[o] && j < nl) ? Ep[o][l0 + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
             if (j < nl) {
-                const i32x4 s4 = *reinterpret_cast<const i32x4*>(S + 4 * (l0 + j));
-                P[j] = (int64_t)s4[0] + (int64_t)s4[1] * 256 + (int64_t)s4[2] * 65536 + (int64_t)s4[3] * 16777216 +
-                       corr;
-            } else {
-                P[j] = 0;
-            }
-        }
+                const int l = l0 + j;
+                i32x4* s4p = reinterpret_cast<i32x4*>(S + 4 * l);
+                const i32x4 s4 = *s4p;
+                const int64_t P = (int64_t)s4[0] + (int64_t)s4[1] * 256 + (int64_t)s4[2] * 65536 +
+                                  (int64_t)s4[3] * 16777216 + corr;
+                const uint32_t Lv = Lw[l], Rv = Rw[l];
+                const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
+                i32x4 out = {0, 0, 0, 0};
 #pragma unroll
-        for (int o = 0; o < kMaxOut; o++) {
-            if (o < it.nout) {
-                gword* dst = ctp(bufs, it.dst[o]) + off;
-                const gword* Ep = it.E[o] >= 0 ? ctp(bufs, it.E[o]) + off : nullptr;
-                uint32_t Ev[8];
-#pragma unroll
-                for (int j = 0; j < 8; j++) Ev[j] = (Ep && j < nl) ? Ep[j] : 0u;
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    if (j < nl) {
-                        const int l = l0 + j;
-                        const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
-                        const int64_t s = carry[o] + (int64_t)it.cL[o] * Lv[j] + (int64_t)it.cR[o] * Rv[j] +
-                                          (int64_t)it.cP[o] * P[j] + (int64_t)it.cG[o] * Gv +
-                                          (int64_t)it.cE[o] * Ev[j];
-                        dst[j] = (uint32_t)s;
-                        carry[o] = s >> 32;
+                for (int o = 0; o < kMaxOut; o++) {
+                    if (o < it.nout) {
+                        const int64_t v = carry[o] + (int64_t)it.cL[o] * Lv + (int64_t)it.cR[o] * Rv +
+                                          (int64_t)it.cP[o] * P + (int64_t)it.cG[o] * Gv +
+                                          (int64_t)it.cE[o] * Ev[o][j];
+                        out[o] = (int32_t)(uint32_t)v;
+                        carry[o] = v >> 32;
                     }
                 }
+                *s4p = out;
             }
         }
     }
@@ -638,6 +628,8 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     constexpr int BP = kMfmaPitch;
     constexpr int SPT = (KC / 4 * 2 * CG * CF + THREADS - 1) / THREADS;  // staged 4-row x 16-byte blocks per thread
     constexpr int APT = (TM * (KC / 32) + THREADS - 1) / THREADS;        // staged words of L per thread
+    constexpr int EPT = (64 * 8 * CG * CF / 4 + THREADS - 1) / THREADS;  // epilogue 16-byte loads per operand
+    constexpr int NP = SPT < KC / 32 ? SPT : KC / 32;                     // staging parts per chunk
 
     extern __shared__ uint32_t lds[];
     const uint32_t v = xcd_order(blockIdx.x, gridDim.x);
@@ -661,17 +653,19 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     const gword* Lp = ctp(bufs, it.L);
     const gword* Rp = ctp(bufs, it.R);
 
-    const int SP = NF * 32 + 4;  // LDS words per row of column sums in the epilogue
-    // epilogue slabs of 32 rows per pass: as many as the launch's LDS holds
-    // beside the popcounts (segments of one launch may differ in width)
-    const int main_bytes = 2 * bsz + 2 * TM * (KC / 8);
+    // epilogue: per row, SP words of column sums (later outputs) and LP words
+    // each of L and R; slabs of 32 rows per pass,
+    // as many (up to 2) as the launch's LDS holds beside the popcounts
+    // (segments of one launch may differ in width)
+    const int SP = NF * 32 + 4;
+    const int LP = 8 * ((W + 7) / 8) + 4;
+    const int slab_bytes = 32 * (SP + 2 * LP) * 4;
+    const int main_bytes = 2 * bsz + 2 * TM * KC;
     int spp = 1;
-    while (spp < 2 * RG &&
-           (main_bytes > 2 * spp * 32 * SP * 4 ? main_bytes : 2 * spp * 32 * SP * 4) + TM * 4 <= lds_bytes)
-        spp *= 2;
-    const int s_bytes = 32 * spp * SP * 4;
-    uint8_t* Bs = reinterpret_cast<uint8_t*>(lds);                // 2 chunks of R, column by column
-    uint32_t* As = reinterpret_cast<uint32_t*>(Bs + 2 * bsz);     // 2 chunks of bits of L, KC/32 words per row
+    if ((main_bytes > 2 * slab_bytes ? main_bytes : 2 * slab_bytes) + TM * 4 <= lds_bytes) spp = 2;
+    const int s_bytes = spp * slab_bytes;
+    uint8_t* Bs = reinterpret_cast<uint8_t*>(lds);  // 2 chunks of R, column by column
+    uint8_t* As = Bs + 2 * bsz;                     // 2 chunks of bits of L as 0/1 bytes, KC bytes per row
     int32_t* Pc = reinterpret_cast<int32_t*>(Bs + (main_bytes > s_bytes ? main_bytes : s_bytes));  // popcount per row
 
     // staging block i of this thread: rows 4 jq .. 4 jq + 3 of the chunk,
@@ -684,11 +678,16 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
         jq = ((t >> 3) & 7) + 8 * (r & 3);
         wq = (t & 7) + 8 * (r >> 2);
     };
-    auto load = [&](int c) {
+    // loads and staging go in NP parts (part p: the blocks i with i % NP ==
+    // p); part p of chunk c + 1 is staged, and its registers refilled with
+    // chunk c + 2, after matrix step kPartStep[p] of chunk c, so that every
+    // load has a whole chunk to arrive
+    auto load_R = [&](int c, int part) {
         const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
         const gword* src = Rp + (size_t)(KC * c) * W;
 #pragma unroll
         for (int i = 0; i < SPT; i++) {
+            if (part >= 0 && i % NP != part) continue;
             int jq, wq;
             block_of(i, jq, wq);
             const bool ok = 4 * wq < W && 4 * jq < rows_c;
@@ -704,7 +703,10 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
                 }
             }
         }
-        // words of L: row a / (KC/32) of the tile, word a % (KC/32) of the chunk
+    };
+    // words of L: row a / (KC/32) of the tile, word a % (KC/32) of the chunk
+    auto load_L = [&](int c) {
+        const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
 #pragma unroll
         for (int i = 0; i < APT; i++) {
             const int a = tid + i * THREADS, r = a / (KC / 32), wq = a % (KC / 32);
@@ -712,11 +714,12 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
             as[i] = ok ? Lp[(size_t)(row_base + r) * W + (KC / 32) * c + wq] : 0u;
         }
     };
-    auto stage = [&](int c) {
+    auto stage_R = [&](int c, int part) {
         const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
         uint8_t* dst = Bs + (c & 1) * bsz;
 #pragma unroll
         for (int i = 0; i < SPT; i++) {
+            if (part >= 0 && i % NP != part) continue;
             int jq, wq;
             block_of(i, jq, wq);
             if (4 * wq < W && 4 * jq < rows_c) {
@@ -735,11 +738,25 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
                 }
             }
         }
-        uint32_t* ad = As + (c & 1) * TM * (KC / 32);
+    };
+    // the chunk's bits of L as bytes: word s of row r gives units 2 s and
+    // 2 s + 1 (its two halves) of the row, XOR-swizzled by row like the
+    // columns of R; the staging thread also counts the bits
+    uint32_t pcs[APT];
+#pragma unroll
+    for (int i = 0; i < APT; i++) pcs[i] = 0u;
+    auto stage_L = [&](int c) {
+        uint8_t* ad = As + (c & 1) * TM * KC;
 #pragma unroll
         for (int i = 0; i < APT; i++) {
-            const int a = tid + i * THREADS;
-            if (a < TM * (KC / 32)) ad[a] = as[i];
+            const int a = tid + i * THREADS, r = a / (KC / 32), wq = a % (KC / 32);
+            if (a < TM * (KC / 32)) {
+                pcs[i] += __builtin_popcount(as[i]);
+#pragma unroll
+                for (int h = 0; h < 2; h++)
+                    *reinterpret_cast<i32x4*>(ad + r * KC + 16 * ((2 * wq + h) ^ mfma_swz(r))) =
+                        spread_bits(as[i] >> (16 * h));
+            }
         }
     };
 
@@ -750,7 +767,6 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
         for (int q = 0; q < CF; q++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[f][q][r] = 0;
-    uint32_t pc[2] = {0u, 0u};
     // B fragments of this lane: column 32 fi + lane % 32 (fragments past the
     // row read the last one; their sums are never used), units 2 s + half
     int bcol[CF], bswz[CF];
@@ -762,60 +778,115 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
         bswz[q] = mfma_swz(n);
     }
 
-    load(0);
-    stage(0);
-    if (1 < nchunks) load(1);
+    // this lane's rows of A: 64 wr + 32 f + lane % 32
+    int arow[2];
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+        const int r = 64 * wr + 32 * f + (lane & 31);
+        arow[f] = r * KC;
+        (void)r;
+    }
+    int aswz[2];
+#pragma unroll
+    for (int f = 0; f < 2; f++) aswz[f] = mfma_swz(64 * wr + 32 * f + (lane & 31));
+
+    load_R(0, -1);
+    load_L(0);
+    stage_R(0, -1);
+    stage_L(0);
+    if (1 < nchunks) {
+        load_R(1, -1);
+        load_L(1);
+    }
     __syncthreads();
     for (int c = 0; c < nchunks; c++) {
         const uint8_t* Bc = Bs + (c & 1) * bsz;
-        const uint32_t* Ac = As + (c & 1) * TM * (KC / 32);
+        const uint8_t* Ac = As + (c & 1) * TM * KC;
         const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
-        uint32_t aw[2][KC / 32];
+        const bool next = c + 1 < nchunks, next2 = c + 2 < nchunks;
+        // fragments of step s + 1 are read from LDS before the products of step s
+        i32x4 B[CF], A[2];
+        auto read_frags = [&](int s) {
 #pragma unroll
-        for (int f = 0; f < 2; f++) {
-            const uint4 q4 = *reinterpret_cast<const uint4*>(Ac + (64 * wr + 32 * f + (lane & 31)) * (KC / 32));
-            aw[f][0] = q4.x, aw[f][1] = q4.y, aw[f][2] = q4.z, aw[f][3] = q4.w;
-        }
+            for (int q = 0; q < CF; q++)
+                B[q] = *reinterpret_cast<const i32x4*>(Bc + bcol[q] + 16 * ((2 * s + half) ^ bswz[q]));
+#pragma unroll
+            for (int f = 0; f < 2; f++)
+                A[f] = *reinterpret_cast<const i32x4*>(Ac + arow[f] + 16 * ((2 * s + half) ^ aswz[f]));
+        };
+        read_frags(0);
 #pragma unroll
         for (int s = 0; s < KC / 32; s++) {
             if (32 * s < rows_c) {
-                i32x4 B[CF];
+                i32x4 Bq[CF], Af[2];
 #pragma unroll
-                for (int q = 0; q < CF; q++)
-                    B[q] = *reinterpret_cast<const i32x4*>(Bc + bcol[q] + 16 * ((2 * s + half) ^ bswz[q]));
-                i32x4 A[2];
-#pragma unroll
-                for (int f = 0; f < 2; f++) {
-                    const uint32_t u = (aw[f][s] >> (16 * half)) & 0xFFFFu;
-                    pc[f] += __builtin_popcount(u);
-                    A[f] = spread_bits(u);
-                }
+                for (int q = 0; q < CF; q++) Bq[q] = B[q];
+                Af[0] = A[0], Af[1] = A[1];
+                if (s + 1 < KC / 32 && 32 * (s + 1) < rows_c) read_frags(s + 1);
 #pragma unroll
                 for (int q = 0; q < CF; q++) {
-                    acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[0], B[q], acc[0][q], 0, 0, 0);
-                    acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[1], B[q], acc[1][q], 0, 0, 0);
+                    acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[0], Bq[q], acc[0][q], 0, 0, 0);
+                    acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[1], Bq[q], acc[1][q], 0, 0, 0);
                 }
             }
+            // staging parts that fall after this step
+#pragma unroll
+            for (int p = 0; p < NP; p++) {
+                if ((p + 1) * (KC / 32) / NP - 1 != s) continue;
+                if (next) stage_R(c + 1, p);
+                if (next2) load_R(c + 2, p);
+            }
         }
-        if (c + 1 < nchunks) stage(c + 1);
-        if (c + 2 < nchunks) load(c + 2);
+        if (next) stage_L(c + 1);
+        if (next2) load_L(c + 2);
         __syncthreads();
     }
 
-    // popcount of each row: the two half-waves hold bits 0..15 and 16..31 of
-    // every 32-bit step
+    // popcount of each row: the sum over the KC/32 staging threads of the
+    // row (consecutive lanes)
 #pragma unroll
-    for (int f = 0; f < 2; f++) pc[f] += __shfl_xor(pc[f], 32);
-    if (wc == 0 && half == 0) {
-#pragma unroll
-        for (int f = 0; f < 2; f++) Pc[64 * wr + 32 * f + lane] = (int32_t)pc[f];
+    for (int i = 0; i < APT; i++) {
+        pcs[i] += __shfl_xor(pcs[i], 1);
+        pcs[i] += __shfl_xor(pcs[i], 2);
+        const int a = tid + i * THREADS;
+        if (a < TM * (KC / 32) && (a & 3) == 0) Pc[a >> 2] = (int32_t)pcs[i];
     }
 
-    // epilogue in passes of spp slabs of 32 rows (slab 2 wr + f is fragment f
-    // of row group wr); the column sums of a pass reuse the chunk buffers
+    // Epilogue in passes of spp slabs of 32 rows (slab 2 wr + f is fragment
+    // f of row group wr).  Per pass: the rows' words of L and R are loaded
+    // (16 bytes a lane, rows contiguous) while the accumulators go to LDS;
+    // one thread per (row, element) runs the carry chains from LDS and leaves
+    // the outputs in place of the column sums; then the outputs are written
+    // row-contiguously.
     int32_t* S = reinterpret_cast<int32_t*>(lds);
+    uint32_t* Le = reinterpret_cast<uint32_t*>(S + 32 * spp * SP);
+    uint32_t* Re = Le + 32 * spp * LP;
     for (int p0 = 0; p0 < 2 * RG; p0 += spp) {
         if (p0 > 0) __syncthreads();
+        const int prow = row_base + 32 * p0;  // first row of the pass
+        const int rows_p = (nct - prow < 32 * spp ? nct - prow : 32 * spp);
+        const int pw = rows_p > 0 ? rows_p * W : 0;  // words of the pass per operand
+        uint32_t el[EPT][4], er[EPT][4];
+#pragma unroll
+        for (int i = 0; i < EPT; i++) {
+            const int f4 = 4 * (tid + i * THREADS);
+#pragma unroll
+            for (int u = 0; u < 4; u++) el[i][u] = er[i][u] = 0u;
+            if (f4 < pw) {
+                const gword* lp = Lp + (size_t)prow * W + f4;
+                const gword* rp = Rp + (size_t)prow * W + f4;
+                if (quads) {
+                    const u32x4 a = *reinterpret_cast<const gu32x4*>(lp);
+                    const u32x4 b = *reinterpret_cast<const gu32x4*>(rp);
+#pragma unroll
+                    for (int u = 0; u < 4; u++) el[i][u] = a[u], er[i][u] = b[u];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        if (f4 + u < pw) el[i][u] = lp[u], er[i][u] = rp[u];
+                }
+            }
+        }
 #pragma unroll
         for (int f = 0; f < 2; f++) {
             const int slab = 2 * wr + f;
@@ -834,14 +905,35 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
                 }
             }
         }
+#pragma unroll
+        for (int i = 0; i < EPT; i++) {
+            const int f4 = 4 * (tid + i * THREADS);
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int fw = f4 + u;
+                if (fw < pw) {
+                    const int rl = fw / W, w = fw - rl * W;
+                    Le[rl * LP + w] = el[i][u];
+                    Re[rl * LP + w] = er[i][u];
+                }
+            }
+        }
         __syncthreads();
-        const int rows_p = 32 * spp;
         for (int tk = tid; tk < rows_p * g.n1; tk += THREADS) {
             const int rl = tk % rows_p, e = tk / rows_p;
-            const int trow = 32 * p0 + rl;
-            const int row = row_base + trow;
-            if (trow >= TM || row >= nct) continue;
-            finish_bytes(bufs, g, it, S + rl * SP + e * 4 * g.kw, Pc[trow], Lp, Rp, row, e);
+            finish_bytes(bufs, g, it, S + rl * SP + e * 4 * g.kw, Pc[32 * p0 + rl], Le + rl * LP + e * g.kw,
+                         Re + rl * LP + e * g.kw, prow + rl, e);
+        }
+        __syncthreads();
+        gword* dst[kMaxOut];
+#pragma unroll
+        for (int o = 0; o < kMaxOut; o++) dst[o] = o < it.nout ? ctp(bufs, it.dst[o]) + (size_t)prow * W : nullptr;
+        for (int fw = tid; fw < pw; fw += THREADS) {
+            const int rl = fw / W, w = fw - rl * W;
+            const i32x4 v4 = *reinterpret_cast<const i32x4*>(S + rl * SP + 4 * w);
+#pragma unroll
+            for (int o = 0; o < kMaxOut; o++)
+                if (dst[o]) dst[o][fw] = (uint32_t)v4[o];
         }
     }
 }
@@ -947,7 +1039,7 @@ struct MfmaTiling {
 constexpr MfmaTiling kMfmaTilings[] = {
     {2, 4, 1}, {2, 4, 2}, {2, 4, 3},                        // 512 threads, 128-row tiles
     {2, 2, 1}, {2, 2, 2}, {2, 2, 3}, {2, 2, 4}, {2, 2, 5}, {2, 2, 6},  // 256 threads, 128-row tiles
-    {4, 2, 3}, {4, 2, 4}, {4, 2, 6},                        // 512 threads, 256-row tiles
+    {4, 2, 2}, {4, 2, 3}, {4, 2, 4},                        // 512 threads, 256-row tiles
 };
 constexpr int kNumMfmaTilings = (int)(sizeof(kMfmaTilings) / sizeof(kMfmaTilings[0]));
 constexpr int kNumTilings = kNumLookupTilings + kNumMfmaTilings;
@@ -1055,11 +1147,10 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
     // rows of column sums (as many as the workgroup's share allows: all of a
     // CU for 512 threads, half for 256), and a popcount per tile row
     const int cap = cfg->threads >= 512 ? 160 * 1024 : 80 * 1024;
-    const int chunks = 2 * nf * 32 * kMfmaPitch + 2 * cfg->tr * (kMfmaChunk / 8);
-    const int slab = 32 * (nf * 32 + 4) * 4;
+    const int chunks = 2 * nf * 32 * kMfmaPitch + 2 * cfg->tr * kMfmaChunk;
+    const int slab = 32 * ((nf * 32 + 4) + 2 * (8 * ((g.W + 7) / 8) + 4)) * 4;
     const int tail = cfg->tr * 4;
-    int spp = 1;
-    while (spp < 2 * t.rg && std::max(chunks, 2 * spp * slab) + tail <= cap) spp *= 2;
+    const int spp = std::max(chunks, 2 * slab) + tail <= cap ? 2 : 1;
     cfg->lds_bytes = std::max(chunks, spp * slab) + tail;
     return cfg->lds_bytes <= 160 * 1024;
 }
