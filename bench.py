@@ -9,9 +9,11 @@ A step is one encrypted FFT of one request (every product level of the
 compiled circuit, inputs already encrypted and resident in HBM).  Prints one
 JSON line: canonical-netlist Boolean gates per second (AND+XOR+OR+XADD), FFT
 points per second, per-step latency percentiles, the gate-product kernel's
-roofline (algorithmic bit-MACs per second from HIP events recorded around
-every product launch on the launch stream) and the CPU oracle's rate on a
-bounded sample of the same products.
+roofline (the algorithmic work of the products per second, from HIP events
+recorded around every product launch on the launch stream, against the
+dense int8 matrix-core peak, or the table-lookup ceiling when the plan runs
+the lookup kernel) and the CPU oracle's rate on a bounded sample of the same
+products.
 """
 from __future__ import annotations
 
@@ -35,6 +37,10 @@ PEAK_LOOKUP = LDS_BYTES_PER_S * 32.0   # 5.03e15 bit-MAC/s
 # For reference, the AND + popcount formulation on the integer VALU
 # (128 lanes/clk/CU, v_and_b32 + v_bcnt_u32_b32 per 32 bit-MACs).
 PEAK_POPCOUNT = 256 * 128 * 2.4e9 * 16.0   # 1.26e15 bit-MAC/s
+# Matrix-core kernel ceiling: MI355X dense int8 MFMA, 5.0 POP/s.  A product's
+# algorithmic work, Nct^3 bit-MACs, is Nct x Nct x Nct/8 byte-MACs of its bits
+# of L times the bytes of R, i.e. Nct^3 / 4 int8 operations.
+PEAK_MFMA_I8 = 5.0e15                   # int8 op/s
 
 
 def pct(xs, q):
@@ -135,7 +141,7 @@ def run_batch(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "i8",
         "data": "synthetic",
         "config": {"workload": "batch_1d_mixed", "requests": len(reqs), "lengths": "%d..%d" % (lengths[0], lengths[-1]),
                    "F": "12/16/24",
@@ -164,6 +170,11 @@ def copy_probe():
     print("[bench] copied 1 GiB three times", flush=True)
 
 
+def _is_gate_product(name):
+    """A gate-product launch of either kernel (encryption launches excluded)."""
+    return ("k_product<" in name and "false>" in name) or "k_product_mfma<" in name
+
+
 def _counter_rows(path, kernel_prefix):
     import csv
     vals = []
@@ -179,9 +190,9 @@ def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_c
     rocprofv3 counter CSVs of one bench step, each counter scaled by what it
     reads for the 1 GiB copy; written next to the kernel trace summaries."""
     import hashlib
-    prod = "void sfft::(anonymous namespace)::k_product<"
-    fetch = [v for v, n in zip(_counter_rows(fetch_csv, prod), _kernel_names(fetch_csv, prod)) if "false>" in n]
-    write = [v for v, n in zip(_counter_rows(write_csv, prod), _kernel_names(write_csv, prod)) if "false>" in n]
+    prod = "void sfft::(anonymous namespace)::k_product"
+    fetch = [v for v, n in zip(_counter_rows(fetch_csv, prod), _kernel_names(fetch_csv, prod)) if _is_gate_product(n)]
+    write = [v for v, n in zip(_counter_rows(write_csv, prod), _kernel_names(write_csv, prod)) if _is_gate_product(n)]
     # the run tunes the plan first: keep the product launches of the one
     # timed FFT, which come last (one per level)
     levels = _product_levels(workload)
@@ -238,7 +249,7 @@ def trace_summary(workload, db_path, steps):
     for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
         print("| %s | %d | %.1f | %.4f | %.4f | %.4f |" % (k, len(v), sum(v) / 1e6, sum(v) / len(v) / 1e6,
                                                         min(v) / 1e6, max(v) / 1e6))
-    prods = [d for name, d in rows if "k_product<" in name and "false>" in name]
+    prods = [d for name, d in rows if _is_gate_product(name)]
     timed = prods[-steps * _product_levels(workload):]
     print("\ntimed product launches: %d, average %.3f ms" % (len(timed), sum(timed) / len(timed) / 1e6))
 
@@ -339,7 +350,7 @@ def run_serve(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "i8",
         "data": "synthetic",
         "config": {"workload": "served_poisson", "requests": len(sigs), "mix": "1D 16..256 complex / 2D 8..32 real",
                    "F": 16, "f": 8, "n_lwe": 1, "rate_per_s": rate, "load": args.load,
@@ -404,7 +415,7 @@ def run_accuracy(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "i8",
         "data": "synthetic",
         "config": {"workload": "accuracy_q32.16", "lengths": "8..128", "signals_per_length": args.signals,
                    "inputs": "complex, real and imaginary parts uniform in [0,1)", "n_lwe": 1},
@@ -529,6 +540,22 @@ def main():
     bitmac_step = float(info.exec_products) * nct ** 3
     achieved = bitmac_step * args.steps / (kern_ms / 1e3)
     npts = sig.points
+    mfma = S.sfft_tiling_describe(info.tiling)[6] == 1
+    if mfma:
+        ops = achieved / 4.0  # int8 op/s of the algorithmic Nct^3 / 4 per product
+        roofline = {"bound": "mfma", "achieved": ops / 1e12, "peak": PEAK_MFMA_I8 / 1e12, "unit": "TOP/s",
+                    "frac": ops / PEAK_MFMA_I8, "dtype": "i8"}
+    else:
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LOOKUP / 1e12, "unit": "Tbitmac/s",
+                    "frac": achieved / PEAK_LOOKUP}
+    roofline.update({
+        "traffic": None,
+        "kernel": "k_product_mfma" if mfma else "k_product",
+        "launches": n_launch,
+        "avg_launch_ms": kern_ms / max(1, n_launch),
+        "bitmac_per_s": achieved,
+        "frac_vs_popcount_ceiling": achieved / PEAK_POPCOUNT,
+    })
     out = {
         "metric": "encrypted gates/s (1 GPU)",
         "value": info.gates / step_s,
@@ -540,7 +567,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        # products: bits of L times bytes of R in int8 (matrix cores) or
+        # 30-bit digits in u32 (lookup kernel); limb arithmetic in u32
+        "dtype": "i8" if mfma else "u32",
         "data": "synthetic",
         "config": {
             "workload": args.workload,
@@ -555,18 +584,7 @@ def main():
         "products_per_s": info.exec_products / step_s,
         "latency_p50_s": pct(lat, 50),
         "latency_p99_s": pct(lat, 99),
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_LOOKUP / 1e12,
-            "unit": "Tbitmac/s",
-            "frac": achieved / PEAK_LOOKUP,
-            "traffic": None,
-            "kernel": "k_product",
-            "launches": n_launch,
-            "avg_launch_ms": kern_ms / max(1, n_launch),
-            "frac_vs_popcount_ceiling": achieved / PEAK_POPCOUNT,
-        },
+        "roofline": roofline,
         "cpu_baseline": None,
     }
     # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
