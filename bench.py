@@ -84,7 +84,7 @@ def run_batch(args):
     from paper_1611_08769_amd import workloads as WL
 
     lengths = tuple(n for n in (8, 16, 32, 64, 128) if n <= args.max_len)
-    sigs = WL.batch_requests(seed=4, count=args.requests, lengths=lengths)
+    sigs = WL.batch_requests(seed=4, count=args.requests or 64, lengths=lengths)
     reqs, plans = [], {}
     for i, sig in enumerate(sigs):
         p = api.size_params(1, sig.length, sig.F, sig.f, True, 1)
@@ -272,7 +272,7 @@ def run_serve(args):
     from paper_1611_08769_amd import api
     from paper_1611_08769_amd import workloads as WL
 
-    sigs = WL.served_requests(seed=5, count=args.requests)
+    sigs = WL.served_requests(seed=5, count=args.requests or 40)
     plans = {}
     for sig in sigs:
         key = (sig.dims, sig.length)
@@ -426,14 +426,14 @@ def run_accuracy(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=64, help="batch mode: number of requests")
+    ap.add_argument("--requests", type=int, default=0, help="batch / serve mode: number of requests (64 / 40)")
     ap.add_argument("--max-active", type=int, default=0, help="batch mode: requests in flight (0 = no limit)")
     ap.add_argument("--budget-gb", type=float, default=0.0,
                     help="batch/serve: workspace memory budget (default 120 GB batch, 180 GB serve)")
     ap.add_argument("--max-len", type=int, default=128, help="batch mode: longest request length (8..128)")
     ap.add_argument("--rate", type=float, default=0.0, help="serve mode: arrivals per second (0 = from --load)")
     ap.add_argument("--load", type=float, default=0.7, help="serve mode: offered load as a fraction of capacity")
-    ap.add_argument("--rate-bitmac", type=float, default=1.3e15, help="serve mode: capacity in bit-MAC/s")
+    ap.add_argument("--rate-bitmac", type=float, default=2.0e15, help="serve mode: capacity in bit-MAC/s")
     ap.add_argument("--io-gb", type=float, default=60.0, help="serve mode: ciphertexts of requests in flight")
     ap.add_argument("--signals", type=int, default=4, help="accuracy mode: signals per length")
     ap.add_argument("--fill-blocks", type=int, default=-1,
