@@ -567,12 +567,14 @@ __device__ __forceinline__ i32x4 spread_bits(uint32_t u)
     return a;
 }
 
-// Output row `row`, element e, from its byte column sums S[0..4 kw) (LDS,
-// each missing 128 popcount), the row's popcount pc and its words of L and
-// R (LDS).  Output o's limb l replaces S[4 l + o] (the sums of limb l are
-// consumed first), for a coalesced write-out afterwards.
+// Output row `row`, element e, limbs [lb, le), from its byte column sums
+// S[0..4 kw) (LDS, each missing 128 popcount), the row's popcount pc and its
+// words of L and R (LDS), with carry-in 0.  Output o's limb l replaces
+// S[4 l + o] (the sums of limb l are consumed first), for a coalesced
+// write-out afterwards; the carry out of limb le - 1 goes to cy[o] (when cy
+// is given), for the next limbs' fix-up.
 __device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it, int32_t* S, int pc,
-                             const uint32_t* Lw, const uint32_t* Rw, int row, int e)
+                             const uint32_t* Lw, const uint32_t* Rw, int row, int e, int lb, int le, int32_t* cy)
 {
     const int br = row / g.k, tr = row % g.k;
     const size_t base = (size_t)row * g.W + (size_t)e * g.kw;
@@ -584,8 +586,8 @@ __device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it,
         carry[o] = 0;
         Ep[o] = o < it.nout && it.E[o] >= 0 ? ctp(bufs, it.E[o]) + base : nullptr;
     }
-    for (int l0 = 0; l0 < g.kw; l0 += 4) {
-        const int nl = g.kw - l0 < 4 ? g.kw - l0 : 4;
+    for (int l0 = lb; l0 < le; l0 += 4) {
+        const int nl = le - l0 < 4 ? le - l0 : 4;
         uint32_t Ev[kMaxOut][4];
 #pragma unroll
         for (int o = 0; o < kMaxOut; o++)
@@ -615,6 +617,10 @@ __device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it,
                 *s4p = out;
             }
         }
+    }
+    if (cy) {
+#pragma unroll
+        for (int o = 0; o < kMaxOut; o++) cy[o] = (int32_t)carry[o];  // |carry| < 2^15
     }
 }
 
@@ -662,11 +668,12 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     const int slab_bytes = 32 * (SP + 2 * LP) * 4;
     const int main_bytes = 2 * bsz + 2 * TM * KC;
     int spp = 1;
-    if ((main_bytes > 2 * slab_bytes ? main_bytes : 2 * slab_bytes) + TM * 4 <= lds_bytes) spp = 2;
+    if ((main_bytes > 2 * slab_bytes ? main_bytes : 2 * slab_bytes) + TM * 4 + THREADS * 16 <= lds_bytes) spp = 2;
     const int s_bytes = spp * slab_bytes;
     uint8_t* Bs = reinterpret_cast<uint8_t*>(lds);  // 2 chunks of R, column by column
     uint8_t* As = Bs + 2 * bsz;                     // 2 chunks of bits of L as 0/1 bytes, KC bytes per row
     int32_t* Pc = reinterpret_cast<int32_t*>(Bs + (main_bytes > s_bytes ? main_bytes : s_bytes));  // popcount per row
+    int32_t* Cy = Pc + TM;  // epilogue: carries out of chain runs, 4 per thread
 
     // staging block i of this thread: rows 4 jq .. 4 jq + 3 of the chunk,
     // words 4 wq .. 4 wq + 3 (one 16-byte load per row).  Within a wave 8
@@ -919,12 +926,41 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
             }
         }
         __syncthreads();
-        for (int tk = tid; tk < rows_p * g.n1; tk += THREADS) {
-            const int rl = tk % rows_p, e = tk / rows_p;
+        // the chains of the pass, each cut into G runs of limbs when that keeps
+        // more threads busy: run gs starts from carry 0 and records its carry
+        // out; then one thread per (row, element, output) ripples each run's
+        // carry into the next run (it stops at the first limb that absorbs it)
+        const int nchain = rows_p > 0 ? rows_p * g.n1 : 0;
+        int G = 1;
+        while (G < 4 && 2 * G * nchain <= THREADS && 2 * G <= g.kw) G *= 2;
+        const int run = (g.kw + G - 1) / G;
+        for (int tk = tid; tk < nchain * G; tk += THREADS) {
+            const int ch = tk % nchain, gs = tk / nchain;
+            const int rl = ch % rows_p, e = ch / rows_p;
+            const int lb = gs * run, le = lb + run < g.kw ? lb + run : g.kw;
             finish_bytes(bufs, g, it, S + rl * SP + e * 4 * g.kw, Pc[32 * p0 + rl], Le + rl * LP + e * g.kw,
-                         Re + rl * LP + e * g.kw, prow + rl, e);
+                         Re + rl * LP + e * g.kw, prow + rl, e, lb, le, G > 1 ? Cy + 4 * tk : nullptr);
         }
         __syncthreads();
+        if (G > 1) {
+            for (int tk = tid; tk < nchain * it.nout; tk += THREADS) {
+                const int ch = tk % nchain, o = tk / nchain;
+                const int rl = ch % rows_p, e = ch / rows_p;
+                int32_t* orow = S + rl * SP + e * 4 * g.kw + o;  // limb l of output o at orow[4 l]
+                int64_t c = 0;
+                for (int gs = 0; gs < G; gs++) {
+                    const int lb = gs * run, le = lb + run < g.kw ? lb + run : g.kw;
+                    if (lb >= le) break;
+                    for (int l = lb; l < le && c != 0; l++) {
+                        const int64_t v = (int64_t)(uint32_t)orow[4 * l] + c;
+                        orow[4 * l] = (int32_t)(uint32_t)v;
+                        c = v >> 32;
+                    }
+                    c += Cy[4 * (gs * nchain + ch) + o];
+                }
+            }
+            __syncthreads();
+        }
         gword* dst[kMaxOut];
 #pragma unroll
         for (int o = 0; o < kMaxOut; o++) dst[o] = o < it.nout ? ctp(bufs, it.dst[o]) + (size_t)prow * W : nullptr;
@@ -1149,7 +1185,7 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
     const int cap = cfg->threads >= 512 ? 160 * 1024 : 80 * 1024;
     const int chunks = 2 * nf * 32 * kMfmaPitch + 2 * cfg->tr * kMfmaChunk;
     const int slab = 32 * ((nf * 32 + 4) + 2 * (8 * ((g.W + 7) / 8) + 4)) * 4;
-    const int tail = cfg->tr * 4;
+    const int tail = cfg->tr * 4 + cfg->threads * 16;  // popcounts, chain-run carries
     const int spp = std::max(chunks, 2 * slab) + tail <= cap ? 2 : 1;
     cfg->lds_bytes = std::max(chunks, spp * slab) + tail;
     return cfg->lds_bytes <= 160 * 1024;
