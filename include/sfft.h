@@ -80,6 +80,9 @@ typedef struct {
     int32_t tiling;               /* product-kernel tiling the plan launches (sfft_tiling_describe) */
     int64_t prod_ct_reads;        /* ciphertexts the product items read: L, R and extra operands */
     int64_t prod_ct_writes;       /* ciphertexts the product items write (their outputs) */
+    int64_t ws_bytes;             /* workspace bytes sfft_execute needs (= sfft_plan_workspace_bytes):
+                                     ws_cts slots, then the matrix-core kernel's copies of one level's
+                                     right operands */
 } sfft_plan_info;
 
 const char* sfft_last_error(void);
@@ -180,8 +183,10 @@ int sfft_gate(const sfft_params* params, int32_t gate, const uint32_t* x_dev, co
 int sfft_tiling_count(void);
 /* fields[7]: fields[6] = 0 for a lookup tiling, then fields[0..5] = threads,
  * lanes per row, digit slots per lane, rows per lane, pipeline depth, groups
- * per chunk; fields[6] = 1 for a matrix-core tiling, then fields[0..3] =
- * threads, row groups, column groups, fragments per wave (fields[4..5] = 0).
+ * per chunk; fields[6] = 1 for a matrix-core tiling, then fields[0..4] =
+ * threads, row groups, column groups, fragments per wave, and 1 where the
+ * right operands are transposed into the workspace by a pass before each
+ * launch (0 where each workgroup transposes its chunks itself); fields[5] = 0.
  * SFFT_EINVAL for an unknown tiling. */
 int sfft_tiling_describe(int32_t tiling, int32_t* fields);
 /* Record a tiling for params' geometry (-1: back to the default).

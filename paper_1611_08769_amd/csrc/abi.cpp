@@ -199,6 +199,7 @@ int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* s
         in.n_inputs = c.n_inputs;
         in.n_outputs = (int64_t)c.outputs.size();
         in.ws_cts = sched->n_slots;
+        in.ws_bytes = sched->n_slots * ct_words(geo) * 4 + sched->max_level_products * rt_item_bytes(geo);
         in.exec_steps = (int64_t)sched->levels.size() + 1;
         in.k_required = choose_k(c, params->n_lwe);
         for (const ProdItem& it : sched->prods) {
@@ -401,7 +402,7 @@ int sfft_plan_info_get(const sfft_plan* plan, sfft_plan_info* info)
 int sfft_plan_workspace_bytes(const sfft_plan* plan, int64_t* bytes)
 {
     if (!plan || !bytes) return fail(SFFT_EINVAL, "null argument");
-    *bytes = plan->sched.n_slots * ct_words(plan->geo) * 4;
+    *bytes = plan->ws_bytes();
     return SFFT_OK;
 }
 
@@ -426,9 +427,10 @@ int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, cons
         if (st < (int32_t)S.levels.size()) {
             const LevelWork& lw = S.levels[st];
             if (lw.prod_count) {
-                const ProdSeg seg{plan->d_prods + lw.prod_begin, b, g, plan->cfg.nd, plan->cfg.wd, 0, 0};
+                const ProdSeg seg{plan->d_prods + lw.prod_begin, b, g, plan->cfg.nd, plan->cfg.wd, 0, 0,
+                                  (uint8_t*)ws_dev + plan->slot_bytes()};
                 hipError_t e = launch_products(plan->cfg, nullptr, 1, seg,
-                                               (int64_t)lw.prod_count * product_tiles(g, plan->cfg), s);
+                                               (int64_t)lw.prod_count * product_tiles(g, plan->cfg), lw.prod_count, s);
                 if (e != hipSuccess) return hip_fail(e, "product launch");
             }
             for (const auto& pass : lw.lin) {
@@ -466,8 +468,8 @@ int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
         plan->graph = nullptr;
         // set the kernel's LDS attribute outside the capture (a launch of
         // no workgroups does only that)
-        const ProdSeg none{nullptr, Bufs{}, plan->geo, plan->cfg.nd, plan->cfg.wd, 0, 0};
-        hipError_t e = launch_products(plan->cfg, nullptr, 1, none, 0, s);
+        const ProdSeg none{nullptr, Bufs{}, plan->geo, plan->cfg.nd, plan->cfg.wd, 0, 0, nullptr};
+        hipError_t e = launch_products(plan->cfg, nullptr, 1, none, 0, 0, s);
         if (e != hipSuccess) return hip_fail(e, "graph preparation");
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture");
@@ -588,7 +590,17 @@ int sfft_gate(const sfft_params* p, int32_t gate, const uint32_t* x_dev, const u
         case 6: it.cL[0] = 1; it.cR[0] = 1; it.cP[0] = -1; break;
         case 8: it.cP[0] = -1; it.cG[0] = 1; break;
         }
-        e = launch_product_one(b, g, cfg, it, s);
+        // the matrix-core kernel's chunk-layout copy of R, stream-ordered
+        void* rt = nullptr;
+        if (cfg.mfma && cfg.pre) {
+            e = hipMallocAsync(&rt, (size_t)rt_item_bytes(g), s);
+            if (e != hipSuccess) return hip_fail(e, "gate scratch");
+        }
+        e = launch_product_one(b, g, cfg, it, (uint8_t*)rt, s);
+        if (rt) {
+            const hipError_t ef = hipFreeAsync(rt, s);
+            if (e == hipSuccess) e = ef;
+        }
     }
     if (e != hipSuccess) return hip_fail(e, "gate launch");
     return SFFT_OK;

@@ -40,6 +40,7 @@ struct ProdCfg {
     // fragments per wave
     bool mfma;
     int rg, cgw, cf;
+    bool pre;  // right operands transposed into rt by a pass before the launch
 };
 
 // Passed to the kernel by value.
@@ -52,7 +53,7 @@ struct KCfg {
 // The kernels' tilings: how many, and the 7 fields of one: for the lookup
 // kernel (threads, lanes per row, digit slots per lane, rows per lane,
 // pipeline depth, groups per chunk, 0), for the matrix-core kernel (threads,
-// row groups, column groups, fragments per wave, 0, 0, 1).
+// row groups, column groups, fragments per wave, transposition pass, 0, 1).
 int tiling_count();
 void tiling_fields(int ti, int* fields7);
 // cfg for tiling ti on geometry g; false if ti cannot serve g (too few digit
@@ -81,7 +82,21 @@ struct ProdSeg {
     int32_t nd, wd;
     uint32_t first;
     uint32_t first_block;
+    // matrix-core tilings: scratch for the segment's right operands in chunk
+    // layout, rt_item_bytes(geo) per item (item i at rt + i * rt_item_bytes)
+    uint8_t* rt;
 };
+
+// Bytes of one right operand in the matrix-core kernel's chunk layout:
+// ceil(Nct/128) chunks of NF = ceil(4 W / 32) fragments x 32 columns x 128
+// rows, one byte each.  0 where no matrix-core tiling serves the geometry
+// (rows of more than 12 fragments).
+__host__ __device__ inline int64_t rt_item_bytes(const Geo& g)
+{
+    const int64_t nf = (4 * (int64_t)g.W + 31) / 32;
+    if (nf > 12) return 0;
+    return ((int64_t)g.nct + 127) / 128 * nf * 32 * 128;
+}
 struct LinSeg {
     const LinItem* items;
     Bufs bufs;
@@ -94,13 +109,15 @@ struct LinSeg {
 inline int product_tiles(const Geo& g, const ProdCfg& cfg) { return (g.nct + cfg.tr - 1) / cfg.tr; }
 
 // One launch over `blocks` workgroups (the sum over the segments of items x
-// product_tiles) in nseg segments: d_segs in device memory when nseg > 1,
-// else seg0 (by value).  cfg is the tiling shared by the segments with
-// lds_bytes the largest any of them needs.
+// product_tiles) in nseg segments of `items` items in all: d_segs in device
+// memory when nseg > 1, else seg0 (by value).  cfg is the tiling shared by
+// the segments with lds_bytes the largest any of them needs.  Under a
+// matrix-core tiling a transposition launch first fills each segment's rt.
 hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                           int64_t blocks, hipStream_t s);
-// One product item passed by value (single gates).
-hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item,
+                           int64_t blocks, int64_t items, hipStream_t s);
+// One product item passed by value (single gates); rt as in ProdSeg (one
+// item's worth, used under a matrix-core tiling).
+hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, uint8_t* rt,
                               hipStream_t s);
 // Linear items; max_elems = the largest Nct * (n+1) among the segments.
 hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,

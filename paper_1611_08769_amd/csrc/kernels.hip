@@ -624,7 +624,82 @@ __device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it,
     }
 }
 
-template <int RG, int CG, int CF>
+// Right operands of a launch's items into the matrix-core kernel's chunk
+// layout, once per item instead of once per row tile: workgroup (y, c)
+// loads chunk c (128 rows) of item y's R with 16-byte row loads (8 lanes per
+// 128 contiguous bytes), transposes 4x4 byte blocks in registers (v_perm),
+// stores them column by column into LDS (bytes xor 0x80, 16-byte units of a
+// column XOR-swizzled) and copies the chunk out with 16-byte stores.
+constexpr int kRtransThreads = 256;
+__global__ void __launch_bounds__(kRtransThreads) k_rtrans(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
+                                                           ProdItem one)
+{
+    constexpr int THREADS = kRtransThreads;
+    constexpr int KC = kMfmaChunk;
+    constexpr int BP = kMfmaPitch;
+    constexpr int SPT = (KC / 4 * 24 + THREADS - 1) / THREADS;  // 32 row quads x up to 24 word quads (W <= 96)
+    extern __shared__ uint32_t lds[];
+    uint8_t* Ts = reinterpret_cast<uint8_t*>(lds);
+    const uint32_t y = blockIdx.x;  // item within the launch
+    ProdSeg sg = seg0;
+    if (nseg > 1) sg = segs[find_segment(segs, nseg, y, [](const ProdSeg& q) { return q.first; })];
+    const Geo g = sg.geo;
+    const int c = blockIdx.y, W = g.W, nct = g.nct;
+    if (KC * c >= nct) return;  // chunks past this item's rows
+    const uint32_t yl = y - sg.first;
+    const ProdItem it = sg.items ? load_global(sg.items + yl) : one;
+    const gword* src = ctp(sg.bufs, it.R) + (size_t)(KC * c) * W;
+    const int NF = (4 * W + 31) / 32, bsz = NF * 32 * BP;
+    const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
+    const bool quads = (W & 3) == 0;
+    const int tid = threadIdx.x;
+    // block i of this thread: rows 4 jq .. 4 jq + 3, words 4 wq .. 4 wq + 3;
+    // within a wave 8 consecutive wq (128 bytes of a row) times 8 consecutive jq
+    uint32_t rs[SPT][4][4];
+#pragma unroll
+    for (int i = 0; i < SPT; i++) {
+        const int t = tid + i * THREADS, r = t >> 6;
+        const int jq = ((t >> 3) & 7) + 8 * (r & 3), wq = (t & 7) + 8 * (r >> 2);
+        const bool ok = 4 * wq < W && 4 * jq < rows_c;
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const gword* p = src + (size_t)(4 * jq + rr) * W + 4 * wq;
+            if (ok && quads) {
+                const u32x4 x = *reinterpret_cast<const gu32x4*>(p);
+                rs[i][rr][0] = x[0], rs[i][rr][1] = x[1], rs[i][rr][2] = x[2], rs[i][rr][3] = x[3];
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; u++) rs[i][rr][u] = ok && 4 * wq + u < W ? p[u] : 0u;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < SPT; i++) {
+        const int t = tid + i * THREADS, r = t >> 6;
+        const int jq = ((t >> 3) & 7) + 8 * (r & 3), wq = (t & 7) + 8 * (r >> 2);
+        if (4 * wq < W && 4 * jq < rows_c) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t blk[4] = {rs[i][0][u], rs[i][1][u], rs[i][2][u], rs[i][3][u]};
+                uint32_t col[4];
+                transpose4x4(blk, col);
+#pragma unroll
+                for (int cc = 0; cc < 4; cc++) {
+                    const int n = 16 * wq + 4 * u + cc;
+                    // columns past the row (a partial last unit) are never read
+                    *reinterpret_cast<uint32_t*>(Ts + n * BP + 16 * ((jq >> 2) ^ mfma_swz(n)) + 4 * (jq & 3)) =
+                        col[cc] ^ 0x80808080u;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint8_t* dst = sg.rt + (size_t)yl * rt_item_bytes(g) + (size_t)c * bsz;
+    for (int u = tid; 16 * u < bsz; u += THREADS)
+        *(gu32x4*)(dst + 16 * u) = *reinterpret_cast<const u32x4*>(Ts + 16 * u);
+}
+
+template <int RG, int CG, int CF, bool PRE>
 __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __restrict__ segs, int nseg,
                                                                ProdSeg seg0, ProdItem one, int lds_bytes)
 {
@@ -632,7 +707,11 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     constexpr int TM = 64 * RG;
     constexpr int KC = kMfmaChunk;
     constexpr int BP = kMfmaPitch;
-    constexpr int SPT = (KC / 4 * 2 * CG * CF + THREADS - 1) / THREADS;  // staged 4-row x 16-byte blocks per thread
+    // staging of R per thread: PRE, 16-byte units of a chunk already in chunk
+    // layout; else 4-row x 16-byte blocks transposed here (W <= 8 CG CF)
+    constexpr int SPT_C = (32 * CG * CF * KC / 16 + THREADS - 1) / THREADS;
+    constexpr int SPT_T = (KC / 4 * 2 * CG * CF + THREADS - 1) / THREADS;
+    constexpr int SPT = PRE ? SPT_C : SPT_T;
     constexpr int APT = (TM * (KC / 32) + THREADS - 1) / THREADS;        // staged words of L per thread
     constexpr int EPT = (64 * 8 * CG * CF / 4 + THREADS - 1) / THREADS;  // epilogue 16-byte loads per operand
     constexpr int NP = SPT < KC / 32 ? SPT : KC / 32;                     // staging parts per chunk
@@ -675,11 +754,28 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     int32_t* Pc = reinterpret_cast<int32_t*>(Bs + (main_bytes > s_bytes ? main_bytes : s_bytes));  // popcount per row
     int32_t* Cy = Pc + TM;  // epilogue: carries out of chain runs, 4 per thread
 
+    // Staging of R.  PRE: R comes already in chunk layout (k_rtrans), and
+    // staging chunk c copies its bsz bytes, 16 per thread and unit, into
+    // LDS.  Else each thread transposes 4x4 byte blocks of the raw rows here.
+    // Loads and staging go in NP parts (part p: the units or blocks i with
+    // i % NP == p); part p of chunk c + 1 is staged, and its registers
+    // refilled with chunk c + 2, after a matrix step of chunk c, so that
+    // every load has a whole chunk to arrive.
+    const uint8_t* rtp = PRE ? sg.rt + (size_t)yl * rt_item_bytes(g) : nullptr;
+    u32x4 rc[SPT_C];
+    auto load_R_c = [&](int c, int part) {
+        const uint8_t* src = rtp + (size_t)c * bsz;
+#pragma unroll
+        for (int i = 0; i < SPT_C; i++) {
+            if (part >= 0 && i % NP != part) continue;
+            const int u = tid + i * THREADS;
+            if (16 * u < bsz) rc[i] = *(const gu32x4*)(src + 16 * u);
+        }
+    };
     // staging block i of this thread: rows 4 jq .. 4 jq + 3 of the chunk,
     // words 4 wq .. 4 wq + 3 (one 16-byte load per row).  Within a wave 8
     // consecutive wq (128 bytes of a row) times 8 consecutive jq.
-    uint32_t rs[SPT][4][4];
-    uint32_t as[APT];
+    uint32_t rs[SPT_T][4][4];
     auto block_of = [&](int i, int& jq, int& wq) {
         const int t = tid + i * THREADS, r = t >> 6;
         jq = ((t >> 3) & 7) + 8 * (r & 3);
@@ -689,11 +785,11 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     // p); part p of chunk c + 1 is staged, and its registers refilled with
     // chunk c + 2, after matrix step kPartStep[p] of chunk c, so that every
     // load has a whole chunk to arrive
-    auto load_R = [&](int c, int part) {
+    auto load_R_t = [&](int c, int part) {
         const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
         const gword* src = Rp + (size_t)(KC * c) * W;
 #pragma unroll
-        for (int i = 0; i < SPT; i++) {
+        for (int i = 0; i < SPT_T; i++) {
             if (part >= 0 && i % NP != part) continue;
             int jq, wq;
             block_of(i, jq, wq);
@@ -711,6 +807,11 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
             }
         }
     };
+    uint32_t as[APT];
+    auto load_R = [&](int c, int part) {
+        if constexpr (PRE) load_R_c(c, part);
+        else load_R_t(c, part);
+    };
     // words of L: row a / (KC/32) of the tile, word a % (KC/32) of the chunk
     auto load_L = [&](int c) {
         const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
@@ -721,11 +822,20 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
             as[i] = ok ? Lp[(size_t)(row_base + r) * W + (KC / 32) * c + wq] : 0u;
         }
     };
-    auto stage_R = [&](int c, int part) {
+    auto stage_R_c = [&](int c, int part) {
+        uint8_t* dst = Bs + (c & 1) * bsz;
+#pragma unroll
+        for (int i = 0; i < SPT_C; i++) {
+            if (part >= 0 && i % NP != part) continue;
+            const int u = tid + i * THREADS;
+            if (16 * u < bsz) *reinterpret_cast<u32x4*>(dst + 16 * u) = rc[i];
+        }
+    };
+    auto stage_R_t = [&](int c, int part) {
         const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
         uint8_t* dst = Bs + (c & 1) * bsz;
 #pragma unroll
-        for (int i = 0; i < SPT; i++) {
+        for (int i = 0; i < SPT_T; i++) {
             if (part >= 0 && i % NP != part) continue;
             int jq, wq;
             block_of(i, jq, wq);
@@ -745,6 +855,10 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
                 }
             }
         }
+    };
+    auto stage_R = [&](int c, int part) {
+        if constexpr (PRE) stage_R_c(c, part);
+        else stage_R_t(c, part);
     };
     // the chunk's bits of L as bytes: word s of row r gives units 2 s and
     // 2 s + 1 (its two halves) of the row, XOR-swizzled by row like the
@@ -1022,20 +1136,20 @@ hipError_t launch_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const P
     return hipGetLastError();
 }
 
-template <int RG, int CG, int CF>
+template <int RG, int CG, int CF, bool PRE>
 hipError_t launch_mfma_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
                          const ProdItem& one, int64_t blocks, hipStream_t s)
 {
     static int attr_bytes = 64 * 1024;
     if (cfg.lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_product_mfma<RG, CG, CF>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_product_mfma<RG, CG, CF, PRE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, cfg.lds_bytes);
         if (e != hipSuccess) return e;
         attr_bytes = cfg.lds_bytes;
     }
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_product_mfma<RG, CG, CF>), dim3((unsigned)blocks), dim3(RG * CG * 64), cfg.lds_bytes, s,
+    hipLaunchKernelGGL((k_product_mfma<RG, CG, CF, PRE>), dim3((unsigned)blocks), dim3(RG * CG * 64), cfg.lds_bytes, s,
                        d_segs, nseg, seg0, one, cfg.lds_bytes);
     return hipGetLastError();
 }
@@ -1071,11 +1185,15 @@ constexpr int kDefaultTilings = 5;
 // group CF of them (the last fewer).
 struct MfmaTiling {
     int rg, cgw, cf;
+    bool pre;  // right operands transposed by k_rtrans before the launch
 };
 constexpr MfmaTiling kMfmaTilings[] = {
-    {2, 4, 1}, {2, 4, 2}, {2, 4, 3},                        // 512 threads, 128-row tiles
-    {2, 2, 1}, {2, 2, 2}, {2, 2, 3}, {2, 2, 4}, {2, 2, 5}, {2, 2, 6},  // 256 threads, 128-row tiles
-    {4, 2, 2}, {4, 2, 3}, {4, 2, 4},                        // 512 threads, 256-row tiles
+    {2, 4, 1, false}, {2, 4, 2, false}, {2, 4, 3, false},  // 512 threads, 128-row tiles
+    {2, 2, 1, false}, {2, 2, 2, false}, {2, 2, 3, false},  // 256 threads, 128-row tiles
+    {2, 2, 4, false}, {2, 2, 5, false}, {2, 2, 6, false},
+    {4, 2, 2, false}, {4, 2, 3, false}, {4, 2, 4, false},  // 512 threads, 256-row tiles
+    {2, 4, 1, true},  {2, 4, 2, true},  {2, 4, 3, true},   // the same with a transposition pass
+    {4, 2, 2, true},  {4, 2, 3, true},  {4, 2, 4, true},
 };
 constexpr int kNumMfmaTilings = (int)(sizeof(kMfmaTilings) / sizeof(kMfmaTilings[0]));
 constexpr int kNumTilings = kNumLookupTilings + kNumMfmaTilings;
@@ -1085,8 +1203,8 @@ hipError_t dispatch_mfma(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
 {
 #define MCASE(I)                                                                                         \
     if (cfg.tiling == kNumLookupTilings + I)                                                             \
-        return launch_mfma_t<kMfmaTilings[I].rg, kMfmaTilings[I].cgw, kMfmaTilings[I].cf>(cfg, d_segs, nseg, \
-                                                                                           seg0, one, blocks, s);
+        return launch_mfma_t<kMfmaTilings[I].rg, kMfmaTilings[I].cgw, kMfmaTilings[I].cf, kMfmaTilings[I].pre>( \
+            cfg, d_segs, nseg, seg0, one, blocks, s);
     MCASE(0)
     MCASE(1)
     MCASE(2)
@@ -1099,8 +1217,14 @@ hipError_t dispatch_mfma(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
     MCASE(9)
     MCASE(10)
     MCASE(11)
+    MCASE(12)
+    MCASE(13)
+    MCASE(14)
+    MCASE(15)
+    MCASE(16)
+    MCASE(17)
 #undef MCASE
-    static_assert(kNumMfmaTilings == 12, "one MCASE per matrix-core tiling");
+    static_assert(kNumMfmaTilings == 18, "one MCASE per matrix-core tiling");
     return hipErrorInvalidValue;
 }
 
@@ -1151,7 +1275,7 @@ void tiling_fields(int ti, int* f)
 {
     if (ti >= kNumLookupTilings) {
         const MfmaTiling& t = kMfmaTilings[ti - kNumLookupTilings];
-        f[0] = t.rg * t.cgw * 64, f[1] = t.rg, f[2] = t.cgw, f[3] = t.cf, f[4] = 0, f[5] = 0, f[6] = 1;
+        f[0] = t.rg * t.cgw * 64, f[1] = t.rg, f[2] = t.cgw, f[3] = t.cf, f[4] = t.pre, f[5] = 0, f[6] = 1;
         return;
     }
     const Tiling& t = kTilings[ti];
@@ -1176,6 +1300,7 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
     cfg->rg = t.rg;
     cfg->cgw = t.cgw;
     cfg->cf = t.cf;
+    cfg->pre = t.pre;
     cfg->tr = 64 * t.rg;
     cfg->nd = (g.k + kDigitBits - 1) / kDigitBits;
     cfg->wd = g.n1 * cfg->nd;
@@ -1257,16 +1382,50 @@ bool lookup_config(const Geo& g, ProdCfg* cfg)
     return false;
 }
 
+namespace {
+// the transposition of a launch's right operands (matrix-core tilings)
+hipError_t launch_rtrans(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                         const ProdItem& one, int64_t items, hipStream_t s)
+{
+    constexpr int kMaxChunkBytes = 12 * 32 * kMfmaChunk;  // rows of up to 12 fragments
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_rtrans, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kMaxChunkBytes);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (items <= 0) return hipSuccess;
+    if (items > 0x7FFFFFFF) return hipErrorInvalidValue;
+    // chunks of the widest row the tiling serves (Nct = 32 W <= 256 CG CF)
+    const unsigned chunks = (unsigned)((256 * cfg.cgw * cfg.cf + kMfmaChunk - 1) / kMfmaChunk);
+    hipLaunchKernelGGL(k_rtrans, dim3((unsigned)items, chunks), dim3(kRtransThreads), kMaxChunkBytes, s, d_segs, nseg,
+                       seg0, one);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                           int64_t blocks, hipStream_t s)
+                           int64_t blocks, int64_t items, hipStream_t s)
 {
     ProdItem none{};
+    if (cfg.mfma && cfg.pre) {
+        hipError_t e = launch_rtrans(cfg, d_segs, nseg, seg0, none, blocks > 0 ? items : 0, s);
+        if (e != hipSuccess) return e;
+    }
     return dispatch<false>(cfg, d_segs, nseg, seg0, none, blocks, 0, 0, nullptr, s);
 }
 
-hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, hipStream_t s)
+hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, uint8_t* rt,
+                              hipStream_t s)
 {
-    return dispatch<false>(cfg, nullptr, 1, single_segment(b, g, cfg), item, product_tiles(g, cfg), 0, 0, nullptr, s);
+    ProdSeg seg = single_segment(b, g, cfg);
+    seg.rt = rt;
+    if (cfg.mfma && cfg.pre) {
+        hipError_t e = launch_rtrans(cfg, nullptr, 1, seg, item, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    return dispatch<false>(cfg, nullptr, 1, seg, item, product_tiles(g, cfg), 0, 0, nullptr, s);
 }
 
 hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,

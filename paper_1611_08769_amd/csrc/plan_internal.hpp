@@ -34,7 +34,11 @@ struct PlanCore {
     const void* graph_ws = nullptr;
 
     int64_t ct_words() const { return (int64_t)geo.nct * geo.W; }
-    int64_t ws_bytes() const { return sched.n_slots * ct_words() * 4; }
+    // workspace: the slots, then (where a matrix-core tiling serves the
+    // geometry) the chunk-layout copies of one level's right operands
+    int64_t slot_bytes() const { return sched.n_slots * ct_words() * 4; }
+    int64_t rt_bytes() const { return sched.max_level_products * rt_item_bytes(geo); }
+    int64_t ws_bytes() const { return slot_bytes() + rt_bytes(); }
     PlanCore() = default;
     PlanCore(const PlanCore&) = delete;
     PlanCore& operator=(const PlanCore&) = delete;

@@ -311,7 +311,8 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
                 if (G.segs.empty()) G.cfg = pc.cfg;
                 G.cfg.lds_bytes = std::max(G.cfg.lds_bytes, pc.cfg.lds_bytes);
                 G.segs.push_back(ProdSeg{pc.d_prods + lw.prod_begin, b, pc.geo, pc.cfg.nd, pc.cfg.wd,
-                                         (uint32_t)lw.prod_count, (uint32_t)product_tiles(pc.geo, pc.cfg)});
+                                         (uint32_t)lw.prod_count, (uint32_t)product_tiles(pc.geo, pc.cfg),
+                                         sv->dry ? nullptr : sv->arena_dev + r->ws_off + pc.slot_bytes()});
                 sv->st.products += lw.prod_count;
                 model_s += (double)lw.prod_count * (double)pc.geo.nct * pc.geo.nct * pc.geo.nct;
             }
@@ -364,7 +365,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         for (auto& kv : pgroups) {
             const ProdGroup& G = kv.second;
             e = launch_products(G.cfg, (const ProdSeg*)((uint8_t*)sv->seg_dev + p_at[gi++]), (int)G.segs.size(),
-                                G.segs[0], G.blocks, s);
+                                G.segs[0], G.blocks, G.n, s);
             if (e != hipSuccess) return sfft_hip_fail(e, "server product launch");
             sv->st.launches++;
         }

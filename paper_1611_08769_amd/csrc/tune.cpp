@@ -92,10 +92,11 @@ int sfft_tune(const sfft_params* params, int32_t reps, int32_t* best_tiling, dou
     int64_t items = (8 * 512 + product_tiles(g, def) - 1) / product_tiles(g, def);
     if (items < 16) items = 16;
     while (items > 16 && (size_t)(2 * items) * ct_bytes > ((size_t)3 << 30)) items /= 2;
-    DevBuf d_pool, d_out, d_items;
+    DevBuf d_pool, d_out, d_items, d_rt;
     hipError_t e = hipMalloc(&d_pool.p, pool * ct_bytes);
     if (e == hipSuccess) e = hipMalloc(&d_out.p, 2 * items * ct_bytes);
     if (e == hipSuccess) e = hipMalloc(&d_items.p, items * sizeof(ProdItem));
+    if (e == hipSuccess && rt_item_bytes(g) > 0) e = hipMalloc(&d_rt.p, (size_t)items * rt_item_bytes(g));
     if (e != hipSuccess) return sfft_hip_fail(e, "tuner buffers");
     {
         std::vector<uint32_t> host((size_t)pool * words);
@@ -131,11 +132,11 @@ int sfft_tune(const sfft_params* params, int32_t reps, int32_t* best_tiling, dou
         if (rates) rates[ti] = 0;
         ProdCfg cfg;
         if (!tiling_config(g, ti, &cfg)) continue;
-        const ProdSeg seg{(const ProdItem*)d_items.p, b, g, cfg.nd, cfg.wd, 0, 0};
+        const ProdSeg seg{(const ProdItem*)d_items.p, b, g, cfg.nd, cfg.wd, 0, 0, (uint8_t*)d_rt.p};
         const int64_t blocks = items * product_tiles(g, cfg);
-        e = launch_products(cfg, nullptr, 1, seg, blocks, s);  // warm-up
+        e = launch_products(cfg, nullptr, 1, seg, blocks, items, s);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(t0, s);
-        for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_products(cfg, nullptr, 1, seg, blocks, s);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_products(cfg, nullptr, 1, seg, blocks, items, s);
         if (e == hipSuccess) e = hipEventRecord(t1, s);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
         float ms = 0;
@@ -190,11 +191,12 @@ int sfft_plan_tune(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_
     for (int ti = 0; ti < nt; ti++) {
         ProdCfg cfg;
         if (!tiling_config(g, ti, &cfg)) continue;
-        const ProdSeg seg{pc->d_prods + S.levels[lv].prod_begin, b, g, cfg.nd, cfg.wd, 0, 0};
+        const ProdSeg seg{pc->d_prods + S.levels[lv].prod_begin, b, g, cfg.nd, cfg.wd, 0, 0,
+                          (uint8_t*)ws_dev + pc->slot_bytes()};
         const int64_t blocks = most * product_tiles(g, cfg);
-        hipError_t e = launch_products(cfg, nullptr, 1, seg, blocks, s);  // warm-up
+        hipError_t e = launch_products(cfg, nullptr, 1, seg, blocks, most, s);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(t0, s);
-        for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_products(cfg, nullptr, 1, seg, blocks, s);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_products(cfg, nullptr, 1, seg, blocks, most, s);
         if (e == hipSuccess) e = hipEventRecord(t1, s);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
         float ms = 0;

@@ -36,7 +36,7 @@ class sfft_plan_info(ctypes.Structure):
                 ("n_outputs", ctypes.c_int64), ("ws_cts", ctypes.c_int64), ("exec_steps", ctypes.c_int64),
                 ("k_required", ctypes.c_int32),
                 ("netlist_sha256", ctypes.c_char * 65), ("tiling", ctypes.c_int32),
-                ("prod_ct_reads", ctypes.c_int64), ("prod_ct_writes", ctypes.c_int64)]
+                ("prod_ct_reads", ctypes.c_int64), ("prod_ct_writes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64)]
 
 
 SFFT_SERVER_DRYRUN = 1

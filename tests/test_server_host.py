@@ -15,7 +15,8 @@ def _plan_info(sh):
 
 
 def _ws_bytes(info, p):
-    return info.ws_cts * S.sfft_ct_bytes(p)
+    assert info.ws_bytes >= info.ws_cts * S.sfft_ct_bytes(p)
+    return info.ws_bytes
 
 
 def test_all_requests_complete_and_products_add_up():
