@@ -7,16 +7,40 @@ import pytest
 import torch
 
 from paper_1611_08769_amd import api
+from paper_1611_08769_amd import sfft as S
 from paper_1611_08769_amd import workloads as WL
 
 pytestmark = pytest.mark.gpu
 
 
-def test_graph_replays_equal_eager():
-    print("[gpu-case] graph replay fft1d_n8_real_q8.4", flush=True)
+def _pre_tiling(p):
+    for ti in range(S.sfft_tiling_count()):
+        f = S.sfft_tiling_describe(ti)
+        if f[6] == 1 and f[4] == 1:
+            try:
+                api.set_tiling(p, ti)
+                return ti
+            except S.SfftError:
+                continue
+    return None
+
+
+@pytest.mark.parametrize("pre", [False, True])
+def test_graph_replays_equal_eager(pre):
+    print("[gpu-case] graph replay fft1d_n8_real_q8.4 pre=%d" % pre, flush=True)
     sys.stdout.flush()
     sig, n, seed = WL.workload("fft1d_n8_real_q8.4")
     p = api.size_params(1, 8, 8, 4, False, n)
+    if pre:
+        # the captured sequence includes the transposition launches
+        assert _pre_tiling(p) is not None
+    try:
+        _replays(sig, p, seed)
+    finally:
+        api.set_tiling(p, -1)
+
+
+def _replays(sig, p, seed):
     keys = api.keygen(p, seed)
     ct_in = api.encrypt_words(keys, api.signal_words(sig), 8, seed=seed)
     plan = api.Plan(1, 8, 8, 4, False, p)

@@ -12,6 +12,7 @@ from oracle import fixedpoint as fx
 from oracle import gsw
 from oracle import netlist as N
 from paper_1611_08769_amd import api
+from paper_1611_08769_amd import sfft as S
 from paper_1611_08769_amd import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -47,10 +48,38 @@ def _emulate(sh, sig):
     return np.stack([er.ravel(), ei.ravel()], 1).ravel()
 
 
-@pytest.mark.parametrize("staggered", [False, True])
-def test_batched_equals_alone(staggered):
-    say("server mix staggered=%d" % staggered)
+def _pre_tiling(p):
+    """A matrix-core tiling with the transposition pass that serves p, or None."""
+    for ti in range(S.sfft_tiling_count()):
+        f = S.sfft_tiling_describe(ti)
+        if f[6] == 1 and f[4] == 1:
+            try:
+                api.set_tiling(p, ti)
+                return ti
+            except S.SfftError:
+                continue
+    return None
+
+
+@pytest.mark.parametrize("staggered,pre", [(False, False), (True, False), (False, True)])
+def test_batched_equals_alone(staggered, pre):
+    say("server mix staggered=%d pre=%d" % (staggered, pre))
     reqs = [_request(i, sh) for i, sh in enumerate(MIX)]
+    if pre:
+        # every geometry of the mix on a transposition-pass tiling: merged
+        # launches transpose each request's right operands into its own
+        # workspace scratch
+        for r in reqs:
+            assert _pre_tiling(r[1]) is not None
+    try:
+        _batched_equals_alone(staggered, reqs)
+    finally:
+        if pre:
+            for r in reqs:
+                api.set_tiling(r[1], -1)
+
+
+def _batched_equals_alone(staggered, reqs):
     outs_mix, outs_alone, tickets = [], [], []
     srv = api.Server(8 << 30)
     plans = []
