@@ -1367,9 +1367,11 @@ bool product_config(const Geo& g, ProdCfg* cfg)
         auto it = g_tuned.find({g.k, g.n1});
         if (it != g_tuned.end() && tiling_config(g, it->second, cfg)) return true;
     }
-    // matrix cores first: two column groups while they have two fragments
-    // or fewer each, four after that
-    static const int order[] = {3, 4, 0, 1, 2};
+    // matrix cores first (the plan tuner's choices on the workloads here):
+    // rows of up to 2 fragments on 256 threads, 3..8 on 256-row tiles with
+    // the transposition pass, 9..12 on four column groups transposing
+    // in-kernel
+    static const int order[] = {3, 15, 16, 17, 4, 0, 1, 2};
     for (int i : order)
         if (tiling_config(g, kNumLookupTilings + i, cfg)) return true;
     return lookup_config(g, cfg);
