@@ -56,23 +56,42 @@ def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
     L = rng.integers(0, 2**32, p.dims(), dtype=np.uint64).astype(np.uint32)
     R = rng.integers(0, 2**32, p.dims(), dtype=np.uint64).astype(np.uint32)
     gsw.product(p, L, R)  # warm the library and page in
-    n, t0 = 0, time.perf_counter()
-    while True:
-        gsw.product(p, L, R)
-        n += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s and n >= 2:
-            break
-    per_product = dt / n
-    fft_s = per_product * canon_products
+
+    def per_product(budget):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            gsw.product(p, L, R)
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget and n >= 2:
+                return dt / n, n
+
+    threads = int(gsw.lib().or_threads())
+    t_all, n_all = per_product(budget_s)
+    gsw.lib().or_set_threads(1)
+    try:
+        t_one, n_one = per_product(budget_s / 2)
+    finally:
+        gsw.lib().or_set_threads(threads)
+    fft_s = t_all * canon_products
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": gates / fft_s,
         "unit": "gates/s",
-        "cores": int(gsw.lib().or_threads()),
+        "cores": threads,
         "kind": "oracle",
         "sample": "%d oracle products at Nct=%d (n+1=%d, k=%d), %.2f ms each; one FFT = %d canonical products "
-                  "-> %.0f s per FFT" % (n, nct, n1, 32 * kw, per_product * 1e3, canon_products, fft_s),
-        "bitmac_per_s": nct ** 3 / per_product,
+                  "-> %.0f s per FFT" % (n_all, nct, n1, 32 * kw, t_all * 1e3, canon_products, fft_s),
+        "bitmac_per_s": nct ** 3 / t_all,
+        "value_1_core": gates / (t_one * canon_products),
+        "bitmac_per_s_1_core": nct ** 3 / t_one,
+        "sample_1_core": "%d oracle products on 1 thread, %.2f ms each" % (n_one, t_one * 1e3),
+        "cpu": model,
     }
 
 

@@ -57,6 +57,8 @@ def lib():
         u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
         L.or_threads.restype = ctypes.c_int
         L.or_threads.argtypes = []
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_word.restype = ctypes.c_uint64
         L.or_word.argtypes = [ctypes.c_uint64] * 3
         L.or_words.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, u64p]

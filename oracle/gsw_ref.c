@@ -33,8 +33,10 @@
 
 #define GAMMA 0x9E3779B97F4A7C15ULL
 
-/* OpenMP threads the oracle's parallel loops use. */
+/* OpenMP threads the oracle's parallel loops use (and a setter, for timing
+   the oracle on one core). */
 int or_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int n) { omp_set_num_threads(n); }
 
 /* SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014). */
 static uint64_t sm_mix(uint64_t z)
