@@ -1,0 +1,171 @@
+/*
+ * Oracle: ring-GSW ciphertext arithmetic over R_p = Z_p[X]/(X^d + 1) in plain C.
+ * TEST INFRASTRUCTURE ONLY: only tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this file's library.  It shares no code with the
+ * HIP path.
+ *
+ * The paper evaluates its circuits with the GSW13 scheme (section "Notation
+ * and Background"): ciphertexts are matrices, the product of two ciphertexts
+ * is a matrix product after bit decomposition, and NAND, AND, XOR and OR are
+ * affine in that product (Lemma "binary gates").  GSW13 also has a ring
+ * instantiation, in which the matrix entries are polynomials of R_p.  This
+ * file is that instantiation, written from its definition:
+ *
+ *   v = (1, -s),  s in R_p small;  ell = bit length of p;  N = 2*ell rows
+ *   G = I_2 (x) (1, 2, 4, ..., 2^(ell-1))^T              (N x 2 over R_p)
+ *   Enc(m)   C = m*G + Z,  row r of Z = (a_r*s + e_r, a_r)  so  Z*v = e
+ *   G^-1(C)  the N x N matrix of binary polynomials with G^-1(C)*G = C:
+ *            entry (i, c*ell + j) holds bit j of every coefficient of C[i][c]
+ *   product  P = G^-1(L) * R                              (N x 2 over R_p)
+ *   AND = P,  XOR = L + R - 2P,  OR = L + R - P,  NAND = G - P,  NOT = G - L,
+ *   XADD = L + R
+ *   Dec      phase of row ell-1: (C*v)[ell-1] = m*2^(ell-1) + e; coefficient 0
+ *            decides m (|centred value| > p/4 reads 1)
+ *
+ * Polynomial products are computed by the definition of the negacyclic
+ * product (x^d = -1), coefficient by coefficient, with 128-bit integers.
+ *
+ * Layout: a ciphertext is N rows x 2 columns x d coefficients, uint64 in
+ * [0, p), row-major (row, column, coefficient).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <omp.h>
+
+typedef unsigned __int128 u128;
+
+static uint64_t addm(uint64_t a, uint64_t b, uint64_t p) { u128 s = (u128)a + b; return (uint64_t)(s % p); }
+static uint64_t subm(uint64_t a, uint64_t b, uint64_t p) { return a >= b ? a - b : (uint64_t)((u128)a + p - b); }
+
+/* out = a * b in Z_p[X]/(X^d + 1):  out_k = sum_{i+j=k} a_i b_j - sum_{i+j=k+d} a_i b_j. */
+void rg_negmul(uint64_t p, int d, const uint64_t *a, const uint64_t *b, uint64_t *out)
+{
+    for (int k = 0; k < d; k++) {
+        u128 pos = 0, neg = 0;
+        for (int i = 0; i < d; i++) {
+            int j = k - i;
+            if (j >= 0) {
+                pos += (u128)a[i] * b[j] % p;
+            } else {
+                neg += (u128)a[i] * b[j + d] % p;
+            }
+        }
+        out[k] = subm((uint64_t)(pos % p), (uint64_t)(neg % p), p);
+    }
+}
+
+/* Encrypt n bits.  s: d coefficients in [0,p).  a: n*N*d uniform in [0,p).
+ * e: n*N*d small signed errors.  m: n bits.  ct: n ciphertexts. */
+void rg_encrypt(uint64_t p, int d, int ell, const uint64_t *s, const uint64_t *a, const int64_t *e,
+                const uint8_t *m, int64_t n, uint64_t *ct)
+{
+    const int N = 2 * ell;
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t c = 0; c < n; c++) {
+        for (int r = 0; r < N; r++) {
+            const uint64_t *ar = a + (c * N + r) * (int64_t)d;
+            const int64_t *er = e + (c * N + r) * (int64_t)d;
+            uint64_t *row = ct + (c * N + r) * 2 * (int64_t)d;
+            rg_negmul(p, d, ar, s, row);                       /* a_r * s */
+            for (int t = 0; t < d; t++) {
+                uint64_t et = er[t] >= 0 ? (uint64_t)er[t] % p : p - (uint64_t)(-er[t]) % p;
+                row[t] = addm(row[t], et % p, p);              /* + e_r   */
+                row[d + t] = ar[t];                            /* a_r     */
+            }
+            if (m[c]) {                                        /* + m*G   */
+                int col = r / ell, j = r % ell;
+                row[col * d] = addm(row[col * d], ((uint64_t)1 << j) % p, p);
+            }
+        }
+    }
+}
+
+/* Row i of G^-1(L) * R: both output polynomials.  scratch: d words. */
+static void product_row(uint64_t p, int d, int ell, const uint64_t *L, const uint64_t *R, int i,
+                        uint64_t *out0, uint64_t *out1, uint64_t *bits, uint64_t *tmp)
+{
+    const int N = 2 * ell;
+    memset(out0, 0, sizeof(uint64_t) * d);
+    memset(out1, 0, sizeof(uint64_t) * d);
+    for (int jj = 0; jj < N; jj++) {
+        int col = jj / ell, j = jj % ell;
+        const uint64_t *src = L + ((int64_t)i * 2 + col) * d;
+        for (int t = 0; t < d; t++) bits[t] = (src[t] >> j) & 1;  /* digit polynomial */
+        const uint64_t *r0 = R + ((int64_t)jj * 2 + 0) * d;
+        const uint64_t *r1 = R + ((int64_t)jj * 2 + 1) * d;
+        rg_negmul(p, d, bits, r0, tmp);
+        for (int t = 0; t < d; t++) out0[t] = addm(out0[t], tmp[t], p);
+        rg_negmul(p, d, bits, r1, tmp);
+        for (int t = 0; t < d; t++) out1[t] = addm(out1[t], tmp[t], p);
+    }
+}
+
+/* out[c] = gate(L[c], R[c]) for n ciphertext pairs.  op: 3 NOT (R ignored),
+ * 4 AND, 5 XOR, 6 OR, 7 XADD, 8 NAND, 9 PRODUCT (= AND).  Returns 0, or -1
+ * for an unknown op. */
+int rg_gate(uint64_t p, int d, int ell, int op, const uint64_t *L, const uint64_t *R, uint64_t *out,
+            int64_t n)
+{
+    if (op < 3 || op > 9) return -1;
+    const int N = 2 * ell;
+    const int64_t ct = (int64_t)N * 2 * d;
+    #pragma omp parallel
+    {
+        uint64_t *P = malloc(sizeof(uint64_t) * 4 * d);
+        uint64_t *bits = P + 2 * d, *tmp = P + 3 * d;
+        #pragma omp for collapse(2) schedule(dynamic)
+        for (int64_t c = 0; c < n; c++) {
+            for (int i = 0; i < N; i++) {
+                const uint64_t *Lc = L + c * ct, *Rc = R + c * ct;
+                uint64_t *o = out + c * ct + (int64_t)i * 2 * d;
+                const uint64_t *li = Lc + (int64_t)i * 2 * d, *ri = Rc + (int64_t)i * 2 * d;
+                int needP = (op == 4 || op == 5 || op == 6 || op == 8 || op == 9);
+                if (needP) product_row(p, d, ell, Lc, Rc, i, P, P + d, bits, tmp);
+                for (int t = 0; t < 2 * d; t++) {
+                    uint64_t g = (t % d == 0 && t / d == i / ell) ? ((uint64_t)1 << (i % ell)) % p : 0;
+                    uint64_t v;
+                    switch (op) {
+                    case 3: v = subm(g, li[t], p); break;
+                    case 4: case 9: v = P[t]; break;
+                    case 5: v = subm(addm(li[t], ri[t], p), addm(P[t], P[t], p), p); break;
+                    case 6: v = subm(addm(li[t], ri[t], p), P[t], p); break;
+                    case 7: v = addm(li[t], ri[t], p); break;
+                    default: v = subm(g, P[t], p); break;
+                    }
+                    o[t] = v;
+                }
+            }
+        }
+        free(P);
+    }
+    return 0;
+}
+
+/* Phase of one row: C[row][0] - C[row][1]*s  (d coefficients). */
+void rg_phase(uint64_t p, int d, int ell, const uint64_t *ct, int row, const uint64_t *s, uint64_t *out)
+{
+    (void)ell;
+    const uint64_t *c0 = ct + (int64_t)row * 2 * d, *c1 = c0 + d;
+    rg_negmul(p, d, c1, s, out);
+    for (int t = 0; t < d; t++) out[t] = subm(c0[t], out[t], p);
+}
+
+/* Decrypt n ciphertexts to bits from coefficient 0 of row ell-1's phase. */
+void rg_decrypt(uint64_t p, int d, int ell, const uint64_t *ct, int64_t n, const uint64_t *s, uint8_t *m)
+{
+    const int64_t sz = (int64_t)2 * ell * 2 * d;
+    #pragma omp parallel
+    {
+        uint64_t *ph = malloc(sizeof(uint64_t) * d);
+        #pragma omp for schedule(static)
+        for (int64_t c = 0; c < n; c++) {
+            rg_phase(p, d, ell, ct + c * sz, ell - 1, s, ph);
+            uint64_t x = ph[0];
+            uint64_t mag = x <= p / 2 ? x : p - x;
+            m[c] = mag > p / 4;
+        }
+        free(ph);
+    }
+}

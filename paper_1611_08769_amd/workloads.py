@@ -164,3 +164,28 @@ def unit_complex(seed: int, n: int, F: int = 32, f: int = 16, stream=None):
     u = stream or Uniforms(seed)
     return Signal(1, n, F, f, u.next(n), u.next(n))
 
+
+
+@dataclass
+class RingDraws:
+    """Random draws of ring-GSW key generation and encryption, for n
+    ciphertexts of rows x d coefficients: the secret's coefficients
+    (ternary, signed), uniform masks in [0, modulus), signed errors in
+    [-err_bound, err_bound] and the plaintext bits.  Both the library and the
+    oracle take these as inputs; neither draws its own."""
+    s: np.ndarray      # (d,) int64 in {-1, 0, 1}
+    a: np.ndarray      # (n, rows, d) uint64 in [0, modulus)
+    e: np.ndarray      # (n, rows, d) int64 in [-err_bound, err_bound]
+    bits: np.ndarray   # (n,) uint8 in {0, 1}
+
+
+def ring_draws(seed: int, n: int, d: int, rows: int, modulus: int, err_bound: int = 2, bits=None) -> RingDraws:
+    """Seeded draws (numpy PCG64) for n ring ciphertexts; bits default to
+    uniform random bits."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    s = g.integers(-1, 2, size=d, dtype=np.int64)
+    a = g.integers(0, modulus, size=(n, rows, d), dtype=np.uint64)
+    e = g.integers(-err_bound, err_bound + 1, size=(n, rows, d), dtype=np.int64)
+    if bits is None:
+        bits = g.integers(0, 2, size=n, dtype=np.uint8)
+    return RingDraws(s, a, e, np.ascontiguousarray(np.asarray(bits, dtype=np.uint8)))

@@ -1,0 +1,146 @@
+"""Pins of the ring-GSW oracle against what the mathematics fixes (no GPU).
+
+* the negacyclic product against a plain full convolution folded with
+  X^d = -1 (Python integers), monomial closed forms, and d = 1 (scalars);
+* the gadget identities: G^-1(G) is the identity matrix, so G (the
+  noiseless encryption of 1) is a two-sided unit of the product, and the
+  zero matrix annihilates it;
+* the exact phase of a fresh encryption, row by row;
+* gate truth tables, the noise bound of one product, and a depth-3 circuit.
+"""
+import numpy as np
+import pytest
+
+from oracle import rgsw as R
+from paper_1611_08769_amd import workloads as WL
+
+
+def _fold_reference(a, b, p):
+    d = len(a)
+    full = [0] * (2 * d - 1)
+    for i in range(d):
+        for j in range(d):
+            full[i + j] += int(a[i]) * int(b[j])
+    return [(full[k] - (full[k + d] if k + d < 2 * d - 1 else 0)) % p for k in range(d)]
+
+
+@pytest.mark.parametrize("d", [1, 2, 8, 32])
+def test_negmul_matches_folded_convolution(d):
+    g = np.random.Generator(np.random.PCG64(d))
+    for _ in range(3):
+        a = g.integers(0, R.P, size=d, dtype=np.uint64)
+        b = g.integers(0, R.P, size=d, dtype=np.uint64)
+        assert R.negmul(a, b).tolist() == _fold_reference(a, b, R.P)
+
+
+def test_negmul_monomials_and_scalars():
+    d = 16
+    for i in range(d):
+        for j in range(d):
+            xi = np.zeros(d, np.uint64)
+            xj = np.zeros(d, np.uint64)
+            xi[i] = 1
+            xj[j] = 1
+            want = np.zeros(d, np.uint64)
+            if i + j < d:
+                want[i + j] = 1
+            else:
+                want[i + j - d] = R.P - 1          # X^d = -1
+            assert R.negmul(xi, xj).tolist() == want.tolist()
+    a, b = 0x3ABCDEF012345678, 0x1234567890ABCDE
+    assert int(R.negmul([a], [b])[0]) == a * b % R.P
+
+
+def _gadget(d, n=1):
+    """Noiseless encryption of 1: G, as (n, ROWS, 2, d)."""
+    G = np.zeros((n, R.ROWS, 2, d), np.uint64)
+    for r in range(R.ROWS):
+        G[:, r, r // R.ELL, 0] = (1 << (r % R.ELL)) % R.P
+    return G
+
+
+def test_gadget_is_a_unit_of_the_product():
+    d = 8
+    dr = WL.ring_draws(1, 2, d, R.ROWS, R.P)
+    L = R.encrypt(dr)
+    G = _gadget(d, 2)
+    # G^-1(L) * G = L  (the decomposition recomposes)
+    assert np.array_equal(R.gate(R.AND, L, G), L)
+    # G^-1(G) = I, so G^-1(G) * L = L
+    assert np.array_equal(R.gate(R.AND, G, L), L)
+    # zero annihilates
+    Z = np.zeros_like(L)
+    assert not R.gate(R.AND, L, Z).any() and not R.gate(R.AND, Z, L).any()
+    # NAND(L, G) = G - L = NOT(L); XOR(L, 0) = L; OR(L, 0) = L
+    assert np.array_equal(R.gate(R.NAND, L, G), R.gate(R.NOT, L))
+    assert np.array_equal(R.gate(R.XOR, L, Z), L)
+    assert np.array_equal(R.gate(R.OR, L, Z), L)
+    assert np.array_equal(R.gate(R.NOT, R.gate(R.NOT, L)), L)
+
+
+def test_fresh_phase_is_exact():
+    d = 16
+    dr = WL.ring_draws(7, 2, d, R.ROWS, R.P, bits=[0, 1])
+    ct = R.encrypt(dr)
+    s = dr.s
+    for c in range(2):
+        m = int(dr.bits[c])
+        for r in (0, 1, R.ELL - 1, R.ELL, 2 * R.ELL - 1):
+            got = R.centred(R.phase(ct[c], r, s))
+            want = [int(x) for x in dr.e[c, r]]
+            if r < R.ELL:
+                want[0] += m << r
+            else:
+                # the gadget on column 1 contributes -m * 2^(r-ell) * s
+                want = [w - m * (1 << (r - R.ELL)) * int(sv) for w, sv in zip(want, s)]
+            want = [((w + R.P // 2) % R.P) - R.P // 2 if abs(w) > R.P // 2 else w for w in want]
+            assert list(got) == want, (c, r)
+
+
+@pytest.mark.parametrize("op,fn", [(R.AND, lambda x, y: x & y), (R.XOR, lambda x, y: x ^ y),
+                                   (R.OR, lambda x, y: x | y), (R.NAND, lambda x, y: 1 - (x & y))])
+def test_truth_tables(op, fn):
+    d = 16
+    xs = np.array([0, 0, 1, 1], np.uint8)
+    ys = np.array([0, 1, 0, 1], np.uint8)
+    dx = WL.ring_draws(11, 4, d, R.ROWS, R.P, bits=xs)
+    dy = WL.ring_draws(12, 4, d, R.ROWS, R.P, bits=ys)
+    dy.s = dx.s                                   # one key
+    X, Y = R.encrypt(dx), R.encrypt(dy)
+    assert R.decrypt(X, dx.s).tolist() == xs.tolist()
+    out = R.gate(op, X, Y)
+    assert R.decrypt(out, dx.s).tolist() == [fn(int(a), int(b)) for a, b in zip(xs, ys)]
+
+
+def test_product_noise_within_bound():
+    """After AND the error of the decrypting row is m2*e1 + (G^-1(L)*e2)_row,
+    whose coefficients are at most B*(1 + 2*ell*d) in magnitude."""
+    d, B = 32, 2
+    xs, ys = np.array([1, 1, 0, 1], np.uint8), np.array([1, 0, 1, 1], np.uint8)
+    dx = WL.ring_draws(21, 4, d, R.ROWS, R.P, B, bits=xs)
+    dy = WL.ring_draws(22, 4, d, R.ROWS, R.P, B, bits=ys)
+    dy.s = dx.s
+    out = R.gate(R.AND, R.encrypt(dx), R.encrypt(dy))
+    for c in range(4):
+        ph = R.centred(R.phase(out[c], R.ELL - 1, dx.s))
+        m = int(xs[c] & ys[c])
+        ph[0] -= m << (R.ELL - 1)
+        ph = [((int(v) + R.P // 2) % R.P) - R.P // 2 for v in ph]
+        assert max(abs(v) for v in ph) <= B * (1 + 2 * R.ELL * d)
+        assert max(abs(v) for v in ph) > 0
+
+
+def test_depth_three_circuit():
+    """((a AND b) XOR c) OR (NOT d) ... evaluated to depth 3 on 8 random inputs."""
+    d = 32
+    n = 8
+    ds = [WL.ring_draws(30 + i, n, d, R.ROWS, R.P) for i in range(4)]
+    for x in ds[1:]:
+        x.s = ds[0].s
+    a, b, c, e = (R.encrypt(x) for x in ds)
+    t1 = R.gate(R.AND, a, b)
+    t2 = R.gate(R.XOR, t1, c)
+    t3 = R.gate(R.OR, t2, R.gate(R.NOT, e))
+    bits = [x.bits.astype(int) for x in ds]
+    want = ((bits[0] & bits[1]) ^ bits[2]) | (1 - bits[3])
+    assert R.decrypt(t3, ds[0].s).tolist() == want.tolist()
