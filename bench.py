@@ -4,6 +4,7 @@
     python bench.py --workload batch [--requests 64] [--max-len 128]
     python bench.py --workload serve [--requests 40] [--load 0.7] [--max-active 0]
     python bench.py --workload accuracy [--signals 4]
+    python bench.py --workload ring_and_d1024 [--requests 128]   # ring-GSW gates
 
 A step is one encrypted FFT of one request (every product level of the
 compiled circuit, inputs already encrypted and resident in HBM).  Prints one
@@ -276,13 +277,20 @@ def trace_summary(workload, db_path, steps):
     rows = list(cur.execute("select name, duration from kernels order by start"))
     by = {}
     for name, d in rows:
-        short = name.replace("sfft::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        short = name.replace("sfft::", "").replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
         by.setdefault(short, []).append(d)
     print("| kernel | calls | total (ms) | average (ms) | min (ms) | max (ms) |")
     print("|:--|--:|--:|--:|--:|--:|")
     for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
         print("| %s | %d | %.1f | %.4f | %.4f | %.4f |" % (k, len(v), sum(v) / 1e6, sum(v) / len(v) / 1e6,
                                                         min(v) / 1e6, max(v) / 1e6))
+    if workload.startswith("ring_and_d"):
+        # one gate call = one forward-transform launch + one product launch
+        fwd = [d for name, d in rows if "k_ring_fwd" in name][-steps:]
+        prod = [d for name, d in rows if "k_ring_product" in name][-steps:]
+        print("\ntimed gate calls: %d, k_ring_fwd %.3f ms + k_ring_product %.3f ms = %.3f ms" % (
+            len(prod), sum(fwd) / len(fwd) / 1e6, sum(prod) / len(prod) / 1e6, (sum(fwd) + sum(prod)) / len(prod) / 1e6))
+        return
     prods = [d for name, d in rows if _is_gate_product(name)]
     timed = prods[-steps * _product_levels(workload):]
     print("\ntimed product launches: %d, average %.3f ms" % (len(timed), sum(timed) / len(timed) / 1e6))
@@ -471,6 +479,120 @@ def run_accuracy(args):
     }
 
 
+# Ring-GSW gate ceiling.  A modular product of two residues below 2^62 needs
+# the 128-bit product of two 64-bit words: at least four 32x32->64-bit
+# partial products (v_mad_u64_u32), which issue at half the VALU's full rate
+# (32 lanes/clk/CU; a register-only loop measures 34 per CU per clock at
+# 2.4 GHz).  256 CUs x 32 lanes x 2.4 GHz, over 4 per modular product.
+PEAK_MODMUL = 256 * 32 * 2.4e9 / 4.0    # 4.92e12 modular products/s
+
+
+def ring_modmuls_per_gate(d, rows=124):
+    """Modular products of one product gate on the transform route: the
+    forward transforms of the rows*rows digit polynomials (their first stage
+    multiplies 0/1 inputs, a select), the pointwise products against both
+    columns, the inverse transforms and d^-1 scaling of the 2*rows outputs,
+    and the forward transforms of the right operand's 2*rows polynomials."""
+    logd = d.bit_length() - 1
+    half = d // 2
+    digit = rows * rows * half * max(logd - 1, 0)
+    pointwise = rows * rows * 2 * d
+    inverse = 2 * rows * (half * logd + d)
+    right = 2 * rows * half * logd
+    return digit + pointwise + inverse + right
+
+
+def run_ring(args):
+    """Ring-GSW AND gates at d = 1024: one step is one sfft_ring_gate call
+    over n ciphertext pairs (the right operands' forward transforms and the
+    product kernel), inputs encrypted and resident in HBM."""
+    import torch
+    from oracle import rgsw as O
+    from paper_1611_08769_amd import sfft as S
+    from paper_1611_08769_amd import workloads as WL
+
+    d = int(args.workload.rsplit("_d", 1)[1])
+    n = args.requests or 128
+    stream = torch.cuda.current_stream().cuda_stream
+    cts = []
+    for seed in (1, 2):
+        dr = WL.ring_draws(seed, n, d, 2 * S.SFFT_RING_ELL, S.SFFT_RING_P)
+        if seed == 1:
+            secret = dr.s
+        dev = [torch.from_numpy(np.ascontiguousarray(x).view(np.int64) if x.dtype == np.uint64 else x).cuda()
+               for x in (secret, dr.a, dr.e, dr.bits)]
+        ct = torch.empty((n, S.sfft_ring_ct_words(d)), dtype=torch.int64, device="cuda")
+        S.sfft_ring_encrypt(d, dev[0].data_ptr(), dev[1].data_ptr(), dev[2].data_ptr(), dev[3].data_ptr(), n,
+                            ct.data_ptr(), stream)
+        cts.append((ct, dr.bits))
+        del dev
+    (X, xb), (Y, yb) = cts
+    out = torch.empty_like(X)
+    ws_b = S.sfft_ring_workspace_bytes(d, n)
+    ws = torch.empty(ws_b // 8, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+
+    def step():
+        S.sfft_ring_gate(d, 4, X.data_ptr(), Y.data_ptr(), out.data_ptr(), n, ws.data_ptr(), ws_b, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    dec = np.zeros(n, np.uint8)
+    s = np.ascontiguousarray(secret, dtype=np.int64)
+    S.sfft_ring_decrypt(d, s.ctypes.data, out.data_ptr(), n, 1, dec.ctypes.data)
+    assert dec.tolist() == (xb & yb).tolist(), "ring AND decryptions differ from the plaintext"
+    avg_s = sum(launch_ms) / len(launch_ms) / 1e3
+    mm = ring_modmuls_per_gate(d) * n
+    res = {
+        "metric": "encrypted ring-GSW gates/s (1 GPU)",
+        "value": n * args.steps / wall,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "d": d, "gates_per_step": n, "gate": "AND", "ell": S.SFFT_RING_ELL,
+                   "p": "2^62-2^16+1", "ct_bytes": S.sfft_ring_ct_words(d) * 8},
+        "roofline": {"bound": "alu", "achieved": mm / avg_s / 1e9, "peak": PEAK_MODMUL / 1e9,
+                     "unit": "Gmodmul/s", "frac": mm / avg_s / PEAK_MODMUL, "traffic": None,
+                     "kernel": "k_ring_fwd + k_ring_product", "avg_launch_ms": avg_s * 1e3,
+                     "modmul_per_gate": ring_modmuls_per_gate(d)},
+    }
+    if not args.no_cpu_baseline:
+        Xh = X.cpu().numpy().view(np.uint64).reshape(n, 2 * O.ELL, 2, d)
+        Yh = Y.cpu().numpy().view(np.uint64).reshape(n, 2 * O.ELL, 2, d)
+        threads = int(O.lib().rg_threads())
+        t1 = time.perf_counter()
+        O.gate_rows(4, Xh, Yh, [0], [5])
+        one = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        O.gate_rows(4, Xh, Yh, [q % n for q in range(threads)], [(7 * q) % (2 * O.ELL) for q in range(threads)])
+        allc = time.perf_counter() - t1
+        res["cpu_baseline"] = {
+            "value": threads / allc / (2 * O.ELL), "unit": "gates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d output rows of AND at d=%d on %d threads, %.2f s (a gate has %d rows)" % (
+                threads, d, threads, allc, 2 * O.ELL),
+            "value_1_core": 1.0 / one / (2 * O.ELL),
+            "sample_1_core": "1 output row on 1 thread, %.2f s" % one,
+        }
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=0, help="batch / serve mode: number of requests (64 / 40)")
@@ -527,6 +649,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(run_serve(args)), flush=True)
+        return
+    if args.workload.startswith("ring_and_d"):
+        print(json.dumps(run_ring(args)), flush=True)
         return
     sig, n_lwe, seed = WL.workload(args.workload)
     cplx = sig.is_complex

@@ -268,6 +268,52 @@ int sfft_server_stats_get(const sfft_server* srv, sfft_server_stats* out);
 /* Waits for all device work, then frees the server and its memory budget. */
 void sfft_server_destroy(sfft_server* srv);
 
+/* ---- ring-GSW gates ------------------------------------------------------
+ * GSW13's ring instantiation of the scheme the paper evaluates its circuits
+ * with (section "Notation and Background"; gates as in Lemma "binary gates"):
+ * matrix entries are polynomials of R_p = Z_p[X]/(X^d + 1) with
+ * p = SFFT_RING_P = 2^62 - 2^16 + 1 (prime, 2^16 | p - 1) and d a power of
+ * two in [1, 2048].  With ell = SFFT_RING_ELL = 62 and v = (1, -s):
+ *   ciphertext  C = m*G + Z, 2*ell rows x 2 columns of polynomials,
+ *               G = I_2 (x) (1, 2, ..., 2^(ell-1))^T, row r of Z is
+ *               (a_r*s + e_r, a_r), so C*v = m*G*v + e
+ *   product     P = G^-1(L)*R, G^-1 = bit decomposition of every coefficient
+ *   gates       AND = P, XOR = L + R - 2P, OR = L + R - P, NAND = G - P,
+ *               NOT = G - L, XADD = L + R (codes as for sfft_gate)
+ *   decryption  coefficient 0 of row ell-1 of C*v: |centred value| > p/4
+ *               reads 1
+ * Layout: (row, column, coefficient) uint64 residues in [0, p),
+ * sfft_ring_ct_words(d) = 2*ell*2*d words per ciphertext, n ciphertexts back
+ * to back.  Every call returns SFFT_EINVAL for a d outside the range, n < 0,
+ * a null buffer or an unknown gate; n = 0 does nothing.  The first call for a
+ * d on a device uploads that d's transform tables (the library's only
+ * allocation here; kept until the process ends).  Launches are asynchronous
+ * on hip_stream. */
+#define SFFT_RING_P 0x3FFFFFFFFFFF0001ULL
+#define SFFT_RING_ELL 62
+
+/* Words per ring ciphertext, or SFFT_EINVAL. */
+int64_t sfft_ring_ct_words(int32_t d);
+/* Workspace of sfft_ring_gate for n product gates: the transformed right
+ * operands, n * sfft_ring_ct_words(d) words. */
+int sfft_ring_workspace_bytes(int32_t d, int64_t n, int64_t* bytes);
+/* Encrypt n bits (bits_dev, one byte each, 0/1).  The random draws are
+ * inputs, all on the device: s_dev the secret's d signed coefficients,
+ * a_dev n*2*ell*d masks in [0, p), e_dev n*2*ell*d signed errors.  ct_dev
+ * receives n ciphertexts. */
+int sfft_ring_encrypt(int32_t d, const int64_t* s_dev, const uint64_t* a_dev, const int64_t* e_dev,
+                      const uint8_t* bits_dev, int64_t n, uint64_t* ct_dev, void* hip_stream);
+/* out[c] = gate(x[c], y[c]) for c < n, device buffers of n ciphertexts each;
+ * out must not alias x or y (SFFT_EINVAL).  Product gates (4, 5, 6, 8, 9)
+ * need a workspace of sfft_ring_workspace_bytes(d, n) bytes (SFFT_EINVAL if
+ * smaller); NOT (3, y ignored) and XADD (7) need none. */
+int sfft_ring_gate(int32_t d, int32_t gate, const uint64_t* x_dev, const uint64_t* y_dev, uint64_t* out_dev,
+                   int64_t n, void* ws_dev, int64_t ws_bytes, void* hip_stream);
+/* Decrypt n ciphertexts (host, or device with ct_on_device = 1: reads row
+ * ell-1 of each, synchronously) under the secret's d signed coefficients. */
+int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int64_t n, int ct_on_device,
+                      uint8_t* bits_out);
+
 #ifdef __cplusplus
 }
 #endif

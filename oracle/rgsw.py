@@ -52,10 +52,15 @@ def lib():
         i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
         u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
         c = ctypes
+        L.rg_threads.restype = c.c_int
+        L.rg_threads.argtypes = []
         L.rg_negmul.argtypes = [c.c_uint64, c.c_int, u64p, u64p, u64p]
         L.rg_encrypt.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, u64p, i64p, u8p, c.c_int64, u64p]
         L.rg_gate.restype = c.c_int
         L.rg_gate.argtypes = [c.c_uint64, c.c_int, c.c_int, c.c_int, u64p, u64p, u64p, c.c_int64]
+        L.rg_gate_rows.restype = c.c_int
+        L.rg_gate_rows.argtypes = [c.c_uint64, c.c_int, c.c_int, c.c_int, u64p, u64p, i64p,
+                                   np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), c.c_int64, u64p]
         L.rg_phase.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int, u64p, u64p]
         L.rg_decrypt.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, u8p]
         _lib = L
@@ -98,6 +103,18 @@ def gate(op: int, L, R=None) -> np.ndarray:
     assert L.shape == R.shape and L.shape[1:3] == (ROWS, 2)
     out = np.zeros_like(L)
     if lib().rg_gate(P, L.shape[3], ELL, op, L, R, out, L.shape[0]) != 0:
+        raise ValueError("unknown gate %d" % op)
+    return out
+
+
+def gate_rows(op: int, L, R, cts, rows) -> np.ndarray:
+    """Rows rows[q] of op(L[cts[q]], R[cts[q]]), one by one: (count, 2, d)."""
+    L, R = _u64(L), _u64(R)
+    cts = np.ascontiguousarray(cts, dtype=np.int64)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    d = L.shape[3]
+    out = np.zeros((len(cts), 2, d), dtype=np.uint64)
+    if lib().rg_gate_rows(P, d, ELL, op, L, R, cts, rows, len(cts), out) != 0:
         raise ValueError("unknown gate %d" % op)
     return out
 

@@ -36,6 +36,9 @@
 
 typedef unsigned __int128 u128;
 
+/* OpenMP threads the oracle's parallel loops use. */
+int rg_threads(void) { return omp_get_max_threads(); }
+
 static uint64_t addm(uint64_t a, uint64_t b, uint64_t p) { u128 s = (u128)a + b; return (uint64_t)(s % p); }
 static uint64_t subm(uint64_t a, uint64_t b, uint64_t p) { return a >= b ? a - b : (uint64_t)((u128)a + p - b); }
 
@@ -136,6 +139,45 @@ int rg_gate(uint64_t p, int d, int ell, int op, const uint64_t *L, const uint64_
                     }
                     o[t] = v;
                 }
+            }
+        }
+        free(P);
+    }
+    return 0;
+}
+
+/* Rows of gate outputs, one by one: for sample q, row rows[q] of
+ * op(L[cts[q]], R[cts[q]]) into out + q*2*d.  op as for rg_gate. */
+int rg_gate_rows(uint64_t p, int d, int ell, int op, const uint64_t *L, const uint64_t *R, const int64_t *cts,
+                 const int32_t *rows, int64_t count, uint64_t *out)
+{
+    if (op < 3 || op > 9) return -1;
+    const int N = 2 * ell;
+    const int64_t ct = (int64_t)N * 2 * d;
+    #pragma omp parallel
+    {
+        uint64_t *P = malloc(sizeof(uint64_t) * 4 * d);
+        uint64_t *bits = P + 2 * d, *tmp = P + 3 * d;
+        #pragma omp for schedule(dynamic)
+        for (int64_t q = 0; q < count; q++) {
+            const int64_t c = cts[q];
+            const int i = rows[q];
+            const uint64_t *Lc = L + c * ct, *Rc = R + c * ct;
+            const uint64_t *li = Lc + (int64_t)i * 2 * d, *ri = Rc + (int64_t)i * 2 * d;
+            uint64_t *o = out + q * 2 * d;
+            if (op != 3 && op != 7) product_row(p, d, ell, Lc, Rc, i, P, P + d, bits, tmp);
+            for (int t = 0; t < 2 * d; t++) {
+                uint64_t g = (t % d == 0 && t / d == i / ell) ? ((uint64_t)1 << (i % ell)) % p : 0;
+                uint64_t v;
+                switch (op) {
+                case 3: v = subm(g, li[t], p); break;
+                case 4: case 9: v = P[t]; break;
+                case 5: v = subm(addm(li[t], ri[t], p), addm(P[t], P[t], p), p); break;
+                case 6: v = subm(addm(li[t], ri[t], p), P[t], p); break;
+                case 7: v = addm(li[t], ri[t], p); break;
+                default: v = subm(g, P[t], p); break;
+                }
+                o[t] = v;
             }
         }
         free(P);

@@ -1,0 +1,466 @@
+// Ring-GSW gates on gfx950: GSW13 over R_p = Z_p[X]/(X^d + 1),
+// p = 2^62 - 2^16 + 1 (GSW13's ring instantiation of the scheme of the
+// paper's section "Notation and Background"; gates as in Lemma "binary
+// gates").
+//
+// A ciphertext is 2*ell rows x 2 columns of polynomials (ell = 62), stored
+// (row, column, coefficient) as uint64 residues in [0, p).  The product of
+// two ciphertexts is P = G^-1(L) * R, where G^-1 splits every coefficient of
+// L into its ell bits: row i of P is the sum over the 2*ell digit
+// polynomials D_ij (bit j mod ell of L[i][j div ell]) of D_ij * R[j], each a
+// negacyclic product.  The kernels compute it in the transform domain:
+//   k_ring_fwd      forward transform of every polynomial of R (once per gate)
+//   k_ring_product  one workgroup per (ciphertext, row i): for each digit,
+//                   build D_ij in LDS, transform it there, multiply-accumulate
+//                   against R's transformed row j in registers; then the
+//                   inverse transform of the two accumulated polynomials and
+//                   the gate's affine epilogue in the coefficient domain
+//   k_ring_linear   NOT and XADD (no product)
+//   k_ring_encrypt  one workgroup per (ciphertext, row): a*s by transforms,
+//                   plus the error and the gadget
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ring_math.hpp"
+#include "sfft.h"
+
+int sfft_fail(int code, const std::string& msg);
+int sfft_hip_fail(hipError_t e, const char* where);
+
+using namespace sfft::ring;
+
+namespace {
+
+constexpr int kT = 256;                       // threads per workgroup
+constexpr int kPer = (1 << kMaxLogD) / kT;    // coefficients per thread in the accumulators
+
+// Transform tables of one d, on the device: forward twiddles psi^brv(k)
+// [0, d), inverse twiddles psi^-brv(k) [d, 2d), d^-1 at [2d].
+struct TwView {
+    const uint64_t* fwd;
+    const uint64_t* inv;
+    uint64_t dinv;
+};
+
+__device__ __forceinline__ void copy_lds(uint64_t* dst, const uint64_t* src, int count)
+{
+    for (int t = threadIdx.x; t < count; t += kT) dst[t] = src[t];
+}
+
+// Forward transforms (natural -> bit-reversed order) of np polynomials held
+// back to back in LDS.  binary: the inputs are 0/1, so the first stage's
+// product by the twiddle is a select.  Ends with a barrier.
+__device__ void fwd_lds(uint64_t* a, int np, int d, int logd, const uint64_t* tw, bool binary)
+{
+    const int half = d >> 1;
+    for (int s = 0; s < logd; ++s) {
+        const int m = 1 << s, t = d >> (s + 1), sh = logd - 1 - s;
+        for (int b = threadIdx.x; b < np * half; b += kT) {
+            const int q = b >> (logd - 1);
+            const int bb = b & (half - 1);
+            const int i = bb >> sh, j = bb & (t - 1);
+            uint64_t* p = a + q * d + 2 * i * t + j;
+            const uint64_t S = tw[m + i];
+            const uint64_t U = p[0];
+            const uint64_t V = (binary && s == 0) ? (p[t] ? S : 0) : mulp(p[t], S);
+            p[0] = addp(U, V);
+            p[t] = subp(U, V);
+        }
+        __syncthreads();
+    }
+}
+
+// Inverse transforms (bit-reversed -> natural order, without the d^-1
+// scaling) of np polynomials in LDS.  Ends with a barrier.
+__device__ void inv_lds(uint64_t* a, int np, int d, int logd, const uint64_t* tw)
+{
+    const int half = d >> 1;
+    for (int s = logd - 1; s >= 0; --s) {
+        const int m = 1 << s, t = d >> (s + 1), sh = logd - 1 - s;
+        for (int b = threadIdx.x; b < np * half; b += kT) {
+            const int q = b >> (logd - 1);
+            const int bb = b & (half - 1);
+            const int i = bb >> sh, j = bb & (t - 1);
+            uint64_t* p = a + q * d + 2 * i * t + j;
+            const uint64_t U = p[0], V = p[t];
+            p[0] = addp(U, V);
+            p[t] = mulp(subp(U, V), tw[m + i]);
+        }
+        __syncthreads();
+    }
+}
+
+// Workgroup order -> (ciphertext, row), keeping the rows of one ciphertext on
+// one XCD (workgroups are dealt to the 8 XCDs round robin) so that the rows
+// share that XCD's L2 copy of the transformed right operand.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t nb)
+{
+    const int64_t nb8 = nb & ~(int64_t)7;
+    return b < nb8 ? (b & 7) * (nb8 >> 3) + (b >> 3) : b;
+}
+
+// Gadget entry of (row, column, coefficient t).
+__device__ __forceinline__ uint64_t gadget(int row, int col, int t)
+{
+    return (t == 0 && col == row / kEll) ? (1ULL << (row % kEll)) : 0;
+}
+
+__device__ __forceinline__ uint64_t epilogue(int op, uint64_t P, uint64_t l, uint64_t r, uint64_t g)
+{
+    switch (op) {
+    case 4: case 9: return P;
+    case 5: return subp(addp(l, r), addp(P, P));
+    case 6: return subp(addp(l, r), P);
+    default: return subp(g, P);  // 8: NAND
+    }
+}
+
+// Forward transforms of n_rows rows (both columns of each) of src into dst.
+__global__ __launch_bounds__(kT) void k_ring_fwd(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                                                 int d, int logd, TwView tw)
+{
+    extern __shared__ uint64_t lds[];
+    uint64_t* t_f = lds;
+    uint64_t* buf = lds + d;
+    const int64_t row = blockIdx.x;
+    const uint64_t* s = src + row * 2 * d;
+    copy_lds(t_f, tw.fwd, d);
+    copy_lds(buf, s, 2 * d);
+    __syncthreads();
+    fwd_lds(buf, 2, d, logd, t_f, false);
+    uint64_t* o = dst + row * 2 * d;
+    for (int t = threadIdx.x; t < 2 * d; t += kT) o[t] = buf[t];
+}
+
+// out[c] = op(L[c], R[c]) for the product gates (AND, XOR, OR, NAND,
+// PRODUCT).  Rn: R's rows, transformed.  DG digit polynomials per pass.
+template <int DG>
+__global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict__ L, const uint64_t* __restrict__ R,
+                                                     const uint64_t* __restrict__ Rn, uint64_t* __restrict__ out,
+                                                     int64_t nblocks, int d, int logd, TwView tw, int op)
+{
+    extern __shared__ uint64_t lds[];
+    constexpr int NB = DG > 2 ? DG : 2;
+    uint64_t* t_w = lds;            // d twiddles (forward, then inverse)
+    uint64_t* lrow = lds + d;       // row i of L: 2d
+    uint64_t* dig = lrow + 2 * d;   // NB polynomials
+    const int64_t lb = xcd_order(blockIdx.x, nblocks);
+    const int64_t c = lb / kRows;
+    const int i = (int)(lb % kRows);
+    const int64_t row_off = (c * kRows + i) * 2 * d;
+    const uint64_t* rn = Rn + c * kRows * 2 * d;
+
+    copy_lds(t_w, tw.fwd, d);
+    copy_lds(lrow, L + row_off, 2 * d);
+    uint64_t acc0[kPer], acc1[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) acc0[q] = acc1[q] = 0;
+    __syncthreads();
+
+    for (int jj0 = 0; jj0 < kRows; jj0 += DG) {
+        // digit polynomials jj0 .. jj0+DG-1: bit (jj mod ell) of L[i][jj div ell]
+        for (int b = threadIdx.x; b < DG * d; b += kT) {
+            const int jj = jj0 + (b >> logd), t = b & (d - 1);
+            dig[b] = (lrow[(jj / kEll) * d + t] >> (jj % kEll)) & 1;
+        }
+        __syncthreads();
+        fwd_lds(dig, DG, d, logd, t_w, true);
+#pragma unroll
+        for (int g = 0; g < DG; ++g) {
+            const uint64_t* r0 = rn + (int64_t)(jj0 + g) * 2 * d;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int k = threadIdx.x + q * kT;
+                if (k < d) {
+                    const uint64_t x = dig[g * d + k];
+                    acc0[q] = addp(acc0[q], mulp(x, r0[k]));
+                    acc1[q] = addp(acc1[q], mulp(x, r0[d + k]));
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // both accumulated polynomials back to coefficients
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int k = threadIdx.x + q * kT;
+        if (k < d) {
+            dig[k] = acc0[q];
+            dig[d + k] = acc1[q];
+        }
+    }
+    copy_lds(t_w, tw.inv, d);
+    __syncthreads();
+    inv_lds(dig, 2, d, logd, t_w);
+
+    const uint64_t* rrow = R + row_off;
+    uint64_t* orow = out + row_off;
+    for (int b = threadIdx.x; b < 2 * d; b += kT) {
+        const int col = b >> logd, t = b & (d - 1);
+        const uint64_t P = mulp(dig[b], tw.dinv);
+        orow[b] = epilogue(op, P, lrow[b], rrow[b], gadget(i, col, t));
+    }
+}
+
+// NOT (3): G - X;  XADD (7): X + Y.  Elementwise over n ciphertexts.
+__global__ __launch_bounds__(kT) void k_ring_linear(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Y,
+                                                    uint64_t* __restrict__ out, int64_t count, int d, int logd,
+                                                    int op)
+{
+    const int64_t stride = (int64_t)gridDim.x * kT;
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < count; e += stride) {
+        if (op == 3) {
+            const int t = (int)(e & (d - 1));
+            const int64_t rc = e >> logd;                 // (ct*rows + row)*2 + col
+            const int col = (int)(rc & 1), row = (int)((rc >> 1) % kRows);
+            out[e] = subp(gadget(row, col, t), X[e]);
+        } else {
+            out[e] = addp(X[e], Y[e]);
+        }
+    }
+}
+
+// Encryption of bits[c] under secret s (signed coefficients): row r of
+// ciphertext c is (a_r*s + e_r, a_r) + bits[c]*G[r].
+__global__ __launch_bounds__(kT) void k_ring_encrypt(const int64_t* __restrict__ s, const uint64_t* __restrict__ A,
+                                                     const int64_t* __restrict__ E, const uint8_t* __restrict__ bits,
+                                                     uint64_t* __restrict__ out, int d, int logd, TwView tw)
+{
+    extern __shared__ uint64_t lds[];
+    uint64_t* t_w = lds;
+    uint64_t* buf = lds + d;  // a_r, then s
+    const int64_t cr = blockIdx.x;   // c*rows + r
+    const int64_t c = cr / kRows;
+    const int r = (int)(cr % kRows);
+    const uint64_t* a = A + cr * d;
+    copy_lds(t_w, tw.fwd, d);
+    for (int t = threadIdx.x; t < d; t += kT) {
+        buf[t] = a[t];
+        buf[d + t] = from_signed(s[t]);
+    }
+    __syncthreads();
+    fwd_lds(buf, 2, d, logd, t_w, false);
+    for (int t = threadIdx.x; t < d; t += kT) buf[t] = mulp(buf[t], buf[d + t]);
+    copy_lds(t_w, tw.inv, d);
+    __syncthreads();
+    inv_lds(buf, 1, d, logd, t_w);
+    const uint64_t m = bits[c] & 1;
+    const int64_t* e = E + cr * d;
+    uint64_t* o = out + cr * 2 * d;
+    for (int t = threadIdx.x; t < d; t += kT) {
+        const uint64_t g0 = m ? gadget(r, 0, t) : 0, g1 = m ? gadget(r, 1, t) : 0;
+        o[t] = addp(addp(mulp(buf[t], tw.dinv), from_signed(e[t])), g0);
+        o[d + t] = addp(a[t], g1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+int log2_exact(int d)
+{
+    if (d < 1 || d > (1 << kMaxLogD) || (d & (d - 1))) return -1;
+    int l = 0;
+    while ((1 << l) < d) ++l;
+    return l;
+}
+
+int brv(int x, int bits)
+{
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r = (r << 1) | ((x >> i) & 1);
+    return r;
+}
+
+// A primitive 2d-th root of unity: g^((p-1)/(2d)) for a generator g of Z_p^*
+// (p - 1 = 2^16 * 3 * 47 * 178481 * 2796203).
+uint64_t root_2d(int d)
+{
+    static const uint64_t f[] = {2, 3, 47, 178481, 2796203};
+    for (uint64_t g = 2;; ++g) {
+        bool gen = true;
+        for (uint64_t q : f)
+            if (powp(g, (kP - 1) / q) == 1) {
+                gen = false;
+                break;
+            }
+        if (gen) return powp(g, (kP - 1) / (2 * (uint64_t)d));
+    }
+}
+
+std::mutex g_tw_mu;
+std::map<std::pair<int, int>, uint64_t*> g_tw;  // (device, d) -> tables
+
+int tables(int d, int logd, TwView* tv)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return sfft_hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    auto it = g_tw.find({dev, d});
+    uint64_t* p = nullptr;
+    if (it != g_tw.end()) {
+        p = it->second;
+    } else {
+        std::vector<uint64_t> h(2 * (size_t)d + 1);
+        const uint64_t psi = root_2d(d), ipsi = powp(psi, kP - 2);
+        for (int k = 0; k < d; ++k) {
+            h[k] = powp(psi, (uint64_t)brv(k, logd));
+            h[d + k] = powp(ipsi, (uint64_t)brv(k, logd));
+        }
+        h[2 * d] = powp((uint64_t)d, kP - 2);
+        e = hipMalloc(&p, h.size() * 8);
+        if (e != hipSuccess) return sfft_hip_fail(e, "ring tables");
+        e = hipMemcpy(p, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            return sfft_hip_fail(e, "ring tables");
+        }
+        g_tw[{dev, d}] = p;
+    }
+    tv->fwd = p;
+    tv->inv = p + d;
+    tv->dinv = powp((uint64_t)d, kP - 2);
+    return SFFT_OK;
+}
+
+template <int DG>
+hipError_t launch_product(const uint64_t* L, const uint64_t* R, const uint64_t* Rn, uint64_t* out, int64_t nb, int d,
+                          int logd, TwView tv, int op, hipStream_t s)
+{
+    constexpr int NB = DG > 2 ? DG : 2;
+    const size_t lds = (size_t)(3 + NB) * d * 8;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_ring_product<DG>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_ring_product<DG>, dim3((unsigned)nb), dim3(kT), lds, s, L, R, Rn, out, nb, d, logd, tv, op);
+    return hipGetLastError();
+}
+
+int check_d(int32_t d, int* logd)
+{
+    *logd = log2_exact(d);
+    if (*logd < 0) return sfft_fail(SFFT_EINVAL, "d must be a power of two in [1, 2048]");
+    return SFFT_OK;
+}
+
+int64_t ct_words_of(int d) { return (int64_t)kRows * 2 * d; }
+
+// Blocks of one launch: grids are split below 2^31 workgroups.
+constexpr int64_t kMaxGrid = 1 << 30;
+
+}  // namespace
+
+extern "C" {
+
+int64_t sfft_ring_ct_words(int32_t d)
+{
+    int logd;
+    if (check_d(d, &logd) != SFFT_OK) return SFFT_EINVAL;
+    return ct_words_of(d);
+}
+
+int sfft_ring_workspace_bytes(int32_t d, int64_t n, int64_t* bytes)
+{
+    int logd;
+    if (check_d(d, &logd) != SFFT_OK) return SFFT_EINVAL;
+    if (n < 0 || !bytes) return sfft_fail(SFFT_EINVAL, "n < 0 or null output");
+    *bytes = n * ct_words_of(d) * 8;
+    return SFFT_OK;
+}
+
+int sfft_ring_encrypt(int32_t d, const int64_t* s_dev, const uint64_t* a_dev, const int64_t* e_dev,
+                      const uint8_t* bits_dev, int64_t n, uint64_t* ct_dev, void* hip_stream)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0) return sfft_fail(SFFT_EINVAL, "n < 0");
+    if (n == 0) return SFFT_OK;
+    if (!s_dev || !a_dev || !e_dev || !bits_dev || !ct_dev) return sfft_fail(SFFT_EINVAL, "null buffer");
+    if (n * kRows > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many ciphertexts for one call");
+    TwView tv;
+    if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_ring_encrypt, dim3((unsigned)(n * kRows)), dim3(kT), (size_t)3 * d * 8, s, s_dev, a_dev,
+                       e_dev, bits_dev, ct_dev, d, logd, tv);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_encrypt");
+}
+
+int sfft_ring_gate(int32_t d, int32_t gate, const uint64_t* x_dev, const uint64_t* y_dev, uint64_t* out_dev,
+                   int64_t n, void* ws_dev, int64_t ws_bytes, void* hip_stream)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (gate < 3 || gate > 9) return sfft_fail(SFFT_EINVAL, "gate must be 3..9");
+    if (n < 0) return sfft_fail(SFFT_EINVAL, "n < 0");
+    if (n == 0) return SFFT_OK;
+    const bool linear = gate == 3 || gate == 7;
+    if (!x_dev || !out_dev || (gate != 3 && !y_dev)) return sfft_fail(SFFT_EINVAL, "null buffer");
+    if (out_dev == x_dev || out_dev == y_dev) return sfft_fail(SFFT_EINVAL, "out must not alias an operand");
+    if (n * kRows > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many ciphertexts for one call");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e;
+    const int64_t words = n * ct_words_of(d);
+    if (linear) {
+        const int64_t blocks = std::min<int64_t>((words + kT - 1) / kT, 1 << 20);
+        hipLaunchKernelGGL(k_ring_linear, dim3((unsigned)blocks), dim3(kT), 0, s, x_dev, y_dev, out_dev, words, d,
+                           logd, gate);
+        e = hipGetLastError();
+        return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_linear");
+    }
+    if (!ws_dev || ws_bytes < words * 8) return sfft_fail(SFFT_EINVAL, "workspace missing or too small");
+    TwView tv;
+    if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
+    uint64_t* rn = (uint64_t*)ws_dev;
+    hipLaunchKernelGGL(k_ring_fwd, dim3((unsigned)(n * kRows)), dim3(kT), (size_t)3 * d * 8, s, y_dev, rn, d, logd,
+                       tv);
+    if ((e = hipGetLastError()) != hipSuccess) return sfft_hip_fail(e, "k_ring_fwd");
+    const int64_t nb = n * kRows;
+    e = d >= 2048 ? launch_product<2>(x_dev, y_dev, rn, out_dev, nb, d, logd, tv, gate, s)
+                  : launch_product<4>(x_dev, y_dev, rn, out_dev, nb, d, logd, tv, gate, s);
+    return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_product");
+}
+
+int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int64_t n, int ct_on_device,
+                      uint8_t* bits_out)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0) return sfft_fail(SFFT_EINVAL, "n < 0");
+    if (n == 0) return SFFT_OK;
+    if (!s_host || !ct || !bits_out) return sfft_fail(SFFT_EINVAL, "null buffer");
+    std::vector<uint64_t> row(2 * (size_t)d);
+    const int r = kEll - 1;  // gadget 2^(ell-1) on column 0
+    for (int64_t c = 0; c < n; ++c) {
+        const uint64_t* src = ct + (c * kRows + r) * 2 * d;
+        if (ct_on_device) {
+            hipError_t e = hipMemcpy(row.data(), src, row.size() * 8, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return sfft_hip_fail(e, "sfft_ring_decrypt");
+        } else {
+            std::memcpy(row.data(), src, row.size() * 8);
+        }
+        // coefficient 0 of c0 - c1*s:  (c1*s)_0 = c1_0 s_0 - sum_{t>0} c1_t s_(d-t)
+        uint64_t cs = mulp(row[d], from_signed(s_host[0]));
+        for (int t = 1; t < d; ++t) cs = subp(cs, mulp(row[d + t], from_signed(s_host[d - t])));
+        const uint64_t x = subp(row[0], cs);
+        const uint64_t mag = x <= kP / 2 ? x : kP - x;
+        bits_out[c] = mag > kP / 4;
+    }
+    return SFFT_OK;
+}
+
+}  // extern "C"

@@ -108,6 +108,12 @@ _SIGS = {
     "sfft_server_drain": (ctypes.c_int, [_vp, _vp]),
     "sfft_server_stats_get": (ctypes.c_int, [_vp, _P(sfft_server_stats)]),
     "sfft_server_destroy": (None, [_vp]),
+    "sfft_ring_ct_words": (ctypes.c_int64, [ctypes.c_int32]),
+    "sfft_ring_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P(ctypes.c_int64)]),
+    "sfft_ring_encrypt": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "sfft_ring_gate": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp,
+                                      ctypes.c_int64, _vp]),
+    "sfft_ring_decrypt": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -285,3 +291,33 @@ def sfft_server_destroy(srv) -> None:
 
 
 EXPORTED = sorted(_SIGS)
+
+
+# ---- ring-GSW gates --------------------------------------------------------
+SFFT_RING_P = 0x3FFFFFFFFFFF0001
+SFFT_RING_ELL = 62
+
+
+def sfft_ring_ct_words(d: int) -> int:
+    w = _lib.sfft_ring_ct_words(d)
+    if w < 0:
+        raise SfftError(int(w), last_error())
+    return w
+
+
+def sfft_ring_workspace_bytes(d: int, n: int) -> int:
+    b = ctypes.c_int64()
+    _check(_lib.sfft_ring_workspace_bytes(d, n, ctypes.byref(b)))
+    return b.value
+
+
+def sfft_ring_encrypt(d, s_dev_ptr, a_dev_ptr, e_dev_ptr, bits_dev_ptr, n, ct_dev_ptr, stream) -> None:
+    _check(_lib.sfft_ring_encrypt(d, s_dev_ptr, a_dev_ptr, e_dev_ptr, bits_dev_ptr, n, ct_dev_ptr, stream))
+
+
+def sfft_ring_gate(d, gate, x_ptr, y_ptr, out_ptr, n, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_ring_gate(d, gate, x_ptr, y_ptr, out_ptr, n, ws_ptr, ws_bytes, stream))
+
+
+def sfft_ring_decrypt(d, s_host_ptr, ct_ptr, n, on_device, bits_out_ptr) -> None:
+    _check(_lib.sfft_ring_decrypt(d, s_host_ptr, ct_ptr, n, int(on_device), bits_out_ptr))
