@@ -38,15 +38,15 @@ using namespace sfft::ring;
 
 namespace {
 
-constexpr int kT = 256;                       // threads per workgroup
-constexpr int kPer = (1 << kMaxLogD) / kT;    // coefficients per thread in the accumulators
+constexpr int kT = 256;  // threads per workgroup
 
 // Transform tables of one d, on the device: forward twiddles psi^brv(k)
-// [0, d), inverse twiddles psi^-brv(k) [d, 2d), d^-1 at [2d].
+// [0, d), inverse twiddles psi^-brv(k) [d, 2d), each with its Shoup
+// quotient, and d^-1.
 struct TwView {
-    const uint64_t* fwd;
-    const uint64_t* inv;
-    uint64_t dinv;
+    const Tw* fwd;
+    const Tw* inv;
+    Tw dinv;
 };
 
 __device__ __forceinline__ void copy_lds(uint64_t* dst, const uint64_t* src, int count)
@@ -54,45 +54,29 @@ __device__ __forceinline__ void copy_lds(uint64_t* dst, const uint64_t* src, int
     for (int t = threadIdx.x; t < count; t += kT) dst[t] = src[t];
 }
 
-// Forward transforms (natural -> bit-reversed order) of np polynomials held
-// back to back in LDS.  binary: the inputs are 0/1, so the first stage's
-// product by the twiddle is a select.  Ends with a barrier.
-__device__ void fwd_lds(uint64_t* a, int np, int d, int logd, const uint64_t* tw, bool binary)
+// Forward transforms (natural -> bit-reversed order) of NP polynomials held
+// back to back in LDS, two stages per barrier.  binary: the inputs are 0/1,
+// so the first stage's products are selects.
+template <int LOGD, int NP>
+__device__ __forceinline__ void fwd_lds(uint64_t* a, const Tw* tw, bool binary)
 {
-    const int half = d >> 1;
-    for (int s = 0; s < logd; ++s) {
-        const int m = 1 << s, t = d >> (s + 1), sh = logd - 1 - s;
-        for (int b = threadIdx.x; b < np * half; b += kT) {
-            const int q = b >> (logd - 1);
-            const int bb = b & (half - 1);
-            const int i = bb >> sh, j = bb & (t - 1);
-            uint64_t* p = a + q * d + 2 * i * t + j;
-            const uint64_t S = tw[m + i];
-            const uint64_t U = p[0];
-            const uint64_t V = (binary && s == 0) ? (p[t] ? S : 0) : mulp(p[t], S);
-            p[0] = addp(U, V);
-            p[t] = subp(U, V);
-        }
+#pragma unroll
+    for (int s = 0; s < LOGD; s += 2) {
+        fwd_round<LOGD, NP>(a, s, tw, threadIdx.x, kT, binary);
         __syncthreads();
     }
 }
 
 // Inverse transforms (bit-reversed -> natural order, without the d^-1
-// scaling) of np polynomials in LDS.  Ends with a barrier.
-__device__ void inv_lds(uint64_t* a, int np, int d, int logd, const uint64_t* tw)
+// scaling) of NP polynomials in LDS.
+template <int LOGD, int NP>
+__device__ __forceinline__ void inv_lds(uint64_t* a, const Tw* tw)
 {
-    const int half = d >> 1;
-    for (int s = logd - 1; s >= 0; --s) {
-        const int m = 1 << s, t = d >> (s + 1), sh = logd - 1 - s;
-        for (int b = threadIdx.x; b < np * half; b += kT) {
-            const int q = b >> (logd - 1);
-            const int bb = b & (half - 1);
-            const int i = bb >> sh, j = bb & (t - 1);
-            uint64_t* p = a + q * d + 2 * i * t + j;
-            const uint64_t U = p[0], V = p[t];
-            p[0] = addp(U, V);
-            p[t] = mulp(subp(U, V), tw[m + i]);
-        }
+#pragma unroll
+    for (int r = 0; r < rounds_of(LOGD); ++r) {
+        bool pair;
+        const int s = inv_stage<LOGD>(r, &pair);
+        inv_round<LOGD, NP>(a, s, pair, tw, threadIdx.x, kT);
         __syncthreads();
     }
 }
@@ -122,66 +106,79 @@ __device__ __forceinline__ uint64_t epilogue(int op, uint64_t P, uint64_t l, uin
     }
 }
 
-// Forward transforms of n_rows rows (both columns of each) of src into dst.
+// Digit polynomials per pass of the product kernel: 4, or 2 at d = 2048
+// (LDS).  Buffers: at least 2 (the two accumulators at the end).
+template <int LOGD>
+struct ProdShape {
+    static constexpr int D = 1 << LOGD;
+    static constexpr int DG = LOGD >= 11 ? 2 : 4;
+    static constexpr int NB = DG > 2 ? DG : 2;
+    static constexpr int PER = D >= kT ? D / kT : 1;        // coefficients per thread
+    static constexpr size_t lds = (size_t)(2 * D + 2 * D + NB * D) * 8;  // twiddles, L row, digits
+};
+
+// Forward transforms of rows (both columns of each) of src into dst.
+template <int LOGD>
 __global__ __launch_bounds__(kT) void k_ring_fwd(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
-                                                 int d, int logd, TwView tw)
+                                                 TwView tw)
 {
+    constexpr int D = 1 << LOGD;
     extern __shared__ uint64_t lds[];
-    uint64_t* t_f = lds;
-    uint64_t* buf = lds + d;
+    Tw* t_f = reinterpret_cast<Tw*>(lds);
+    uint64_t* buf = lds + 2 * D;
     const int64_t row = blockIdx.x;
-    const uint64_t* s = src + row * 2 * d;
-    copy_lds(t_f, tw.fwd, d);
-    copy_lds(buf, s, 2 * d);
+    copy_lds(lds, reinterpret_cast<const uint64_t*>(tw.fwd), 2 * D);
+    copy_lds(buf, src + row * 2 * D, 2 * D);
     __syncthreads();
-    fwd_lds(buf, 2, d, logd, t_f, false);
-    uint64_t* o = dst + row * 2 * d;
-    for (int t = threadIdx.x; t < 2 * d; t += kT) o[t] = buf[t];
+    fwd_lds<LOGD, 2>(buf, t_f, false);
+    uint64_t* o = dst + row * 2 * D;
+    for (int t = threadIdx.x; t < 2 * D; t += kT) o[t] = buf[t];
 }
 
 // out[c] = op(L[c], R[c]) for the product gates (AND, XOR, OR, NAND,
-// PRODUCT).  Rn: R's rows, transformed.  DG digit polynomials per pass.
-template <int DG>
+// PRODUCT).  Rn: R's rows, transformed.
+template <int LOGD>
 __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict__ L, const uint64_t* __restrict__ R,
                                                      const uint64_t* __restrict__ Rn, uint64_t* __restrict__ out,
-                                                     int64_t nblocks, int d, int logd, TwView tw, int op)
+                                                     int64_t nblocks, TwView tw, int op)
 {
+    using S = ProdShape<LOGD>;
+    constexpr int D = S::D, DG = S::DG, PER = S::PER;
     extern __shared__ uint64_t lds[];
-    constexpr int NB = DG > 2 ? DG : 2;
-    uint64_t* t_w = lds;            // d twiddles (forward, then inverse)
-    uint64_t* lrow = lds + d;       // row i of L: 2d
-    uint64_t* dig = lrow + 2 * d;   // NB polynomials
+    Tw* t_w = reinterpret_cast<Tw*>(lds);   // D twiddles (forward, then inverse)
+    uint64_t* lrow = lds + 2 * D;           // row i of L: 2D
+    uint64_t* dig = lrow + 2 * D;           // NB polynomials
     const int64_t lb = xcd_order(blockIdx.x, nblocks);
     const int64_t c = lb / kRows;
     const int i = (int)(lb % kRows);
-    const int64_t row_off = (c * kRows + i) * 2 * d;
-    const uint64_t* rn = Rn + c * kRows * 2 * d;
+    const int64_t row_off = (c * kRows + i) * 2 * D;
+    const uint64_t* rn = Rn + c * kRows * 2 * D;
 
-    copy_lds(t_w, tw.fwd, d);
-    copy_lds(lrow, L + row_off, 2 * d);
-    uint64_t acc0[kPer], acc1[kPer];
+    copy_lds(lds, reinterpret_cast<const uint64_t*>(tw.fwd), 2 * D);
+    copy_lds(lrow, L + row_off, 2 * D);
+    uint64_t acc0[PER], acc1[PER];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) acc0[q] = acc1[q] = 0;
+    for (int q = 0; q < PER; ++q) acc0[q] = acc1[q] = 0;
     __syncthreads();
 
     for (int jj0 = 0; jj0 < kRows; jj0 += DG) {
         // digit polynomials jj0 .. jj0+DG-1: bit (jj mod ell) of L[i][jj div ell]
-        for (int b = threadIdx.x; b < DG * d; b += kT) {
-            const int jj = jj0 + (b >> logd), t = b & (d - 1);
-            dig[b] = (lrow[(jj / kEll) * d + t] >> (jj % kEll)) & 1;
+        for (int b = threadIdx.x; b < DG * D; b += kT) {
+            const int jj = jj0 + b / D, t = b % D;
+            dig[b] = (lrow[(jj / kEll) * D + t] >> (jj % kEll)) & 1;
         }
         __syncthreads();
-        fwd_lds(dig, DG, d, logd, t_w, true);
+        fwd_lds<LOGD, DG>(dig, t_w, true);
 #pragma unroll
         for (int g = 0; g < DG; ++g) {
-            const uint64_t* r0 = rn + (int64_t)(jj0 + g) * 2 * d;
+            const uint64_t* r0 = rn + (int64_t)(jj0 + g) * 2 * D;
 #pragma unroll
-            for (int q = 0; q < kPer; ++q) {
+            for (int q = 0; q < PER; ++q) {
                 const int k = threadIdx.x + q * kT;
-                if (k < d) {
-                    const uint64_t x = dig[g * d + k];
+                if (D >= kT || k < D) {
+                    const uint64_t x = dig[g * D + k];
                     acc0[q] = addp(acc0[q], mulp(x, r0[k]));
-                    acc1[q] = addp(acc1[q], mulp(x, r0[d + k]));
+                    acc1[q] = addp(acc1[q], mulp(x, r0[D + k]));
                 }
             }
         }
@@ -190,22 +187,22 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
 
     // both accumulated polynomials back to coefficients
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < PER; ++q) {
         const int k = threadIdx.x + q * kT;
-        if (k < d) {
+        if (D >= kT || k < D) {
             dig[k] = acc0[q];
-            dig[d + k] = acc1[q];
+            dig[D + k] = acc1[q];
         }
     }
-    copy_lds(t_w, tw.inv, d);
+    copy_lds(lds, reinterpret_cast<const uint64_t*>(tw.inv), 2 * D);
     __syncthreads();
-    inv_lds(dig, 2, d, logd, t_w);
+    inv_lds<LOGD, 2>(dig, t_w);
 
     const uint64_t* rrow = R + row_off;
     uint64_t* orow = out + row_off;
-    for (int b = threadIdx.x; b < 2 * d; b += kT) {
-        const int col = b >> logd, t = b & (d - 1);
-        const uint64_t P = mulp(dig[b], tw.dinv);
+    for (int b = threadIdx.x; b < 2 * D; b += kT) {
+        const int col = b / D, t = b % D;
+        const uint64_t P = mulw(dig[b], tw.dinv);
         orow[b] = epilogue(op, P, lrow[b], rrow[b], gadget(i, col, t));
     }
 }
@@ -230,35 +227,37 @@ __global__ __launch_bounds__(kT) void k_ring_linear(const uint64_t* __restrict__
 
 // Encryption of bits[c] under secret s (signed coefficients): row r of
 // ciphertext c is (a_r*s + e_r, a_r) + bits[c]*G[r].
+template <int LOGD>
 __global__ __launch_bounds__(kT) void k_ring_encrypt(const int64_t* __restrict__ s, const uint64_t* __restrict__ A,
                                                      const int64_t* __restrict__ E, const uint8_t* __restrict__ bits,
-                                                     uint64_t* __restrict__ out, int d, int logd, TwView tw)
+                                                     uint64_t* __restrict__ out, TwView tw)
 {
+    constexpr int D = 1 << LOGD;
     extern __shared__ uint64_t lds[];
-    uint64_t* t_w = lds;
-    uint64_t* buf = lds + d;  // a_r, then s
+    Tw* t_w = reinterpret_cast<Tw*>(lds);
+    uint64_t* buf = lds + 2 * D;  // a_r, then s
     const int64_t cr = blockIdx.x;   // c*rows + r
     const int64_t c = cr / kRows;
     const int r = (int)(cr % kRows);
-    const uint64_t* a = A + cr * d;
-    copy_lds(t_w, tw.fwd, d);
-    for (int t = threadIdx.x; t < d; t += kT) {
+    const uint64_t* a = A + cr * D;
+    copy_lds(lds, reinterpret_cast<const uint64_t*>(tw.fwd), 2 * D);
+    for (int t = threadIdx.x; t < D; t += kT) {
         buf[t] = a[t];
-        buf[d + t] = from_signed(s[t]);
+        buf[D + t] = from_signed(s[t]);
     }
     __syncthreads();
-    fwd_lds(buf, 2, d, logd, t_w, false);
-    for (int t = threadIdx.x; t < d; t += kT) buf[t] = mulp(buf[t], buf[d + t]);
-    copy_lds(t_w, tw.inv, d);
+    fwd_lds<LOGD, 2>(buf, t_w, false);
+    for (int t = threadIdx.x; t < D; t += kT) buf[t] = mulp(buf[t], buf[D + t]);
+    copy_lds(lds, reinterpret_cast<const uint64_t*>(tw.inv), 2 * D);
     __syncthreads();
-    inv_lds(buf, 1, d, logd, t_w);
+    inv_lds<LOGD, 1>(buf, t_w);
     const uint64_t m = bits[c] & 1;
-    const int64_t* e = E + cr * d;
-    uint64_t* o = out + cr * 2 * d;
-    for (int t = threadIdx.x; t < d; t += kT) {
+    const int64_t* e = E + cr * D;
+    uint64_t* o = out + cr * 2 * D;
+    for (int t = threadIdx.x; t < D; t += kT) {
         const uint64_t g0 = m ? gadget(r, 0, t) : 0, g1 = m ? gadget(r, 1, t) : 0;
-        o[t] = addp(addp(mulp(buf[t], tw.dinv), from_signed(e[t])), g0);
-        o[d + t] = addp(a[t], g1);
+        o[t] = addp(addp(mulw(buf[t], tw.dinv), from_signed(e[t])), g0);
+        o[D + t] = addp(a[t], g1);
     }
 }
 
@@ -297,8 +296,10 @@ uint64_t root_2d(int d)
     }
 }
 
+Tw shoup(uint64_t w) { return Tw{w, (uint64_t)(((unsigned __int128)w << 64) / kP)}; }
+
 std::mutex g_tw_mu;
-std::map<std::pair<int, int>, uint64_t*> g_tw;  // (device, d) -> tables
+std::map<std::pair<int, int>, Tw*> g_tw;  // (device, d) -> tables
 
 int tables(int d, int logd, TwView* tv)
 {
@@ -307,20 +308,19 @@ int tables(int d, int logd, TwView* tv)
     if (e != hipSuccess) return sfft_hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_tw_mu);
     auto it = g_tw.find({dev, d});
-    uint64_t* p = nullptr;
+    Tw* p = nullptr;
     if (it != g_tw.end()) {
         p = it->second;
     } else {
-        std::vector<uint64_t> h(2 * (size_t)d + 1);
+        std::vector<Tw> h(2 * (size_t)d);
         const uint64_t psi = root_2d(d), ipsi = powp(psi, kP - 2);
         for (int k = 0; k < d; ++k) {
-            h[k] = powp(psi, (uint64_t)brv(k, logd));
-            h[d + k] = powp(ipsi, (uint64_t)brv(k, logd));
+            h[k] = shoup(powp(psi, (uint64_t)brv(k, logd)));
+            h[d + k] = shoup(powp(ipsi, (uint64_t)brv(k, logd)));
         }
-        h[2 * d] = powp((uint64_t)d, kP - 2);
-        e = hipMalloc(&p, h.size() * 8);
+        e = hipMalloc(&p, h.size() * sizeof(Tw));
         if (e != hipSuccess) return sfft_hip_fail(e, "ring tables");
-        e = hipMemcpy(p, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+        e = hipMemcpy(p, h.data(), h.size() * sizeof(Tw), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(p);
             return sfft_hip_fail(e, "ring tables");
@@ -329,26 +329,56 @@ int tables(int d, int logd, TwView* tv)
     }
     tv->fwd = p;
     tv->inv = p + d;
-    tv->dinv = powp((uint64_t)d, kP - 2);
+    tv->dinv = shoup(powp((uint64_t)d, kP - 2));
     return SFFT_OK;
 }
 
-template <int DG>
-hipError_t launch_product(const uint64_t* L, const uint64_t* R, const uint64_t* Rn, uint64_t* out, int64_t nb, int d,
-                          int logd, TwView tv, int op, hipStream_t s)
+// Lets a kernel take up to 160 KB of LDS, once per instantiation.
+template <typename K>
+hipError_t allow_lds(K kernel, bool* done)
 {
-    constexpr int NB = DG > 2 ? DG : 2;
-    const size_t lds = (size_t)(3 + NB) * d * 8;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_ring_product<DG>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL(k_ring_product<DG>, dim3((unsigned)nb), dim3(kT), lds, s, L, R, Rn, out, nb, d, logd, tv, op);
+    if (*done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess) *done = true;
+    return e;
+}
+
+template <int LOGD>
+hipError_t launch_gate(const uint64_t* L, const uint64_t* R, uint64_t* Rn, uint64_t* out, int64_t n, TwView tv, int op,
+                       hipStream_t s)
+{
+    constexpr int D = 1 << LOGD;
+    static bool a1 = false, a2 = false;
+    hipError_t e = allow_lds(k_ring_fwd<LOGD>, &a1);
+    if (e == hipSuccess) e = allow_lds(k_ring_product<LOGD>, &a2);
+    if (e != hipSuccess) return e;
+    const int64_t nb = n * kRows;
+    hipLaunchKernelGGL(k_ring_fwd<LOGD>, dim3((unsigned)nb), dim3(kT), (size_t)4 * D * 8, s, R, Rn, tv);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ring_product<LOGD>, dim3((unsigned)nb), dim3(kT), ProdShape<LOGD>::lds, s, L, R, Rn, out, nb,
+                       tv, op);
     return hipGetLastError();
 }
+
+template <int LOGD>
+hipError_t launch_encrypt(const int64_t* sd, const uint64_t* a, const int64_t* ed, const uint8_t* bits, int64_t n,
+                          uint64_t* ct, TwView tv, hipStream_t s)
+{
+    constexpr int D = 1 << LOGD;
+    static bool a1 = false;
+    hipError_t e = allow_lds(k_ring_encrypt<LOGD>, &a1);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ring_encrypt<LOGD>, dim3((unsigned)(n * kRows)), dim3(kT), (size_t)4 * D * 8, s, sd, a, ed,
+                       bits, ct, tv);
+    return hipGetLastError();
+}
+
+// Calls F<LOGD>::run(args...) for the run-time logd (0..kMaxLogD).
+#define SFFT_RING_DISPATCH(logd, CALL)                                                                            \
+    switch (logd) {                                                                                               \
+    case 0: CALL(0); case 1: CALL(1); case 2: CALL(2); case 3: CALL(3); case 4: CALL(4); case 5: CALL(5);        \
+    case 6: CALL(6); case 7: CALL(7); case 8: CALL(8); case 9: CALL(9); case 10: CALL(10); default: CALL(11);    \
+    }
 
 int check_d(int32_t d, int* logd)
 {
@@ -394,9 +424,10 @@ int sfft_ring_encrypt(int32_t d, const int64_t* s_dev, const uint64_t* a_dev, co
     TwView tv;
     if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    hipLaunchKernelGGL(k_ring_encrypt, dim3((unsigned)(n * kRows)), dim3(kT), (size_t)3 * d * 8, s, s_dev, a_dev,
-                       e_dev, bits_dev, ct_dev, d, logd, tv);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
+#define SFFT_ENC(L) { e = launch_encrypt<L>(s_dev, a_dev, e_dev, bits_dev, n, ct_dev, tv, s); break; }
+    SFFT_RING_DISPATCH(logd, SFFT_ENC)
+#undef SFFT_ENC
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_encrypt");
 }
 
@@ -426,12 +457,9 @@ int sfft_ring_gate(int32_t d, int32_t gate, const uint64_t* x_dev, const uint64_
     TwView tv;
     if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
     uint64_t* rn = (uint64_t*)ws_dev;
-    hipLaunchKernelGGL(k_ring_fwd, dim3((unsigned)(n * kRows)), dim3(kT), (size_t)3 * d * 8, s, y_dev, rn, d, logd,
-                       tv);
-    if ((e = hipGetLastError()) != hipSuccess) return sfft_hip_fail(e, "k_ring_fwd");
-    const int64_t nb = n * kRows;
-    e = d >= 2048 ? launch_product<2>(x_dev, y_dev, rn, out_dev, nb, d, logd, tv, gate, s)
-                  : launch_product<4>(x_dev, y_dev, rn, out_dev, nb, d, logd, tv, gate, s);
+#define SFFT_GATE(L) { e = launch_gate<L>(x_dev, y_dev, rn, out_dev, n, tv, gate, s); break; }
+    SFFT_RING_DISPATCH(logd, SFFT_GATE)
+#undef SFFT_GATE
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_product");
 }
 

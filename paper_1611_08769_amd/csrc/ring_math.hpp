@@ -65,6 +65,30 @@ __host__ __device__ __forceinline__ uint64_t mulp(uint64_t a, uint64_t b)
     return w >= kP ? w - kP : w;
 }
 
+// A constant multiplier w < p with its Shoup quotient ws = floor(w * 2^64 / p)
+// (V. Shoup, NTL; D. Harvey, "Faster arithmetic for number-theoretic
+// transforms", J. Symb. Comp. 2014).
+struct Tw {
+    uint64_t w, ws;
+};
+
+// a*w mod p for a < p by Shoup's method: q = floor(a*ws / 2^64) estimates
+// floor(a*w / p) from below by at most 1, so a*w - q*p (computed mod 2^64)
+// lies in [0, 2p).  q is taken from three of the four partial products of
+// a*ws (the dropped low one moves it down by at most 1 more), so the
+// remainder lies in [0, 3p) before the final corrections.  q*p mod 2^64 is
+// (q << 62) - (q << 16) + q.
+__host__ __device__ __forceinline__ uint64_t mulw(uint64_t a, Tw t)
+{
+    const uint64_t al = (uint32_t)a, ah = a >> 32, wl = (uint32_t)t.ws, wh = t.ws >> 32;
+    const uint64_t m1 = al * wh, m2 = ah * wl;
+    const uint64_t ms = m1 + m2;
+    const uint64_t q = ah * wh + (ms >> 32) + ((uint64_t)(ms < m1) << 32);
+    uint64_t r = a * t.w - ((q << 62) - (q << 16) + q);
+    r = r >= 2 * kP ? r - 2 * kP : r;
+    return r >= kP ? r - kP : r;
+}
+
 inline uint64_t powp(uint64_t a, uint64_t e)
 {
     uint64_t r = 1;
@@ -81,6 +105,128 @@ __host__ __device__ __forceinline__ uint64_t from_signed(int64_t v)
 {
     return v >= 0 ? (uint64_t)v % kP : kP - (uint64_t)(-v) % kP;
 }
+
+// ---- transforms, one LDS round at a time --------------------------------
+// The caller runs the rounds in order with a barrier after each; a round
+// spreads its butterflies over nt threads (thread tid takes every nt-th).
+// np polynomials of 2^LOGD coefficients lie back to back at a.  tw holds the
+// 2^LOGD twiddles of the direction, index m + i for group i of a stage with
+// m groups.
+
+// Cooley-Tukey butterfly (x, y) -> (x + w*y, x - w*y); Gentleman-Sande
+// butterfly (x, y) -> (x + y, (x - y)*w).
+__host__ __device__ __forceinline__ void bf_ct(uint64_t& x, uint64_t& y, Tw t)
+{
+    const uint64_t v = mulw(y, t);
+    y = subp(x, v);
+    x = addp(x, v);
+}
+__host__ __device__ __forceinline__ void bf_gs(uint64_t& x, uint64_t& y, Tw t)
+{
+    const uint64_t u = x;
+    x = addp(u, y);
+    y = mulw(subp(u, y), t);
+}
+// A Cooley-Tukey butterfly whose y is 0 or 1 (a digit): the product is a select.
+__host__ __device__ __forceinline__ void bf_ct_bit(uint64_t& x, uint64_t& y, Tw t)
+{
+    const uint64_t v = y ? t.w : 0;
+    y = subp(x, v);
+    x = addp(x, v);
+}
+
+// Forward round starting at stage s (natural -> bit-reversed order): stages s
+// and s+1 as radix-4 on quadruples, or stage s alone when it is the last.
+// binary: the inputs are 0/1 (only meaningful for s = 0).
+template <int LOGD, int NP>
+__host__ __device__ __forceinline__ void fwd_round(uint64_t* a, int s, const Tw* tw, int tid, int nt, bool binary)
+{
+    constexpr int D = 1 << LOGD;
+    if (s + 1 < LOGD) {
+        const int t = D >> (s + 1), h = t >> 1, m = 1 << s;
+        constexpr int Q = D >> 2;
+        for (int b = tid; b < NP * Q; b += nt) {
+            const int q = b / Q, bb = b % Q;
+            const int i = bb / h, j = bb % h;
+            uint64_t* p = a + q * D + 2 * i * t + j;
+            uint64_t x0 = p[0], x1 = p[h], x2 = p[t], x3 = p[t + h];
+            const Tw w1 = tw[m + i];
+            if (binary && s == 0) {
+                bf_ct_bit(x0, x2, w1);
+                bf_ct_bit(x1, x3, w1);
+            } else {
+                bf_ct(x0, x2, w1);
+                bf_ct(x1, x3, w1);
+            }
+            bf_ct(x0, x1, tw[2 * m + 2 * i]);
+            bf_ct(x2, x3, tw[2 * m + 2 * i + 1]);
+            p[0] = x0;
+            p[h] = x1;
+            p[t] = x2;
+            p[t + h] = x3;
+        }
+    } else if (s < LOGD) {
+        constexpr int H = D >> 1;
+        for (int b = tid; b < NP * H; b += nt) {
+            const int q = b / H, i = b % H;
+            uint64_t* p = a + q * D + 2 * i;
+            if (binary && s == 0)
+                bf_ct_bit(p[0], p[1], tw[H + i]);
+            else
+                bf_ct(p[0], p[1], tw[H + i]);
+        }
+    }
+}
+
+// Inverse round (bit-reversed -> natural order): pair = stages s and s-1 as
+// radix-4, else stage s alone.
+template <int LOGD, int NP>
+__host__ __device__ __forceinline__ void inv_round(uint64_t* a, int s, bool pair, const Tw* tw, int tid, int nt)
+{
+    constexpr int D = 1 << LOGD;
+    if (pair) {
+        const int t = D >> (s + 1), m = 1 << s;
+        constexpr int Q = D >> 2;
+        for (int b = tid; b < NP * Q; b += nt) {
+            const int q = b / Q, bb = b % Q;
+            const int i2 = bb / t, j = bb % t;
+            uint64_t* p = a + q * D + 4 * i2 * t + j;
+            uint64_t x0 = p[0], x1 = p[t], x2 = p[2 * t], x3 = p[3 * t];
+            bf_gs(x0, x1, tw[m + 2 * i2]);
+            bf_gs(x2, x3, tw[m + 2 * i2 + 1]);
+            const Tw w2 = tw[(m >> 1) + i2];
+            bf_gs(x0, x2, w2);
+            bf_gs(x1, x3, w2);
+            p[0] = x0;
+            p[t] = x1;
+            p[2 * t] = x2;
+            p[3 * t] = x3;
+        }
+    } else {
+        const int t = D >> (s + 1), m = 1 << s;
+        for (int b = tid; b < NP * (D >> 1); b += nt) {
+            const int q = b / (D >> 1), bb = b % (D >> 1);
+            const int i = bb / t, j = bb % t;
+            uint64_t* p = a + q * D + 2 * i * t + j;
+            bf_gs(p[0], p[t], tw[m + i]);
+        }
+    }
+}
+
+// Round schedules.  Forward: rounds start at s = 0, 2, 4, ... (< LOGD).
+// Inverse: with LOGD odd, stage LOGD-1 alone first; then pairs (s, s-1) for s
+// descending by 2 down to 1.
+template <int LOGD>
+__host__ __device__ __forceinline__ int inv_stage(int r, bool* pair)
+{
+    if (LOGD & 1) {
+        *pair = r > 0;
+        return r == 0 ? LOGD - 1 : LOGD - 2 - 2 * (r - 1);
+    }
+    *pair = true;
+    return LOGD - 1 - 2 * r;
+}
+constexpr int rounds_of(int logd) { return (logd + 1) / 2; }
 
 }  // namespace ring
 }  // namespace sfft
