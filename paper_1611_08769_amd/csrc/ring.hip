@@ -14,7 +14,10 @@
 //                   build D_ij in LDS, transform it there, multiply-accumulate
 //                   against R's transformed row j in registers; then the
 //                   inverse transform of the two accumulated polynomials and
-//                   the gate's affine epilogue in the coefficient domain
+//                   the gate's affine epilogue in the coefficient domain.
+//                   Twiddles are read from the (L1-resident) global tables,
+//                   which keeps the workgroup's LDS at 48 KB for d = 1024
+//                   (three workgroups per CU).
 //   k_ring_linear   NOT and XADD (no product)
 //   k_ring_encrypt  one workgroup per (ciphertext, row): a*s by transforms,
 //                   plus the error and the gadget
@@ -111,10 +114,10 @@ __device__ __forceinline__ uint64_t epilogue(int op, uint64_t P, uint64_t l, uin
 template <int LOGD>
 struct ProdShape {
     static constexpr int D = 1 << LOGD;
-    static constexpr int DG = LOGD >= 11 ? 2 : 4;
+    static constexpr int DG = LOGD >= 11 ? 2 : 4;   // also bounds the unreduced pointwise sums (<= 4 terms)
     static constexpr int NB = DG > 2 ? DG : 2;
     static constexpr int PER = D >= kT ? D / kT : 1;        // coefficients per thread
-    static constexpr size_t lds = (size_t)(2 * D + 2 * D + NB * D) * 8;  // twiddles, L row, digits
+    static constexpr size_t lds = (size_t)(2 * D + NB * D) * 8;  // L row, digits
 };
 
 // Forward transforms of rows (both columns of each) of src into dst.
@@ -145,8 +148,7 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
     using S = ProdShape<LOGD>;
     constexpr int D = S::D, DG = S::DG, PER = S::PER;
     extern __shared__ uint64_t lds[];
-    Tw* t_w = reinterpret_cast<Tw*>(lds);   // D twiddles (forward, then inverse)
-    uint64_t* lrow = lds + 2 * D;           // row i of L: 2D
+    uint64_t* lrow = lds;                   // row i of L: 2D
     uint64_t* dig = lrow + 2 * D;           // NB polynomials
     const int64_t lb = xcd_order(blockIdx.x, nblocks);
     const int64_t c = lb / kRows;
@@ -154,7 +156,6 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
     const int64_t row_off = (c * kRows + i) * 2 * D;
     const uint64_t* rn = Rn + c * kRows * 2 * D;
 
-    copy_lds(lds, reinterpret_cast<const uint64_t*>(tw.fwd), 2 * D);
     copy_lds(lrow, L + row_off, 2 * D);
     uint64_t acc0[PER], acc1[PER];
 #pragma unroll
@@ -168,18 +169,23 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
             dig[b] = (lrow[(jj / kEll) * D + t] >> (jj % kEll)) & 1;
         }
         __syncthreads();
-        fwd_lds<LOGD, DG>(dig, t_w, true);
+        fwd_lds<LOGD, DG>(dig, tw.fwd, true);
+        // pointwise products against R's transformed rows jj0..jj0+DG-1,
+        // summed unreduced (DG <= 4 products stay below 2^126), reduced once
 #pragma unroll
-        for (int g = 0; g < DG; ++g) {
-            const uint64_t* r0 = rn + (int64_t)(jj0 + g) * 2 * D;
+        for (int q = 0; q < PER; ++q) {
+            const int k = threadIdx.x + q * kT;
+            if (D >= kT || k < D) {
+                uint64_t l0 = 0, h0 = 0, l1 = 0, h1 = 0;
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int k = threadIdx.x + q * kT;
-                if (D >= kT || k < D) {
+                for (int g = 0; g < DG; ++g) {
+                    const uint64_t* r0 = rn + (int64_t)(jj0 + g) * 2 * D;
                     const uint64_t x = dig[g * D + k];
-                    acc0[q] = addp(acc0[q], mulp(x, r0[k]));
-                    acc1[q] = addp(acc1[q], mulp(x, r0[D + k]));
+                    mac128(x, r0[k], &l0, &h0);
+                    mac128(x, r0[D + k], &l1, &h1);
                 }
+                acc0[q] = addp(acc0[q], red126(l0, h0));
+                acc1[q] = addp(acc1[q], red126(l1, h1));
             }
         }
         __syncthreads();
@@ -194,9 +200,8 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
             dig[D + k] = acc1[q];
         }
     }
-    copy_lds(lds, reinterpret_cast<const uint64_t*>(tw.inv), 2 * D);
     __syncthreads();
-    inv_lds<LOGD, 2>(dig, t_w);
+    inv_lds<LOGD, 2>(dig, tw.inv);
 
     const uint64_t* rrow = R + row_off;
     uint64_t* orow = out + row_off;

@@ -65,6 +65,32 @@ __host__ __device__ __forceinline__ uint64_t mulp(uint64_t a, uint64_t b)
     return w >= kP ? w - kP : w;
 }
 
+// x mod p for a 128-bit x = hi*2^64 + lo below 2^126 (a sum of up to four
+// products of residues).  x = xh*2^62 + xl with xh < 2^64; xh*2^62 = xh*(2^16 - 1)
+// and xh*2^16 splits again at bit 62; -xh enters as p - (xh mod p).
+__host__ __device__ __forceinline__ uint64_t red126(uint64_t lo, uint64_t hi)
+{
+    const uint64_t xl = lo & kM62;
+    const uint64_t xh = (hi << 2) | (lo >> 62);
+    const uint64_t yh = xh >> 46, yl = (xh << 16) & kM62;
+    uint64_t xr = (xh & kM62) + (((xh >> 62) << 16) - (xh >> 62));  // xh mod p, below 2p
+    xr = xr >= kP ? xr - kP : xr;
+    const uint64_t z = xl + yl + ((yh << 16) - yh) + (kP - xr);      // < 3*2^62 + 2^34
+    const uint64_t zh = z >> 62, zl = z & kM62;
+    const uint64_t w = zl + ((zh << 16) - zh);
+    return w >= kP ? w - kP : w;
+}
+
+// (hi, lo) += a*b for residues a, b (no reduction).
+__host__ __device__ __forceinline__ void mac128(uint64_t a, uint64_t b, uint64_t* lo, uint64_t* hi)
+{
+    uint64_t l, h;
+    mul128(a, b, &l, &h);
+    const uint64_t s = *lo + l;
+    *hi += h + (s < l);
+    *lo = s;
+}
+
 // A constant multiplier w < p with its Shoup quotient ws = floor(w * 2^64 / p)
 // (V. Shoup, NTL; D. Harvey, "Faster arithmetic for number-theoretic
 // transforms", J. Symb. Comp. 2014).
