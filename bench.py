@@ -259,6 +259,46 @@ def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_c
     print(json.dumps(out, indent=1))
 
 
+def ring_traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """HBM bytes of the last ring gate call (k_ring_fwd + k_ring_product) from
+    the rocprofv3 counter CSVs of a bench run, each counter scaled by what it
+    reads for the 1 GiB copy."""
+    import csv
+    import hashlib
+
+    def per_call(path):
+        rows = [(r["Kernel_Name"], float(r["Counter_Value"])) for r in csv.DictReader(open(path))]
+        fwd = [v for n, v in rows if "k_ring_fwd" in n]
+        prod = [v for n, v in rows if "k_ring_product" in n]
+        return fwd[-1] + prod[-1], prod[-1]
+
+    (fk, fk_prod), (wk, wk_prod) = per_call(fetch_csv), per_call(write_csv)
+    cf = max(_counter_rows(copy_fetch_csv, "__amd_rocclr_copyBuffer"))
+    cw = max(_counter_rows(copy_write_csv, "__amd_rocclr_copyBuffer"))
+    gib = float(1 << 30)
+    fetch_scale, write_scale = gib / (cf * 1024), gib / (cw * 1024)
+    src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "ring.hip")
+    out = {
+        "workload": workload,
+        "kernel": "k_ring_fwd + k_ring_product",
+        "ring_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "fetch_kib_per_call": fk,
+        "write_kib_per_call": wk,
+        "fetch_kib_product": fk_prod,
+        "write_kib_product": wk_prod,
+        "fetch_scale": fetch_scale,
+        "write_scale": write_scale,
+        "traffic_bytes_per_call": (fk * fetch_scale + wk * write_scale) * 1024,
+        "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py "
+                   "--workload %s --steps 1 --warmup 0 --no-cpu-baseline; the same for python3 bench.py "
+                   "--copy-probe; python3 bench.py --traffic-summary on the four CSVs (the last gate call)" % workload,
+    }
+    path = os.path.join(ROOT, "profiles", "traffic_k_ring_product_%s.json" % workload)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def _product_levels(workload):
     from paper_1611_08769_amd import sfft as S
     from paper_1611_08769_amd import workloads as WL
@@ -553,6 +593,14 @@ def run_ring(args):
     assert dec.tolist() == (xb & yb).tolist(), "ring AND decryptions differ from the plaintext"
     avg_s = sum(launch_ms) / len(launch_ms) / 1e3
     mm = ring_modmuls_per_gate(d) * n
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_k_ring_product_%s.json" % args.workload)
+    if os.path.exists(tpath) and n == 128:
+        import hashlib
+        tr = json.load(open(tpath))
+        src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "ring.hip")
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() == tr.get("ring_hip_sha256"):
+            traffic = tr["traffic_bytes_per_call"]
     res = {
         "metric": "encrypted ring-GSW gates/s (1 GPU)",
         "value": n * args.steps / wall,
@@ -569,7 +617,8 @@ def run_ring(args):
         "config": {"workload": args.workload, "d": d, "gates_per_step": n, "gate": "AND", "ell": S.SFFT_RING_ELL,
                    "p": "2^62-2^16+1", "ct_bytes": S.sfft_ring_ct_words(d) * 8},
         "roofline": {"bound": "alu", "achieved": mm / avg_s / 1e9, "peak": PEAK_MODMUL / 1e9,
-                     "unit": "Gmodmul/s", "frac": mm / avg_s / PEAK_MODMUL, "traffic": None,
+                     "unit": "Gmodmul/s", "frac": mm / avg_s / PEAK_MODMUL, "traffic": traffic,
+                     "algorithmic_bytes": 3 * n * S.sfft_ring_ct_words(d) * 8,
                      "kernel": "k_ring_fwd + k_ring_product", "avg_launch_ms": avg_s * 1e3,
                      "modmul_per_gate": ring_modmuls_per_gate(d)},
     }
@@ -622,7 +671,10 @@ def main():
                     help="summarise a rocprofv3 kernel trace of a bench run (its --steps timed FFTs)")
     args = ap.parse_args()
     if args.traffic_summary:
-        traffic_summary(args.workload, *args.traffic_summary)
+        if args.workload.startswith("ring_and_d"):
+            ring_traffic_summary(args.workload, *args.traffic_summary)
+        else:
+            traffic_summary(args.workload, *args.traffic_summary)
         return
     if args.trace_summary:
         trace_summary(args.workload, args.trace_summary, args.steps)
