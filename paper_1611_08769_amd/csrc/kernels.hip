@@ -1120,13 +1120,10 @@ template <int THREADS, int LPR, int DPL, int RPL, int PD, int CG, bool ENC>
 hipError_t launch_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0, const ProdItem& one,
                     int64_t blocks, uint64_t seed, uint64_t first_id, const MuBits* mu, hipStream_t s)
 {
-    static int attr_bytes = 64 * 1024;
-    if (cfg.lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_product<THREADS, LPR, DPL, RPL, PD, CG, ENC>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, cfg.lds_bytes);
-        if (e != hipSuccess) return e;
-        attr_bytes = cfg.lds_bytes;
-    }
+    // the LDS cap, once per instantiation (thread-safe static initialisation)
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)k_product<THREADS, LPR, DPL, RPL, PD, CG, ENC>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     const KCfg kc{1u};
@@ -1140,13 +1137,10 @@ template <int RG, int CG, int CF, bool PRE>
 hipError_t launch_mfma_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
                          const ProdItem& one, int64_t blocks, hipStream_t s)
 {
-    static int attr_bytes = 64 * 1024;
-    if (cfg.lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_product_mfma<RG, CG, CF, PRE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, cfg.lds_bytes);
-        if (e != hipSuccess) return e;
-        attr_bytes = cfg.lds_bytes;
-    }
+    // the LDS cap, once per instantiation (thread-safe static initialisation)
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)k_product_mfma<RG, CG, CF, PRE>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_product_mfma<RG, CG, CF, PRE>), dim3((unsigned)blocks), dim3(RG * CG * 64), cfg.lds_bytes, s,
@@ -1390,13 +1384,10 @@ hipError_t launch_rtrans(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
                          const ProdItem& one, int64_t items, hipStream_t s)
 {
     constexpr int kMaxChunkBytes = 12 * 32 * kMfmaChunk;  // rows of up to 12 fragments
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_rtrans, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kMaxChunkBytes);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    // once (thread-safe static initialisation)
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)k_rtrans, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxChunkBytes);
+    if (attr != hipSuccess) return attr;
     if (items <= 0) return hipSuccess;
     if (items > 0x7FFFFFFF) return hipErrorInvalidValue;
     // chunks of the widest row the tiling serves (Nct = 32 W <= 256 CG CF)

@@ -338,14 +338,11 @@ int tables(int d, int logd, TwView* tv)
     return SFFT_OK;
 }
 
-// Lets a kernel take up to 160 KB of LDS, once per instantiation.
+// Lets a kernel take up to 160 KB of LDS.
 template <typename K>
-hipError_t allow_lds(K kernel, bool* done)
+hipError_t allow_lds(K kernel)
 {
-    if (*done) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e == hipSuccess) *done = true;
-    return e;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 template <int LOGD>
@@ -353,9 +350,12 @@ hipError_t launch_gate(const uint64_t* L, const uint64_t* R, uint64_t* Rn, uint6
                        hipStream_t s)
 {
     constexpr int D = 1 << LOGD;
-    static bool a1 = false, a2 = false;
-    hipError_t e = allow_lds(k_ring_fwd<LOGD>, &a1);
-    if (e == hipSuccess) e = allow_lds(k_ring_product<LOGD>, &a2);
+    // once per instantiation (thread-safe static initialisation)
+    static const hipError_t attr = [] {
+        hipError_t e = allow_lds(k_ring_fwd<LOGD>);
+        return e == hipSuccess ? allow_lds(k_ring_product<LOGD>) : e;
+    }();
+    hipError_t e = attr;
     if (e != hipSuccess) return e;
     const int64_t nb = n * kRows;
     hipLaunchKernelGGL(k_ring_fwd<LOGD>, dim3((unsigned)nb), dim3(kT), (size_t)4 * D * 8, s, R, Rn, tv);
@@ -370,8 +370,8 @@ hipError_t launch_encrypt(const int64_t* sd, const uint64_t* a, const int64_t* e
                           uint64_t* ct, TwView tv, hipStream_t s)
 {
     constexpr int D = 1 << LOGD;
-    static bool a1 = false;
-    hipError_t e = allow_lds(k_ring_encrypt<LOGD>, &a1);
+    static const hipError_t attr = allow_lds(k_ring_encrypt<LOGD>);
+    hipError_t e = attr;
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ring_encrypt<LOGD>, dim3((unsigned)(n * kRows)), dim3(kT), (size_t)4 * D * 8, s, sd, a, ed,
                        bits, ct, tv);
