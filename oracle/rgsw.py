@@ -61,6 +61,8 @@ def lib():
         L.rg_gate_rows.restype = c.c_int
         L.rg_gate_rows.argtypes = [c.c_uint64, c.c_int, c.c_int, c.c_int, u64p, u64p, i64p,
                                    np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), c.c_int64, u64p]
+        L.rg_blind_rotate.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64,
+                                      np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), u64p, c.c_int64]
         L.rg_phase.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int, u64p, u64p]
         L.rg_decrypt.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, u8p]
         _lib = L
@@ -116,6 +118,27 @@ def gate_rows(op: int, L, R, cts, rows) -> np.ndarray:
     out = np.zeros((len(cts), 2, d), dtype=np.uint64)
     if lib().rg_gate_rows(P, d, ELL, op, L, R, cts, rows, len(cts), out) != 0:
         raise ValueError("unknown gate %d" % op)
+    return out
+
+
+def blind_rotate(bk, rot, acc) -> np.ndarray:
+    """Blind rotation of ring-LWE accumulators acc (m, 2, d) by the ring-GSW
+    key bk (n, ROWS, 2, d) with rotations rot (m, n) in [0, 2d): returns the
+    accumulators after the n CMux steps (see rgsw_ref.c)."""
+    bk = _u64(bk)
+    out = np.array(acc, dtype=np.uint64, copy=True, order="C")
+    rot = np.ascontiguousarray(rot, dtype=np.int32)
+    m, n = rot.shape
+    assert bk.shape[0] == n and out.shape == (m, 2, bk.shape[3])
+    lib().rg_blind_rotate(P, bk.shape[3], ELL, bk, n, rot, out, m)
+    return out
+
+
+def rlwe_phase(acc, s_signed) -> np.ndarray:
+    """b - a*s of one ring-LWE ciphertext (2, d)."""
+    acc = _u64(acc)
+    out = np.zeros(acc.shape[1], dtype=np.uint64)
+    lib().rg_phase(P, acc.shape[1], ELL, acc, 0, _u64(mod_p(s_signed)), out)
     return out
 
 

@@ -185,6 +185,46 @@ int rg_gate_rows(uint64_t p, int d, int ell, int op, const uint64_t *L, const ui
     return 0;
 }
 
+/* Blind rotation (the core of FHEW/TFHE-style refresh, written for this
+ * scheme's ring-GSW ciphertexts as the key): m ring-LWE accumulators acc[j] =
+ * (b, a), 2d words each, and n ring-GSW encryptions bk[i] of bits s_i.  Step i
+ * replaces acc[j] by the CMux of bk[i] between acc[j] and X^r acc[j]
+ * (r = rot[j*n + i] in [0, 2d)):
+ *     acc <- acc + G^-1(X^r acc - acc) * bk[i]
+ * (external product: the row vector of digit polynomials of X^r acc - acc
+ * times the 2*ell x 2 matrix bk[i]).  X^r is applied as a product with the
+ * monomial X^r (X^d = -1).  So acc[j] ends as an encryption of
+ * X^(sum_i r_i s_i) times what it encrypted. */
+void rg_blind_rotate(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, const int32_t *rot, uint64_t *acc,
+                     int64_t m)
+{
+    const int64_t ct = (int64_t)2 * ell * 2 * d;
+    #pragma omp parallel
+    {
+        uint64_t *w = malloc(sizeof(uint64_t) * 9 * d);
+        uint64_t *mono = w, *diff = w + d, *o0 = w + 3 * d, *o1 = w + 4 * d, *bits = w + 5 * d, *tmp = w + 6 * d;
+        #pragma omp for schedule(dynamic)
+        for (int64_t j = 0; j < m; j++) {
+            uint64_t *a = acc + j * 2 * d;
+            for (int64_t i = 0; i < n; i++) {
+                int r = rot[j * n + i];
+                memset(mono, 0, sizeof(uint64_t) * d);
+                if (r < d) mono[r] = 1; else mono[r - d] = p - 1;       /* X^r */
+                for (int col = 0; col < 2; col++) {
+                    rg_negmul(p, d, mono, a + col * d, tmp);
+                    for (int t = 0; t < d; t++) diff[col * d + t] = subm(tmp[t], a[col * d + t], p);
+                }
+                product_row(p, d, ell, diff, bk + i * ct, 0, o0, o1, bits, tmp);
+                for (int t = 0; t < d; t++) {
+                    a[t] = addm(a[t], o0[t], p);
+                    a[d + t] = addm(a[d + t], o1[t], p);
+                }
+            }
+        }
+        free(w);
+    }
+}
+
 /* Phase of one row: C[row][0] - C[row][1]*s  (d coefficients). */
 void rg_phase(uint64_t p, int d, int ell, const uint64_t *ct, int row, const uint64_t *s, uint64_t *out)
 {

@@ -6,7 +6,10 @@
   noiseless encryption of 1) is a two-sided unit of the product, and the
   zero matrix annihilates it;
 * the exact phase of a fresh encryption, row by row;
-* gate truth tables, the noise bound of one product, and a depth-3 circuit.
+* gate truth tables, the noise bound of one product, and a depth-3 circuit;
+* blind rotation: with a noiseless key it is exactly the rotation by
+  X^(sum r_i s_i) (coefficients moved by hand); with a real key it decrypts
+  to the rotated test polynomial within n * 2*ell*d * B.
 """
 import numpy as np
 import pytest
@@ -144,3 +147,60 @@ def test_depth_three_circuit():
     bits = [x.bits.astype(int) for x in ds]
     want = ((bits[0] & bits[1]) ^ bits[2]) | (1 - bits[3])
     assert R.decrypt(t3, ds[0].s).tolist() == want.tolist()
+
+
+def _rotate(a, r, d):
+    """X^r * a in Z_p[X]/(X^d + 1), by moving coefficients (r taken mod 2d)."""
+    out = [0] * d
+    r %= 2 * d
+    for u in range(d):
+        e = u + r
+        sign = 1
+        while e >= d:
+            e -= d
+            sign = -sign
+        out[e] = (out[e] + sign * int(a[u])) % R.P
+    return out
+
+
+def test_blind_rotation_with_noiseless_key_is_an_exact_rotation():
+    """With bk[i] = s_i * G (no error), each CMux step is exact: the result is
+    X^(sum r_i s_i) * acc, coefficient for coefficient."""
+    d, n, m = 16, 5, 3
+    g = np.random.Generator(np.random.PCG64(8))
+    bits = g.integers(0, 2, size=n)
+    bk = np.zeros((n, R.ROWS, 2, d), np.uint64)
+    for i in range(n):
+        if bits[i]:
+            bk[i] = _gadget(d)[0]
+    rot = g.integers(0, 2 * d, size=(m, n)).astype(np.int32)
+    acc = g.integers(0, R.P, size=(m, 2, d), dtype=np.uint64)
+    out = R.blind_rotate(bk, rot, acc)
+    for j in range(m):
+        k = int(sum(int(rot[j, i]) * int(bits[i]) for i in range(n)))
+        for col in range(2):
+            assert out[j, col].tolist() == _rotate(acc[j, col], k, d), (j, col)
+
+
+def test_blind_rotation_decrypts_to_the_rotated_test_polynomial():
+    """Noisy key (fresh encryptions of s_i), trivial accumulator (TV, 0) with
+    TV = 2^61 * t for a 0/1 pattern t: the phase of the result is
+    X^(sum r_i s_i) * TV plus an error of at most n * (2*ell*d) * B."""
+    d, n, m, B = 32, 4, 2, 2
+    dk = WL.ring_draws(60, n, d, R.ROWS, R.P, B)
+    bk = R.encrypt(dk)
+    g = np.random.Generator(np.random.PCG64(61))
+    t = g.integers(0, 2, size=d)
+    acc = np.zeros((m, 2, d), np.uint64)
+    acc[:, 0, :] = (t.astype(np.uint64) << np.uint64(61)) % np.uint64(R.P)
+    rot = g.integers(0, 2 * d, size=(m, n)).astype(np.int32)
+    out = R.blind_rotate(bk, rot, acc)
+    bound = n * 2 * R.ELL * d * B
+    for j in range(m):
+        k = int(sum(int(rot[j, i]) * int(dk.bits[i]) for i in range(n)))
+        want = _rotate(acc[j, 0], k, d)
+        ph = R.rlwe_phase(out[j], dk.s)
+        err = [((int(a) - int(b) + R.P // 2) % R.P) - R.P // 2 for a, b in zip(ph, want)]
+        assert max(abs(x) for x in err) <= bound
+        got_bits = [1 if min(int(v), R.P - int(v)) > R.P // 4 else 0 for v in ph]
+        assert got_bits == [1 if min(int(v), R.P - int(v)) > R.P // 4 else 0 for v in want]
