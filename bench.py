@@ -5,6 +5,7 @@
     python bench.py --workload serve [--requests 40] [--load 0.7] [--max-active 0]
     python bench.py --workload accuracy [--signals 4]
     python bench.py --workload ring_and_d1024 [--requests 128]   # ring-GSW gates
+    python bench.py --workload ring_br_d1024 [--requests 1024]   # ring-GSW blind rotation
 
 A step is one encrypted FFT of one request (every product level of the
 compiled circuit, inputs already encrypted and resident in HBM).  Prints one
@@ -542,6 +543,102 @@ def ring_modmuls_per_gate(d, rows=124):
     return digit + pointwise + inverse + right
 
 
+def ring_modmuls_per_cmux(d, rows=124):
+    """Modular products of one CMux step of blind rotation (one row of the
+    product): the rows digit transforms, the pointwise products against both
+    columns, and the inverse transforms and scaling of the two sums."""
+    logd = d.bit_length() - 1
+    half = d // 2
+    return rows * half * max(logd - 1, 0) + rows * 2 * d + 2 * (half * logd + d)
+
+
+def run_ring_br(args):
+    """Blind rotation at d = 1024: one step is one sfft_ring_blind_rotate call
+    that runs m accumulators through n CMux steps each (a 64-bit key), key
+    prepared and accumulators resident in HBM."""
+    import torch
+    from paper_1611_08769_amd import sfft as S
+    from paper_1611_08769_amd import workloads as WL
+
+    d = int(args.workload.rsplit("_d", 1)[1])
+    m, n = args.requests or 1024, 64
+    stream = torch.cuda.current_stream().cuda_stream
+    rows = 2 * S.SFFT_RING_ELL
+    dk = WL.ring_draws(9, n, d, rows, S.SFFT_RING_P)
+    dev = [torch.from_numpy(np.ascontiguousarray(x).view(np.int64) if x.dtype == np.uint64 else x).cuda()
+           for x in (dk.s, dk.a, dk.e, dk.bits)]
+    bk = torch.empty((n, S.sfft_ring_ct_words(d)), dtype=torch.int64, device="cuda")
+    S.sfft_ring_encrypt(d, dev[0].data_ptr(), dev[1].data_ptr(), dev[2].data_ptr(), dev[3].data_ptr(), n,
+                        bk.data_ptr(), stream)
+    bkt = torch.empty_like(bk)
+    S.sfft_ring_bk_prepare(d, bk.data_ptr(), n, bkt.data_ptr(), stream)
+    g = np.random.Generator(np.random.PCG64(10))
+    t = g.integers(0, 2, size=d).astype(np.uint64)
+    acc0 = np.zeros((m, 2, d), np.uint64)
+    acc0[:, 0, :] = t << np.uint64(61)          # trivial encryptions of 2^61 * t
+    rot = g.integers(0, 2 * d, size=(m, n)).astype(np.int32)
+    acc0_d = torch.from_numpy(acc0.view(np.int64)).cuda()
+    acc = torch.empty_like(acc0_d)
+    rot_d = torch.from_numpy(rot).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        acc.copy_(acc0_d)
+        S.sfft_ring_blind_rotate(d, bkt.data_ptr(), n, rot_d.data_ptr(), acc.data_ptr(), m, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        acc.copy_(acc0_d)
+        a.record()
+        S.sfft_ring_blind_rotate(d, bkt.data_ptr(), n, rot_d.data_ptr(), acc.data_ptr(), m, stream)
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_s = sum(a.elapsed_time(b) for a, b in ev) / len(ev) / 1e3
+    # the first accumulators decrypt to the rotated pattern (host decryption of
+    # coefficient by coefficient phases, library-side arithmetic only)
+    out = acc.cpu().numpy().view(np.uint64)
+    ok = True
+    P = S.SFFT_RING_P
+    for j in range(4):
+        k = int(sum(int(rot[j, i]) * int(dk.bits[i]) for i in range(n))) % (2 * d)
+        want = np.roll(t, k % d)
+        b, a = out[j, 0].astype(object), out[j, 1].astype(object)
+        a_s = np.zeros(d, dtype=object)       # a*s for the ternary secret: sum of s_v X^v a
+        for v in np.nonzero(dk.s)[0]:
+            a_s += int(dk.s[v]) * np.concatenate((-a[d - v:], a[:d - v]))
+        ph = [int(x) % P for x in (b - a_s)]
+        got = np.array([1 if min(x, P - x) > P // 4 else 0 for x in ph], np.uint64)
+        ok = ok and got.tolist() == want.tolist()
+    assert ok, "blind-rotated accumulators do not decrypt to the rotated pattern"
+    mm = ring_modmuls_per_cmux(d) * m * n
+    return {
+        "metric": "CMux steps/s of ring-GSW blind rotation (1 GPU)",
+        "value": m * n / launch_s,
+        "unit": "CMux/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "d": d, "accumulators": m, "key_bits": n, "ell": S.SFFT_RING_ELL,
+                   "p": "2^62-2^16+1"},
+        "blind_rotations_per_s": m / launch_s,
+        "roofline": {"bound": "alu", "achieved": mm / launch_s / 1e9, "peak": PEAK_MODMUL / 1e9,
+                     "unit": "Gmodmul/s", "frac": mm / launch_s / PEAK_MODMUL, "traffic": None,
+                     "kernel": "k_ring_blind_rotate", "avg_launch_ms": launch_s * 1e3,
+                     "modmul_per_cmux": ring_modmuls_per_cmux(d)},
+    }
+
+
 def run_ring(args):
     """Ring-GSW AND gates at d = 1024: one step is one sfft_ring_gate call
     over n ciphertext pairs (the right operands' forward transforms and the
@@ -704,6 +801,9 @@ def main():
         return
     if args.workload.startswith("ring_and_d"):
         print(json.dumps(run_ring(args)), flush=True)
+        return
+    if args.workload.startswith("ring_br_d"):
+        print(json.dumps(run_ring_br(args)), flush=True)
         return
     sig, n_lwe, seed = WL.workload(args.workload)
     cplx = sig.is_complex

@@ -314,6 +314,29 @@ int sfft_ring_gate(int32_t d, int32_t gate, const uint64_t* x_dev, const uint64_
 int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int64_t n, int ct_on_device,
                       uint8_t* bits_out);
 
+/* ---- blind rotation (the core of a refresh) --------------------------------
+ * Refresh is only mentioned by the paper (section "Error Analysis"); this is
+ * the step that FHEW/TFHE-style refresh is built on, written for the ring-GSW
+ * ciphertexts above as the key.  A ring-LWE accumulator is a pair of
+ * polynomials (b, a), 2*d words, encrypting b - a*s.  Blind rotation by a key
+ * of n ring-GSW encryptions bk[i] of bits s_i and rotations r_i runs, for
+ * i = 0..n-1, the CMux step
+ *     acc <- acc + G^-1(X^r_i acc - acc) * bk[i]
+ * so that acc ends encrypting X^(sum r_i s_i) times what it encrypted.  Each
+ * step adds at most 2*ell*d times the key's error bound, whatever the
+ * accumulator's own error: that is what makes refresh possible.  Modulus
+ * switching, sample extraction and key switching back to the LWE path are not
+ * provided. */
+/* Forward transforms of the key's rows into bkt_dev (n * sfft_ring_ct_words(d)
+ * words, must not alias bk_dev); done once per key. */
+int sfft_ring_bk_prepare(int32_t d, const uint64_t* bk_dev, int64_t n, uint64_t* bkt_dev, void* hip_stream);
+/* Blind-rotate m accumulators in place (acc_dev: m * 2d words, device) by the
+ * prepared key bkt_dev (n ciphertexts); rot_dev: m * n int32 rotations, row j
+ * for accumulator j, taken mod 2d.  One launch; one workgroup per
+ * accumulator runs its n steps in order. */
+int sfft_ring_blind_rotate(int32_t d, const uint64_t* bkt_dev, int64_t n, const int32_t* rot_dev, uint64_t* acc_dev,
+                           int64_t m, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

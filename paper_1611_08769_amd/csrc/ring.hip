@@ -138,32 +138,25 @@ __global__ __launch_bounds__(kT) void k_ring_fwd(const uint64_t* __restrict__ sr
     for (int t = threadIdx.x; t < 2 * D; t += kT) o[t] = buf[t];
 }
 
-// out[c] = op(L[c], R[c]) for the product gates (AND, XOR, OR, NAND,
-// PRODUCT).  Rn: R's rows, transformed.
+// One row of G^-1(L) * R: lrow (LDS, 2D words) is a row of L, i.e. a pair of
+// polynomials, and rn holds R's 2*ell rows transformed (2D words each).  For
+// each group of DG digit polynomials (bit j mod ell of lrow's column j div
+// ell), transform them in dig and multiply-accumulate against rn in
+// registers; at the end the two sums are transformed back and left, not yet
+// scaled by d^-1, in dig[0, 2D).  Starts and ends with a barrier.
 template <int LOGD>
-__global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict__ L, const uint64_t* __restrict__ R,
-                                                     const uint64_t* __restrict__ Rn, uint64_t* __restrict__ out,
-                                                     int64_t nblocks, TwView tw, int op)
+__device__ __forceinline__ void row_product(const uint64_t* lrow, const uint64_t* __restrict__ rn, uint64_t* dig,
+                                            const TwView& tw)
 {
     using S = ProdShape<LOGD>;
     constexpr int D = S::D, DG = S::DG, PER = S::PER;
-    extern __shared__ uint64_t lds[];
-    uint64_t* lrow = lds;                   // row i of L: 2D
-    uint64_t* dig = lrow + 2 * D;           // NB polynomials
-    const int64_t lb = xcd_order(blockIdx.x, nblocks);
-    const int64_t c = lb / kRows;
-    const int i = (int)(lb % kRows);
-    const int64_t row_off = (c * kRows + i) * 2 * D;
-    const uint64_t* rn = Rn + c * kRows * 2 * D;
-
-    copy_lds(lrow, L + row_off, 2 * D);
     uint64_t acc0[PER], acc1[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) acc0[q] = acc1[q] = 0;
     __syncthreads();
 
     for (int jj0 = 0; jj0 < kRows; jj0 += DG) {
-        // digit polynomials jj0 .. jj0+DG-1: bit (jj mod ell) of L[i][jj div ell]
+        // digit polynomials jj0 .. jj0+DG-1: bit (jj mod ell) of lrow[jj div ell]
         for (int b = threadIdx.x; b < DG * D; b += kT) {
             const int jj = jj0 + b / D, t = b % D;
             dig[b] = (lrow[(jj / kEll) * D + t] >> (jj % kEll)) & 1;
@@ -202,6 +195,26 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
     }
     __syncthreads();
     inv_lds<LOGD, 2>(dig, tw.inv);
+}
+
+// out[c] = op(L[c], R[c]) for the product gates (AND, XOR, OR, NAND,
+// PRODUCT).  Rn: R's rows, transformed.
+template <int LOGD>
+__global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict__ L, const uint64_t* __restrict__ R,
+                                                     const uint64_t* __restrict__ Rn, uint64_t* __restrict__ out,
+                                                     int64_t nblocks, TwView tw, int op)
+{
+    constexpr int D = 1 << LOGD;
+    extern __shared__ uint64_t lds[];
+    uint64_t* lrow = lds;                   // row i of L: 2D
+    uint64_t* dig = lrow + 2 * D;           // NB polynomials
+    const int64_t lb = xcd_order(blockIdx.x, nblocks);
+    const int64_t c = lb / kRows;
+    const int i = (int)(lb % kRows);
+    const int64_t row_off = (c * kRows + i) * 2 * D;
+
+    copy_lds(lrow, L + row_off, 2 * D);
+    row_product<LOGD>(lrow, Rn + c * kRows * 2 * D, dig, tw);
 
     const uint64_t* rrow = R + row_off;
     uint64_t* orow = out + row_off;
@@ -210,6 +223,40 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
         const uint64_t P = mulw(dig[b], tw.dinv);
         orow[b] = epilogue(op, P, lrow[b], rrow[b], gadget(i, col, t));
     }
+}
+
+// Blind rotation of m ring-LWE accumulators (2D words each, in place) by a
+// key of n ring-GSW ciphertexts, transformed (bkt: n x 2*ell rows of 2D
+// words).  Workgroup j runs all n steps of accumulator j:
+//   acc <- acc + G^-1(X^r acc - acc) * bk[i],  r = rot[j*n + i] mod 2D
+// (the CMux of bk[i]'s bit between acc and X^r acc; X^D = -1).
+template <int LOGD>
+__global__ __launch_bounds__(kT) void k_ring_blind_rotate(const uint64_t* __restrict__ bkt, int64_t n,
+                                                          const int32_t* __restrict__ rot, uint64_t* __restrict__ acc,
+                                                          TwView tw)
+{
+    constexpr int D = 1 << LOGD;
+    extern __shared__ uint64_t lds[];
+    uint64_t* a = lds;            // the accumulator: 2D
+    uint64_t* dif = a + 2 * D;    // X^r acc - acc: 2D
+    uint64_t* dig = dif + 2 * D;  // NB polynomials
+    const int64_t j = blockIdx.x;
+    uint64_t* ga = acc + j * 2 * D;
+    copy_lds(a, ga, 2 * D);
+    __syncthreads();
+    for (int64_t i = 0; i < n; ++i) {
+        const int r = ((rot[j * n + i] % (2 * D)) + 2 * D) % (2 * D);
+        for (int b = threadIdx.x; b < 2 * D; b += kT) {
+            const int col = b / D, t = b % D;
+            const int u = (t - r + 2 * D) % (2 * D);   // X^r a at t: +a[u], or -a[u - D] past the wrap
+            const uint64_t v = u < D ? a[col * D + u] : subp(0, a[col * D + u - D]);
+            dif[b] = subp(v, a[b]);
+        }
+        row_product<LOGD>(dif, bkt + i * kRows * 2 * D, dig, tw);
+        for (int b = threadIdx.x; b < 2 * D; b += kT) a[b] = addp(a[b], mulw(dig[b], tw.dinv));
+        __syncthreads();
+    }
+    for (int b = threadIdx.x; b < 2 * D; b += kT) ga[b] = a[b];
 }
 
 // NOT (3): G - X;  XADD (7): X + Y.  Elementwise over n ciphertexts.
@@ -366,6 +413,28 @@ hipError_t launch_gate(const uint64_t* L, const uint64_t* R, uint64_t* Rn, uint6
 }
 
 template <int LOGD>
+hipError_t launch_bk_prepare(const uint64_t* bk, int64_t n, uint64_t* bkt, TwView tv, hipStream_t s)
+{
+    constexpr int D = 1 << LOGD;
+    static const hipError_t attr = allow_lds(k_ring_fwd<LOGD>);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_ring_fwd<LOGD>, dim3((unsigned)(n * kRows)), dim3(kT), (size_t)4 * D * 8, s, bk, bkt, tv);
+    return hipGetLastError();
+}
+
+template <int LOGD>
+hipError_t launch_blind_rotate(const uint64_t* bkt, int64_t n, const int32_t* rot, uint64_t* acc, int64_t m, TwView tv,
+                               hipStream_t s)
+{
+    constexpr int D = 1 << LOGD;
+    static const hipError_t attr = allow_lds(k_ring_blind_rotate<LOGD>);
+    if (attr != hipSuccess) return attr;
+    const size_t lds = (size_t)(4 * D) * 8 + (size_t)ProdShape<LOGD>::NB * D * 8;
+    hipLaunchKernelGGL(k_ring_blind_rotate<LOGD>, dim3((unsigned)m), dim3(kT), lds, s, bkt, n, rot, acc, tv);
+    return hipGetLastError();
+}
+
+template <int LOGD>
 hipError_t launch_encrypt(const int64_t* sd, const uint64_t* a, const int64_t* ed, const uint8_t* bits, int64_t n,
                           uint64_t* ct, TwView tv, hipStream_t s)
 {
@@ -466,6 +535,44 @@ int sfft_ring_gate(int32_t d, int32_t gate, const uint64_t* x_dev, const uint64_
     SFFT_RING_DISPATCH(logd, SFFT_GATE)
 #undef SFFT_GATE
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_product");
+}
+
+int sfft_ring_bk_prepare(int32_t d, const uint64_t* bk_dev, int64_t n, uint64_t* bkt_dev, void* hip_stream)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0) return sfft_fail(SFFT_EINVAL, "n < 0");
+    if (n == 0) return SFFT_OK;
+    if (!bk_dev || !bkt_dev) return sfft_fail(SFFT_EINVAL, "null buffer");
+    if (bkt_dev == bk_dev) return sfft_fail(SFFT_EINVAL, "bkt must not alias bk");
+    if (n * kRows > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many key ciphertexts for one call");
+    TwView tv;
+    if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSuccess;
+#define SFFT_BKP(L) { e = launch_bk_prepare<L>(bk_dev, n, bkt_dev, tv, s); break; }
+    SFFT_RING_DISPATCH(logd, SFFT_BKP)
+#undef SFFT_BKP
+    return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_fwd");
+}
+
+int sfft_ring_blind_rotate(int32_t d, const uint64_t* bkt_dev, int64_t n, const int32_t* rot_dev, uint64_t* acc_dev,
+                           int64_t m, void* hip_stream)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0 || m < 0) return sfft_fail(SFFT_EINVAL, "n < 0 or m < 0");
+    if (n == 0 || m == 0) return SFFT_OK;
+    if (!bkt_dev || !rot_dev || !acc_dev) return sfft_fail(SFFT_EINVAL, "null buffer");
+    if (m > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many accumulators for one call");
+    TwView tv;
+    if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSuccess;
+#define SFFT_BR(L) { e = launch_blind_rotate<L>(bkt_dev, n, rot_dev, acc_dev, m, tv, s); break; }
+    SFFT_RING_DISPATCH(logd, SFFT_BR)
+#undef SFFT_BR
+    return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_blind_rotate");
 }
 
 int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int64_t n, int ct_on_device,

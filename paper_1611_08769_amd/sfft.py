@@ -114,6 +114,8 @@ _SIGS = {
     "sfft_ring_gate": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp,
                                       ctypes.c_int64, _vp]),
     "sfft_ring_decrypt": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
+    "sfft_ring_bk_prepare": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]),
+    "sfft_ring_blind_rotate": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -321,3 +323,11 @@ def sfft_ring_gate(d, gate, x_ptr, y_ptr, out_ptr, n, ws_ptr, ws_bytes, stream) 
 
 def sfft_ring_decrypt(d, s_host_ptr, ct_ptr, n, on_device, bits_out_ptr) -> None:
     _check(_lib.sfft_ring_decrypt(d, s_host_ptr, ct_ptr, n, int(on_device), bits_out_ptr))
+
+
+def sfft_ring_bk_prepare(d, bk_ptr, n, bkt_ptr, stream) -> None:
+    _check(_lib.sfft_ring_bk_prepare(d, bk_ptr, n, bkt_ptr, stream))
+
+
+def sfft_ring_blind_rotate(d, bkt_ptr, n, rot_ptr, acc_ptr, m, stream) -> None:
+    _check(_lib.sfft_ring_blind_rotate(d, bkt_ptr, n, rot_ptr, acc_ptr, m, stream))

@@ -155,3 +155,77 @@ def test_empty_and_errors():
         assert e.value.code == S.SFFT_EINVAL
     torch.cuda.synchronize()
     assert not out.any()
+
+
+def _prepared_key(dk, d):
+    """Ring-GSW key on the device, and its transformed rows."""
+    bk = _encrypt(dk, d)
+    n = bk.shape[0]
+    bkt = torch.empty_like(bk)
+    S.sfft_ring_bk_prepare(d, bk.data_ptr(), n, bkt.data_ptr(), _stream())
+    return bk, bkt
+
+
+@pytest.mark.parametrize("d,n,m", [(1, 3, 2), (16, 5, 3), (64, 3, 9), (1024, 2, 2)])
+def test_blind_rotate_matches_oracle(d, n, m):
+    """Blind rotation of m random accumulators by an n-bit key, bit for bit;
+    rotations include values outside [0, 2d) (taken mod 2d) at small d."""
+    say("ring blind rotation d=%d n=%d m=%d" % (d, n, m))
+    dk = WL.ring_draws(500 + d, n, d, O.ROWS, O.P)
+    bk, bkt = _prepared_key(dk, d)
+    g = np.random.Generator(np.random.PCG64(d + n))
+    lo, hi = (-3 * d, 5 * d) if d <= 64 else (0, 2 * d)
+    rot = g.integers(lo, hi, size=(m, n)).astype(np.int32)
+    acc = g.integers(0, O.P, size=(m, 2, d), dtype=np.uint64)
+    acc_d = _dev(acc)
+    rot_d = _dev(rot)
+    S.sfft_ring_blind_rotate(d, bkt.data_ptr(), n, rot_d.data_ptr(), acc_d.data_ptr(), m, _stream())
+    torch.cuda.synchronize()
+    want = O.blind_rotate(_host(bk), np.mod(rot, 2 * d), acc)
+    assert np.array_equal(_host(acc_d), want)
+
+
+def test_blind_rotate_decrypts_to_rotated_test_polynomial():
+    """d = 1024, a 16-bit key, 8 accumulators (TV, 0) with TV = 2^61 * t: the
+    decrypted pattern is t rotated by sum r_i s_i (negacyclic)."""
+    d, n, m = 1024, 16, 8
+    say("ring blind rotation decrypt d=%d n=%d m=%d" % (d, n, m))
+    dk = WL.ring_draws(700, n, d, O.ROWS, O.P)
+    _, bkt = _prepared_key(dk, d)
+    g = np.random.Generator(np.random.PCG64(701))
+    t = g.integers(0, 2, size=d).astype(np.uint64)
+    acc = np.zeros((m, 2, d), np.uint64)
+    acc[:, 0, :] = t << np.uint64(61)
+    rot = g.integers(0, 2 * d, size=(m, n)).astype(np.int32)
+    acc_d, rot_d = _dev(acc), _dev(rot)
+    S.sfft_ring_blind_rotate(d, bkt.data_ptr(), n, rot_d.data_ptr(), acc_d.data_ptr(), m, _stream())
+    torch.cuda.synchronize()
+    out = _host(acc_d)
+    for j in range(m):
+        k = int(sum(int(rot[j, i]) * int(dk.bits[i]) for i in range(n))) % (2 * d)
+        want = np.roll(t, k % d)                  # X^k moves coefficient u to u + k (sign irrelevant)
+        ph = O.rlwe_phase(out[j], dk.s)
+        got = np.array([1 if min(int(v), O.P - int(v)) > O.P // 4 else 0 for v in ph])
+        assert got.tolist() == want.tolist(), j
+
+
+def test_blind_rotate_edge_cases():
+    say("ring blind rotation edge cases")
+    d = 16
+    dk = WL.ring_draws(5, 2, d, O.ROWS, O.P)
+    bk, bkt = _prepared_key(dk, d)
+    acc = torch.zeros((1, 2, d), dtype=torch.int64, device="cuda")
+    rot = torch.zeros((1, 2), dtype=torch.int32, device="cuda")
+    # n = 0 and m = 0 leave the accumulator alone
+    acc.fill_(7)
+    S.sfft_ring_blind_rotate(d, bkt.data_ptr(), 0, rot.data_ptr(), acc.data_ptr(), 1, _stream())
+    S.sfft_ring_blind_rotate(d, bkt.data_ptr(), 2, rot.data_ptr(), acc.data_ptr(), 0, _stream())
+    torch.cuda.synchronize()
+    assert bool((acc == 7).all())
+    for args in ((3, bkt.data_ptr(), 2, rot.data_ptr(), acc.data_ptr(), 1), (d, 0, 2, rot.data_ptr(), acc.data_ptr(), 1),
+                 (d, bkt.data_ptr(), -1, rot.data_ptr(), acc.data_ptr(), 1)):
+        with pytest.raises(S.SfftError) as e:
+            S.sfft_ring_blind_rotate(*args, _stream())
+        assert e.value.code == S.SFFT_EINVAL
+    with pytest.raises(S.SfftError):
+        S.sfft_ring_bk_prepare(d, bk.data_ptr(), 2, bk.data_ptr(), _stream())

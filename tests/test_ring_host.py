@@ -65,3 +65,19 @@ def test_host_decrypt_of_oracle_ciphertexts(d):
         got = np.zeros(n, np.uint8)
         S.sfft_ring_decrypt(d, s.ctypes.data, ct.ctypes.data, n, 0, got.ctypes.data)
         assert got.tolist() == want.tolist()
+
+
+def test_blind_rotation_argument_checks():
+    d = 16
+    S.sfft_ring_blind_rotate(d, 8, 0, 16, 24, 1, None)     # n = 0
+    S.sfft_ring_blind_rotate(d, 8, 3, 16, 24, 0, None)     # m = 0
+    S.sfft_ring_bk_prepare(d, 8, 0, 16, None)               # n = 0
+    for args in ((3, 8, 1, 16, 24, 1), (d, 0, 1, 16, 24, 1), (d, 8, 1, 0, 24, 1), (d, 8, 1, 16, 0, 1),
+                 (d, 8, -1, 16, 24, 1), (d, 8, 1, 16, 24, -1)):
+        with pytest.raises(S.SfftError) as e:
+            S.sfft_ring_blind_rotate(*args, None)
+        assert e.value.code == S.SFFT_EINVAL, args
+    for args in ((d, 8, 1, 8), (d, 0, 1, 16), (4096, 8, 1, 16), (d, 8, -1, 16)):
+        with pytest.raises(S.SfftError) as e:
+            S.sfft_ring_bk_prepare(*args, None)
+        assert e.value.code == S.SFFT_EINVAL, args
