@@ -138,14 +138,15 @@ __global__ __launch_bounds__(kT) void k_ring_fwd(const uint64_t* __restrict__ sr
     for (int t = threadIdx.x; t < 2 * D; t += kT) o[t] = buf[t];
 }
 
-// One row of G^-1(L) * R: lrow (LDS, 2D words) is a row of L, i.e. a pair of
-// polynomials, and rn holds R's 2*ell rows transformed (2D words each).  For
-// each group of DG digit polynomials (bit j mod ell of lrow's column j div
-// ell), transform them in dig and multiply-accumulate against rn in
-// registers; at the end the two sums are transformed back and left, not yet
-// scaled by d^-1, in dig[0, 2D).  Starts and ends with a barrier.
-template <int LOGD>
-__device__ __forceinline__ void row_product(const uint64_t* lrow, const uint64_t* __restrict__ rn, uint64_t* dig,
+// One row of G^-1(L) * R: src(col, t) gives coefficient t of column col of
+// the row of L (a pair of polynomials), and rn holds R's 2*ell rows
+// transformed (2D words each).  For each group of DG digit polynomials (bit j
+// mod ell of the row's column j div ell), transform them in dig and
+// multiply-accumulate against rn in registers; at the end the two sums are
+// transformed back and left, not yet scaled by d^-1, in dig[0, 2D).  Starts
+// and ends with a barrier.
+template <int LOGD, typename Src>
+__device__ __forceinline__ void row_product(Src src, const uint64_t* __restrict__ rn, uint64_t* dig,
                                             const TwView& tw)
 {
     using S = ProdShape<LOGD>;
@@ -156,10 +157,10 @@ __device__ __forceinline__ void row_product(const uint64_t* lrow, const uint64_t
     __syncthreads();
 
     for (int jj0 = 0; jj0 < kRows; jj0 += DG) {
-        // digit polynomials jj0 .. jj0+DG-1: bit (jj mod ell) of lrow[jj div ell]
+        // digit polynomials jj0 .. jj0+DG-1: bit (jj mod ell) of column jj div ell
         for (int b = threadIdx.x; b < DG * D; b += kT) {
             const int jj = jj0 + b / D, t = b % D;
-            dig[b] = (lrow[(jj / kEll) * D + t] >> (jj % kEll)) & 1;
+            dig[b] = (src(jj / kEll, t) >> (jj % kEll)) & 1;
         }
         __syncthreads();
         fwd_lds<LOGD, DG>(dig, tw.fwd, true);
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kT) void k_ring_product(const uint64_t* __restrict_
     const int64_t row_off = (c * kRows + i) * 2 * D;
 
     copy_lds(lrow, L + row_off, 2 * D);
-    row_product<LOGD>(lrow, Rn + c * kRows * 2 * D, dig, tw);
+    row_product<LOGD>([lrow](int col, int t) { return lrow[col * D + t]; }, Rn + c * kRows * 2 * D, dig, tw);
 
     const uint64_t* rrow = R + row_off;
     uint64_t* orow = out + row_off;
@@ -238,20 +239,19 @@ __global__ __launch_bounds__(kT) void k_ring_blind_rotate(const uint64_t* __rest
     constexpr int D = 1 << LOGD;
     extern __shared__ uint64_t lds[];
     uint64_t* a = lds;            // the accumulator: 2D
-    uint64_t* dif = a + 2 * D;    // X^r acc - acc: 2D
-    uint64_t* dig = dif + 2 * D;  // NB polynomials
+    uint64_t* dig = a + 2 * D;    // NB polynomials
     const int64_t j = blockIdx.x;
     uint64_t* ga = acc + j * 2 * D;
     copy_lds(a, ga, 2 * D);
-    __syncthreads();
     for (int64_t i = 0; i < n; ++i) {
         const int r = ((rot[j * n + i] % (2 * D)) + 2 * D) % (2 * D);
-        for (int b = threadIdx.x; b < 2 * D; b += kT) {
-            const int col = b / D, t = b % D;
-            const int u = (t - r + 2 * D) % (2 * D);   // X^r a at t: +a[u], or -a[u - D] past the wrap
+        // coefficient t of column col of X^r a - a, formed where the digits
+        // are taken (X^r a at t is +a[u], or -a[u - D] past the wrap)
+        auto dif = [a, r](int col, int t) {
+            const int u = (t - r + 2 * D) % (2 * D);
             const uint64_t v = u < D ? a[col * D + u] : subp(0, a[col * D + u - D]);
-            dif[b] = subp(v, a[b]);
-        }
+            return subp(v, a[col * D + t]);
+        };
         row_product<LOGD>(dif, bkt + i * kRows * 2 * D, dig, tw);
         for (int b = threadIdx.x; b < 2 * D; b += kT) a[b] = addp(a[b], mulw(dig[b], tw.dinv));
         __syncthreads();
@@ -429,7 +429,7 @@ hipError_t launch_blind_rotate(const uint64_t* bkt, int64_t n, const int32_t* ro
     constexpr int D = 1 << LOGD;
     static const hipError_t attr = allow_lds(k_ring_blind_rotate<LOGD>);
     if (attr != hipSuccess) return attr;
-    const size_t lds = (size_t)(4 * D) * 8 + (size_t)ProdShape<LOGD>::NB * D * 8;
+    const size_t lds = (size_t)(2 * D) * 8 + (size_t)ProdShape<LOGD>::NB * D * 8;
     hipLaunchKernelGGL(k_ring_blind_rotate<LOGD>, dim3((unsigned)m), dim3(kT), lds, s, bkt, n, rot, acc, tv);
     return hipGetLastError();
 }
