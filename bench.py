@@ -615,6 +615,36 @@ def run_ring_br(args):
         got = np.array([1 if min(x, P - x) > P // 4 else 0 for x in ph], np.uint64)
         ok = ok and got.tolist() == want.tolist()
     assert ok, "blind-rotated accumulators do not decrypt to the rotated pattern"
+    # full gate bootstrapping of m LWE ciphertexts (n = 64, binary secret =
+    # the key's bits) through sfft_ring_bootstrap, timed the same way
+    mus = g.integers(0, 2, size=m)
+    lwe = np.zeros((m, n + 1), np.uint64)
+    lwe[:, :n] = g.integers(0, P, size=(m, n), dtype=np.uint64)
+    for j in range(m):
+        lwe[j, n] = (sum(int(x) for x, bit in zip(lwe[j, :n], dk.bits) if bit) + int(mus[j]) * (P // 2)) % P
+    lwe_d = torch.from_numpy(lwe.view(np.int64)).cuda()
+    bs_out = torch.empty((m, d + 1), dtype=torch.int64, device="cuda")
+    ws_b = S.sfft_ring_bootstrap_workspace_bytes(d, n, m)
+    ws = torch.empty(ws_b // 8 + 1, dtype=torch.int64, device="cuda")
+
+    def bootstrap():
+        S.sfft_ring_bootstrap(d, bkt.data_ptr(), n, lwe_d.data_ptr(), m, bs_out.data_ptr(), ws.data_ptr(), ws_b,
+                              stream)
+
+    bootstrap()
+    torch.cuda.synchronize()
+    ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a_, b_ in ev2:
+        a_.record()
+        bootstrap()
+        b_.record()
+    torch.cuda.synchronize()
+    bs_s = sum(a_.elapsed_time(b_) for a_, b_ in ev2) / len(ev2) / 1e3
+    o = bs_out.cpu().numpy().view(np.uint64)
+    for j in range(4):   # phase b' - <a', s_ring> reads mu * 2 * floor(p/4)
+        ph = (int(o[j, d]) - sum(int(o[j, t]) * int(dk.s[t]) for t in range(d) if dk.s[t])) % P
+        got = 1 if min(ph, P - ph) > P // 4 else 0
+        assert got == int(mus[j]), "bootstrapped ciphertext %d decrypts to the wrong bit" % j
     mm = ring_modmuls_per_cmux(d) * m * n
     return {
         "metric": "CMux steps/s of ring-GSW blind rotation (1 GPU)",
@@ -632,6 +662,8 @@ def run_ring_br(args):
         "config": {"workload": args.workload, "d": d, "accumulators": m, "key_bits": n, "ell": S.SFFT_RING_ELL,
                    "p": "2^62-2^16+1"},
         "blind_rotations_per_s": m / launch_s,
+        "bootstraps_per_s": m / bs_s,
+        "bootstrap_ms_per_call": bs_s * 1e3,
         "roofline": {"bound": "alu", "achieved": mm / launch_s / 1e9, "peak": PEAK_MODMUL / 1e9,
                      "unit": "Gmodmul/s", "frac": mm / launch_s / PEAK_MODMUL, "traffic": None,
                      "kernel": "k_ring_blind_rotate", "avg_launch_ms": launch_s * 1e3,

@@ -324,9 +324,9 @@ int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int6
  *     acc <- acc + G^-1(X^r_i acc - acc) * bk[i]
  * so that acc ends encrypting X^(sum r_i s_i) times what it encrypted.  Each
  * step adds at most 2*ell*d times the key's error bound, whatever the
- * accumulator's own error: that is what makes refresh possible.  Modulus
- * switching, sample extraction and key switching back to the LWE path are not
- * provided. */
+ * accumulator's own error: that is what makes refresh possible.  Key switching
+ * back to the LWE path is not provided; modulus switching and sample
+ * extraction come with sfft_ring_bootstrap. */
 /* Forward transforms of the key's rows into bkt_dev (n * sfft_ring_ct_words(d)
  * words, must not alias bk_dev); done once per key. */
 int sfft_ring_bk_prepare(int32_t d, const uint64_t* bk_dev, int64_t n, uint64_t* bkt_dev, void* hip_stream);
@@ -336,6 +336,22 @@ int sfft_ring_bk_prepare(int32_t d, const uint64_t* bk_dev, int64_t n, uint64_t*
  * accumulator runs its n steps in order. */
 int sfft_ring_blind_rotate(int32_t d, const uint64_t* bkt_dev, int64_t n, const int32_t* rot_dev, uint64_t* acc_dev,
                            int64_t m, void* hip_stream);
+/* Gate bootstrapping within the ring scheme (FHEW-style refresh without the
+ * final key switch).  lwe_dev: m LWE ciphertexts mod p, n+1 words each
+ * (a_0..a_{n-1}, b), under a binary secret of n bits s_i, encrypting mu in
+ * {0,1} as b - <a,s> = mu*floor(p/2) + e with |e| < p/8 less the rounding of
+ * the modulus switch.  bkt_dev: the prepared key of ring-GSW encryptions of
+ * the s_i (sfft_ring_bk_prepare).  Steps: switch a, b to the modulus 2d
+ * (floor((x*2d + floor(p/2))/p) mod 2d); accumulator
+ * (X^(b~ + d/2) * Delta*(1 + X + ... + X^(d-1)), 0), Delta = floor(p/4);
+ * blind rotation by -a~_i; coefficient 0 extracted.  out_dev: m LWE
+ * ciphertexts of d+1 words (a'_0..a'_{d-1}, b') under the ring secret's
+ * coefficients, a'_0 = a_0, a'_t = -a_{d-t}, b' = b_0 + Delta, whose phase is
+ * mu*2*Delta plus the blind rotation's error only.  ws: at least
+ * sfft_ring_bootstrap_workspace_bytes (accumulators and rotations). */
+int sfft_ring_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes);
+int sfft_ring_bootstrap(int32_t d, const uint64_t* bkt_dev, int64_t n, const uint64_t* lwe_dev, int64_t m,
+                        uint64_t* out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,7 @@ def lib():
                                    np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), c.c_int64, u64p]
         L.rg_blind_rotate.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64,
                                       np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), u64p, c.c_int64]
+        L.rg_bootstrap.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, c.c_int64, u64p]
         L.rg_phase.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int, u64p, u64p]
         L.rg_decrypt.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, u8p]
         _lib = L
@@ -132,6 +133,25 @@ def blind_rotate(bk, rot, acc) -> np.ndarray:
     assert bk.shape[0] == n and out.shape == (m, 2, bk.shape[3])
     lib().rg_blind_rotate(P, bk.shape[3], ELL, bk, n, rot, out, m)
     return out
+
+
+def bootstrap(bk, lwe) -> np.ndarray:
+    """Gate bootstrapping of LWE ciphertexts lwe (m, n+1) mod p under the
+    binary secret whose bits bk (n, ROWS, 2, d) encrypts: returns (m, d+1) LWE
+    ciphertexts under the ring secret's coefficients (see rgsw_ref.c)."""
+    bk, lwe = _u64(bk), _u64(lwe)
+    m, n1 = lwe.shape
+    assert bk.shape[0] == n1 - 1
+    d = bk.shape[3]
+    out = np.zeros((m, d + 1), dtype=np.uint64)
+    lib().rg_bootstrap(P, d, ELL, bk, n1 - 1, lwe, m, out)
+    return out
+
+
+def lwe_phase(c, s_signed) -> int:
+    """b - <a, s> mod p of one LWE ciphertext (a_0..a_{k-1}, b)."""
+    k = len(c) - 1
+    return (int(c[k]) - sum(int(c[i]) * int(s_signed[i]) for i in range(k))) % P
 
 
 def rlwe_phase(acc, s_signed) -> np.ndarray:

@@ -225,6 +225,53 @@ void rg_blind_rotate(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, 
     }
 }
 
+/* Gate bootstrapping within the ring scheme (FHEW-style refresh, without the
+ * final key switch).  Input: m LWE ciphertexts (a_0..a_{n-1}, b) mod p under
+ * a binary secret of n bits s_i, encrypting mu in {0,1} as
+ * b - <a, s> = mu*p/2 + e.  The key bk holds ring-GSW encryptions of the s_i.
+ *   1. modulus switch to 2d: x~ = floor((x*2d + floor(p/2)) / p) mod 2d
+ *   2. accumulator (X^(b~ + d/2) * TV, 0) with TV = Delta*(1 + X + ... + X^(d-1)),
+ *      Delta = floor(p/4); rotations r_i = -a~_i mod 2d
+ *   3. blind rotation: the accumulator encrypts X^(b~ + d/2 - sum a~_i s_i) TV,
+ *      whose coefficient 0 is -Delta when that exponent lies in (0, d) and
+ *      +Delta in (d, 2d)
+ *   4. sample extraction of coefficient 0, plus Delta on b: an LWE ciphertext
+ *      (a'_0..a'_{d-1}, b') under the ring secret's coefficients with
+ *      a'_0 = a_0, a'_t = -a_{d-t}, whose phase is mu*2*Delta + fresh error.
+ * out: m x (d+1) words. */
+void rg_bootstrap(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, const uint64_t *lwe, int64_t m,
+                  uint64_t *out)
+{
+    const uint64_t delta = p / 4, two_d = 2 * (uint64_t)d;
+    uint64_t *acc = malloc(sizeof(uint64_t) * 2 * d * (m > 0 ? m : 1));
+    int32_t *rot = malloc(sizeof(int32_t) * (n * m > 0 ? n * m : 1));
+    for (int64_t j = 0; j < m; j++) {
+        const uint64_t *c = lwe + j * (n + 1);
+        for (int64_t i = 0; i < n; i++) {
+            uint64_t ai = (uint64_t)(((u128)c[i] * two_d + p / 2) / p) % two_d;
+            rot[j * n + i] = (int32_t)((two_d - ai) % two_d);
+        }
+        uint64_t bt = (uint64_t)(((u128)c[n] * two_d + p / 2) / p) % two_d;
+        uint64_t k = (bt + (uint64_t)d / 2) % two_d;
+        for (int u = 0; u < d; u++) {
+            /* coefficient u of X^k * TV: +Delta if (u - k) mod 2d < d, else -Delta */
+            uint64_t t = ((uint64_t)u + two_d - k) % two_d;
+            acc[j * 2 * d + u] = t < (uint64_t)d ? delta : p - delta;
+            acc[j * 2 * d + d + u] = 0;
+        }
+    }
+    rg_blind_rotate(p, d, ell, bk, n, rot, acc, m);
+    for (int64_t j = 0; j < m; j++) {
+        const uint64_t *A = acc + j * 2 * d;
+        uint64_t *o = out + j * (d + 1);
+        o[0] = A[d];
+        for (int t = 1; t < d; t++) o[t] = (p - A[d + d - t]) % p;
+        o[d] = addm(A[0], delta, p);
+    }
+    free(acc);
+    free(rot);
+}
+
 /* Phase of one row: C[row][0] - C[row][1]*s  (d coefficients). */
 void rg_phase(uint64_t p, int d, int ell, const uint64_t *ct, int row, const uint64_t *s, uint64_t *out)
 {

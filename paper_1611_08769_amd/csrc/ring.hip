@@ -259,6 +259,56 @@ __global__ __launch_bounds__(kT) void k_ring_blind_rotate(const uint64_t* __rest
     for (int b = threadIdx.x; b < 2 * D; b += kT) ga[b] = a[b];
 }
 
+// floor((x * 2D + floor(p/2)) / p) mod 2D for x < p: x switched to the
+// modulus 2D with rounding.  y = x*2D + floor(p/2) < 2^75 is split at bit 62;
+// with 2^62 = p + 2^16 - 1 the quotient estimate y >> 62 leaves a remainder
+// below 2p, corrected once.
+template <int LOGD>
+__device__ __forceinline__ int32_t switch_2d(uint64_t x)
+{
+    constexpr uint64_t half = kP / 2;
+    const uint64_t lo0 = x << (LOGD + 1), hi0 = x >> (63 - LOGD);
+    const uint64_t lo = lo0 + half, hi = hi0 + (lo < lo0);
+    uint64_t q = (hi << 2) | (lo >> 62);
+    uint64_t r = (lo & kM62) + ((q << 16) - q);
+    if (r >= kP) ++q;
+    return (int32_t)(q & ((2u << LOGD) - 1));
+}
+
+// Gate bootstrapping, step 1: for LWE ciphertext j (a_0..a_{n-1}, b), the
+// rotations -a~_i mod 2D and the accumulator (X^(b~ + D/2) * TV, 0), TV =
+// Delta * (1 + X + ... + X^(D-1)), Delta = floor(p/4).
+template <int LOGD>
+__global__ __launch_bounds__(kT) void k_ring_br_init(const uint64_t* __restrict__ lwe, int64_t n,
+                                                     int32_t* __restrict__ rot, uint64_t* __restrict__ acc)
+{
+    constexpr int D = 1 << LOGD;
+    constexpr uint64_t delta = kP / 4;
+    const int64_t j = blockIdx.x;
+    const uint64_t* c = lwe + j * (n + 1);
+    for (int64_t i = threadIdx.x; i < n; i += kT) rot[j * n + i] = (2 * D - switch_2d<LOGD>(c[i])) % (2 * D);
+    const int k = (switch_2d<LOGD>(c[n]) + D / 2) % (2 * D);
+    uint64_t* a = acc + j * 2 * D;
+    for (int u = threadIdx.x; u < D; u += kT) {
+        a[u] = ((u - k + 2 * D) % (2 * D)) < D ? delta : kP - delta;
+        a[D + u] = 0;
+    }
+}
+
+// Gate bootstrapping, step 3: coefficient 0 of accumulator j as an LWE
+// ciphertext under the ring secret's coefficients, (a_0, -a_{D-1}, ...,
+// -a_1, b_0 + Delta).
+template <int LOGD>
+__global__ __launch_bounds__(kT) void k_ring_extract(const uint64_t* __restrict__ acc, uint64_t* __restrict__ out)
+{
+    constexpr int D = 1 << LOGD;
+    const int64_t j = blockIdx.x;
+    const uint64_t* a = acc + j * 2 * D;
+    uint64_t* o = out + j * (D + 1);
+    for (int t = threadIdx.x; t <= D; t += kT)
+        o[t] = t == D ? addp(a[0], kP / 4) : (t == 0 ? a[D] : subp(0, a[2 * D - t]));
+}
+
 // NOT (3): G - X;  XADD (7): X + Y.  Elementwise over n ciphertexts.
 __global__ __launch_bounds__(kT) void k_ring_linear(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Y,
                                                     uint64_t* __restrict__ out, int64_t count, int d, int logd,
@@ -435,6 +485,18 @@ hipError_t launch_blind_rotate(const uint64_t* bkt, int64_t n, const int32_t* ro
 }
 
 template <int LOGD>
+hipError_t launch_bootstrap(const uint64_t* bkt, int64_t n, const uint64_t* lwe, int64_t m, uint64_t* out,
+                            uint64_t* acc, int32_t* rot, TwView tv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ring_br_init<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, lwe, n, rot, acc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (n > 0 && (e = launch_blind_rotate<LOGD>(bkt, n, rot, acc, m, tv, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ring_extract<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, acc, out);
+    return hipGetLastError();
+}
+
+template <int LOGD>
 hipError_t launch_encrypt(const int64_t* sd, const uint64_t* a, const int64_t* ed, const uint8_t* bits, int64_t n,
                           uint64_t* ct, TwView tv, hipStream_t s)
 {
@@ -573,6 +635,37 @@ int sfft_ring_blind_rotate(int32_t d, const uint64_t* bkt_dev, int64_t n, const 
     SFFT_RING_DISPATCH(logd, SFFT_BR)
 #undef SFFT_BR
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_blind_rotate");
+}
+
+int sfft_ring_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0 || m < 0 || !bytes) return sfft_fail(SFFT_EINVAL, "n < 0, m < 0 or null output");
+    *bytes = m * 2 * d * 8 + m * n * 4;
+    return SFFT_OK;
+}
+
+int sfft_ring_bootstrap(int32_t d, const uint64_t* bkt_dev, int64_t n, const uint64_t* lwe_dev, int64_t m,
+                        uint64_t* out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0 || m < 0) return sfft_fail(SFFT_EINVAL, "n < 0 or m < 0");
+    if (m == 0) return SFFT_OK;
+    if (!lwe_dev || !out_dev || !ws_dev || (n > 0 && !bkt_dev)) return sfft_fail(SFFT_EINVAL, "null buffer");
+    if (m > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many ciphertexts for one call");
+    if (ws_bytes < m * 2 * d * 8 + m * n * 4) return sfft_fail(SFFT_EINVAL, "workspace too small");
+    TwView tv;
+    if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
+    uint64_t* acc = (uint64_t*)ws_dev;
+    int32_t* rot = (int32_t*)(acc + m * 2 * d);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSuccess;
+#define SFFT_BS(L) { e = launch_bootstrap<L>(bkt_dev, n, lwe_dev, m, out_dev, acc, rot, tv, s); break; }
+    SFFT_RING_DISPATCH(logd, SFFT_BS)
+#undef SFFT_BS
+    return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "ring bootstrap");
 }
 
 int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int64_t n, int ct_on_device,

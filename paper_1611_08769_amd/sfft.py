@@ -116,6 +116,10 @@ _SIGS = {
     "sfft_ring_decrypt": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
     "sfft_ring_bk_prepare": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]),
     "sfft_ring_blind_rotate": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp]),
+    "sfft_ring_bootstrap_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                           _P(ctypes.c_int64)]),
+    "sfft_ring_bootstrap": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp,
+                                           ctypes.c_int64, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -331,3 +335,13 @@ def sfft_ring_bk_prepare(d, bk_ptr, n, bkt_ptr, stream) -> None:
 
 def sfft_ring_blind_rotate(d, bkt_ptr, n, rot_ptr, acc_ptr, m, stream) -> None:
     _check(_lib.sfft_ring_blind_rotate(d, bkt_ptr, n, rot_ptr, acc_ptr, m, stream))
+
+
+def sfft_ring_bootstrap_workspace_bytes(d: int, n: int, m: int) -> int:
+    b = ctypes.c_int64()
+    _check(_lib.sfft_ring_bootstrap_workspace_bytes(d, n, m, ctypes.byref(b)))
+    return b.value
+
+
+def sfft_ring_bootstrap(d, bkt_ptr, n, lwe_ptr, m, out_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_ring_bootstrap(d, bkt_ptr, n, lwe_ptr, m, out_ptr, ws_ptr, ws_bytes, stream))

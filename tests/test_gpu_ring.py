@@ -229,3 +229,60 @@ def test_blind_rotate_edge_cases():
         assert e.value.code == S.SFFT_EINVAL
     with pytest.raises(S.SfftError):
         S.sfft_ring_bk_prepare(d, bk.data_ptr(), 2, bk.data_ptr(), _stream())
+
+
+def _lwe_inputs(seed, m, n, mus, B=3):
+    """LWE ciphertexts mod p of bits mus under a binary secret (test-side
+    encryption with Python integers): b = <a, s> + mu*floor(p/2) + e."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    s = g.integers(0, 2, size=n)
+    lwe = np.zeros((m, n + 1), np.uint64)
+    for j in range(m):
+        a = g.integers(0, O.P, size=n, dtype=np.uint64)
+        e = int(g.integers(-B, B + 1))
+        lwe[j, :n] = a
+        lwe[j, n] = (sum(int(x) * int(y) for x, y in zip(a, s)) + int(mus[j]) * (O.P // 2) + e) % O.P
+    return s, lwe
+
+
+def _bootstrap(dk, lwe, d):
+    n = lwe.shape[1] - 1
+    m = lwe.shape[0]
+    _, bkt = _prepared_key(dk, d)
+    lwe_d = _dev(lwe)
+    out = torch.zeros((m, d + 1), dtype=torch.int64, device="cuda")
+    ws_b = S.sfft_ring_bootstrap_workspace_bytes(d, n, m)
+    ws = torch.empty(ws_b // 8 + 1, dtype=torch.int64, device="cuda")
+    S.sfft_ring_bootstrap(d, bkt.data_ptr(), n, lwe_d.data_ptr(), m, out.data_ptr(), ws.data_ptr(), ws_b, _stream())
+    torch.cuda.synchronize()
+    return _host(out)
+
+
+@pytest.mark.parametrize("d,n,m", [(16, 4, 5), (64, 6, 3), (1024, 3, 2)])
+def test_bootstrap_matches_oracle(d, n, m):
+    say("ring bootstrap d=%d n=%d m=%d" % (d, n, m))
+    g = np.random.Generator(np.random.PCG64(900 + d))
+    mus = g.integers(0, 2, size=m)
+    s_lwe, lwe = _lwe_inputs(901 + d, m, n, mus)
+    dk = WL.ring_draws(902 + d, n, d, O.ROWS, O.P, bits=s_lwe.astype(np.uint8))
+    got = _bootstrap(dk, lwe, d)
+    want = O.bootstrap(O.encrypt(dk), lwe)
+    assert np.array_equal(got, want)
+
+
+def test_bootstrap_refreshes_noisy_bits():
+    """d = 1024, a 32-bit LWE key, 16 inputs with errors up to p/16: every
+    output decrypts (under the ring secret) to its input bit, with a phase
+    within the blind rotation's bound of mu * 2 * floor(p/4)."""
+    d, n, m = 1024, 32, 16
+    say("ring bootstrap refresh d=%d n=%d m=%d" % (d, n, m))
+    g = np.random.Generator(np.random.PCG64(950))
+    mus = g.integers(0, 2, size=m)
+    s_lwe, lwe = _lwe_inputs(951, m, n, mus, B=O.P // 16)
+    dk = WL.ring_draws(952, n, d, O.ROWS, O.P, bits=s_lwe.astype(np.uint8))
+    out = _bootstrap(dk, lwe, d)
+    bound = n * 2 * O.ELL * d * 2
+    for j in range(m):
+        ph = O.lwe_phase(out[j], dk.s)
+        err = ((ph - int(mus[j]) * 2 * (O.P // 4) + O.P // 2) % O.P) - O.P // 2
+        assert abs(err) <= bound, (j, err)

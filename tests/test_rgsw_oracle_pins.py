@@ -9,7 +9,9 @@
 * gate truth tables, the noise bound of one product, and a depth-3 circuit;
 * blind rotation: with a noiseless key it is exactly the rotation by
   X^(sum r_i s_i) (coefficients moved by hand); with a real key it decrypts
-  to the rotated test polynomial within n * 2*ell*d * B.
+  to the rotated test polynomial within n * 2*ell*d * B;
+* gate bootstrapping: exact output phase mu * 2 * floor(p/4) under a
+  noiseless key and noiseless inputs, within the bound under a real key.
 """
 import numpy as np
 import pytest
@@ -204,3 +206,51 @@ def test_blind_rotation_decrypts_to_the_rotated_test_polynomial():
         assert max(abs(x) for x in err) <= bound
         got_bits = [1 if min(int(v), R.P - int(v)) > R.P // 4 else 0 for v in ph]
         assert got_bits == [1 if min(int(v), R.P - int(v)) > R.P // 4 else 0 for v in want]
+
+
+def _lwe_inputs(seed, m, n, mus, B=3):
+    """LWE ciphertexts mod p of bits mus under a binary secret (test-side
+    encryption with Python integers): b = <a, s> + mu*floor(p/2) + e."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    s = g.integers(0, 2, size=n)
+    lwe = np.zeros((m, n + 1), np.uint64)
+    for j in range(m):
+        a = g.integers(0, R.P, size=n, dtype=np.uint64)
+        e = int(g.integers(-B, B + 1))
+        b = (sum(int(x) * int(y) for x, y in zip(a, s)) + int(mus[j]) * (R.P // 2) + e) % R.P
+        lwe[j, :n] = a
+        lwe[j, n] = b
+    return s, lwe
+
+
+def test_bootstrap_refreshes_bits():
+    """Gate bootstrapping: the output LWE ciphertexts (under the ring secret)
+    decrypt to the input bits, with a phase within the blind rotation's error
+    bound of mu * 2 * floor(p/4) -- whatever the inputs' error was."""
+    d, n, m, B = 32, 6, 8, 2
+    mus = np.array([0, 1, 1, 0, 1, 0, 0, 1])
+    s_lwe, lwe = _lwe_inputs(70, m, n, mus)
+    dk = WL.ring_draws(71, n, d, R.ROWS, R.P, B, bits=s_lwe.astype(np.uint8))
+    out = R.bootstrap(R.encrypt(dk), lwe)
+    delta = R.P // 4
+    bound = n * 2 * R.ELL * d * B
+    for j in range(m):
+        ph = R.lwe_phase(out[j], dk.s)
+        err = ((ph - int(mus[j]) * 2 * delta + R.P // 2) % R.P) - R.P // 2
+        assert abs(err) <= bound, (j, err)
+
+
+def test_bootstrap_with_noiseless_key_hits_the_encoding_exactly():
+    """With a noiseless key (bk[i] = s_i * G) and noiseless inputs, the output
+    phase is exactly mu * 2 * floor(p/4)."""
+    d, n, m = 16, 4, 6
+    mus = np.array([1, 0, 1, 1, 0, 0])
+    s_lwe, lwe = _lwe_inputs(80, m, n, mus, B=0)
+    bk = np.zeros((n, R.ROWS, 2, d), np.uint64)
+    for i in range(n):
+        if s_lwe[i]:
+            bk[i] = _gadget(d)[0]
+    out = R.bootstrap(bk, lwe)
+    zero = np.zeros(d, np.int64)   # the ring secret of a noiseless trivial key: its phase is b' itself
+    for j in range(m):
+        assert R.lwe_phase(out[j], zero) == int(mus[j]) * 2 * (R.P // 4) % R.P, j

@@ -81,3 +81,16 @@ def test_blind_rotation_argument_checks():
         with pytest.raises(S.SfftError) as e:
             S.sfft_ring_bk_prepare(*args, None)
         assert e.value.code == S.SFFT_EINVAL, args
+
+
+def test_bootstrap_argument_checks():
+    d = 16
+    assert S.sfft_ring_bootstrap_workspace_bytes(d, 5, 3) == 3 * 2 * d * 8 + 3 * 5 * 4
+    S.sfft_ring_bootstrap(d, 8, 5, 16, 0, 24, 32, 0, None)             # m = 0
+    ws = S.sfft_ring_bootstrap_workspace_bytes(d, 5, 3)
+    for args in ((3, 8, 5, 16, 3, 24, 32, ws), (d, 0, 5, 16, 3, 24, 32, ws), (d, 8, 5, 0, 3, 24, 32, ws),
+                 (d, 8, 5, 16, 3, 0, 32, ws), (d, 8, 5, 16, 3, 24, 0, ws), (d, 8, 5, 16, 3, 24, 32, ws - 1),
+                 (d, 8, -1, 16, 3, 24, 32, ws), (d, 8, 5, 16, -3, 24, 32, ws)):
+        with pytest.raises(S.SfftError) as e:
+            S.sfft_ring_bootstrap(*args, None)
+        assert e.value.code == S.SFFT_EINVAL, args
