@@ -645,6 +645,35 @@ def run_ring_br(args):
         ph = (int(o[j, d]) - sum(int(o[j, t]) * int(dk.s[t]) for t in range(d) if dk.s[t])) % P
         got = 1 if min(ph, P - ph) > P // 4 else 0
         assert got == int(mus[j]), "bootstrapped ciphertext %d decrypts to the wrong bit" % j
+    # key switching back to the 64-bit LWE secret closes the refresh loop; the
+    # key-switching key encrypts s_ring[t] * 16^k under it (errors in [-2, 2])
+    ksk = np.zeros((d, 16, n + 1), np.uint64)
+    ksk[:, :, :n] = g.integers(0, P, size=(d, 16, n), dtype=np.uint64)
+    ke = g.integers(-2, 3, size=(d, 16))
+    on = np.nonzero(dk.bits)[0]
+    for t_ in range(d):
+        for k_ in range(16):
+            dot = sum(int(ksk[t_, k_, i]) for i in on)
+            ksk[t_, k_, n] = (dot + int(dk.s[t_]) * (16 ** k_) + int(ke[t_, k_])) % P
+    ksk_d = torch.from_numpy(ksk.view(np.int64)).cuda()
+    ks_out = torch.empty((m, n + 1), dtype=torch.int64, device="cuda")
+
+    def keyswitch():
+        S.sfft_ring_keyswitch(d, n, ksk_d.data_ptr(), bs_out.data_ptr(), m, ks_out.data_ptr(), stream)
+
+    keyswitch()
+    torch.cuda.synchronize()
+    ev3 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a_, b_ in ev3:
+        a_.record()
+        keyswitch()
+        b_.record()
+    torch.cuda.synchronize()
+    ks_s = sum(a_.elapsed_time(b_) for a_, b_ in ev3) / len(ev3) / 1e3
+    o = ks_out.cpu().numpy().view(np.uint64)
+    for j in range(4):   # back under the LWE secret: phase reads mu * floor(p/2)
+        ph = (int(o[j, n]) - sum(int(o[j, i]) for i in on)) % P
+        assert (1 if min(ph, P - ph) > P // 4 else 0) == int(mus[j]), "refreshed ciphertext %d is wrong" % j
     mm = ring_modmuls_per_cmux(d) * m * n
     return {
         "metric": "CMux steps/s of ring-GSW blind rotation (1 GPU)",
@@ -664,6 +693,8 @@ def run_ring_br(args):
         "blind_rotations_per_s": m / launch_s,
         "bootstraps_per_s": m / bs_s,
         "bootstrap_ms_per_call": bs_s * 1e3,
+        "keyswitch_ms_per_call": ks_s * 1e3,
+        "refreshes_per_s": m / (bs_s + ks_s),
         "roofline": {"bound": "alu", "achieved": mm / launch_s / 1e9, "peak": PEAK_MODMUL / 1e9,
                      "unit": "Gmodmul/s", "frac": mm / launch_s / PEAK_MODMUL, "traffic": None,
                      "kernel": "k_ring_blind_rotate", "avg_launch_ms": launch_s * 1e3,

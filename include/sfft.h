@@ -324,9 +324,9 @@ int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int6
  *     acc <- acc + G^-1(X^r_i acc - acc) * bk[i]
  * so that acc ends encrypting X^(sum r_i s_i) times what it encrypted.  Each
  * step adds at most 2*ell*d times the key's error bound, whatever the
- * accumulator's own error: that is what makes refresh possible.  Key switching
- * back to the LWE path is not provided; modulus switching and sample
- * extraction come with sfft_ring_bootstrap. */
+ * accumulator's own error: that is what makes refresh possible
+ * (sfft_ring_bootstrap and sfft_ring_keyswitch complete it for LWE
+ * ciphertexts mod p). */
 /* Forward transforms of the key's rows into bkt_dev (n * sfft_ring_ct_words(d)
  * words, must not alias bk_dev); done once per key. */
 int sfft_ring_bk_prepare(int32_t d, const uint64_t* bk_dev, int64_t n, uint64_t* bkt_dev, void* hip_stream);
@@ -352,6 +352,16 @@ int sfft_ring_blind_rotate(int32_t d, const uint64_t* bkt_dev, int64_t n, const 
 int sfft_ring_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes);
 int sfft_ring_bootstrap(int32_t d, const uint64_t* bkt_dev, int64_t n, const uint64_t* lwe_dev, int64_t m,
                         uint64_t* out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream);
+/* Key switching from the ring secret back to the LWE secret, which closes the
+ * refresh loop: in_dev holds m LWE ciphertexts of d+1 words under the ring
+ * secret's coefficients (sfft_ring_bootstrap's output), out_dev receives m of
+ * n+1 words under the LWE secret of the key-switching key.  ksk_dev: d x 16 x
+ * (n+1) words, entry [t][k] an LWE encryption (a_0..a_{n-1}, b) of
+ * s_ring[t] * 16^k (caller-made, like the key).  out = (0, .., 0, b') -
+ * sum_{t,k} digit_k(a'_t) * ksk[t][k], digit_k the base-16 digits.  The error
+ * added is at most d*16*15 times the key's. */
+int sfft_ring_keyswitch(int32_t d, int64_t n, const uint64_t* ksk_dev, const uint64_t* in_dev, int64_t m,
+                        uint64_t* out_dev, void* hip_stream);
 
 #ifdef __cplusplus
 }

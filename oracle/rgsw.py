@@ -64,6 +64,7 @@ def lib():
         L.rg_blind_rotate.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64,
                                       np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), u64p, c.c_int64]
         L.rg_bootstrap.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, c.c_int64, u64p]
+        L.rg_keyswitch.argtypes = [c.c_uint64, c.c_int, c.c_int64, u64p, u64p, c.c_int64, u64p]
         L.rg_phase.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int, u64p, u64p]
         L.rg_decrypt.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, u8p]
         _lib = L
@@ -145,6 +146,17 @@ def bootstrap(bk, lwe) -> np.ndarray:
     d = bk.shape[3]
     out = np.zeros((m, d + 1), dtype=np.uint64)
     lib().rg_bootstrap(P, d, ELL, bk, n1 - 1, lwe, m, out)
+    return out
+
+
+def keyswitch(ksk, lwe) -> np.ndarray:
+    """Key switching of LWE ciphertexts lwe (m, d+1) under the ring secret to
+    the LWE secret of the key-switching key ksk (d, 16, n+1): (m, n+1)."""
+    ksk, lwe = _u64(ksk), _u64(lwe)
+    d, K, n1 = ksk.shape
+    assert K == 16 and lwe.shape[1] == d + 1
+    out = np.zeros((lwe.shape[0], n1), dtype=np.uint64)
+    lib().rg_keyswitch(P, d, n1 - 1, ksk, lwe, lwe.shape[0], out)
     return out
 
 

@@ -272,6 +272,32 @@ void rg_bootstrap(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, con
     free(rot);
 }
 
+/* Key switching of m LWE ciphertexts (a'_0..a'_{d-1}, b') mod p under the
+ * ring secret's coefficients to the LWE secret of n coefficients, with the
+ * key-switching key ksk[t][k] = an LWE encryption (n+1 words) under the LWE
+ * secret of s_ring[t] * 2^(4k), t < d, k < 16 (base-16 digits of a'_t):
+ *   out = (0, ..., 0, b') - sum_{t,k} digit_k(a'_t) * ksk[t][k]
+ * out: m x (n+1) words. */
+void rg_keyswitch(uint64_t p, int d, int64_t n, const uint64_t *ksk, const uint64_t *in, int64_t m, uint64_t *out)
+{
+    const int K = 16;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; j++) {
+        const uint64_t *c = in + j * (d + 1);
+        uint64_t *o = out + j * (n + 1);
+        for (int64_t q = 0; q <= n; q++) {
+            u128 sum = 0;
+            for (int t = 0; t < d; t++)
+                for (int k = 0; k < K; k++) {
+                    uint64_t dig = (c[t] >> (4 * k)) & 15;
+                    sum += (u128)dig * ksk[((int64_t)t * K + k) * (n + 1) + q];
+                }
+            uint64_t v = (uint64_t)(sum % p);
+            o[q] = subm(q == n ? c[d] : 0, v, p);
+        }
+    }
+}
+
 /* Phase of one row: C[row][0] - C[row][1]*s  (d coefficients). */
 void rg_phase(uint64_t p, int d, int ell, const uint64_t *ct, int row, const uint64_t *s, uint64_t *out)
 {

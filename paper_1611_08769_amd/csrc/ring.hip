@@ -309,6 +309,34 @@ __global__ __launch_bounds__(kT) void k_ring_extract(const uint64_t* __restrict_
         o[t] = t == D ? addp(a[0], kP / 4) : (t == 0 ? a[D] : subp(0, a[2 * D - t]));
 }
 
+// Key switching of LWE ciphertext j (a'_0..a'_{d-1}, b') under the ring
+// secret to the LWE secret of ksk ([t][k][n+1]: an encryption of
+// s_ring[t] * 16^k): out = (0, .., 0, b') - sum_{t,k} digit_k(a'_t) ksk[t][k].
+// One workgroup per ciphertext, a thread per output coordinate; the a'_t
+// sit in LDS, the key is read coalesced along the coordinate (L2-resident
+// across workgroups), and each coordinate's sum of d*16 products of a 4-bit
+// digit by a residue (below 2^80) is kept unreduced and reduced once.
+constexpr int kKsDigits = 16;  // base-16 digits of a residue below 2^64
+__global__ __launch_bounds__(kT) void k_ring_keyswitch(const uint64_t* __restrict__ ksk, const uint64_t* __restrict__ in,
+                                                       uint64_t* __restrict__ out, int d, int64_t n)
+{
+    extern __shared__ uint64_t lds[];
+    const int64_t j = blockIdx.x;
+    const uint64_t* c = in + j * (d + 1);
+    copy_lds(lds, c, d + 1);
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q <= n; q += kT) {
+        uint64_t lo = 0, hi = 0;
+        for (int t = 0; t < d; ++t) {
+            const uint64_t at = lds[t];
+            const uint64_t* kp = ksk + (int64_t)t * kKsDigits * (n + 1) + q;
+#pragma unroll
+            for (int k = 0; k < kKsDigits; ++k) mac128((at >> (4 * k)) & 15, kp[k * (n + 1)], &lo, &hi);
+        }
+        out[j * (n + 1) + q] = subp(q == n ? lds[d] : 0, red126(lo, hi));
+    }
+}
+
 // NOT (3): G - X;  XADD (7): X + Y.  Elementwise over n ciphertexts.
 __global__ __launch_bounds__(kT) void k_ring_linear(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Y,
                                                     uint64_t* __restrict__ out, int64_t count, int d, int logd,
@@ -666,6 +694,22 @@ int sfft_ring_bootstrap(int32_t d, const uint64_t* bkt_dev, int64_t n, const uin
     SFFT_RING_DISPATCH(logd, SFFT_BS)
 #undef SFFT_BS
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "ring bootstrap");
+}
+
+int sfft_ring_keyswitch(int32_t d, int64_t n, const uint64_t* ksk_dev, const uint64_t* in_dev, int64_t m,
+                        uint64_t* out_dev, void* hip_stream)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0 || m < 0) return sfft_fail(SFFT_EINVAL, "n < 0 or m < 0");
+    if (m == 0) return SFFT_OK;
+    if (!ksk_dev || !in_dev || !out_dev) return sfft_fail(SFFT_EINVAL, "null buffer");
+    if (m > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many ciphertexts for one call");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_ring_keyswitch, dim3((unsigned)m), dim3(kT), (size_t)(d + 1) * 8, s, ksk_dev, in_dev, out_dev,
+                       (int)d, n);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_keyswitch");
 }
 
 int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int64_t n, int ct_on_device,

@@ -120,6 +120,7 @@ _SIGS = {
                                                            _P(ctypes.c_int64)]),
     "sfft_ring_bootstrap": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp,
                                            ctypes.c_int64, _vp]),
+    "sfft_ring_keyswitch": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -345,3 +346,7 @@ def sfft_ring_bootstrap_workspace_bytes(d: int, n: int, m: int) -> int:
 
 def sfft_ring_bootstrap(d, bkt_ptr, n, lwe_ptr, m, out_ptr, ws_ptr, ws_bytes, stream) -> None:
     _check(_lib.sfft_ring_bootstrap(d, bkt_ptr, n, lwe_ptr, m, out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_ring_keyswitch(d, n, ksk_ptr, in_ptr, m, out_ptr, stream) -> None:
+    _check(_lib.sfft_ring_keyswitch(d, n, ksk_ptr, in_ptr, m, out_ptr, stream))

@@ -286,3 +286,60 @@ def test_bootstrap_refreshes_noisy_bits():
         ph = O.lwe_phase(out[j], dk.s)
         err = ((ph - int(mus[j]) * 2 * (O.P // 4) + O.P // 2) % O.P) - O.P // 2
         assert abs(err) <= bound, (j, err)
+
+
+def _ksk(seed, s_ring, s_lwe, B):
+    """Key-switching key (test-side encryption with Python integers): entry
+    [t][k] encrypts s_ring[t] * 16^k under s_lwe, errors in [-B, B]."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    d, n = len(s_ring), len(s_lwe)
+    ksk = np.zeros((d, 16, n + 1), np.uint64)
+    ksk[:, :, :n] = g.integers(0, O.P, size=(d, 16, n), dtype=np.uint64)
+    e = g.integers(-B, B + 1, size=(d, 16))
+    on = [i for i in range(n) if s_lwe[i]]
+    for t in range(d):
+        for k in range(16):
+            dot = sum(int(ksk[t, k, i]) for i in on)
+            ksk[t, k, n] = (dot + int(s_ring[t]) * (16 ** k) + int(e[t, k])) % O.P
+    return ksk
+
+
+def _keyswitch(ksk, lwe, d):
+    n = ksk.shape[2] - 1
+    m = lwe.shape[0]
+    k_d, in_d = _dev(ksk), _dev(lwe)
+    out = torch.zeros((m, n + 1), dtype=torch.int64, device="cuda")
+    S.sfft_ring_keyswitch(d, n, k_d.data_ptr(), in_d.data_ptr(), m, out.data_ptr(), _stream())
+    torch.cuda.synchronize()
+    return _host(out)
+
+
+@pytest.mark.parametrize("d,n,m", [(16, 5, 4), (1024, 32, 3)])
+def test_keyswitch_matches_oracle(d, n, m):
+    say("ring key switch d=%d n=%d m=%d" % (d, n, m))
+    g = np.random.Generator(np.random.PCG64(980 + d))
+    s_ring = g.integers(-1, 2, size=d)
+    s_lwe = g.integers(0, 2, size=n)
+    ksk = _ksk(981 + d, s_ring, s_lwe, 2)
+    lwe = g.integers(0, O.P, size=(m, d + 1), dtype=np.uint64)
+    assert np.array_equal(_keyswitch(ksk, lwe, d), O.keyswitch(ksk, lwe))
+
+
+def test_refresh_round_trip_d1024():
+    """LWE ciphertexts under a 32-bit binary secret with errors up to p/16,
+    bootstrapped and key-switched back twice: every round decrypts under the
+    same secret to the input bits with an error inside the two steps' bound."""
+    d, n, m = 1024, 32, 8
+    say("ring refresh round trip d=%d n=%d m=%d" % (d, n, m))
+    g = np.random.Generator(np.random.PCG64(990))
+    mus = g.integers(0, 2, size=m)
+    s_lwe, lwe = _lwe_inputs(991, m, n, mus, B=O.P // 16)
+    dk = WL.ring_draws(992, n, d, O.ROWS, O.P, bits=s_lwe.astype(np.uint8))
+    ksk = _ksk(993, dk.s, s_lwe, 2)
+    bound = n * 2 * O.ELL * d * 2 + d * 16 * 15 * 2
+    cur = lwe
+    for _ in range(2):
+        cur = _keyswitch(ksk, _bootstrap(dk, cur, d), d)
+        for j in range(m):
+            err = ((O.lwe_phase(cur[j], s_lwe) - int(mus[j]) * (O.P // 2) + O.P // 2) % O.P) - O.P // 2
+            assert abs(err) <= bound, (j, err)

@@ -11,7 +11,9 @@
   X^(sum r_i s_i) (coefficients moved by hand); with a real key it decrypts
   to the rotated test polynomial within n * 2*ell*d * B;
 * gate bootstrapping: exact output phase mu * 2 * floor(p/4) under a
-  noiseless key and noiseless inputs, within the bound under a real key.
+  noiseless key and noiseless inputs, within the bound under a real key;
+* key switching keeps the phase exactly under a noiseless key; bootstrapping
+  plus key switching refreshes LWE ciphertexts twice in a row.
 """
 import numpy as np
 import pytest
@@ -254,3 +256,55 @@ def test_bootstrap_with_noiseless_key_hits_the_encoding_exactly():
     zero = np.zeros(d, np.int64)   # the ring secret of a noiseless trivial key: its phase is b' itself
     for j in range(m):
         assert R.lwe_phase(out[j], zero) == int(mus[j]) * 2 * (R.P // 4) % R.P, j
+
+
+def _ksk(seed, s_ring, s_lwe, B):
+    """Key-switching key (test-side encryption with Python integers): entry
+    [t][k] encrypts s_ring[t] * 16^k under s_lwe, errors in [-B, B]."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    d, n = len(s_ring), len(s_lwe)
+    ksk = np.zeros((d, 16, n + 1), np.uint64)
+    ksk[:, :, :n] = g.integers(0, R.P, size=(d, 16, n), dtype=np.uint64)
+    e = g.integers(-B, B + 1, size=(d, 16)) if B else np.zeros((d, 16), np.int64)
+    sl = [int(x) for x in s_lwe]
+    for t in range(d):
+        for k in range(16):
+            dot = sum(int(x) * y for x, y in zip(ksk[t, k, :n], sl) if y)
+            ksk[t, k, n] = (dot + int(s_ring[t]) * (16 ** k) + int(e[t, k])) % R.P
+    return ksk
+
+
+def test_keyswitch_with_noiseless_key_keeps_the_phase():
+    """Under a noiseless key-switching key the phase under the new secret
+    equals the phase under the old one, exactly."""
+    d, n, m = 16, 5, 4
+    g = np.random.Generator(np.random.PCG64(90))
+    s_ring = g.integers(-1, 2, size=d)
+    s_lwe = g.integers(0, 2, size=n)
+    ksk = _ksk(91, s_ring, s_lwe, 0)
+    lwe = g.integers(0, R.P, size=(m, d + 1), dtype=np.uint64)
+    out = R.keyswitch(ksk, lwe)
+    for j in range(m):
+        assert R.lwe_phase(out[j], s_lwe) == R.lwe_phase(lwe[j], s_ring), j
+
+
+def test_refresh_round_trip():
+    """Bootstrapping then key switching maps LWE ciphertexts under s_lwe back
+    to LWE ciphertexts under s_lwe, with errors reset: inputs with errors up
+    to p/16 come out with errors below the bound of the two steps, twice in
+    a row (2*floor(p/4) = floor(p/2) for this p, so the output encoding is
+    the input's)."""
+    d, n, m, B = 32, 6, 6, 2
+    mus = np.array([1, 0, 0, 1, 1, 0])
+    s_lwe, lwe = _lwe_inputs(95, m, n, mus, B=R.P // 16)
+    dk = WL.ring_draws(96, n, d, R.ROWS, R.P, B, bits=s_lwe.astype(np.uint8))
+    bk = R.encrypt(dk)
+    ksk = _ksk(97, dk.s, s_lwe, B)
+    bound = n * 2 * R.ELL * d * B + d * 16 * 15 * B
+    cur = lwe
+    for _ in range(2):
+        cur = R.keyswitch(ksk, R.bootstrap(bk, cur))
+        assert cur.shape == lwe.shape
+        for j in range(m):
+            err = ((R.lwe_phase(cur[j], s_lwe) - int(mus[j]) * 2 * (R.P // 4) + R.P // 2) % R.P) - R.P // 2
+            assert abs(err) <= bound, (j, err)

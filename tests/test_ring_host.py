@@ -94,3 +94,13 @@ def test_bootstrap_argument_checks():
         with pytest.raises(S.SfftError) as e:
             S.sfft_ring_bootstrap(*args, None)
         assert e.value.code == S.SFFT_EINVAL, args
+
+
+def test_keyswitch_argument_checks():
+    d = 16
+    S.sfft_ring_keyswitch(d, 5, 8, 16, 0, 24, None)                  # m = 0
+    for args in ((3, 5, 8, 16, 1, 24), (d, -1, 8, 16, 1, 24), (d, 5, 8, 16, -1, 24), (d, 5, 0, 16, 1, 24),
+                 (d, 5, 8, 0, 1, 24), (d, 5, 8, 16, 1, 0)):
+        with pytest.raises(S.SfftError) as e:
+            S.sfft_ring_keyswitch(*args, None)
+        assert e.value.code == S.SFFT_EINVAL, args
