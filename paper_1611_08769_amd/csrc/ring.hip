@@ -21,6 +21,14 @@
 //   k_ring_linear   NOT and XADD (no product)
 //   k_ring_encrypt  one workgroup per (ciphertext, row): a*s by transforms,
 //                   plus the error and the gadget
+// and the refresh of LWE ciphertexts mod p (refresh is only mentioned by the
+// paper's section "Error Analysis"; this is the FHEW/TFHE construction with
+// these ring-GSW ciphertexts as the key):
+//   k_ring_br_init       modulus switch to 2d, accumulator and rotations
+//   k_ring_blind_rotate  one workgroup per accumulator runs all its CMux
+//                        steps, each one row of the same product
+//   k_ring_extract       coefficient 0 as an LWE ciphertext (ring secret)
+//   k_ring_keyswitch     back to the LWE secret
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
