@@ -65,6 +65,9 @@ def lib():
                                       np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), u64p, c.c_int64]
         L.rg_bootstrap.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, c.c_int64, u64p]
         L.rg_keyswitch.argtypes = [c.c_uint64, c.c_int, c.c_int64, u64p, u64p, c.c_int64, u64p]
+        L.rg_gate_bootstrap.restype = c.c_int
+        L.rg_gate_bootstrap.argtypes = [c.c_uint64, c.c_int, c.c_int, c.c_int, u64p, c.c_int64, u64p, u64p, u64p,
+                                        c.c_int64, u64p]
         L.rg_phase.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int, u64p, u64p]
         L.rg_decrypt.argtypes = [c.c_uint64, c.c_int, c.c_int, u64p, c.c_int64, u64p, u8p]
         _lib = L
@@ -157,6 +160,18 @@ def keyswitch(ksk, lwe) -> np.ndarray:
     assert K == 16 and lwe.shape[1] == d + 1
     out = np.zeros((lwe.shape[0], n1), dtype=np.uint64)
     lib().rg_keyswitch(P, d, n1 - 1, ksk, lwe, lwe.shape[0], out)
+    return out
+
+
+def gate_bootstrap(gate: int, bk, ksk, x, y) -> np.ndarray:
+    """Bootstrapped gate (4 AND, 5 XOR, 6 OR, 8 NAND) on LWE ciphertexts x, y
+    (m, n+1) mod p, bits encoded as mu * 2 * floor(p/8): (m, n+1) outputs in
+    the same encoding under the same secret (see rgsw_ref.c)."""
+    bk, ksk, x, y = _u64(bk), _u64(ksk), _u64(x), _u64(y)
+    m, n1 = x.shape
+    out = np.zeros_like(x)
+    if lib().rg_gate_bootstrap(P, bk.shape[3], ELL, gate, bk, n1 - 1, ksk, x, y, m, out) != 0:
+        raise ValueError("gate must be 4, 5, 6 or 8")
     return out
 
 

@@ -239,10 +239,10 @@ void rg_blind_rotate(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, 
  *      (a'_0..a'_{d-1}, b') under the ring secret's coefficients with
  *      a'_0 = a_0, a'_t = -a_{d-t}, whose phase is mu*2*Delta + fresh error.
  * out: m x (d+1) words. */
-void rg_bootstrap(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, const uint64_t *lwe, int64_t m,
-                  uint64_t *out)
+static void bootstrap_delta(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, const uint64_t *lwe,
+                            int64_t m, uint64_t *out, uint64_t delta)
 {
-    const uint64_t delta = p / 4, two_d = 2 * (uint64_t)d;
+    const uint64_t two_d = 2 * (uint64_t)d;
     uint64_t *acc = malloc(sizeof(uint64_t) * 2 * d * (m > 0 ? m : 1));
     int32_t *rot = malloc(sizeof(int32_t) * (n * m > 0 ? n * m : 1));
     for (int64_t j = 0; j < m; j++) {
@@ -272,6 +272,12 @@ void rg_bootstrap(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, con
     free(rot);
 }
 
+void rg_bootstrap(uint64_t p, int d, int ell, const uint64_t *bk, int64_t n, const uint64_t *lwe, int64_t m,
+                  uint64_t *out)
+{
+    bootstrap_delta(p, d, ell, bk, n, lwe, m, out, p / 4);
+}
+
 /* Key switching of m LWE ciphertexts (a'_0..a'_{d-1}, b') mod p under the
  * ring secret's coefficients to the LWE secret of n coefficients, with the
  * key-switching key ksk[t][k] = an LWE encryption (n+1 words) under the LWE
@@ -296,6 +302,43 @@ void rg_keyswitch(uint64_t p, int d, int64_t n, const uint64_t *ksk, const uint6
             o[q] = subm(q == n ? c[d] : 0, v, p);
         }
     }
+}
+
+/* Bootstrapped binary gates (FHEW-style) on LWE ciphertexts mod p under a
+ * binary secret of n bits, bits encoded as mu * 2 * q8, q8 = floor(p/8):
+ *   combine  c = cx*x + cy*y + (0, .., 0, k*q8): AND (1, 1, -1), OR (1, 1, 1),
+ *            NAND (-1, -1, 5), XOR (2, 2, 0) -- so that the phase of c lies
+ *            in (-p/4, p/4) for a 0 result and in (p/4, 3p/4) for a 1, at
+ *            least p/8 from either edge
+ *   refresh  the bootstrap with Delta = q8 (accumulator value and the constant
+ *            added at extraction): phase mu * 2 * q8 under the ring secret
+ *   switch   back to the LWE secret with ksk (as rg_keyswitch).
+ * gate: 4 AND, 5 XOR, 6 OR, 8 NAND.  x, y, out: m x (n+1) words.  Returns 0,
+ * or -1 for another gate. */
+int rg_gate_bootstrap(uint64_t p, int d, int ell, int gate, const uint64_t *bk, int64_t n, const uint64_t *ksk,
+                      const uint64_t *x, const uint64_t *y, int64_t m, uint64_t *out)
+{
+    int64_t cx, cy, k;
+    switch (gate) {
+    case 4: cx = 1, cy = 1, k = -1; break;
+    case 6: cx = 1, cy = 1, k = 1; break;
+    case 8: cx = -1, cy = -1, k = 5; break;
+    case 5: cx = 2, cy = 2, k = 0; break;
+    default: return -1;
+    }
+    const uint64_t q8 = p / 8;
+    uint64_t *c = malloc(sizeof(uint64_t) * (n + 1) * (m > 0 ? m : 1));
+    uint64_t *mid = malloc(sizeof(uint64_t) * (d + 1) * (m > 0 ? m : 1));
+    for (int64_t j = 0; j < m * (n + 1); j++) {
+        u128 v = ((u128)(uint64_t)(cx < 0 ? p + cx : cx) * x[j] + (u128)(uint64_t)(cy < 0 ? p + cy : cy) * y[j]) % p;
+        if (j % (n + 1) == n) v = (v + (u128)(uint64_t)(k < 0 ? p + k : k) * q8) % p;
+        c[j] = (uint64_t)v;
+    }
+    bootstrap_delta(p, d, ell, bk, n, c, m, mid, q8);
+    rg_keyswitch(p, d, n, ksk, mid, m, out);
+    free(c);
+    free(mid);
+    return 0;
 }
 
 /* Phase of one row: C[row][0] - C[row][1]*s  (d coefficients). */

@@ -308,3 +308,56 @@ def test_refresh_round_trip():
         for j in range(m):
             err = ((R.lwe_phase(cur[j], s_lwe) - int(mus[j]) * 2 * (R.P // 4) + R.P // 2) % R.P) - R.P // 2
             assert abs(err) <= bound, (j, err)
+
+
+def _lwe_bits(seed, s, mus, B):
+    """LWE ciphertexts of bits mus encoded as mu * 2 * floor(p/8) under s."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    n = len(s)
+    out = np.zeros((len(mus), n + 1), np.uint64)
+    out[:, :n] = g.integers(0, R.P, size=(len(mus), n), dtype=np.uint64)
+    for j, mu in enumerate(mus):
+        e = int(g.integers(-B, B + 1))
+        out[j, n] = (sum(int(out[j, i]) for i in range(n) if s[i]) + int(mu) * 2 * (R.P // 8) + e) % R.P
+    return out
+
+
+def _decode_q4(c, s):
+    ph = R.lwe_phase(c, s)
+    return 1 if abs(((ph - 2 * (R.P // 8) + R.P // 2) % R.P) - R.P // 2) < R.P // 8 else 0
+
+
+def _gate_keys(d, n, seed, B=2):
+    g = np.random.Generator(np.random.PCG64(seed))
+    s_lwe = g.integers(0, 2, size=n)
+    dk = WL.ring_draws(seed + 1, n, d, R.ROWS, R.P, B, bits=s_lwe.astype(np.uint8))
+    return s_lwe, R.encrypt(dk), _ksk(seed + 2, dk.s, s_lwe, B)
+
+
+@pytest.mark.parametrize("gate,fn", [(4, lambda a, b: a & b), (6, lambda a, b: a | b),
+                                     (8, lambda a, b: 1 - (a & b)), (5, lambda a, b: a ^ b)])
+def test_bootstrapped_gate_truth_tables(gate, fn):
+    d, n = 16, 6
+    s_lwe, bk, ksk = _gate_keys(d, n, 300 + gate)
+    xs, ys = [0, 0, 1, 1], [0, 1, 0, 1]
+    x = _lwe_bits(310 + gate, s_lwe, xs, R.P // 64)
+    y = _lwe_bits(320 + gate, s_lwe, ys, R.P // 64)
+    out = R.gate_bootstrap(gate, bk, ksk, x, y)
+    assert [_decode_q4(out[j], s_lwe) for j in range(4)] == [fn(a, b) for a, b in zip(xs, ys)]
+
+
+def test_bootstrapped_gates_compose():
+    """A full adder from bootstrapped gates, twice chained (carry into the
+    next), on all 8 input triples: outputs decode exactly, errors stay fresh."""
+    d, n = 16, 6
+    s_lwe, bk, ksk = _gate_keys(d, n, 400)
+    trip = [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+    A = _lwe_bits(401, s_lwe, [t[0] for t in trip], 2)
+    Bc = _lwe_bits(402, s_lwe, [t[1] for t in trip], 2)
+    C = _lwe_bits(403, s_lwe, [t[2] for t in trip], 2)
+    axb = R.gate_bootstrap(5, bk, ksk, A, Bc)
+    s_ = R.gate_bootstrap(5, bk, ksk, axb, C)
+    carry = R.gate_bootstrap(6, bk, ksk, R.gate_bootstrap(4, bk, ksk, A, Bc), R.gate_bootstrap(4, bk, ksk, axb, C))
+    for j, (a, b, c) in enumerate(trip):
+        assert _decode_q4(s_[j], s_lwe) == a ^ b ^ c
+        assert _decode_q4(carry[j], s_lwe) == (a & b) | (c & (a ^ b))
