@@ -362,6 +362,21 @@ int sfft_ring_bootstrap(int32_t d, const uint64_t* bkt_dev, int64_t n, const uin
  * added is at most d*16*15 times the key's. */
 int sfft_ring_keyswitch(int32_t d, int64_t n, const uint64_t* ksk_dev, const uint64_t* in_dev, int64_t m,
                         uint64_t* out_dev, void* hip_stream);
+/* Bootstrapped binary gates (FHEW-style: every gate refreshes, so circuits
+ * of any depth decrypt).  x_dev, y_dev: m LWE ciphertexts mod p of n+1 words
+ * under the LWE secret, bits encoded as mu * 2 * floor(p/8) (error below
+ * p/16).  gate: 4 AND, 5 XOR, 6 OR, 8 NAND.  Each output is
+ *   keyswitch(bootstrap(cx*x + cy*y + (0, .., 0, k*floor(p/8))))
+ * with (cx, cy, k) = (1, 1, -1) AND, (1, 1, 1) OR, (-1, -1, 5) NAND,
+ * (2, 2, 0) XOR, and the bootstrap's accumulator value floor(p/8) (in place
+ * of sfft_ring_bootstrap's floor(p/4)), so out_dev (m x (n+1) words) holds
+ * the gate's bit in the same encoding under the same secret.  ws: at least
+ * sfft_ring_gate_bootstrap_workspace_bytes.  NOT needs no bootstrap:
+ * (0, .., 0, 2*floor(p/8)) - x. */
+int sfft_ring_gate_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes);
+int sfft_ring_gate_bootstrap(int32_t d, int32_t gate, const uint64_t* bkt_dev, int64_t n, const uint64_t* ksk_dev,
+                             const uint64_t* x_dev, const uint64_t* y_dev, int64_t m, uint64_t* out_dev, void* ws_dev,
+                             int64_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,8 @@
 //                        steps, each one row of the same product
 //   k_ring_extract       coefficient 0 as an LWE ciphertext (ring secret)
 //   k_ring_keyswitch     back to the LWE secret
+// (k_ring_br_init also forms the linear combination of two ciphertexts that
+// turns a refresh into a bootstrapped AND, OR, NAND or XOR gate)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -283,19 +285,31 @@ __device__ __forceinline__ int32_t switch_2d(uint64_t x)
     return (int32_t)(q & ((2u << LOGD) - 1));
 }
 
-// Gate bootstrapping, step 1: for LWE ciphertext j (a_0..a_{n-1}, b), the
-// rotations -a~_i mod 2D and the accumulator (X^(b~ + D/2) * TV, 0), TV =
-// Delta * (1 + X + ... + X^(D-1)), Delta = floor(p/4).
+// cx * v for a small signed coefficient cx in {-1, 0, 1, 2}.
+__device__ __forceinline__ uint64_t small_mul(int cx, uint64_t v)
+{
+    return cx == 1 ? v : cx == 2 ? addp(v, v) : cx == -1 ? subp(0, v) : 0;
+}
+
+// Gate bootstrapping, step 1: for LWE ciphertext j, c = cx*x_j + cy*y_j
+// (+ cb on b) with c = (a_0..a_{n-1}, b), the rotations -a~_i mod 2D and
+// the accumulator (X^(b~ + D/2) * TV, 0), TV = delta * (1 + X + ... +
+// X^(D-1)).  y may be null (cy = 0).
 template <int LOGD>
-__global__ __launch_bounds__(kT) void k_ring_br_init(const uint64_t* __restrict__ lwe, int64_t n,
-                                                     int32_t* __restrict__ rot, uint64_t* __restrict__ acc)
+__global__ __launch_bounds__(kT) void k_ring_br_init(const uint64_t* __restrict__ x, const uint64_t* __restrict__ y,
+                                                     int cx, int cy, uint64_t cb, int64_t n, int32_t* __restrict__ rot,
+                                                     uint64_t* __restrict__ acc, uint64_t delta)
 {
     constexpr int D = 1 << LOGD;
-    constexpr uint64_t delta = kP / 4;
     const int64_t j = blockIdx.x;
-    const uint64_t* c = lwe + j * (n + 1);
-    for (int64_t i = threadIdx.x; i < n; i += kT) rot[j * n + i] = (2 * D - switch_2d<LOGD>(c[i])) % (2 * D);
-    const int k = (switch_2d<LOGD>(c[n]) + D / 2) % (2 * D);
+    const uint64_t* xc = x + j * (n + 1);
+    const uint64_t* yc = y ? y + j * (n + 1) : nullptr;
+    auto coord = [&](int64_t i) {
+        const uint64_t v = small_mul(cx, xc[i]);
+        return yc ? addp(v, small_mul(cy, yc[i])) : v;
+    };
+    for (int64_t i = threadIdx.x; i < n; i += kT) rot[j * n + i] = (2 * D - switch_2d<LOGD>(coord(i))) % (2 * D);
+    const int k = (switch_2d<LOGD>(addp(coord(n), cb)) + D / 2) % (2 * D);
     uint64_t* a = acc + j * 2 * D;
     for (int u = threadIdx.x; u < D; u += kT) {
         a[u] = ((u - k + 2 * D) % (2 * D)) < D ? delta : kP - delta;
@@ -305,16 +319,17 @@ __global__ __launch_bounds__(kT) void k_ring_br_init(const uint64_t* __restrict_
 
 // Gate bootstrapping, step 3: coefficient 0 of accumulator j as an LWE
 // ciphertext under the ring secret's coefficients, (a_0, -a_{D-1}, ...,
-// -a_1, b_0 + Delta).
+// -a_1, b_0 + delta).
 template <int LOGD>
-__global__ __launch_bounds__(kT) void k_ring_extract(const uint64_t* __restrict__ acc, uint64_t* __restrict__ out)
+__global__ __launch_bounds__(kT) void k_ring_extract(const uint64_t* __restrict__ acc, uint64_t* __restrict__ out,
+                                                     uint64_t delta)
 {
     constexpr int D = 1 << LOGD;
     const int64_t j = blockIdx.x;
     const uint64_t* a = acc + j * 2 * D;
     uint64_t* o = out + j * (D + 1);
     for (int t = threadIdx.x; t <= D; t += kT)
-        o[t] = t == D ? addp(a[0], kP / 4) : (t == 0 ? a[D] : subp(0, a[2 * D - t]));
+        o[t] = t == D ? addp(a[0], delta) : (t == 0 ? a[D] : subp(0, a[2 * D - t]));
 }
 
 // Key switching of LWE ciphertext j (a'_0..a'_{d-1}, b') under the ring
@@ -520,15 +535,25 @@ hipError_t launch_blind_rotate(const uint64_t* bkt, int64_t n, const int32_t* ro
     return hipGetLastError();
 }
 
+// The combination (cx, cy, cb) of x and y, switched, blind-rotated and
+// extracted with accumulator value delta.
+struct Combine {
+    const uint64_t* x;
+    const uint64_t* y;
+    int cx, cy;
+    uint64_t cb, delta;
+};
+
 template <int LOGD>
-hipError_t launch_bootstrap(const uint64_t* bkt, int64_t n, const uint64_t* lwe, int64_t m, uint64_t* out,
-                            uint64_t* acc, int32_t* rot, TwView tv, hipStream_t s)
+hipError_t launch_bootstrap(const uint64_t* bkt, int64_t n, const Combine& cm, int64_t m, uint64_t* out, uint64_t* acc,
+                            int32_t* rot, TwView tv, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ring_br_init<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, lwe, n, rot, acc);
+    hipLaunchKernelGGL(k_ring_br_init<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, cm.x, cm.y, cm.cx, cm.cy, cm.cb, n, rot,
+                       acc, cm.delta);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n > 0 && (e = launch_blind_rotate<LOGD>(bkt, n, rot, acc, m, tv, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ring_extract<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, acc, out);
+    hipLaunchKernelGGL(k_ring_extract<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, acc, out, cm.delta);
     return hipGetLastError();
 }
 
@@ -698,7 +723,8 @@ int sfft_ring_bootstrap(int32_t d, const uint64_t* bkt_dev, int64_t n, const uin
     int32_t* rot = (int32_t*)(acc + m * 2 * d);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipSuccess;
-#define SFFT_BS(L) { e = launch_bootstrap<L>(bkt_dev, n, lwe_dev, m, out_dev, acc, rot, tv, s); break; }
+    const Combine cm{lwe_dev, nullptr, 1, 0, 0, kP / 4};
+#define SFFT_BS(L) { e = launch_bootstrap<L>(bkt_dev, n, cm, m, out_dev, acc, rot, tv, s); break; }
     SFFT_RING_DISPATCH(logd, SFFT_BS)
 #undef SFFT_BS
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "ring bootstrap");
@@ -718,6 +744,51 @@ int sfft_ring_keyswitch(int32_t d, int64_t n, const uint64_t* ksk_dev, const uin
                        (int)d, n);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_keyswitch");
+}
+
+int sfft_ring_gate_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 0 || m < 0 || !bytes) return sfft_fail(SFFT_EINVAL, "n < 0, m < 0 or null output");
+    *bytes = m * 2 * d * 8 + m * (d + 1) * 8 + m * n * 4;
+    return SFFT_OK;
+}
+
+int sfft_ring_gate_bootstrap(int32_t d, int32_t gate, const uint64_t* bkt_dev, int64_t n, const uint64_t* ksk_dev,
+                             const uint64_t* x_dev, const uint64_t* y_dev, int64_t m, uint64_t* out_dev, void* ws_dev,
+                             int64_t ws_bytes, void* hip_stream)
+{
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    int cx, cy, k;
+    switch (gate) {
+    case 4: cx = 1, cy = 1, k = -1; break;   // AND
+    case 6: cx = 1, cy = 1, k = 1; break;    // OR
+    case 8: cx = -1, cy = -1, k = 5; break;  // NAND
+    case 5: cx = 2, cy = 2, k = 0; break;    // XOR
+    default: return sfft_fail(SFFT_EINVAL, "gate must be 4 (AND), 5 (XOR), 6 (OR) or 8 (NAND)");
+    }
+    if (n < 0 || m < 0) return sfft_fail(SFFT_EINVAL, "n < 0 or m < 0");
+    if (m == 0) return SFFT_OK;
+    if (!x_dev || !y_dev || !out_dev || !ksk_dev || !ws_dev || (n > 0 && !bkt_dev))
+        return sfft_fail(SFFT_EINVAL, "null buffer");
+    if (m > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many ciphertexts for one call");
+    if (ws_bytes < m * 2 * d * 8 + m * (d + 1) * 8 + m * n * 4) return sfft_fail(SFFT_EINVAL, "workspace too small");
+    TwView tv;
+    if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
+    const uint64_t q8 = kP / 8;
+    const Combine cm{x_dev, y_dev, cx, cy, k >= 0 ? (uint64_t)k * q8 : kP - (uint64_t)(-k) * q8, q8};
+    uint64_t* acc = (uint64_t*)ws_dev;
+    uint64_t* mid = acc + m * 2 * d;
+    int32_t* rot = (int32_t*)(mid + m * (d + 1));
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSuccess;
+#define SFFT_GBS(L) { e = launch_bootstrap<L>(bkt_dev, n, cm, m, mid, acc, rot, tv, s); break; }
+    SFFT_RING_DISPATCH(logd, SFFT_GBS)
+#undef SFFT_GBS
+    if (e != hipSuccess) return sfft_hip_fail(e, "ring gate bootstrap");
+    return sfft_ring_keyswitch(d, n, ksk_dev, mid, m, out_dev, hip_stream);
 }
 
 int sfft_ring_decrypt(int32_t d, const int64_t* s_host, const uint64_t* ct, int64_t n, int ct_on_device,

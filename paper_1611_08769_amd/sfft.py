@@ -121,6 +121,10 @@ _SIGS = {
     "sfft_ring_bootstrap": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp,
                                            ctypes.c_int64, _vp]),
     "sfft_ring_keyswitch": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "sfft_ring_gate_bootstrap_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                                _P(ctypes.c_int64)]),
+    "sfft_ring_gate_bootstrap": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp,
+                                                ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -350,3 +354,14 @@ def sfft_ring_bootstrap(d, bkt_ptr, n, lwe_ptr, m, out_ptr, ws_ptr, ws_bytes, st
 
 def sfft_ring_keyswitch(d, n, ksk_ptr, in_ptr, m, out_ptr, stream) -> None:
     _check(_lib.sfft_ring_keyswitch(d, n, ksk_ptr, in_ptr, m, out_ptr, stream))
+
+
+def sfft_ring_gate_bootstrap_workspace_bytes(d: int, n: int, m: int) -> int:
+    b = ctypes.c_int64()
+    _check(_lib.sfft_ring_gate_bootstrap_workspace_bytes(d, n, m, ctypes.byref(b)))
+    return b.value
+
+
+def sfft_ring_gate_bootstrap(d, gate, bkt_ptr, n, ksk_ptr, x_ptr, y_ptr, m, out_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_ring_gate_bootstrap(d, gate, bkt_ptr, n, ksk_ptr, x_ptr, y_ptr, m, out_ptr, ws_ptr, ws_bytes,
+                                         stream))

@@ -343,3 +343,87 @@ def test_refresh_round_trip_d1024():
         for j in range(m):
             err = ((O.lwe_phase(cur[j], s_lwe) - int(mus[j]) * (O.P // 2) + O.P // 2) % O.P) - O.P // 2
             assert abs(err) <= bound, (j, err)
+
+
+def _lwe_bits(seed, s, mus, B):
+    """LWE ciphertexts of bits mus encoded as mu * 2 * floor(p/8) under s."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    n = len(s)
+    out = np.zeros((len(mus), n + 1), np.uint64)
+    out[:, :n] = g.integers(0, O.P, size=(len(mus), n), dtype=np.uint64)
+    on = [i for i in range(n) if s[i]]
+    for j, mu in enumerate(mus):
+        e = int(g.integers(-B, B + 1))
+        out[j, n] = (sum(int(out[j, i]) for i in on) + int(mu) * 2 * (O.P // 8) + e) % O.P
+    return out
+
+
+def _decode_q4(c, s):
+    ph = O.lwe_phase(c, s)
+    return 1 if abs(((ph - 2 * (O.P // 8) + O.P // 2) % O.P) - O.P // 2) < O.P // 8 else 0
+
+
+class _GateKeys:
+    def __init__(self, d, n, seed):
+        g = np.random.Generator(np.random.PCG64(seed))
+        self.d, self.n = d, n
+        self.s = g.integers(0, 2, size=n)
+        dk = WL.ring_draws(seed + 1, n, d, O.ROWS, O.P, bits=self.s.astype(np.uint8))
+        self.bk, self.bkt = _prepared_key(dk, d)
+        self.ksk = _ksk(seed + 2, dk.s, self.s, 2)
+        self.ksk_d = _dev(self.ksk)
+
+    def gate(self, g, x, y):
+        m = x.shape[0]
+        xd, yd = _dev(x), _dev(y)
+        out = torch.zeros((m, self.n + 1), dtype=torch.int64, device="cuda")
+        ws_b = S.sfft_ring_gate_bootstrap_workspace_bytes(self.d, self.n, m)
+        ws = torch.empty(ws_b // 8 + 1, dtype=torch.int64, device="cuda")
+        S.sfft_ring_gate_bootstrap(self.d, g, self.bkt.data_ptr(), self.n, self.ksk_d.data_ptr(), xd.data_ptr(),
+                                   yd.data_ptr(), m, out.data_ptr(), ws.data_ptr(), ws_b, _stream())
+        torch.cuda.synchronize()
+        return _host(out)
+
+
+@pytest.mark.parametrize("d,n", [(16, 5), (1024, 4)])
+def test_bootstrapped_gates_match_oracle(d, n):
+    """AND, XOR, OR, NAND on all four input pairs (errors up to p/64), bit for
+    bit against the oracle, and decoding to the truth tables."""
+    say("ring bootstrapped gates d=%d n=%d" % (d, n))
+    K = _GateKeys(d, n, 1200 + d)
+    xs, ys = [0, 0, 1, 1], [0, 1, 0, 1]
+    x = _lwe_bits(1210 + d, K.s, xs, O.P // 64)
+    y = _lwe_bits(1220 + d, K.s, ys, O.P // 64)
+    for g, fn in ((4, lambda a, b: a & b), (5, lambda a, b: a ^ b), (6, lambda a, b: a | b),
+                  (8, lambda a, b: 1 - (a & b))):
+        got = K.gate(g, x, y)
+        assert np.array_equal(got, O.gate_bootstrap(g, _host(K.bk), K.ksk, x, y)), g
+        assert [_decode_q4(got[j], K.s) for j in range(4)] == [fn(a, b) for a, b in zip(xs, ys)], g
+
+
+def test_bootstrapped_ripple_adder_d1024():
+    """An 8-bit ripple-carry adder of bootstrapped gates at d = 1024 (depth 17
+    gates on the carry chain, far beyond what an unrefreshed ring product
+    survives), on 16 random operand pairs at once: every sum bit decodes."""
+    d, n, m, w = 1024, 16, 16, 8
+    say("ring bootstrapped ripple adder d=%d n=%d m=%d" % (d, n, m))
+    K = _GateKeys(d, n, 1300)
+    g = np.random.Generator(np.random.PCG64(1301))
+    a = g.integers(0, 1 << w, size=m)
+    b = g.integers(0, 1 << w, size=m)
+    A = [_lwe_bits(1310 + i, K.s, (a >> i) & 1, 2) for i in range(w)]
+    Bv = [_lwe_bits(1330 + i, K.s, (b >> i) & 1, 2) for i in range(w)]
+    carry = None
+    bits = []
+    for i in range(w):
+        if carry is None:
+            bits.append(K.gate(5, A[i], Bv[i]))
+            carry = K.gate(4, A[i], Bv[i])
+        else:
+            t = K.gate(5, A[i], Bv[i])
+            bits.append(K.gate(5, t, carry))
+            carry = K.gate(6, K.gate(4, A[i], Bv[i]), K.gate(4, t, carry))
+    bits.append(carry)
+    for j in range(m):
+        got = sum(_decode_q4(bits[i][j], K.s) << i for i in range(w + 1))
+        assert got == int(a[j] + b[j]), j

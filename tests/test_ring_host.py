@@ -104,3 +104,17 @@ def test_keyswitch_argument_checks():
         with pytest.raises(S.SfftError) as e:
             S.sfft_ring_keyswitch(*args, None)
         assert e.value.code == S.SFFT_EINVAL, args
+
+
+def test_gate_bootstrap_argument_checks():
+    d = 16
+    ws = S.sfft_ring_gate_bootstrap_workspace_bytes(d, 5, 3)
+    assert ws == 3 * 2 * d * 8 + 3 * (d + 1) * 8 + 3 * 5 * 4
+    S.sfft_ring_gate_bootstrap(d, 4, 8, 5, 16, 24, 32, 0, 40, 48, ws, None)     # m = 0
+    for args in ((d, 3, 8, 5, 16, 24, 32, 3, 40, 48, ws), (d, 9, 8, 5, 16, 24, 32, 3, 40, 48, ws),
+                 (5, 4, 8, 5, 16, 24, 32, 3, 40, 48, ws), (d, 4, 8, 5, 16, 24, 0, 3, 40, 48, ws),
+                 (d, 4, 8, 5, 0, 24, 32, 3, 40, 48, ws), (d, 4, 8, 5, 16, 24, 32, 3, 40, 48, ws - 1),
+                 (d, 4, 8, -5, 16, 24, 32, 3, 40, 48, ws)):
+        with pytest.raises(S.SfftError) as e:
+            S.sfft_ring_gate_bootstrap(*args, None)
+        assert e.value.code == S.SFFT_EINVAL, args
