@@ -427,3 +427,33 @@ def test_bootstrapped_ripple_adder_d1024():
     for j in range(m):
         got = sum(_decode_q4(bits[i][j], K.s) << i for i in range(w + 1))
         assert got == int(a[j] + b[j]), j
+
+
+def test_fft_circuit_on_bootstrapped_gates_d1024():
+    """An encrypted FFT with no depth limit: the N=4 complex Q(8,4) circuit
+    evaluated gate by gate on the library's bootstrapped gates at d = 1024
+    (one batched call per level and gate kind); the decrypted outputs equal
+    the Boolean simulation and the fixed-point emulation."""
+    from oracle import fixedpoint as fx
+    from oracle import netlist as N
+    from tests import ring_fft_driver as RF
+    d, n = 1024, 16
+    say("ring bootstrapped FFT N=4 d=%d n=%d" % (d, n))
+    K = _GateKeys(d, n, 1400)
+    cn = N.Compact(N.build_fft_netlist(1, 4, 8, 4, True))
+    sig = WL.uniform_pm1(1401, 4, 8, 4, True)
+    re, im = fx.quantize(np.asarray(sig.re), 8, 4), fx.quantize(np.asarray(sig.im), 8, 4)
+    words = np.stack([re, im], 1).ravel()
+    bits = fx.words_to_bits(words, 8)
+    cts = _lwe_bits(1402, K.s, bits, 2)
+    out, levels, calls = RF.evaluate(cn, cts, n, K.gate)
+    got = [_decode_q4(c, K.s) for c in out]
+    assert got == N.simulate(cn, [int(b) for b in bits], 1)
+    er, ei = fx.fft1d_fixed(re[None], im[None], 8, 4)
+    want = np.stack([er[0], ei[0]], 1).ravel()
+    vals = []
+    for v in range(len(want)):
+        u = sum(got[v * 8 + i] << i for i in range(8))
+        vals.append(u - 256 if u & 128 else u)
+    assert vals == want.tolist()
+    print("[gpu-case] %d levels, %d gate calls" % (levels, calls), flush=True)

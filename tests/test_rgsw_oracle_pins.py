@@ -361,3 +361,21 @@ def test_bootstrapped_gates_compose():
     for j, (a, b, c) in enumerate(trip):
         assert _decode_q4(s_[j], s_lwe) == a ^ b ^ c
         assert _decode_q4(carry[j], s_lwe) == (a & b) | (c & (a ^ b))
+
+
+def test_fft_circuit_on_bootstrapped_gates():
+    """The N=4 complex Q(8,4) FFT circuit evaluated gate by gate on the
+    oracle's bootstrapped gates (d = 16): every output bit equals the Boolean
+    simulation of the same circuit, whatever its depth."""
+    from oracle import netlist as N
+    from tests import ring_fft_driver as RF
+    d, n = 16, 4
+    s_lwe, bk, ksk = _gate_keys(d, n, 500)
+    cn = N.Compact(N.build_fft_netlist(1, 4, 8, 4, True))
+    g = np.random.Generator(np.random.PCG64(501))
+    bits = g.integers(0, 2, size=cn.n_inputs)
+    cts = _lwe_bits(502, s_lwe, bits, 2)
+    out, levels, calls = RF.evaluate(cn, cts, n, lambda gt, x, y: R.gate_bootstrap(gt, bk, ksk, x, y))
+    want = N.simulate(cn, [int(b) for b in bits], 1)
+    assert levels > 10
+    assert [_decode_q4(c, s_lwe) for c in out] == want
