@@ -446,7 +446,10 @@ def test_fft_circuit_on_bootstrapped_gates_d1024():
     words = np.stack([re, im], 1).ravel()
     bits = fx.words_to_bits(words, 8)
     cts = _lwe_bits(1402, K.s, bits, 2)
+    import time
+    t0 = time.perf_counter()
     out, levels, calls = RF.evaluate(cn, cts, n, K.gate)
+    t_eval = time.perf_counter() - t0
     got = [_decode_q4(c, K.s) for c in out]
     assert got == N.simulate(cn, [int(b) for b in bits], 1)
     er, ei = fx.fft1d_fixed(re[None], im[None], 8, 4)
@@ -456,4 +459,5 @@ def test_fft_circuit_on_bootstrapped_gates_d1024():
         u = sum(got[v * 8 + i] << i for i in range(8))
         vals.append(u - 256 if u & 128 else u)
     assert vals == want.tolist()
-    print("[gpu-case] %d levels, %d gate calls" % (levels, calls), flush=True)
+    print("[gpu-case] %d levels, %d gate calls, %d gates, %.3f s (host copies included)" % (
+        levels, calls, sum(1 for t in cn.t if t in N.BINARY), t_eval), flush=True)
