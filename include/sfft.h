@@ -373,6 +373,33 @@ int sfft_ring_keyswitch(int32_t d, int64_t n, const uint64_t* ksk_dev, const uin
  * the gate's bit in the same encoding under the same secret.  ws: at least
  * sfft_ring_gate_bootstrap_workspace_bytes.  NOT needs no bootstrap:
  * (0, .., 0, 2*floor(p/8)) - x. */
+/* Encrypted FFT plans on bootstrapped gates: the shape's canonical netlist
+ * (as for sfft_plan_create; shared nodes merged) evaluated gate by gate on
+ * LWE ciphertexts mod p of n+1 words, every binary gate a
+ * sfft_ring_gate_bootstrap gate, so the circuit's depth puts no bound on the
+ * parameters.  Binary nodes are levelised (NOT is free and takes its
+ * operand's level); one batched bootstrapped call per level and gate kind.
+ * Input ciphertext order is that of sfft_execute (value, component, bit LSB
+ * first), bits encoded as mu * 2 * floor(p/8) under the LWE secret; outputs
+ * likewise, always complex.  The workspace holds a slot of n+1 words per node
+ * and one call's scratch. */
+typedef struct sfft_ring_plan sfft_ring_plan;
+typedef struct {
+    int64_t nodes, gates;      /* netlist nodes; binary gates (= bootstraps per FFT) */
+    int32_t levels, calls;     /* gate levels; batched gate calls per FFT */
+    int64_t max_batch;         /* the largest call's gates */
+    int64_t n_inputs, n_outputs;
+    int64_t ws_bytes;
+} sfft_ring_plan_info;
+/* Host only: the plan's figures without building it on a device. */
+int sfft_ring_plan_analyze(const sfft_shape* shape, int32_t d, int64_t n, sfft_ring_plan_info* info);
+int sfft_ring_plan_create(const sfft_shape* shape, int32_t d, int64_t n, sfft_ring_plan** out);
+/* bkt_dev: prepared key of the n LWE secret bits (sfft_ring_bk_prepare);
+ * ksk_dev: key-switching key (sfft_ring_keyswitch).  Asynchronous on
+ * hip_stream. */
+int sfft_ring_fft_execute(const sfft_ring_plan* plan, const uint64_t* bkt_dev, const uint64_t* ksk_dev,
+                          const uint64_t* in_dev, uint64_t* out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream);
+void sfft_ring_plan_destroy(sfft_ring_plan* plan);
 int sfft_ring_gate_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes);
 int sfft_ring_gate_bootstrap(int32_t d, int32_t gate, const uint64_t* bkt_dev, int64_t n, const uint64_t* ksk_dev,
                              const uint64_t* x_dev, const uint64_t* y_dev, int64_t m, uint64_t* out_dev, void* ws_dev,

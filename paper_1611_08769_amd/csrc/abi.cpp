@@ -165,6 +165,10 @@ int decrypt_row(const uint32_t* row, const uint32_t* sk, int n1, int kw, int k)
 
 }  // namespace
 
+// The shape checks and conversion, for the ring executor.
+bool sfft_shape_check(const sfft_shape* s, std::string* why) { return shape_ok(s, why); }
+Shape sfft_shape_of(const sfft_shape* s) { return to_shape(s); }
+
 struct sfft_plan : PlanCore {};
 
 const PlanCore* plan_core_of(const sfft_plan* plan) { return plan; }

@@ -38,14 +38,18 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
+#include "netlist.hpp"
 #include "ring_math.hpp"
 #include "sfft.h"
 
 int sfft_fail(int code, const std::string& msg);
 int sfft_hip_fail(hipError_t e, const char* where);
+bool sfft_shape_check(const sfft_shape* s, std::string* why);
+sfft::Shape sfft_shape_of(const sfft_shape* s);
 
 using namespace sfft::ring;
 
@@ -297,13 +301,15 @@ __device__ __forceinline__ uint64_t small_mul(int cx, uint64_t v)
 // X^(D-1)).  y may be null (cy = 0).
 template <int LOGD>
 __global__ __launch_bounds__(kT) void k_ring_br_init(const uint64_t* __restrict__ x, const uint64_t* __restrict__ y,
+                                                     const int32_t* __restrict__ xi, const int32_t* __restrict__ yi,
                                                      int cx, int cy, uint64_t cb, int64_t n, int32_t* __restrict__ rot,
                                                      uint64_t* __restrict__ acc, uint64_t delta)
 {
     constexpr int D = 1 << LOGD;
     const int64_t j = blockIdx.x;
-    const uint64_t* xc = x + j * (n + 1);
-    const uint64_t* yc = y ? y + j * (n + 1) : nullptr;
+    // operand j is row j, or row xi[j] / yi[j] of a slot array
+    const uint64_t* xc = x + (xi ? (int64_t)xi[j] : j) * (n + 1);
+    const uint64_t* yc = y ? y + (yi ? (int64_t)yi[j] : j) * (n + 1) : nullptr;
     auto coord = [&](int64_t i) {
         const uint64_t v = small_mul(cx, xc[i]);
         return yc ? addp(v, small_mul(cy, yc[i])) : v;
@@ -341,7 +347,8 @@ __global__ __launch_bounds__(kT) void k_ring_extract(const uint64_t* __restrict_
 // digit by a residue (below 2^80) is kept unreduced and reduced once.
 constexpr int kKsDigits = 16;  // base-16 digits of a residue below 2^64
 __global__ __launch_bounds__(kT) void k_ring_keyswitch(const uint64_t* __restrict__ ksk, const uint64_t* __restrict__ in,
-                                                       uint64_t* __restrict__ out, int d, int64_t n)
+                                                       uint64_t* __restrict__ out, const int32_t* __restrict__ oi, int d,
+                                                       int64_t n)
 {
     extern __shared__ uint64_t lds[];
     const int64_t j = blockIdx.x;
@@ -356,8 +363,27 @@ __global__ __launch_bounds__(kT) void k_ring_keyswitch(const uint64_t* __restric
 #pragma unroll
             for (int k = 0; k < kKsDigits; ++k) mac128((at >> (4 * k)) & 15, kp[k * (n + 1)], &lo, &hi);
         }
-        out[j * (n + 1) + q] = subp(q == n ? lds[d] : 0, red126(lo, hi));
+        out[(oi ? (int64_t)oi[j] : j) * (n + 1) + q] = subp(q == n ? lds[d] : 0, red126(lo, hi));
     }
+}
+
+// Row moves of the FFT executor (rows of w words): dst[di ? di[j] : j] =
+// src[si ? si[j] : j], and NOT rows dst[di[j]] = (0, .., 0, 2 floor(p/8)) -
+// src[si[j]]; slots 0 and 1 set to the trivial encryptions of 0 and 1.
+__global__ __launch_bounds__(kT) void k_ring_rows(const uint64_t* __restrict__ src, const int32_t* __restrict__ si,
+                                                  uint64_t* __restrict__ dst, const int32_t* __restrict__ di,
+                                                  int64_t count, int64_t w, int negate)
+{
+    const int64_t total = count * w, stride = (int64_t)gridDim.x * kT;
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < total; e += stride) {
+        const int64_t j = e / w, q = e % w;
+        const uint64_t v = src[(si ? (int64_t)si[j] : j) * w + q];
+        dst[(di ? (int64_t)di[j] : j) * w + q] = negate ? subp(q == w - 1 ? 2 * (kP / 8) : 0, v) : v;
+    }
+}
+__global__ __launch_bounds__(kT) void k_ring_consts(uint64_t* __restrict__ slots, int64_t w)
+{
+    for (int64_t q = threadIdx.x; q < 2 * w; q += kT) slots[q] = q == 2 * w - 1 ? 2 * (kP / 8) : 0;
 }
 
 // NOT (3): G - X;  XADD (7): X + Y.  Elementwise over n ciphertexts.
@@ -542,14 +568,16 @@ struct Combine {
     const uint64_t* y;
     int cx, cy;
     uint64_t cb, delta;
+    const int32_t* xi = nullptr;  // row indices into x / y (null: row j)
+    const int32_t* yi = nullptr;
 };
 
 template <int LOGD>
 hipError_t launch_bootstrap(const uint64_t* bkt, int64_t n, const Combine& cm, int64_t m, uint64_t* out, uint64_t* acc,
                             int32_t* rot, TwView tv, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ring_br_init<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, cm.x, cm.y, cm.cx, cm.cy, cm.cb, n, rot,
-                       acc, cm.delta);
+    hipLaunchKernelGGL(k_ring_br_init<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, cm.x, cm.y, cm.xi, cm.yi, cm.cx, cm.cy,
+                       cm.cb, n, rot, acc, cm.delta);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n > 0 && (e = launch_blind_rotate<LOGD>(bkt, n, rot, acc, m, tv, s)) != hipSuccess) return e;
@@ -589,9 +617,213 @@ int64_t ct_words_of(int d) { return (int64_t)kRows * 2 * d; }
 // Blocks of one launch: grids are split below 2^31 workgroups.
 constexpr int64_t kMaxGrid = 1 << 30;
 
+// ---- FFT plans on bootstrapped gates ---------------------------------------
+// Every node of the (shared) FFT netlist gets a slot of n+1 words: slot v
+// holds node v's LWE ciphertext.  Binary nodes are levelised (a NOT takes
+// its operand's level) and each level's nodes of one kind form one batched
+// bootstrapped gate: operands gathered from the slots by index, outputs
+// key-switched straight into theirs.  NOTs run after their level's gates, in
+// rank order (a NOT of a NOT of the same level one rank later).
+struct RingStep {
+    bool is_not;
+    int gate;          // 4 AND, 5 XOR (and XADD), 6 OR, 8 NAND
+    int count;
+    int64_t x, y, o;   // offsets of the index arrays (NOT: x = sources, o = destinations)
+};
+struct RingPlanHost {
+    int d = 0, logd = 0;
+    int64_t n = 0, nodes = 0, gates = 0, n_in = 0, n_out = 0, max_batch = 0;
+    int32_t levels = 0, calls = 0;
+    int64_t in_off = 0, out_off = 0;
+    std::vector<int32_t> idx;
+    std::vector<RingStep> steps;
+    int64_t ws_bytes() const
+    {
+        const int64_t slots = nodes * (n + 1) * 8, scratch = max_batch * (2 * d * 8 + (d + 1) * 8 + n * 4);
+        return ((slots + 255) & ~(int64_t)255) + scratch;
+    }
+};
+
+int ring_plan_build(const sfft_shape* shape, int32_t d, int64_t n, RingPlanHost* pl)
+{
+    std::string why;
+    if (!sfft_shape_check(shape, &why)) return sfft_fail(SFFT_EINVAL, why);
+    int logd, rc;
+    if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
+    if (n < 1) return sfft_fail(SFFT_EINVAL, "n must be >= 1");
+    const sfft::Compact c = sfft::share(sfft::compact(sfft::build_fft_netlist(sfft_shape_of(shape))));
+    const int64_t N = (int64_t)c.size();
+    std::vector<int32_t> depth(N, 0), rank(N, 0);
+    int32_t L = 0;
+    for (int64_t v = 0; v < N; ++v) {
+        const int8_t t = c.t[v];
+        if (t == sfft::T_NOT) {
+            depth[v] = depth[c.a[v]];
+            rank[v] = c.t[c.a[v]] == sfft::T_NOT && depth[c.a[v]] == depth[v] ? rank[c.a[v]] + 1 : 0;
+        } else if (t >= sfft::T_AND) {
+            depth[v] = std::max(depth[c.a[v]], depth[c.b[v]]) + 1;
+        }
+        L = std::max(L, depth[v]);
+    }
+    pl->d = d, pl->logd = logd, pl->n = n, pl->nodes = N, pl->levels = L;
+    pl->n_in = c.n_inputs, pl->n_out = (int64_t)c.outputs.size();
+    auto push = [&](const std::vector<int32_t>& v) {
+        const int64_t off = (int64_t)pl->idx.size();
+        pl->idx.insert(pl->idx.end(), v.begin(), v.end());
+        return off;
+    };
+    std::vector<int32_t> ins(c.n_inputs, 0);
+    for (int64_t v = 0; v < N; ++v)
+        if (c.t[v] == sfft::T_IN) ins[c.a[v]] = (int32_t)v;
+    pl->in_off = push(ins);
+    pl->out_off = push(std::vector<int32_t>(c.outputs.begin(), c.outputs.end()));
+    const int kinds[4][2] = {{sfft::T_AND, 4}, {sfft::T_XOR, 5}, {sfft::T_OR, 6}, {sfft::T_NAND, 8}};
+    for (int32_t lev = 0; lev <= L; ++lev) {
+        if (lev > 0)
+            for (const auto& k : kinds) {
+                std::vector<int32_t> xs, ys, os;
+                for (int64_t v = 0; v < N; ++v) {
+                    const int8_t t = c.t[v];
+                    const bool match = t == k[0] || (k[0] == sfft::T_XOR && t == sfft::T_XADD);
+                    if (depth[v] == lev && match) {
+                        xs.push_back(c.a[v]);
+                        ys.push_back(c.b[v]);
+                        os.push_back((int32_t)v);
+                    }
+                }
+                if (xs.empty()) continue;
+                RingStep st{false, k[1], (int)xs.size(), push(xs), push(ys), push(os)};
+                pl->steps.push_back(st);
+                pl->gates += (int64_t)xs.size();
+                pl->max_batch = std::max(pl->max_batch, (int64_t)xs.size());
+                ++pl->calls;
+            }
+        for (int r = 0;; ++r) {
+            std::vector<int32_t> src, dst;
+            for (int64_t v = 0; v < N; ++v)
+                if (c.t[v] == sfft::T_NOT && depth[v] == lev && rank[v] == r) {
+                    src.push_back(c.a[v]);
+                    dst.push_back((int32_t)v);
+                }
+            if (src.empty()) break;
+            pl->steps.push_back(RingStep{true, 3, (int)src.size(), push(src), 0, push(dst)});
+        }
+    }
+    return SFFT_OK;
+}
+
 }  // namespace
 
+struct sfft_ring_plan {
+    RingPlanHost h;
+    int32_t* dev = nullptr;  // the index arrays
+};
+
 extern "C" {
+
+int sfft_ring_plan_analyze(const sfft_shape* shape, int32_t d, int64_t n, sfft_ring_plan_info* info)
+{
+    if (!info) return sfft_fail(SFFT_EINVAL, "null info");
+    RingPlanHost h;
+    int rc;
+    try {
+        if ((rc = ring_plan_build(shape, d, n, &h)) != SFFT_OK) return rc;
+    } catch (const std::bad_alloc&) {
+        return sfft_fail(SFFT_ENOMEM, "host allocation failed");
+    }
+    info->nodes = h.nodes, info->gates = h.gates, info->levels = h.levels, info->calls = h.calls;
+    info->max_batch = h.max_batch, info->n_inputs = h.n_in, info->n_outputs = h.n_out, info->ws_bytes = h.ws_bytes();
+    return SFFT_OK;
+}
+
+int sfft_ring_plan_create(const sfft_shape* shape, int32_t d, int64_t n, sfft_ring_plan** out)
+{
+    if (!out) return sfft_fail(SFFT_EINVAL, "null output");
+    *out = nullptr;
+    sfft_ring_plan* pl = nullptr;
+    try {
+        pl = new sfft_ring_plan();
+        int rc = ring_plan_build(shape, d, n, &pl->h);
+        if (rc != SFFT_OK) {
+            delete pl;
+            return rc;
+        }
+    } catch (const std::bad_alloc&) {
+        delete pl;
+        return sfft_fail(SFFT_ENOMEM, "host allocation failed");
+    }
+    const size_t bytes = pl->h.idx.size() * sizeof(int32_t);
+    hipError_t e = hipMalloc(&pl->dev, bytes ? bytes : 4);
+    if (e == hipSuccess && bytes) e = hipMemcpy(pl->dev, pl->h.idx.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (pl->dev) (void)hipFree(pl->dev);
+        delete pl;
+        return sfft_hip_fail(e, "sfft_ring_plan_create");
+    }
+    *out = pl;
+    return SFFT_OK;
+}
+
+void sfft_ring_plan_destroy(sfft_ring_plan* plan)
+{
+    if (!plan) return;
+    if (plan->dev) (void)hipFree(plan->dev);
+    delete plan;
+}
+
+int sfft_ring_fft_execute(const sfft_ring_plan* plan, const uint64_t* bkt_dev, const uint64_t* ksk_dev,
+                          const uint64_t* in_dev, uint64_t* out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream)
+{
+    if (!plan || !bkt_dev || !ksk_dev || !in_dev || !out_dev || !ws_dev) return sfft_fail(SFFT_EINVAL, "null argument");
+    const RingPlanHost& h = plan->h;
+    if (ws_bytes < h.ws_bytes()) return sfft_fail(SFFT_EINVAL, "workspace too small");
+    TwView tv;
+    int rc;
+    if ((rc = tables(h.d, h.logd, &tv)) != SFFT_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t w = h.n + 1;
+    uint64_t* slots = (uint64_t*)ws_dev;
+    uint8_t* scratch = (uint8_t*)ws_dev + ((h.nodes * w * 8 + 255) & ~(int64_t)255);
+    uint64_t* acc = (uint64_t*)scratch;
+    uint64_t* mid = acc + h.max_batch * 2 * h.d;
+    int32_t* rot = (int32_t*)(mid + h.max_batch * (h.d + 1));
+    const int32_t* I = plan->dev;
+    auto rows = [&](const uint64_t* src, const int32_t* si, uint64_t* dst, const int32_t* di, int64_t count, int neg) {
+        const int64_t blocks = std::min<int64_t>((count * w + kT - 1) / kT, 1 << 16);
+        hipLaunchKernelGGL(k_ring_rows, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kT), 0, s, src, si, dst, di,
+                           count, w, neg);
+        return hipGetLastError();
+    };
+    hipLaunchKernelGGL(k_ring_consts, dim3(1), dim3(kT), 0, s, slots, w);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && h.n_in > 0) e = rows(in_dev, nullptr, slots, I + h.in_off, h.n_in, 0);
+    const uint64_t q8 = kP / 8;
+    for (const RingStep& st : h.steps) {
+        if (e != hipSuccess) break;
+        if (st.is_not) {
+            e = rows(slots, I + st.x, slots, I + st.o, st.count, 1);
+            continue;
+        }
+        int cx, cy, k;
+        switch (st.gate) {
+        case 4: cx = 1, cy = 1, k = -1; break;
+        case 6: cx = 1, cy = 1, k = 1; break;
+        case 8: cx = -1, cy = -1, k = 5; break;
+        default: cx = 2, cy = 2, k = 0; break;
+        }
+        Combine cm{slots, slots, cx, cy, k >= 0 ? (uint64_t)k * q8 : kP - (uint64_t)(-k) * q8, q8, I + st.x, I + st.y};
+#define SFFT_PBS(L) { e = launch_bootstrap<L>(bkt_dev, h.n, cm, st.count, mid, acc, rot, tv, s); break; }
+        SFFT_RING_DISPATCH(h.logd, SFFT_PBS)
+#undef SFFT_PBS
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_ring_keyswitch, dim3((unsigned)st.count), dim3(kT), (size_t)(h.d + 1) * 8, s, ksk_dev, mid,
+                           slots, I + st.o, h.d, h.n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && h.n_out > 0) e = rows(slots, I + h.out_off, out_dev, nullptr, h.n_out, 0);
+    return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "sfft_ring_fft_execute");
+}
+
 
 int64_t sfft_ring_ct_words(int32_t d)
 {
@@ -741,7 +973,7 @@ int sfft_ring_keyswitch(int32_t d, int64_t n, const uint64_t* ksk_dev, const uin
     if (m > kMaxGrid) return sfft_fail(SFFT_EINVAL, "too many ciphertexts for one call");
     hipStream_t s = (hipStream_t)hip_stream;
     hipLaunchKernelGGL(k_ring_keyswitch, dim3((unsigned)m), dim3(kT), (size_t)(d + 1) * 8, s, ksk_dev, in_dev, out_dev,
-                       (int)d, n);
+                       (const int32_t*)nullptr, (int)d, n);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFFT_OK : sfft_hip_fail(e, "k_ring_keyswitch");
 }

@@ -53,6 +53,12 @@ class sfft_server_stats(ctypes.Structure):
                                               "peak_ws_bytes")] + [("clock_s", ctypes.c_double)]
 
 
+class sfft_ring_plan_info(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_int64), ("gates", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("calls", ctypes.c_int32), ("max_batch", ctypes.c_int64), ("n_inputs", ctypes.c_int64),
+                ("n_outputs", ctypes.c_int64), ("ws_bytes", ctypes.c_int64)]
+
+
 class SfftError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("sfft error %d: %s" % (code, msg))
@@ -121,6 +127,10 @@ _SIGS = {
     "sfft_ring_bootstrap": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp,
                                            ctypes.c_int64, _vp]),
     "sfft_ring_keyswitch": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "sfft_ring_plan_analyze": (ctypes.c_int, [_P(sfft_shape), ctypes.c_int32, ctypes.c_int64, _P(sfft_ring_plan_info)]),
+    "sfft_ring_plan_create": (ctypes.c_int, [_P(sfft_shape), ctypes.c_int32, ctypes.c_int64, _P(_vp)]),
+    "sfft_ring_fft_execute": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "sfft_ring_plan_destroy": (None, [_vp]),
     "sfft_ring_gate_bootstrap_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                                                 _P(ctypes.c_int64)]),
     "sfft_ring_gate_bootstrap": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp,
@@ -365,3 +375,23 @@ def sfft_ring_gate_bootstrap_workspace_bytes(d: int, n: int, m: int) -> int:
 def sfft_ring_gate_bootstrap(d, gate, bkt_ptr, n, ksk_ptr, x_ptr, y_ptr, m, out_ptr, ws_ptr, ws_bytes, stream) -> None:
     _check(_lib.sfft_ring_gate_bootstrap(d, gate, bkt_ptr, n, ksk_ptr, x_ptr, y_ptr, m, out_ptr, ws_ptr, ws_bytes,
                                          stream))
+
+
+def sfft_ring_plan_analyze(shp: sfft_shape, d: int, n: int) -> sfft_ring_plan_info:
+    info = sfft_ring_plan_info()
+    _check(_lib.sfft_ring_plan_analyze(ctypes.byref(shp), d, n, ctypes.byref(info)))
+    return info
+
+
+def sfft_ring_plan_create(shp: sfft_shape, d: int, n: int) -> int:
+    h = _vp()
+    _check(_lib.sfft_ring_plan_create(ctypes.byref(shp), d, n, ctypes.byref(h)))
+    return h.value
+
+
+def sfft_ring_fft_execute(plan, bkt_ptr, ksk_ptr, in_ptr, out_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_ring_fft_execute(plan, bkt_ptr, ksk_ptr, in_ptr, out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_ring_plan_destroy(plan) -> None:
+    _lib.sfft_ring_plan_destroy(plan)

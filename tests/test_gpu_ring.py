@@ -461,3 +461,41 @@ def test_fft_circuit_on_bootstrapped_gates_d1024():
     assert vals == want.tolist()
     print("[gpu-case] %d levels, %d gate calls, %d gates, %.3f s (host copies included)" % (
         levels, calls, sum(1 for t in cn.t if t in N.BINARY), t_eval), flush=True)
+
+
+@pytest.mark.parametrize("dims,L,F,f,cplx", [(1, 4, 8, 4, True), (1, 8, 8, 4, False)])
+def test_ring_fft_plan_matches_emulation(dims, L, F, f, cplx):
+    """The native executor of FFT plans on bootstrapped gates
+    (sfft_ring_fft_execute) at d = 1024 with a 16-bit LWE key: decrypted
+    outputs equal the integer fixed-point emulation."""
+    from oracle import fixedpoint as fx
+    d, n = 1024, 16
+    say("ring FFT plan N=%d F=%d cplx=%d d=%d n=%d" % (L, F, cplx, d, n))
+    K = _GateKeys(d, n, 1500 + L)
+    shp = S.shape(dims, L, F, f, cplx)
+    info = S.sfft_ring_plan_analyze(shp, d, n)
+    plan = S.sfft_ring_plan_create(shp, d, n)
+    try:
+        sig = WL.uniform_pm1(1501 + L, L, F, f, cplx)
+        re = fx.quantize(np.asarray(sig.re), F, f)
+        im = fx.quantize(np.asarray(sig.im), F, f) if cplx else np.zeros(L, np.int64)
+        words = np.stack([re, im], 1).ravel() if cplx else re
+        bits = fx.words_to_bits(words, F)
+        assert len(bits) == info.n_inputs
+        cts = _dev(_lwe_bits(1502 + L, K.s, bits, 2))
+        out = torch.zeros((info.n_outputs, n + 1), dtype=torch.int64, device="cuda")
+        ws = torch.empty(info.ws_bytes // 8 + 1, dtype=torch.int64, device="cuda")
+        S.sfft_ring_fft_execute(plan, K.bkt.data_ptr(), K.ksk_d.data_ptr(), cts.data_ptr(), out.data_ptr(),
+                                ws.data_ptr(), info.ws_bytes, _stream())
+        torch.cuda.synchronize()
+        got = [_decode_q4(c, K.s) for c in _host(out)]
+        er, ei = fx.fft1d_fixed(re[None], im[None], F, f)
+        want = np.stack([er[0], ei[0]], 1).ravel()
+        vals = []
+        for v in range(len(want)):
+            u = sum(got[v * F + i] << i for i in range(F))
+            vals.append(u - (1 << F) if u >> (F - 1) & 1 else u)
+        assert vals == want.tolist()
+        print("[gpu-case] %d gates, %d levels, %d calls" % (info.gates, info.levels, info.calls), flush=True)
+    finally:
+        S.sfft_ring_plan_destroy(plan)

@@ -118,3 +118,27 @@ def test_gate_bootstrap_argument_checks():
         with pytest.raises(S.SfftError) as e:
             S.sfft_ring_gate_bootstrap(*args, None)
         assert e.value.code == S.SFFT_EINVAL, args
+
+
+def test_ring_fft_plan_figures():
+    """The executor's levelisation of the N=4 complex Q(8,4) circuit: as many
+    levels as the oracle netlist's depth (NOT free), one call per level and
+    gate kind present, at most as many gates as the unshared circuit has."""
+    from oracle import netlist as N
+    info = S.sfft_ring_plan_analyze(S.shape(1, 4, 8, 4, True), 1024, 16)
+    cn = N.Compact(N.build_fft_netlist(1, 4, 8, 4, True))
+    depth = [0] * len(cn.t)
+    for v, t in enumerate(cn.t):
+        if t == N.NOT:
+            depth[v] = depth[cn.a[v]]
+        elif t in N.BINARY:
+            depth[v] = max(depth[cn.a[v]], depth[cn.b[v]]) + 1
+    assert info.levels == max(depth)
+    assert 0 < info.gates <= sum(1 for t in cn.t if t in N.BINARY)
+    assert info.levels <= info.calls <= 4 * info.levels
+    assert info.n_inputs == 64 and info.n_outputs == 64
+    assert info.ws_bytes >= info.nodes * 17 * 8
+    with pytest.raises(S.SfftError):
+        S.sfft_ring_plan_analyze(S.shape(1, 4, 8, 4, True), 1000, 16)
+    with pytest.raises(S.SfftError):
+        S.sfft_ring_plan_analyze(S.shape(1, 4, 8, 4, True), 1024, 0)
