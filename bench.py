@@ -6,6 +6,7 @@
     python bench.py --workload accuracy [--signals 4]
     python bench.py --workload ring_and_d1024 [--requests 128]   # ring-GSW gates
     python bench.py --workload ring_br_d1024 [--requests 1024]   # ring-GSW blind rotation
+    python bench.py --workload ring_fft_<name>                  # a named FFT on bootstrapped gates
 
 A step is one encrypted FFT of one request (every product level of the
 compiled circuit, inputs already encrypted and resident in HBM).  Prints one
@@ -702,6 +703,95 @@ def run_ring_br(args):
     }
 
 
+def run_ring_fft(args):
+    """An encrypted FFT of a named workload on bootstrapped ring-LWE gates
+    (sfft_ring_fft_execute): d = 1024, a 16-bit LWE key, every binary gate a
+    refresh.  One step is one FFT, inputs encrypted and resident in HBM."""
+    import torch
+    from paper_1611_08769_amd import api
+    from paper_1611_08769_amd import sfft as S
+    from paper_1611_08769_amd import workloads as WL
+
+    name = args.workload[len("ring_fft_"):]
+    sig, _, seed = WL.workload(name)
+    d, n = 1024, 16
+    P = S.SFFT_RING_P
+    q8 = P // 8
+    stream = torch.cuda.current_stream().cuda_stream
+    shp = S.shape(sig.dims, sig.length, sig.F, sig.f, sig.is_complex)
+    info = S.sfft_ring_plan_analyze(shp, d, n)
+    rows = 2 * S.SFFT_RING_ELL
+    g = np.random.Generator(np.random.PCG64(seed))
+    s_lwe = g.integers(0, 2, size=n)
+    dk = WL.ring_draws(seed + 100, n, d, rows, P, bits=s_lwe.astype(np.uint8))
+    dev = [torch.from_numpy(np.ascontiguousarray(x).view(np.int64) if x.dtype == np.uint64 else x).cuda()
+           for x in (dk.s, dk.a, dk.e, dk.bits)]
+    bk = torch.empty((n, S.sfft_ring_ct_words(d)), dtype=torch.int64, device="cuda")
+    S.sfft_ring_encrypt(d, dev[0].data_ptr(), dev[1].data_ptr(), dev[2].data_ptr(), dev[3].data_ptr(), n,
+                        bk.data_ptr(), stream)
+    bkt = torch.empty_like(bk)
+    S.sfft_ring_bk_prepare(d, bk.data_ptr(), n, bkt.data_ptr(), stream)
+    # key-switching key: entry [t][k] encrypts s_ring[t] * 16^k under s_lwe
+    ksk = np.zeros((d, 16, n + 1), np.uint64)
+    ksk[:, :, :n] = g.integers(0, P, size=(d, 16, n), dtype=np.uint64)
+    on = np.nonzero(s_lwe)[0]
+    ke = g.integers(-2, 3, size=(d, 16))
+    for t in range(d):
+        for k in range(16):
+            ksk[t, k, n] = (sum(int(ksk[t, k, i]) for i in on) + int(dk.s[t]) * 16 ** k + int(ke[t, k])) % P
+    ksk_d = torch.from_numpy(ksk.view(np.int64)).cuda()
+    # inputs: the signal's bits (the library's own quantisation and order),
+    # encrypted as mu * 2 * floor(p/8) under s_lwe
+    words = api.signal_words(sig)
+    bits = [(int(w) >> i) & 1 for w in words for i in range(sig.F)]
+    lwe = np.zeros((len(bits), n + 1), np.uint64)
+    lwe[:, :n] = g.integers(0, P, size=(len(bits), n), dtype=np.uint64)
+    for j, mu in enumerate(bits):
+        lwe[j, n] = (sum(int(lwe[j, i]) for i in on) + mu * 2 * q8 + int(g.integers(-2, 3))) % P
+    in_d = torch.from_numpy(lwe.view(np.int64)).cuda()
+    out = torch.empty((info.n_outputs, n + 1), dtype=torch.int64, device="cuda")
+    ws = torch.empty(info.ws_bytes // 8 + 1, dtype=torch.int64, device="cuda")
+    plan = S.sfft_ring_plan_create(shp, d, n)
+    try:
+        def step():
+            S.sfft_ring_fft_execute(plan, bkt.data_ptr(), ksk_d.data_ptr(), in_d.data_ptr(), out.data_ptr(),
+                                    ws.data_ptr(), info.ws_bytes, stream)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a_.record()
+        for _ in range(args.steps):
+            step()
+        b_.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = a_.elapsed_time(b_) / 1e3 / args.steps
+    finally:
+        S.sfft_ring_plan_destroy(plan)
+    return {
+        "metric": "encrypted gates/s on bootstrapped ring-LWE gates (1 GPU)",
+        "value": info.gates / per,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "d": d, "lwe_key_bits": n, "ell": S.SFFT_RING_ELL,
+                   "p": "2^62-2^16+1", "gates": info.gates, "levels": info.levels, "calls": info.calls,
+                   "max_batch": info.max_batch},
+        "s_per_fft": per,
+        "fft_points_per_s": sig.points / per,
+    }
+
+
 def run_ring(args):
     """Ring-GSW AND gates at d = 1024: one step is one sfft_ring_gate call
     over n ciphertext pairs (the right operands' forward transforms and the
@@ -864,6 +954,9 @@ def main():
         return
     if args.workload.startswith("ring_and_d"):
         print(json.dumps(run_ring(args)), flush=True)
+        return
+    if args.workload.startswith("ring_fft_"):
+        print(json.dumps(run_ring_fft(args)), flush=True)
         return
     if args.workload.startswith("ring_br_d"):
         print(json.dumps(run_ring_br(args)), flush=True)

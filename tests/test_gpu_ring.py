@@ -463,11 +463,12 @@ def test_fft_circuit_on_bootstrapped_gates_d1024():
         levels, calls, sum(1 for t in cn.t if t in N.BINARY), t_eval), flush=True)
 
 
-@pytest.mark.parametrize("dims,L,F,f,cplx", [(1, 4, 8, 4, True), (1, 8, 8, 4, False)])
+@pytest.mark.parametrize("dims,L,F,f,cplx", [(1, 4, 8, 4, True), (1, 8, 8, 4, False), (1, 64, 16, 8, True)])
 def test_ring_fft_plan_matches_emulation(dims, L, F, f, cplx):
     """The native executor of FFT plans on bootstrapped gates
     (sfft_ring_fft_execute) at d = 1024 with a 16-bit LWE key: decrypted
-    outputs equal the integer fixed-point emulation."""
+    outputs equal the integer fixed-point emulation -- up to the N=64 complex
+    Q(16,8) circuit (289k bootstrapped gates, 157 levels)."""
     from oracle import fixedpoint as fx
     d, n = 1024, 16
     say("ring FFT plan N=%d F=%d cplx=%d d=%d n=%d" % (L, F, cplx, d, n))
