@@ -299,14 +299,30 @@ __device__ __forceinline__ uint64_t small_mul(int cx, uint64_t v)
 // (+ cb on b) with c = (a_0..a_{n-1}, b), the rotations -a~_i mod 2D and
 // the accumulator (X^(b~ + D/2) * TV, 0), TV = delta * (1 + X + ... +
 // X^(D-1)).  y may be null (cy = 0).
+// The linear combination of a bootstrapped gate (bits encoded as mu * 2 *
+// floor(p/8)): c = cx*x + cy*y + (0, .., 0, k*floor(p/8)).
+__host__ __device__ __forceinline__ void gate_combination(int gate, int* cx, int* cy, uint64_t* cb)
+{
+    int k;
+    switch (gate) {
+    case 4: *cx = 1, *cy = 1, k = -1; break;   // AND
+    case 6: *cx = 1, *cy = 1, k = 1; break;    // OR
+    case 8: *cx = -1, *cy = -1, k = 5; break;  // NAND
+    default: *cx = 2, *cy = 2, k = 0; break;   // XOR (and XADD)
+    }
+    *cb = k >= 0 ? (uint64_t)k * (kP / 8) : kP - (uint64_t)(-k) * (kP / 8);
+}
+
 template <int LOGD>
 __global__ __launch_bounds__(kT) void k_ring_br_init(const uint64_t* __restrict__ x, const uint64_t* __restrict__ y,
                                                      const int32_t* __restrict__ xi, const int32_t* __restrict__ yi,
-                                                     int cx, int cy, uint64_t cb, int64_t n, int32_t* __restrict__ rot,
-                                                     uint64_t* __restrict__ acc, uint64_t delta)
+                                                     const int32_t* __restrict__ gk, int cx, int cy, uint64_t cb,
+                                                     int64_t n, int32_t* __restrict__ rot, uint64_t* __restrict__ acc,
+                                                     uint64_t delta)
 {
     constexpr int D = 1 << LOGD;
     const int64_t j = blockIdx.x;
+    if (gk) gate_combination(gk[j], &cx, &cy, &cb);   // per-row gate (mixed-gate calls)
     // operand j is row j, or row xi[j] / yi[j] of a slot array
     const uint64_t* xc = x + (xi ? (int64_t)xi[j] : j) * (n + 1);
     const uint64_t* yc = y ? y + (yi ? (int64_t)yi[j] : j) * (n + 1) : nullptr;
@@ -570,14 +586,15 @@ struct Combine {
     uint64_t cb, delta;
     const int32_t* xi = nullptr;  // row indices into x / y (null: row j)
     const int32_t* yi = nullptr;
+    const int32_t* gk = nullptr;  // per-row gate codes (null: cx, cy, cb for every row)
 };
 
 template <int LOGD>
 hipError_t launch_bootstrap(const uint64_t* bkt, int64_t n, const Combine& cm, int64_t m, uint64_t* out, uint64_t* acc,
                             int32_t* rot, TwView tv, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ring_br_init<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, cm.x, cm.y, cm.xi, cm.yi, cm.cx, cm.cy,
-                       cm.cb, n, rot, acc, cm.delta);
+    hipLaunchKernelGGL(k_ring_br_init<LOGD>, dim3((unsigned)m), dim3(kT), 0, s, cm.x, cm.y, cm.xi, cm.yi, cm.gk, cm.cx,
+                       cm.cy, cm.cb, n, rot, acc, cm.delta);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n > 0 && (e = launch_blind_rotate<LOGD>(bkt, n, rot, acc, m, tv, s)) != hipSuccess) return e;
@@ -626,9 +643,8 @@ constexpr int64_t kMaxGrid = 1 << 30;
 // rank order (a NOT of a NOT of the same level one rank later).
 struct RingStep {
     bool is_not;
-    int gate;          // 4 AND, 5 XOR (and XADD), 6 OR, 8 NAND
     int count;
-    int64_t x, y, o;   // offsets of the index arrays (NOT: x = sources, o = destinations)
+    int64_t x, y, o, g;  // offsets of the index arrays and gate codes (NOT: x = sources, o = destinations)
 };
 struct RingPlanHost {
     int d = 0, logd = 0;
@@ -677,27 +693,26 @@ int ring_plan_build(const sfft_shape* shape, int32_t d, int64_t n, RingPlanHost*
         if (c.t[v] == sfft::T_IN) ins[c.a[v]] = (int32_t)v;
     pl->in_off = push(ins);
     pl->out_off = push(std::vector<int32_t>(c.outputs.begin(), c.outputs.end()));
-    const int kinds[4][2] = {{sfft::T_AND, 4}, {sfft::T_XOR, 5}, {sfft::T_OR, 6}, {sfft::T_NAND, 8}};
     for (int32_t lev = 0; lev <= L; ++lev) {
-        if (lev > 0)
-            for (const auto& k : kinds) {
-                std::vector<int32_t> xs, ys, os;
-                for (int64_t v = 0; v < N; ++v) {
-                    const int8_t t = c.t[v];
-                    const bool match = t == k[0] || (k[0] == sfft::T_XOR && t == sfft::T_XADD);
-                    if (depth[v] == lev && match) {
-                        xs.push_back(c.a[v]);
-                        ys.push_back(c.b[v]);
-                        os.push_back((int32_t)v);
-                    }
-                }
-                if (xs.empty()) continue;
-                RingStep st{false, k[1], (int)xs.size(), push(xs), push(ys), push(os)};
+        if (lev > 0) {
+            // every binary node of the level in one call, each with its gate
+            std::vector<int32_t> xs, ys, os, gs;
+            for (int64_t v = 0; v < N; ++v) {
+                const int8_t t = c.t[v];
+                if (depth[v] != lev || t < sfft::T_AND) continue;
+                xs.push_back(c.a[v]);
+                ys.push_back(c.b[v]);
+                os.push_back((int32_t)v);
+                gs.push_back(t == sfft::T_XADD ? sfft::T_XOR : t);   // the gate codes are the node types
+            }
+            if (!xs.empty()) {
+                RingStep st{false, (int)xs.size(), push(xs), push(ys), push(os), push(gs)};
                 pl->steps.push_back(st);
                 pl->gates += (int64_t)xs.size();
                 pl->max_batch = std::max(pl->max_batch, (int64_t)xs.size());
                 ++pl->calls;
             }
+        }
         for (int r = 0;; ++r) {
             std::vector<int32_t> src, dst;
             for (int64_t v = 0; v < N; ++v)
@@ -706,7 +721,7 @@ int ring_plan_build(const sfft_shape* shape, int32_t d, int64_t n, RingPlanHost*
                     dst.push_back((int32_t)v);
                 }
             if (src.empty()) break;
-            pl->steps.push_back(RingStep{true, 3, (int)src.size(), push(src), 0, push(dst)});
+            pl->steps.push_back(RingStep{true, (int)src.size(), push(src), 0, push(dst), 0});
         }
     }
     return SFFT_OK;
@@ -804,14 +819,7 @@ int sfft_ring_fft_execute(const sfft_ring_plan* plan, const uint64_t* bkt_dev, c
             e = rows(slots, I + st.x, slots, I + st.o, st.count, 1);
             continue;
         }
-        int cx, cy, k;
-        switch (st.gate) {
-        case 4: cx = 1, cy = 1, k = -1; break;
-        case 6: cx = 1, cy = 1, k = 1; break;
-        case 8: cx = -1, cy = -1, k = 5; break;
-        default: cx = 2, cy = 2, k = 0; break;
-        }
-        Combine cm{slots, slots, cx, cy, k >= 0 ? (uint64_t)k * q8 : kP - (uint64_t)(-k) * q8, q8, I + st.x, I + st.y};
+        Combine cm{slots, slots, 0, 0, 0, q8, I + st.x, I + st.y, I + st.g};
 #define SFFT_PBS(L) { e = launch_bootstrap<L>(bkt_dev, h.n, cm, st.count, mid, acc, rot, tv, s); break; }
         SFFT_RING_DISPATCH(h.logd, SFFT_PBS)
 #undef SFFT_PBS
@@ -993,14 +1001,11 @@ int sfft_ring_gate_bootstrap(int32_t d, int32_t gate, const uint64_t* bkt_dev, i
 {
     int logd, rc;
     if ((rc = check_d(d, &logd)) != SFFT_OK) return rc;
-    int cx, cy, k;
-    switch (gate) {
-    case 4: cx = 1, cy = 1, k = -1; break;   // AND
-    case 6: cx = 1, cy = 1, k = 1; break;    // OR
-    case 8: cx = -1, cy = -1, k = 5; break;  // NAND
-    case 5: cx = 2, cy = 2, k = 0; break;    // XOR
-    default: return sfft_fail(SFFT_EINVAL, "gate must be 4 (AND), 5 (XOR), 6 (OR) or 8 (NAND)");
-    }
+    if (gate != 4 && gate != 5 && gate != 6 && gate != 8)
+        return sfft_fail(SFFT_EINVAL, "gate must be 4 (AND), 5 (XOR), 6 (OR) or 8 (NAND)");
+    int cx, cy;
+    uint64_t cb;
+    gate_combination(gate, &cx, &cy, &cb);
     if (n < 0 || m < 0) return sfft_fail(SFFT_EINVAL, "n < 0 or m < 0");
     if (m == 0) return SFFT_OK;
     if (!x_dev || !y_dev || !out_dev || !ksk_dev || !ws_dev || (n > 0 && !bkt_dev))
@@ -1009,8 +1014,7 @@ int sfft_ring_gate_bootstrap(int32_t d, int32_t gate, const uint64_t* bkt_dev, i
     if (ws_bytes < m * 2 * d * 8 + m * (d + 1) * 8 + m * n * 4) return sfft_fail(SFFT_EINVAL, "workspace too small");
     TwView tv;
     if ((rc = tables(d, logd, &tv)) != SFFT_OK) return rc;
-    const uint64_t q8 = kP / 8;
-    const Combine cm{x_dev, y_dev, cx, cy, k >= 0 ? (uint64_t)k * q8 : kP - (uint64_t)(-k) * q8, q8};
+    const Combine cm{x_dev, y_dev, cx, cy, cb, kP / 8};
     uint64_t* acc = (uint64_t*)ws_dev;
     uint64_t* mid = acc + m * 2 * d;
     int32_t* rot = (int32_t*)(mid + m * (d + 1));
