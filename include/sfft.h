@@ -16,6 +16,12 @@
  * THE SIZES USED HERE ARE NOT SECURE: k is sized for correctness (noise)
  * only and the LWE dimension is tiny.
  *
+ * A second family of calls (sfft_ring_*) works with the ring instantiation
+ * of the same scheme over Z_p[X]/(X^d+1), p = 2^62 - 2^16 + 1: gates, blind
+ * rotation, refresh of LWE ciphertexts mod p, bootstrapped gates, and FFT
+ * plans evaluated on bootstrapped gates, whose parameters do not depend on
+ * the circuit's depth (the same warning about security applies).
+ *
  * Conventions for every call:
  *  - return value 0 (SFFT_OK) or a negative status; nothing is thrown across
  *    the ABI; sfft_last_error() gives a thread-local message for the last
