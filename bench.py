@@ -931,7 +931,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(requests and levels would shard across GPUs as described in the design notes)", file=sys.stderr)
         sys.exit(2)
 
