@@ -108,14 +108,28 @@ WORKLOADS = {
 }
 
 
+# Key and encryption seeds of request i of the batched and served mixes.
+BATCH_SEED0 = 1000
+SERVE_SEED0 = 5000
+
+
 def workload(name: str):
-    """(Signal, n_lwe, seed) of a named single-request workload."""
+    """(Signal, n_lwe, seed) of a named single-request workload, or of one
+    request of the batched or served mix: "batch4_req<i>" is request i of
+    batch_requests(4, ...), "serve5_req<i>" request i of served_requests(5,
+    ...), each with n_lwe = 1 and the seed its mix gives it."""
     if name == "fft1d_n8_real_q8.4":
         return uniform_pm1(1, 8, 8, 4, False), 1, 1
     if name == "fft1d_n64_cplx_q16.8":
         return gaussian_clipped(2, 64, 16, 8), 3, 2
     if name == "fft2d_16x16_real_q16.8":
         return image(3, 16, 16, 8), 1, 3
+    if name.startswith("batch4_req"):
+        i = int(name[len("batch4_req"):])
+        return batch_requests(4, i + 1)[i], 1, BATCH_SEED0 + i
+    if name.startswith("serve5_req"):
+        i = int(name[len("serve5_req"):])
+        return served_requests(5, i + 1)[i], 1, SERVE_SEED0 + i
     raise KeyError(name)
 
 

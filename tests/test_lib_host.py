@@ -27,6 +27,10 @@ SHAPES = [
     (1, 2, 6, 3, True, 1), (1, 4, 8, 4, False, 1), (1, 8, 8, 4, False, 1), (1, 8, 12, 6, True, 1),
     (1, 16, 16, 8, True, 1), (1, 32, 12, 6, True, 2), (2, 4, 8, 4, False, 1), (2, 8, 12, 6, True, 1),
     (1, 64, 16, 8, True, 3),
+    # the batched mix's extremes (N = 8..128, F = 12/16/24) and the served
+    # mix's (1D up to 256 points, images 8x8 to 32x32, Q(16,8))
+    (1, 8, 24, 12, True, 1), (1, 128, 12, 6, True, 1), (1, 128, 16, 8, True, 1), (1, 128, 24, 12, True, 1),
+    (1, 256, 16, 8, True, 1), (2, 8, 16, 8, False, 1), (2, 16, 16, 8, False, 1), (2, 32, 16, 8, False, 1),
 ]
 
 
