@@ -170,7 +170,9 @@ int sfft_decrypt_bits(const sfft_params* params, const uint32_t* sk_host, const 
  * addition, multiplication and NAND of ciphertexts; Lemma "binary gates"):
  * gate = 3 NOT (y ignored), 4 AND, 5 XOR, 6 OR, 7 XADD (addition; the result
  * encrypts x+y, a bit only if x,y are never both 1), 8 NAND, 9 PRODUCT
- * (= AND).  x, y, out: one ciphertext each, device; out must not alias. */
+ * (= AND).  x, y, out: one ciphertext each, device; out must not alias.
+ * Allocates nothing and holds no shared state, so calls on different streams
+ * may overlap. */
 int sfft_gate(const sfft_params* params, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev,
               uint32_t* out_dev, void* hip_stream);
 

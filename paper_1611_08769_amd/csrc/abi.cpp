@@ -553,8 +553,12 @@ int sfft_decrypt(const sfft_params* p, const uint32_t* sk_host, const uint32_t* 
     return SFFT_OK;
 }
 
-int sfft_gate(const sfft_params* p, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev, uint32_t* out_dev,
-              void* hip_stream)
+}  // extern "C"
+
+// One gate.  A transposition-pass tiling is replaced by its in-kernel twin,
+// so no scratch is needed and nothing is allocated.
+static int gate_impl(const sfft_params* p, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev,
+                     uint32_t* out_dev, void* hip_stream)
 {
     std::string why;
     if (!params_ok(p, &why)) return fail(SFFT_EINVAL, why);
@@ -594,20 +598,20 @@ int sfft_gate(const sfft_params* p, int32_t gate, const uint32_t* x_dev, const u
         case 6: it.cL[0] = 1; it.cR[0] = 1; it.cP[0] = -1; break;
         case 8: it.cP[0] = -1; it.cG[0] = 1; break;
         }
-        // the matrix-core kernel's chunk-layout copy of R, stream-ordered
-        void* rt = nullptr;
-        if (cfg.mfma && cfg.pre) {
-            e = hipMallocAsync(&rt, (size_t)rt_item_bytes(g), s);
-            if (e != hipSuccess) return hip_fail(e, "gate scratch");
-        }
-        e = launch_product_one(b, g, cfg, it, (uint8_t*)rt, s);
-        if (rt) {
-            const hipError_t ef = hipFreeAsync(rt, s);
-            if (e == hipSuccess) e = ef;
-        }
+        if (!inkernel_twin(g, &cfg)) return fail(SFFT_EUNSUPPORTED, "no kernel configuration for this geometry");
+        e = launch_product_one(b, g, cfg, it, nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(e, "gate launch");
     return SFFT_OK;
 }
+
+extern "C" {
+
+int sfft_gate(const sfft_params* p, int32_t gate, const uint32_t* x_dev, const uint32_t* y_dev, uint32_t* out_dev,
+              void* hip_stream)
+{
+    return gate_impl(p, gate, x_dev, y_dev, out_dev, hip_stream);
+}
+
 
 }  // extern "C"

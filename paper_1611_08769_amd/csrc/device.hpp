@@ -119,6 +119,10 @@ hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, 
 // item's worth, used under a matrix-core tiling).
 hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, uint8_t* rt,
                               hipStream_t s);
+// Replace a transposition-pass tiling by its twin that transposes inside
+// the product kernel (same tile shape, same results, no rt scratch); false
+// if the twin cannot serve g.  Other tilings are left as they are.
+bool inkernel_twin(const Geo& g, ProdCfg* cfg);
 // Linear items; max_elems = the largest Nct * (n+1) among the segments.
 hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
                          hipStream_t s);

@@ -555,6 +555,40 @@ __device__ __forceinline__ void transpose4x4(const uint32_t r[4], uint32_t c[4])
     c[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
 }
 
+// Direct loads from global memory into LDS: every lane of the wave loads
+// BYTES bytes from its own address, and lane i's bytes land at
+// lds_base + BYTES * i (lds_base the same for the whole wave).  They count
+// as vector-memory operations of the wave (vmcnt) and write LDS without
+// passing through registers.
+typedef __attribute__((address_space(3))) void lds_void;
+template <int BYTES>
+__device__ __forceinline__ void load_to_lds(const void* src, void* lds_base)
+{
+    static_assert(BYTES == 4 || BYTES == 16, "4- or 16-byte lanes");
+    if constexpr (BYTES == 16) __builtin_amdgcn_global_load_lds(src, (lds_void*)lds_base, 16, 0, 0);
+    else __builtin_amdgcn_global_load_lds(src, (lds_void*)lds_base, 4, 0, 0);
+}
+
+// Wait until at most N vector-memory operations of this wave are
+// outstanding (s_waitcnt: vmcnt in bits 3:0 and 15:14, expcnt (6:4) and
+// lgkmcnt (11:8) left at their maxima, i.e. not waited for).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Workgroup barrier without the memory fence of __syncthreads (which would
+// wait for every outstanding load, prefetches included); the empty asm
+// statements keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void barrier_only()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // 16 bits to 16 bytes of 0/1 (byte p = bit p): x * 0x204081 places bits
 // 0..3 of a nibble at bits 0, 8, 16, 24 without carries.
 __device__ __forceinline__ i32x4 spread_bits(uint32_t u)
@@ -745,7 +779,7 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     const int SP = NF * 32 + 4;
     const int LP = 8 * ((W + 7) / 8) + 4;
     const int slab_bytes = 32 * (SP + 2 * LP) * 4;
-    const int main_bytes = 2 * bsz + 2 * TM * KC;
+    const int main_bytes = PRE ? 3 * bsz + 3 * TM * 16 : 2 * bsz + 2 * TM * KC;
     int spp = 1;
     if ((main_bytes > 2 * slab_bytes ? main_bytes : 2 * slab_bytes) + TM * 4 + THREADS * 16 <= lds_bytes) spp = 2;
     const int s_bytes = spp * slab_bytes;
@@ -899,78 +933,172 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
         bswz[q] = mfma_swz(n);
     }
 
-    // this lane's rows of A: 64 wr + 32 f + lane % 32
-    int arow[2];
+    if constexpr (PRE) {
+        // Chunks of R (already in chunk layout) and of the bits of L go from
+        // global memory straight into LDS, three chunks deep: chunk c + 2 is
+        // requested while chunk c is multiplied, and each wave waits only for
+        // its own requests of chunk c before the barrier that opens it.
+        // Every wave issues DR + DL requests per chunk (units past the chunk
+        // repeat its last unit, rows past the product its last row, words
+        // past the row its last word: all in bounds), so that the wait is a
+        // constant count.  Bits of L past the product (the last chunk's
+        // missing rows of R) are cleared before they are spread.
+        constexpr int NW = RG * CG;
+        constexpr int DR = (4 * CG * CF + NW - 1) / NW;  // 1 KB units of R per wave per chunk
+        constexpr int DL = 4 / CG;                        // 256-byte row groups of L per wave per chunk
+        static_assert(4 % CG == 0, "row groups of L split evenly over the waves");
+        const int units = 4 * NF;
+        uint8_t* Rb = reinterpret_cast<uint8_t*>(lds);  // 3 chunks of R
+        uint8_t* Lb = Rb + 3 * bsz;                      // 3 chunks of L: 16 bytes (128 bits) per tile row
+        const uint8_t* rsrc = sg.rt + (size_t)yl * rt_item_bytes(g);
+        const uint8_t* Lbytes = (const uint8_t*)Lp;
+        auto request = [&](int c) {
+            const int buf = c % 3;
+            const uint8_t* src = rsrc + (size_t)c * bsz;
+            uint8_t* dst = Rb + buf * bsz;
 #pragma unroll
-    for (int f = 0; f < 2; f++) {
-        const int r = 64 * wr + 32 * f + (lane & 31);
-        arow[f] = r * KC;
-        (void)r;
-    }
-    int aswz[2];
+            for (int t = 0; t < DR; t++) {
+                const int u = wave + NW * t < units ? wave + NW * t : units - 1;
+                load_to_lds<16>(src + (size_t)u * 1024 + lane * 16, dst + u * 1024);
+            }
 #pragma unroll
-    for (int f = 0; f < 2; f++) aswz[f] = mfma_swz(64 * wr + 32 * f + (lane & 31));
+            for (int t = 0; t < DL; t++) {
+                const int j = wave * DL + t;  // rows 16 j .. 16 j + 15 of the tile
+                int row = row_base + 16 * j + (lane >> 2);
+                row = row < nct ? row : nct - 1;
+                int word = 4 * c + (lane & 3);
+                word = word < W ? word : W - 1;
+                load_to_lds<4>(Lbytes + ((size_t)row * W + word) * 4, Lb + buf * TM * 16 + j * 256);
+            }
+        };
+        // this lane's rows of A: 64 wr + 32 f + lane % 32, 16 bytes each per chunk
+        int arow16[2];
+#pragma unroll
+        for (int f = 0; f < 2; f++) arow16[f] = (64 * wr + 32 * f + (lane & 31)) * 16;
+        uint32_t pc[2] = {0u, 0u};
 
-    load_R(0, -1);
-    load_L(0);
-    stage_R(0, -1);
-    stage_L(0);
-    if (1 < nchunks) {
-        load_R(1, -1);
-        load_L(1);
-    }
-    __syncthreads();
-    for (int c = 0; c < nchunks; c++) {
-        const uint8_t* Bc = Bs + (c & 1) * bsz;
-        const uint8_t* Ac = As + (c & 1) * TM * KC;
-        const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
-        const bool next = c + 1 < nchunks, next2 = c + 2 < nchunks;
-        // fragments of step s + 1 are read from LDS before the products of step s
-        i32x4 B[CF], A[2];
-        auto read_frags = [&](int s) {
+        request(0);
+        if (1 < nchunks) request(1);
+        for (int c = 0; c < nchunks; c++) {
+            if (c + 1 < nchunks) wait_vmcnt<DR + DL>();
+            else wait_vmcnt<0>();
+            barrier_only();
+            if (c + 2 < nchunks) request(c + 2);
+            const uint8_t* Bc = Rb + (c % 3) * bsz;
+            const uint8_t* Lc = Lb + (c % 3) * TM * 16;
+            const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
+            u32x4 lw[2];
+#pragma unroll
+            for (int f = 0; f < 2; f++) lw[f] = *reinterpret_cast<const u32x4*>(Lc + arow16[f]);
+            i32x4 Bx[2][CF];
 #pragma unroll
             for (int q = 0; q < CF; q++)
-                B[q] = *reinterpret_cast<const i32x4*>(Bc + bcol[q] + 16 * ((2 * s + half) ^ bswz[q]));
+                Bx[0][q] = *reinterpret_cast<const i32x4*>(Bc + bcol[q] + 16 * (half ^ bswz[q]));
 #pragma unroll
-            for (int f = 0; f < 2; f++)
-                A[f] = *reinterpret_cast<const i32x4*>(Ac + arow[f] + 16 * ((2 * s + half) ^ aswz[f]));
-        };
-        read_frags(0);
+            for (int st = 0; st < KC / 32; st++) {
+                if (st + 1 < KC / 32) {
 #pragma unroll
-        for (int s = 0; s < KC / 32; s++) {
-            if (32 * s < rows_c) {
-                i32x4 Bq[CF], Af[2];
+                    for (int q = 0; q < CF; q++)
+                        Bx[(st + 1) & 1][q] =
+                            *reinterpret_cast<const i32x4*>(Bc + bcol[q] + 16 * ((2 * (st + 1) + half) ^ bswz[q]));
+                }
+                i32x4 Af[2];
 #pragma unroll
-                for (int q = 0; q < CF; q++) Bq[q] = B[q];
-                Af[0] = A[0], Af[1] = A[1];
-                if (s + 1 < KC / 32 && 32 * (s + 1) < rows_c) read_frags(s + 1);
+                for (int f = 0; f < 2; f++) {
+                    const uint32_t w = 32 * st < rows_c ? lw[f][st] : 0u;
+                    const uint32_t b16 = (w >> (16 * half)) & 0xFFFFu;
+                    pc[f] += __builtin_popcount(b16);
+                    Af[f] = spread_bits(b16);
+                }
 #pragma unroll
                 for (int q = 0; q < CF; q++) {
-                    acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[0], Bq[q], acc[0][q], 0, 0, 0);
-                    acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[1], Bq[q], acc[1][q], 0, 0, 0);
+                    acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[0], Bx[st & 1][q], acc[0][q], 0, 0, 0);
+                    acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[1], Bx[st & 1][q], acc[1][q], 0, 0, 0);
                 }
             }
-            // staging parts that fall after this step
-#pragma unroll
-            for (int p = 0; p < NP; p++) {
-                if ((p + 1) * (KC / 32) / NP - 1 != s) continue;
-                if (next) stage_R(c + 1, p);
-                if (next2) load_R(c + 2, p);
-            }
         }
-        if (next) stage_L(c + 1);
-        if (next2) load_L(c + 2);
+        // every wave done with the chunk buffers before the epilogue reuses
+        // them; the popcount of a row is the sum over its two half-lanes
         __syncthreads();
-    }
-
-    // popcount of each row: the sum over the KC/32 staging threads of the
-    // row (consecutive lanes)
 #pragma unroll
-    for (int i = 0; i < APT; i++) {
-        pcs[i] += __shfl_xor(pcs[i], 1);
-        pcs[i] += __shfl_xor(pcs[i], 2);
-        const int a = tid + i * THREADS;
-        if (a < TM * (KC / 32) && (a & 3) == 0) Pc[a >> 2] = (int32_t)pcs[i];
+        for (int f = 0; f < 2; f++) {
+            const uint32_t tot = pc[f] + __shfl_xor(pc[f], 32);
+            if (wc == 0 && half == 0) Pc[64 * wr + 32 * f + (lane & 31)] = (int32_t)tot;
+        }
+    } else {
+    // this lane's rows of A: 64 wr + 32 f + lane % 32
+        int arow[2];
+    #pragma unroll
+        for (int f = 0; f < 2; f++) {
+            const int r = 64 * wr + 32 * f + (lane & 31);
+            arow[f] = r * KC;
+            (void)r;
+        }
+        int aswz[2];
+    #pragma unroll
+        for (int f = 0; f < 2; f++) aswz[f] = mfma_swz(64 * wr + 32 * f + (lane & 31));
+    
+        load_R(0, -1);
+        load_L(0);
+        stage_R(0, -1);
+        stage_L(0);
+        if (1 < nchunks) {
+            load_R(1, -1);
+            load_L(1);
+        }
+        __syncthreads();
+        for (int c = 0; c < nchunks; c++) {
+            const uint8_t* Bc = Bs + (c & 1) * bsz;
+            const uint8_t* Ac = As + (c & 1) * TM * KC;
+            const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
+            const bool next = c + 1 < nchunks, next2 = c + 2 < nchunks;
+            // fragments of step s + 1 are read from LDS before the products of step s
+            i32x4 B[CF], A[2];
+            auto read_frags = [&](int s) {
+    #pragma unroll
+                for (int q = 0; q < CF; q++)
+                    B[q] = *reinterpret_cast<const i32x4*>(Bc + bcol[q] + 16 * ((2 * s + half) ^ bswz[q]));
+    #pragma unroll
+                for (int f = 0; f < 2; f++)
+                    A[f] = *reinterpret_cast<const i32x4*>(Ac + arow[f] + 16 * ((2 * s + half) ^ aswz[f]));
+            };
+            read_frags(0);
+    #pragma unroll
+            for (int s = 0; s < KC / 32; s++) {
+                if (32 * s < rows_c) {
+                    i32x4 Bq[CF], Af[2];
+    #pragma unroll
+                    for (int q = 0; q < CF; q++) Bq[q] = B[q];
+                    Af[0] = A[0], Af[1] = A[1];
+                    if (s + 1 < KC / 32 && 32 * (s + 1) < rows_c) read_frags(s + 1);
+    #pragma unroll
+                    for (int q = 0; q < CF; q++) {
+                        acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[0], Bq[q], acc[0][q], 0, 0, 0);
+                        acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[1], Bq[q], acc[1][q], 0, 0, 0);
+                    }
+                }
+                // staging parts that fall after this step
+    #pragma unroll
+                for (int p = 0; p < NP; p++) {
+                    if ((p + 1) * (KC / 32) / NP - 1 != s) continue;
+                    if (next) stage_R(c + 1, p);
+                    if (next2) load_R(c + 2, p);
+                }
+            }
+            if (next) stage_L(c + 1);
+            if (next2) load_L(c + 2);
+            __syncthreads();
+        }
+    
+        // popcount of each row: the sum over the KC/32 staging threads of the
+        // row (consecutive lanes)
+    #pragma unroll
+        for (int i = 0; i < APT; i++) {
+            pcs[i] += __shfl_xor(pcs[i], 1);
+            pcs[i] += __shfl_xor(pcs[i], 2);
+            const int a = tid + i * THREADS;
+            if (a < TM * (KC / 32) && (a & 3) == 0) Pc[a >> 2] = (int32_t)pcs[i];
+        }
     }
 
     // Epilogue in passes of spp slabs of 32 rows (slab 2 wr + f is fragment
@@ -1302,7 +1430,10 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
     // rows of column sums (as many as the workgroup's share allows: all of a
     // CU for 512 threads, half for 256), and a popcount per tile row
     const int cap = cfg->threads >= 512 ? 160 * 1024 : 80 * 1024;
-    const int chunks = 2 * nf * 32 * kMfmaPitch + 2 * cfg->tr * kMfmaChunk;
+    // (the transposition-pass tilings keep three chunks of R and of the bits
+    // of L in flight, the others two chunks of R and of L as bytes)
+    const int chunks = t.pre ? 3 * nf * 32 * kMfmaPitch + 3 * cfg->tr * 16
+                             : 2 * nf * 32 * kMfmaPitch + 2 * cfg->tr * kMfmaChunk;
     const int slab = 32 * ((nf * 32 + 4) + 2 * (8 * ((g.W + 7) / 8) + 4)) * 4;
     const int tail = cfg->tr * 4 + cfg->threads * 16;  // popcounts, chain-run carries
     const int spp = std::max(chunks, 2 * slab) + tail <= cap ? 2 : 1;
@@ -1407,6 +1538,17 @@ hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, 
         if (e != hipSuccess) return e;
     }
     return dispatch<false>(cfg, d_segs, nseg, seg0, none, blocks, 0, 0, nullptr, s);
+}
+
+bool inkernel_twin(const Geo& g, ProdCfg* cfg)
+{
+    if (!cfg->mfma || !cfg->pre) return true;
+    for (int i = 0; i < kNumMfmaTilings; i++) {
+        const MfmaTiling& t = kMfmaTilings[i];
+        if (!t.pre && t.rg == cfg->rg && t.cgw == cfg->cgw && t.cf == cfg->cf)
+            return tiling_config(g, kNumLookupTilings + i, cfg);
+    }
+    return false;
 }
 
 hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, uint8_t* rt,
