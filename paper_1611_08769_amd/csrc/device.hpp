@@ -40,7 +40,8 @@ struct ProdCfg {
     // fragments per wave
     bool mfma;
     int rg, cgw, cf;
-    bool pre;  // right operands transposed into rt by a pass before the launch
+    int pre;   // right operands transposed into rt by a pass before the launch (1: 128-row chunks, 2: 64-row)
+    int cs;    // workgroups per row tile: column splits of whole elements (the 256-thread kernel), else 1
 };
 
 // Passed to the kernel by value.
@@ -105,8 +106,24 @@ struct LinSeg {
     uint32_t pad;
 };
 
-// Workgroups (row tiles) per product item of geometry g.
-inline int product_tiles(const Geo& g, const ProdCfg& cfg) { return (g.nct + cfg.tr - 1) / cfg.tr; }
+// Workgroups per product item of geometry g: row tiles times column splits.
+inline int product_tiles(const Geo& g, const ProdCfg& cfg)
+{
+    return (g.nct + cfg.tr - 1) / cfg.tr * (cfg.cs > 1 ? cfg.cs : 1);
+}
+
+// Elements per column split of the 256-thread matrix-core kernel with cf
+// fragments per wave (a tile spans 64 cf byte columns): all n + 1 where the
+// row fits; else the most whole elements that fit and start every split on
+// a multiple of 4 words (rows of a multiple of 4 words); 0 if none.
+__host__ __device__ inline int mfma2_eps(const Geo& g, int cf)
+{
+    if (4 * g.W <= 64 * cf) return g.n1;
+    if (g.W % 4 != 0) return 0;
+    for (int e = g.n1 - 1; e >= 1; e--)
+        if (e * g.k / 8 <= 64 * cf && (e * g.kw) % 4 == 0) return e;
+    return 0;
+}
 
 // One launch over `blocks` workgroups (the sum over the segments of items x
 // product_tiles) in nseg segments of `items` items in all: d_segs in device

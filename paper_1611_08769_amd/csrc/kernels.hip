@@ -85,6 +85,21 @@ __device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t n)
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// A copy of a value that is the same in every lane of the wave, taken word by
+// word from the first active lane: the compiler keeps it in scalar registers
+// instead of vector ones.
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T& x)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T v;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&x);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); i++) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return v;
+}
+
 // A work item read word by word through the global address space.
 template <class T>
 __device__ __forceinline__ T load_global(const T* p)
@@ -541,6 +556,47 @@ constexpr int kMfmaPitch = kMfmaChunk;          // LDS bytes per staged column
 // the 64 banks, and distinct values on n = 16 w + k for w = 0..7, so that
 // the dword stores of a staging wave spread over all banks (two lanes each).
 __device__ __forceinline__ int mfma_swz(int n) { return ((n >> 1) + (n >> 4)) & 7; }
+// The 16-byte units of a column of a 64-row chunk (4 units): unit ^
+// swz64(n), so that 16 lanes reading one unit of 16 consecutive columns hit
+// distinct 4-bank groups.
+__device__ __forceinline__ int swz64(int n) { return (n >> 2) & 3; }
+template <int KC>
+__device__ __forceinline__ int chunk_swz(int n) { return KC == 128 ? mfma_swz(n) : swz64(n); }
+
+// Epilogue layout of the column sums: a row of NF fragments takes SP =
+// 32 NF + 8 words (rows 4 apart, as the two halves of a fragment's lanes
+// store them, then fall on disjoint halves of the 64 banks).  Word w of a
+// row (its four byte sums, 16 bytes) sits in unit mfma_sum_unit(w): the
+// units of a quad stay in the quad, permuted so that 16 lanes reading word u
+// of 16 consecutive quads hit distinct 4-bank groups.
+__host__ __device__ constexpr int mfma_sum_pitch(int nf) { return 32 * nf + 8; }
+__device__ __forceinline__ int mfma_sum_unit(int w) { return w ^ ((w >> 4) & 3); }
+// LDS bytes of one operand's words in a pass of 32 rows (whole KB: the
+// loads straight into LDS fill 1 KB per wave instruction).
+__host__ __device__ constexpr int mfma_op_bytes(int W) { return (128 * W + 1023) / 1024 * 1024; }
+// LDS bytes of the epilogue: a slab of 32 rows of column sums, one carry
+// per quad of words and output, and two passes' words of L, R and up to
+// kMaxE extra operands.
+__host__ __device__ constexpr int mfma_epi_bytes(int nf, int W)
+{
+    return 32 * mfma_sum_pitch(nf) * 4 + kMaxOut * 8 * W * 4 + 2 * (2 + kMaxE) * mfma_op_bytes(W);
+}
+// LDS bytes of the 256-thread kernel (k_product_mfma2): its main loop's
+// chunks in flight of 2 x 2 CF 1 KB units of R and of 128 rows' 64 bits of
+// L, and its epilogue's passes of 16 rows (qp quads of words): column sums
+// and two passes' quads of L, R and up to kMaxE extra operands.
+// Chunks of R in flight: as many as about 78 KB hold, at most 6 (a chunk
+// keeps the matrix cores busy for a short time, so the requests must be
+// issued several chunks ahead to cover the memory latency).
+__host__ __device__ constexpr int mfma2_depth(int cf)
+{
+    return (78 * 1024) / (4 * cf * 1024 + 1024) < 6 ? (78 * 1024) / (4 * cf * 1024 + 1024) : 6;
+}
+__host__ __device__ constexpr int mfma2_main_bytes(int cf) { return mfma2_depth(cf) * (4 * cf * 1024 + 128 * 8); }
+__host__ __device__ constexpr int mfma2_epi_bytes(int cf, int qp)
+{
+    return 16 * mfma_sum_pitch(2 * cf) * 4 + 2 * (2 + kMaxE) * ((16 * qp + 1023) / 1024 * 1024);
+}
 
 // r[i] holds bytes (i, 0..3) of a 4x4 byte block; c[j] gets bytes (0..3, j)
 __device__ __forceinline__ void transpose4x4(const uint32_t r[4], uint32_t c[4])
@@ -579,12 +635,39 @@ __device__ __forceinline__ void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Wait until at most n * STEP (n <= MAX / STEP, run-time) vector-memory
+// operations of this wave are outstanding: the counts are immediates, so
+// one s_waitcnt per possible n.
+template <int MAX, int STEP>
+__device__ __forceinline__ void wait_vmcnt_upto(int n)
+{
+    if constexpr (MAX >= STEP) {
+        if (n >= MAX / STEP) {
+            wait_vmcnt<MAX>();
+            return;
+        }
+        wait_vmcnt_upto<MAX - STEP, STEP>(n);
+    } else {
+        wait_vmcnt<0>();
+    }
+}
+
 // Workgroup barrier without the memory fence of __syncthreads (which would
 // wait for every outstanding load, prefetches included); the empty asm
 // statements keep the compiler from moving memory accesses across it.
 __device__ __forceinline__ void barrier_only()
 {
     asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Workgroup barrier after this wave's LDS accesses (lgkmcnt 0) but without
+// waiting for its global loads or stores.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));  // vmcnt and expcnt at their maxima, lgkmcnt 0
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }
@@ -601,77 +684,23 @@ __device__ __forceinline__ i32x4 spread_bits(uint32_t u)
     return a;
 }
 
-// Output row `row`, element e, limbs [lb, le), from its byte column sums
-// S[0..4 kw) (LDS, each missing 128 popcount), the row's popcount pc and its
-// words of L and R (LDS), with carry-in 0.  Output o's limb l replaces
-// S[4 l + o] (the sums of limb l are consumed first), for a coalesced
-// write-out afterwards; the carry out of limb le - 1 goes to cy[o] (when cy
-// is given), for the next limbs' fix-up.
-__device__ void finish_bytes(const Bufs& bufs, const Geo& g, const ProdItem& it, int32_t* S, int pc,
-                             const uint32_t* Lw, const uint32_t* Rw, int row, int e, int lb, int le, int32_t* cy)
-{
-    const int br = row / g.k, tr = row % g.k;
-    const size_t base = (size_t)row * g.W + (size_t)e * g.kw;
-    const int64_t corr = 128ll * pc * 0x01010101ll;
-    int64_t carry[kMaxOut];
-    const gword* Ep[kMaxOut];
-#pragma unroll
-    for (int o = 0; o < kMaxOut; o++) {
-        carry[o] = 0;
-        Ep[o] = o < it.nout && it.E[o] >= 0 ? ctp(bufs, it.E[o]) + base : nullptr;
-    }
-    for (int l0 = lb; l0 < le; l0 += 4) {
-        const int nl = le - l0 < 4 ? le - l0 : 4;
-        uint32_t Ev[kMaxOut][4];
-#pragma unroll
-        for (int o = 0; o < kMaxOut; o++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) Ev[o][j] = (Ep[o] && j < nl) ? Ep[o][l0 + j] : 0u;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            if (j < nl) {
-                const int l = l0 + j;
-                i32x4* s4p = reinterpret_cast<i32x4*>(S + 4 * l);
-                const i32x4 s4 = *s4p;
-                const int64_t P = (int64_t)s4[0] + (int64_t)s4[1] * 256 + (int64_t)s4[2] * 65536 +
-                                  (int64_t)s4[3] * 16777216 + corr;
-                const uint32_t Lv = Lw[l], Rv = Rw[l];
-                const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
-                i32x4 out = {0, 0, 0, 0};
-#pragma unroll
-                for (int o = 0; o < kMaxOut; o++) {
-                    if (o < it.nout) {
-                        const int64_t v = carry[o] + (int64_t)it.cL[o] * Lv + (int64_t)it.cR[o] * Rv +
-                                          (int64_t)it.cP[o] * P + (int64_t)it.cG[o] * Gv +
-                                          (int64_t)it.cE[o] * Ev[o][j];
-                        out[o] = (int32_t)(uint32_t)v;
-                        carry[o] = v >> 32;
-                    }
-                }
-                *s4p = out;
-            }
-        }
-    }
-    if (cy) {
-#pragma unroll
-        for (int o = 0; o < kMaxOut; o++) cy[o] = (int32_t)carry[o];  // |carry| < 2^15
-    }
-}
-
 // Right operands of a launch's items into the matrix-core kernel's chunk
 // layout, once per item instead of once per row tile: workgroup (y, c)
 // loads chunk c (128 rows) of item y's R with 16-byte row loads (8 lanes per
 // 128 contiguous bytes), transposes 4x4 byte blocks in registers (v_perm),
 // stores them column by column into LDS (bytes xor 0x80, 16-byte units of a
 // column XOR-swizzled) and copies the chunk out with 16-byte stores.
+// KC = 128 for the 512-thread kernel's chunks; KC = 64 for the 256-thread
+// kernel's, whose columns keep their 4 units in the order unit ^ swz64(n).
 constexpr int kRtransThreads = 256;
+template <int KC>
 __global__ void __launch_bounds__(kRtransThreads) k_rtrans(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
                                                            ProdItem one)
 {
     constexpr int THREADS = kRtransThreads;
-    constexpr int KC = kMfmaChunk;
-    constexpr int BP = kMfmaPitch;
-    constexpr int SPT = (KC / 4 * 24 + THREADS - 1) / THREADS;  // 32 row quads x up to 24 word quads (W <= 96)
+    constexpr int BP = KC;                                       // bytes per column of a chunk
+    constexpr int JG = KC / 32;                                  // groups of 8 row quads
+    constexpr int SPT = (KC / 4 * 24 + THREADS - 1) / THREADS;  // KC/4 row quads x up to 24 word quads (W <= 96)
     extern __shared__ uint32_t lds[];
     uint8_t* Ts = reinterpret_cast<uint8_t*>(lds);
     const uint32_t y = blockIdx.x;  // item within the launch
@@ -693,7 +722,7 @@ __global__ void __launch_bounds__(kRtransThreads) k_rtrans(const ProdSeg* __rest
 #pragma unroll
     for (int i = 0; i < SPT; i++) {
         const int t = tid + i * THREADS, r = t >> 6;
-        const int jq = ((t >> 3) & 7) + 8 * (r & 3), wq = (t & 7) + 8 * (r >> 2);
+        const int jq = ((t >> 3) & 7) + 8 * (r % JG), wq = (t & 7) + 8 * (r / JG);
         const bool ok = 4 * wq < W && 4 * jq < rows_c;
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
@@ -710,7 +739,7 @@ __global__ void __launch_bounds__(kRtransThreads) k_rtrans(const ProdSeg* __rest
 #pragma unroll
     for (int i = 0; i < SPT; i++) {
         const int t = tid + i * THREADS, r = t >> 6;
-        const int jq = ((t >> 3) & 7) + 8 * (r & 3), wq = (t & 7) + 8 * (r >> 2);
+        const int jq = ((t >> 3) & 7) + 8 * (r % JG), wq = (t & 7) + 8 * (r / JG);
         if (4 * wq < W && 4 * jq < rows_c) {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
@@ -721,7 +750,7 @@ __global__ void __launch_bounds__(kRtransThreads) k_rtrans(const ProdSeg* __rest
                 for (int cc = 0; cc < 4; cc++) {
                     const int n = 16 * wq + 4 * u + cc;
                     // columns past the row (a partial last unit) are never read
-                    *reinterpret_cast<uint32_t*>(Ts + n * BP + 16 * ((jq >> 2) ^ mfma_swz(n)) + 4 * (jq & 3)) =
+                    *reinterpret_cast<uint32_t*>(Ts + n * BP + 16 * ((jq >> 2) ^ chunk_swz<KC>(n)) + 4 * (jq & 3)) =
                         col[cc] ^ 0x80808080u;
                 }
             }
@@ -747,7 +776,7 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     constexpr int SPT_T = (KC / 4 * 2 * CG * CF + THREADS - 1) / THREADS;
     constexpr int SPT = PRE ? SPT_C : SPT_T;
     constexpr int APT = (TM * (KC / 32) + THREADS - 1) / THREADS;        // staged words of L per thread
-    constexpr int EPT = (64 * 8 * CG * CF / 4 + THREADS - 1) / THREADS;  // epilogue 16-byte loads per operand
+    constexpr int EPT = (8 * 8 * CG * CF + THREADS - 1) / THREADS;  // epilogue quads of words per thread and pass
     constexpr int NP = SPT < KC / 32 ? SPT : KC / 32;                     // staging parts per chunk
 
     extern __shared__ uint32_t lds[];
@@ -772,21 +801,15 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     const gword* Lp = ctp(bufs, it.L);
     const gword* Rp = ctp(bufs, it.R);
 
-    // epilogue: per row, SP words of column sums (later outputs) and LP words
-    // each of L and R; slabs of 32 rows per pass,
-    // as many (up to 2) as the launch's LDS holds beside the popcounts
-    // (segments of one launch may differ in width)
-    const int SP = NF * 32 + 4;
-    const int LP = 8 * ((W + 7) / 8) + 4;
-    const int slab_bytes = 32 * (SP + 2 * LP) * 4;
+    // epilogue: a slab of 32 rows of column sums (SP words per row), a carry
+    // per quad of words and output, the operands of two passes (segments of
+    // one launch may differ in width)
+    const int SP = mfma_sum_pitch(NF);
     const int main_bytes = PRE ? 3 * bsz + 3 * TM * 16 : 2 * bsz + 2 * TM * KC;
-    int spp = 1;
-    if ((main_bytes > 2 * slab_bytes ? main_bytes : 2 * slab_bytes) + TM * 4 + THREADS * 16 <= lds_bytes) spp = 2;
-    const int s_bytes = spp * slab_bytes;
+    const int e_bytes = mfma_epi_bytes(NF, W);
     uint8_t* Bs = reinterpret_cast<uint8_t*>(lds);  // 2 chunks of R, column by column
     uint8_t* As = Bs + 2 * bsz;                     // 2 chunks of bits of L as 0/1 bytes, KC bytes per row
-    int32_t* Pc = reinterpret_cast<int32_t*>(Bs + (main_bytes > s_bytes ? main_bytes : s_bytes));  // popcount per row
-    int32_t* Cy = Pc + TM;  // epilogue: carries out of chain runs, 4 per thread
+    int32_t* Pc = reinterpret_cast<int32_t*>(Bs + (main_bytes > e_bytes ? main_bytes : e_bytes));  // popcount per row
 
     // Staging of R.  PRE: R comes already in chunk layout (k_rtrans), and
     // staging chunk c copies its bsz bytes, 16 per thread and unit, into
@@ -1101,117 +1124,569 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
         }
     }
 
-    // Epilogue in passes of spp slabs of 32 rows (slab 2 wr + f is fragment
-    // f of row group wr).  Per pass: the rows' words of L and R are loaded
-    // (16 bytes a lane, rows contiguous) while the accumulators go to LDS;
-    // one thread per (row, element) runs the carry chains from LDS and leaves
-    // the outputs in place of the column sums; then the outputs are written
-    // row-contiguously.
+    // Epilogue, in passes of one slab of 32 rows (slab 2 wr + f is fragment f
+    // of row group wr; Nct is a multiple of 32, so every pass is whole).  The
+    // 32 W words of a pass (row-major, flat) go to the threads as quads of 4
+    // consecutive words.  The pass's words of L, R and of the item's extra
+    // operands come from global memory straight into LDS, one pass ahead.
+    //  1. The waves holding the pass's rows store their column sums in S.
+    //  2. Per quad and output, each word's limb of a L + b R + c P + g G + e E
+    //     (P's limb from its four byte column sums) is rippled through the
+    //     quad from carry 0, restarting at the first limb of every element;
+    //     the carry out of the quad goes to Cq (0 where the quad ends an
+    //     element).  The limb is A + 2^16 B with A and B sums of small
+    //     coefficients times 16-bit halves and byte sums (24-bit products).
+    //  3. Each quad takes the carry out of the quad before it (unless it
+    //     starts an element) and ripples it through its words; repeated while
+    //     any carry leaves a quad.  Carries never cross an element: the sums
+    //     are mod 2^k per element.
+    //  4. The outputs are written with 16-byte stores.
+    // The item's coefficients and operands are the same for the whole
+    // workgroup.
+    const int nout = __builtin_amdgcn_readfirstlane(it.nout);
+    int cLo[kMaxOut], cRo[kMaxOut], cPo[kMaxOut], cGo[kMaxOut], cEo[kMaxOut], eso[kMaxOut];
+    gword* Do[kMaxOut];
+    // operand slots: 0 = L, 1 = R, then the distinct extra operands
+    const gword* opsrc[2 + kMaxE] = {Lp, Rp};
+    int32_t eref[kMaxE];
+    int nops = 2;
+#pragma unroll
+    for (int o = 0; o < kMaxOut; o++) {
+        cLo[o] = __builtin_amdgcn_readfirstlane((int)it.cL[o]);
+        cRo[o] = __builtin_amdgcn_readfirstlane((int)it.cR[o]);
+        cPo[o] = __builtin_amdgcn_readfirstlane((int)it.cP[o]);
+        cGo[o] = __builtin_amdgcn_readfirstlane((int)it.cG[o]);
+        cEo[o] = __builtin_amdgcn_readfirstlane((int)it.cE[o]);
+        const int32_t er = __builtin_amdgcn_readfirstlane(it.E[o]);
+        const int32_t dr = __builtin_amdgcn_readfirstlane(it.dst[o]);
+        Do[o] = o < nout ? ctp(bufs, dr) : nullptr;
+        eso[o] = -1;
+        if (o < nout && er >= 0) {
+#pragma unroll
+            for (int q = 0; q < kMaxE; q++)
+                if (q + 2 < nops && eref[q] == er) eso[o] = q;
+            if (eso[o] < 0 && nops < 2 + kMaxE) {  // (the plan keeps at most kMaxE per item)
+                eref[nops - 2] = er;
+                opsrc[nops] = ctp(bufs, er);
+                eso[o] = nops - 2;
+                ++nops;
+            }
+        }
+    }
+    const int kw = g.kw, kb = g.k;
+    const int QP = 8 * W;  // quads of a pass
     int32_t* S = reinterpret_cast<int32_t*>(lds);
-    uint32_t* Le = reinterpret_cast<uint32_t*>(S + 32 * spp * SP);
-    uint32_t* Re = Le + 32 * spp * LP;
-    for (int p0 = 0; p0 < 2 * RG; p0 += spp) {
-        if (p0 > 0) __syncthreads();
+    int32_t* Cq = S + 32 * SP;
+    uint8_t* OPS = reinterpret_cast<uint8_t*>(Cq + kMaxOut * QP);  // 2 buffers x (2 + kMaxE) operands
+    const int OPB = mfma_op_bytes(W);
+    int32_t* more = Pc + TM;  // the last round in which a carry left a quad
+    int round = 0;
+    if (tid == 0) *more = 0;  // (read only after the barriers below)
+    // the pass's words of every operand into buffer b: 16-byte units, 64
+    // consecutive units per wave instruction (the last block's lanes past
+    // the pass re-read its last unit and land in the block's padding)
+    auto stage_ops = [&](int p0, int b) {
+        const size_t pbase = (size_t)(row_base + 32 * p0) * W;
+        for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < QP; blk += RG * CG) {
+            const int u = 64 * blk + lane < QP ? 64 * blk + lane : QP - 1;
+#pragma unroll
+            for (int s = 0; s < 2 + kMaxE; s++)
+                if (s < nops)
+                    load_to_lds<16>((const uint8_t*)(opsrc[s] + pbase + 4 * u), OPS + (b * (2 + kMaxE) + s) * OPB + 1024 * blk);
+        }
+    };
+    stage_ops(0, 0);
+    for (int p0 = 0; p0 < 2 * RG; p0++) {
         const int prow = row_base + 32 * p0;  // first row of the pass
-        const int rows_p = (nct - prow < 32 * spp ? nct - prow : 32 * spp);
-        const int pw = rows_p > 0 ? rows_p * W : 0;  // words of the pass per operand
-        uint32_t el[EPT][4], er[EPT][4];
+        if (prow >= nct) break;               // (the same for every thread)
+        const int b = p0 & 1;
+        // this pass's operands in LDS (each wave waits for its own loads, and
+        // its stores of the pass before); the pass before is done with S,
+        // Cq and the other buffer
+        wait_vmcnt<0>();
+        lds_barrier();
+        if (p0 + 1 < 2 * RG && prow + 32 < nct) stage_ops(p0 + 1, b ^ 1);
+        // 1. column sums: column c of row rl at word c / 4 (16-byte units
+        // permuted as mfma_sum_unit), byte c % 4
 #pragma unroll
-        for (int i = 0; i < EPT; i++) {
-            const int f4 = 4 * (tid + i * THREADS);
+        for (int f = 0; f < 2; f++) {
+            if (2 * wr + f != p0) continue;
 #pragma unroll
-            for (int u = 0; u < 4; u++) el[i][u] = er[i][u] = 0u;
-            if (f4 < pw) {
-                const gword* lp = Lp + (size_t)prow * W + f4;
-                const gword* rp = Rp + (size_t)prow * W + f4;
-                if (quads) {
-                    const u32x4 a = *reinterpret_cast<const gu32x4*>(lp);
-                    const u32x4 b = *reinterpret_cast<const gu32x4*>(rp);
+            for (int q = 0; q < CF; q++) {
+                const int fi = wc * CF + q;
+                if (fi < NF) {
+                    const int col = 32 * fi + (lane & 31);
+                    const int cu = 4 * mfma_sum_unit(col >> 2) + (col & 3);
 #pragma unroll
-                    for (int u = 0; u < 4; u++) el[i][u] = a[u], er[i][u] = b[u];
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; u++)
-                        if (f4 + u < pw) el[i][u] = lp[u], er[i][u] = rp[u];
+                    for (int r = 0; r < 16; r++) S[(8 * (r >> 2) + 4 * half + (r & 3)) * SP + cu] = acc[f][q][r];
                 }
             }
         }
+        lds_barrier();
+        // 2. limbs of every output, rippled within the quad
+        const uint8_t* ob = OPS + b * (2 + kMaxE) * OPB;
+        u32x4 oq[EPT][kMaxOut];
+        // per quad: bit u (0..3) = word u starts an element, bit 4 = a quad
+        // of the pass, bit 5 = its last word ends an element
+        int qv[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; i++) {
+            const int j = tid + i * THREADS, fw = 4 * j;
+            qv[i] = 0;
+#pragma unroll
+            for (int o = 0; o < kMaxOut; o++) oq[i][o] = u32x4{0u, 0u, 0u, 0u};
+            if (j >= QP) continue;
+            int rl = fw / W, w = fw - rl * W;
+            int e = w / kw, l = w - e * kw;
+            int row = prow + rl;
+            int br = row / kb, tr = row - br * kb;
+            int cpc = 128 * Pc[32 * p0 + rl];  // each byte sum misses 128 per set bit of the row of L
+            const u32x4 lv = *reinterpret_cast<const u32x4*>(ob + 16 * j);
+            const u32x4 rv = *reinterpret_cast<const u32x4*>(ob + OPB + 16 * j);
+            u32x4 ev[kMaxE];
+#pragma unroll
+            for (int q = 0; q < kMaxE; q++)
+                ev[q] = q + 2 < nops ? *reinterpret_cast<const u32x4*>(ob + (2 + q) * OPB + 16 * j)
+                                     : u32x4{0u, 0u, 0u, 0u};
+            int64_t cy[kMaxOut];
+#pragma unroll
+            for (int o = 0; o < kMaxOut; o++) cy[o] = 0;
+            int qm = 1 << 4;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (u > 0) {
+                    ++w, ++l;
+                    if (l == kw) l = 0, ++e;
+                    if (w == W) {
+                        w = 0, e = 0, l = 0, ++rl, ++row, ++tr;
+                        if (tr == kb) tr = 0, ++br;
+                        cpc = 128 * Pc[32 * p0 + rl];
+                    }
+                }
+                if (l == 0) {
+                    qm |= 1 << u;
+#pragma unroll
+                    for (int o = 0; o < kMaxOut; o++) cy[o] = 0;
+                }
+                const i32x4 s4 = *reinterpret_cast<const i32x4*>(S + rl * SP + 4 * mfma_sum_unit(w));
+                const int s0 = s4[0] + cpc, s1 = s4[1] + cpc, s2 = s4[2] + cpc, s3 = s4[3] + cpc;
+                const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
+                const int Ll = lv[u] & 0xFFFF, Lh = lv[u] >> 16, Rl = rv[u] & 0xFFFF, Rh = rv[u] >> 16;
+                const int Gl = Gv & 0xFFFF, Gh = Gv >> 16;
+#pragma unroll
+                for (int o = 0; o < kMaxOut; o++) {
+                    if (o < nout) {
+                        // P's limb = s0 + 2^8 s1 + 2^16 (s2 + 2^8 s3) with the byte sums
+                        // s below 2^20, so every partial sum stays below 2^31
+                        int A = __mul24(cPo[o], s0) + (__mul24(cPo[o], s1) << 8) + __mul24(cLo[o], Ll) +
+                                __mul24(cRo[o], Rl) + __mul24(cGo[o], Gl);
+                        int B = __mul24(cPo[o], s2) + (__mul24(cPo[o], s3) << 8) + __mul24(cLo[o], Lh) +
+                                __mul24(cRo[o], Rh) + __mul24(cGo[o], Gh);
+                        if (eso[o] >= 0) {
+                            const uint32_t x = eso[o] == 0 ? ev[0][u] : ev[kMaxE - 1][u];
+                            A += __mul24(cEo[o], (int)(x & 0xFFFF));
+                            B += __mul24(cEo[o], (int)(x >> 16));
+                        }
+                        const int64_t v = cy[o] + (int64_t)A + (int64_t)B * 65536;
+                        oq[i][o][u] = (uint32_t)v;
+                        cy[o] = v >> 32;
+                    }
+                }
+            }
+            if (l == kw - 1) qm |= 1 << 5;
+            qv[i] = qm;
+#pragma unroll
+            for (int o = 0; o < kMaxOut; o++)
+                if (o < nout) Cq[o * QP + j] = (qm >> 5) ? 0 : (int32_t)cy[o];  // |carry| < 2^15
+        }
+        lds_barrier();
+        // 3. carries between quads, until none leaves a quad (a thread that
+        // passes one on marks the round in `more`; round numbers grow over
+        // the passes, so the mark needs no clearing)
+        for (;;) {
+            ++round;
+            int32_t cin[EPT][kMaxOut];
+#pragma unroll
+            for (int i = 0; i < EPT; i++) {
+                const int j = tid + i * THREADS;
+#pragma unroll
+                for (int o = 0; o < kMaxOut; o++)
+                    cin[i][o] = (o < nout && qv[i] && !(qv[i] & 1)) ? Cq[o * QP + j - 1] : 0;
+            }
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < EPT; i++) {
+                if (!qv[i]) continue;
+                const int j = tid + i * THREADS;
+#pragma unroll
+                for (int o = 0; o < kMaxOut; o++) {
+                    if (o >= nout) continue;
+                    int64_t c = cin[i][o];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        if (u > 0 && (qv[i] >> u & 1)) c = 0;  // a new element: the carry stops
+                        const int64_t v = (int64_t)oq[i][o][u] + c;
+                        oq[i][o][u] = (uint32_t)v;
+                        c = v >> 32;
+                    }
+                    if (qv[i] >> 5) c = 0;
+                    Cq[o * QP + j] = (int32_t)c;
+                    if (c != 0) *more = round;
+                }
+            }
+            lds_barrier();
+            if (*more != round) break;
+        }
+        // 4. outputs
+        const size_t pbase = (size_t)prow * W;
+#pragma unroll
+        for (int i = 0; i < EPT; i++) {
+            if (!qv[i]) continue;
+            const int fw = 4 * (tid + i * THREADS);
+#pragma unroll
+            for (int o = 0; o < kMaxOut; o++)
+                if (o < nout) *reinterpret_cast<gu32x4*>(Do[o] + pbase + fw) = oq[i][o];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The matrix-core product with 256 threads and little LDS, so that two
+// workgroups share a CU and one's epilogue (carry chains: VALU, LDS and
+// memory latency) runs while the other's matrix cores are busy.
+//
+// A product's rows go in tiles of 128, and its row of n + 1 elements in
+// column splits of mfma2_eps(g, CF) whole elements (one split, the whole row,
+// where it fits 64 CF byte columns); a workgroup owns one tile of one split.
+// The carry chains run within an element, so the splits are independent.
+// Waves: 2 x 2; wave (wr, wc) owns rows 64 wr .. 64 wr + 63 of the tile (two
+// 32-row A fragments) and the split's 32-column fragments wc CF .. wc CF +
+// CF - 1.  R comes in the 64-row chunk layout of k_rtrans<64> (a column's 64
+// bytes contiguous, its 16-byte units permuted by swz64), the split's 1 KB
+// units of it straight from global memory into LDS three chunks deep, with
+// the chunk's 64 bits of each tile row of L; one barrier per chunk.  The
+// epilogue is that of k_product_mfma in passes of 16 rows.
+template <int CF>
+__global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
+                                                           ProdItem one, int lds_bytes)
+{
+    constexpr int RG = 2, CG = 2, NW = RG * CG, THREADS = 64 * NW, TM = 64 * RG, KC = 64;
+    constexpr int PR = 16;                  // rows per epilogue pass
+    constexpr int UT = 2 * CG * CF;         // 1 KB units of a chunk a tile reads
+    constexpr int DR = (UT + NW - 1) / NW;  // of them per wave
+    constexpr int SP = mfma_sum_pitch(CG * CF);
+    constexpr int D = mfma2_depth(CF);      // chunks in flight (D - 1 ahead of the one multiplied)
+    (void)lds_bytes;
+    extern __shared__ uint32_t lds[];
+    const uint32_t v = xcd_order(blockIdx.x, gridDim.x);
+    ProdSeg sg0 = seg0;
+    if (nseg > 1) sg0 = segs[find_segment(segs, nseg, v, [](const ProdSeg& q) { return q.first_block; })];
+    // the segment and the item are the same for the whole workgroup: scalar
+    // registers keep the vector ones for the accumulators
+    const ProdSeg sg = wave_uniform(sg0);
+    const Geo g = sg.geo;
+    const int W = g.W, nct = g.nct, kw = g.kw, kb = g.k;
+    const int eps = mfma2_eps(g, CF);  // (> 0: the host launches only geometries it serves)
+    const int cs = (g.n1 + eps - 1) / eps;
+    const uint32_t tiles = ((uint32_t)nct + TM - 1) / TM * cs;
+    const uint32_t local = v - sg.first_block;
+    const uint32_t yl = local / tiles;
+    const int rem = (int)(local % tiles);
+    const int row_base = rem / cs * TM;
+    const int split = rem % cs;
+    const bool whole = cs == 1;
+    const int e0 = split * eps;
+    const int ww = whole ? W : (g.n1 - e0 < eps ? g.n1 - e0 : eps) * kw;  // words of the split per row
+    const int w0 = e0 * kw;                                                 // its first word (a multiple of 4)
+    const Bufs bufs = sg.bufs;
+    const ProdItem it = wave_uniform(sg.items ? load_global(sg.items + yl) : one);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave % RG, wc = wave / RG;
+    const int half = lane >> 5;
+    const int NF = (4 * W + 31) / 32;
+    const int gsz = NF * 32 * KC;  // bytes per chunk of R in global memory
+    const int nchunks = (nct + KC - 1) / KC;
+    const gword* Lp = ctp(bufs, it.L);
+    const gword* Rp = ctp(bufs, it.R);
+    const int QP = PR * (ww / 4);                   // quads of words of an epilogue pass
+    const int OPB = (16 * QP + 1023) / 1024 * 1024;     // LDS bytes of one operand's quads
+    const int main_bytes = mfma2_main_bytes(CF);
+    const int e_bytes = mfma2_epi_bytes(CF, QP);
+    int32_t* Pc = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) + (main_bytes > e_bytes ? main_bytes : e_bytes));
+
+    // ---- main loop ----
+    uint8_t* Rb = reinterpret_cast<uint8_t*>(lds);  // D chunks of the split's columns of R
+    uint8_t* Lb = Rb + D * UT * 1024;               // D chunks of L: 8 bytes (64 bits) per tile row
+    const uint8_t* rsrc = sg.rt + (size_t)yl * rt_item_bytes(g);
+    const uint8_t* Lbytes = (const uint8_t*)Lp;
+    const int u0 = w0 / 4;  // the split's first unit (16 columns) of a chunk
+    // Every wave issues DR + 1 requests per chunk (units past the row repeat
+    // its last unit, rows past the product its last row, words past the row
+    // its last word: all in bounds), so that the wait is a constant count.
+    auto request = [&](int c) {
+        const int buf = c % D;
+        const uint8_t* src = rsrc + (size_t)c * gsz;
+        uint8_t* dst = Rb + buf * UT * 1024;
+#pragma unroll
+        for (int t = 0; t < DR; t++) {
+            const int lu = wave + NW * t < UT ? wave + NW * t : UT - 1;
+            const int su = u0 + lu < 2 * NF ? u0 + lu : 2 * NF - 1;
+            load_to_lds<16>(src + (size_t)su * 1024 + lane * 16, dst + lu * 1024);
+        }
+        int row = row_base + 32 * wave + (lane >> 1);  // rows 32 wave .. 32 wave + 31 of the tile, 2 words each
+        row = row < nct ? row : nct - 1;
+        int word = 2 * c + (lane & 1);
+        word = word < W ? word : W - 1;
+        load_to_lds<4>(Lbytes + ((size_t)row * W + word) * 4, Lb + buf * TM * 8 + wave * 256);
+    };
+    i32x16 acc[2][CF];
+#pragma unroll
+    for (int f = 0; f < 2; f++)
+#pragma unroll
+        for (int q = 0; q < CF; q++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[f][q][r] = 0;
+    // B fragment q of this lane: the split's column 32 (wc CF + q) + lane %
+    // 32, at bcol + 2048 q; its unit permutation swz64 is the same for every
+    // q (the split starts on a multiple of 16 columns).  Columns past the
+    // split are read from in-bounds LDS and their sums never used.
+    const int bcol = (32 * wc * CF + (lane & 31)) * KC;
+    const int bswz = swz64(lane & 31);
+    const int arow8 = (64 * wr + (lane & 31)) * 8;  // A fragment f: + 256 f
+    uint32_t pc[2] = {0u, 0u};
+
+#pragma unroll
+    for (int c = 0; c < D - 1; c++)
+        if (c < nchunks) request(c);
+    for (int c = 0; c < nchunks; c++) {
+        // chunk c has landed once at most the requests of the chunks after it
+        // are outstanding (every chunk's are DR + 1 per wave)
+        const int later = nchunks - 1 - c < D - 2 ? nchunks - 1 - c : D - 2;
+        wait_vmcnt_upto<(D - 2) * (DR + 1), DR + 1>(later);
+        barrier_only();
+        if (c + D - 1 < nchunks) request(c + D - 1);
+        const uint8_t* Bc = Rb + (c % D) * UT * 1024;
+        const uint8_t* Lc = Lb + (c % D) * TM * 8;
+        const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
+        uint32_t lw[2][2];
 #pragma unroll
         for (int f = 0; f < 2; f++) {
-            const int slab = 2 * wr + f;
-            if (slab >= p0 && slab < p0 + spp) {
+            // (two 4-byte reads: an 8-byte read here makes the compiler wait
+            // for every outstanding load into LDS, the chunks in flight too)
+            lw[f][0] = *reinterpret_cast<const uint32_t*>(Lc + arow8 + 256 * f);
+            lw[f][1] = *reinterpret_cast<const uint32_t*>(Lc + arow8 + 256 * f + 4);
+        }
+#pragma unroll
+        for (int st = 0; st < KC / 32; st++) {
+            const uint8_t* bp = Bc + bcol + 16 * ((2 * st + half) ^ bswz);
+            i32x4 Bx[CF];
+#pragma unroll
+            for (int q = 0; q < CF; q++) Bx[q] = *reinterpret_cast<const i32x4*>(bp + 2048 * q);
+            i32x4 Af[2];
+#pragma unroll
+            for (int f = 0; f < 2; f++) {
+                // bits of L past the product (rows of R past Nct) count as 0
+                const uint32_t w = 32 * st < rows_c ? lw[f][st] : 0u;
+                const uint32_t b16 = (w >> (16 * half)) & 0xFFFFu;
+                pc[f] += __builtin_popcount(b16);
+                Af[f] = spread_bits(b16);
+            }
+#pragma unroll
+            for (int q = 0; q < CF; q++) {
+                acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[0], Bx[q], acc[0][q], 0, 0, 0);
+                acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[1], Bx[q], acc[1][q], 0, 0, 0);
+            }
+        }
+    }
+    // every wave done with the chunk buffers before the epilogue reuses them;
+    // the popcount of a row is the sum over its two half-lanes
+    lds_barrier();
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+        const uint32_t tot = pc[f] + __shfl_xor(pc[f], 32);
+        if (wc == 0 && half == 0) Pc[64 * wr + 32 * f + (lane & 31)] = (int32_t)tot;
+    }
+
+    // ---- epilogue: passes of PR = 16 rows (see k_product_mfma) ----
+    const int nout = it.nout;
+    int eso[kMaxOut];
+    gword* Do[kMaxOut];
+    const gword* opsrc[2 + kMaxE] = {Lp, Rp};
+    int32_t eref[kMaxE];
+    int nops = 2;
+#pragma unroll
+    for (int o = 0; o < kMaxOut; o++) {
+        Do[o] = o < nout ? ctp(bufs, it.dst[o]) : nullptr;
+        eso[o] = -1;
+        if (o < nout && it.E[o] >= 0) {
+#pragma unroll
+            for (int q = 0; q < kMaxE; q++)
+                if (q + 2 < nops && eref[q] == it.E[o]) eso[o] = q;
+            if (eso[o] < 0 && nops < 2 + kMaxE) {  // (the plan keeps at most kMaxE per item)
+                eref[nops - 2] = it.E[o];
+                opsrc[nops] = ctp(bufs, it.E[o]);
+                eso[o] = nops - 2;
+                ++nops;
+            }
+        }
+    }
+    // Each wave takes whole rows of a pass (rpw of them, the qr quads of 4
+    // words of a row in consecutive lanes; the host serves only geometries
+    // whose split rows are whole quads, at most 16), so the carries between
+    // quads pass from lane to lane, with no LDS and no barrier.
+    const int qr = ww / 4;  // quads per row of the split
+    const int rpw = 64 / qr;
+    const int rw_rl = wave * rpw + lane / qr;  // this lane's row of a pass
+    const int rw_jj = lane % qr;              // and quad of the row
+    const bool rw_ok = lane < rpw * qr && rw_rl < PR;
+    const int rw_w = w0 + 4 * rw_jj;  // its first word
+    const int rw_e = rw_w / kw, rw_l = rw_w - rw_e * kw;
+    int32_t* S = reinterpret_cast<int32_t*>(lds);
+    uint8_t* OPS = reinterpret_cast<uint8_t*>(S + PR * SP);  // 2 buffers x (2 + kMaxE) operands
+    // every operand's quads of pass p into buffer b, 64 quads per wave
+    // instruction (lanes past the pass re-read its last quad and land in the
+    // buffer's padding)
+    auto stage_ops = [&](int p, int b) {
+        for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < QP; blk += NW) {
+            const int j = 64 * blk + lane < QP ? 64 * blk + lane : QP - 1;
+            const int rl = j / qr;
+            const size_t off = (size_t)(row_base + PR * p + rl) * W + w0 + 4 * (j - rl * qr);
+#pragma unroll
+            for (int s = 0; s < 2 + kMaxE; s++)
+                if (s < nops)
+                    load_to_lds<16>((const uint8_t*)(opsrc[s] + off), OPS + (b * (2 + kMaxE) + s) * OPB + 1024 * blk);
+        }
+    };
+    // store instructions this wave issues per pass: one per output, where
+    // any of its lanes holds a quad
+    const int nst = wave * rpw < PR ? nout : 0;
+    stage_ops(0, 0);
+    const int npass = (nct - row_base < TM ? nct - row_base : TM) / PR;  // Nct is a multiple of 32
+    for (int p = 0; p < npass; p++) {
+        const int prow = row_base + PR * p;  // first row of the pass
+        const int b = p & 1;
+        // this pass's operands in LDS: each wave waits for its own loads of
+        // them, issued before its stores of the pass before, which need not
+        // be done; the pass before is done with S and the other buffer
+        wait_vmcnt_upto<kMaxOut, 1>(p > 0 ? nst : 0);
+        lds_barrier();
+        if (p + 1 < npass) stage_ops(p + 1, b ^ 1);
+        // 1. column sums of the pass's rows: rows 16 h .. 16 h + 15 of
+        // fragment f of row group wr, i.e. its registers r = 8 h .. 8 h + 7
+#pragma unroll
+        for (int f = 0; f < 2; f++) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                if (p != 4 * wr + 2 * f + h) continue;
 #pragma unroll
                 for (int q = 0; q < CF; q++) {
-                    const int fi = wc * CF + q;
-                    if (fi < NF) {
-                        const int col = 32 * fi + (lane & 31);
+                    const int col = 32 * (wc * CF + q) + (lane & 31);  // of the split
+                    if (col < 4 * ww) {
+                        const int cu = 4 * mfma_sum_unit(col >> 2) + (col & 3);
 #pragma unroll
-                        for (int r = 0; r < 16; r++) {
-                            const int rl = 32 * (slab - p0) + 8 * (r >> 2) + 4 * half + (r & 3);
-                            S[rl * SP + col] = acc[f][q][r];
+                        for (int r = 8 * h; r < 8 * h + 8; r++)
+                            S[(8 * ((r >> 2) - 2 * h) + 4 * half + (r & 3)) * SP + cu] = acc[f][q][r];
+                    }
+                }
+            }
+        }
+        lds_barrier();
+        const uint8_t* ob = OPS + b * (2 + kMaxE) * OPB;
+        {
+            // 2. this lane's quad (row rw_rl, words rw_w ..): limbs of every
+            // output rippled within the quad, kept in registers
+            u32x4 oq[kMaxOut];
+            int32_t cq[kMaxOut];
+            int qm = 0;
+#pragma unroll
+            for (int o = 0; o < kMaxOut; o++) oq[o] = u32x4{0u, 0u, 0u, 0u}, cq[o] = 0;
+            if (rw_ok) {
+                const int j = rw_rl * qr + rw_jj;  // the quad's place in the staged operands
+                int w = rw_w, e = rw_e, l = rw_l;
+                const int row = prow + rw_rl;
+                const int br = row / kb, tr = row - br * kb;
+                const int cpc = 128 * Pc[PR * p + rw_rl];  // each byte sum misses 128 per set bit of the row of L
+                const u32x4 lv = *reinterpret_cast<const u32x4*>(ob + 16 * j);
+                const u32x4 rv = *reinterpret_cast<const u32x4*>(ob + OPB + 16 * j);
+                u32x4 ev[kMaxE];
+#pragma unroll
+                for (int q = 0; q < kMaxE; q++)
+                    ev[q] = q + 2 < nops ? *reinterpret_cast<const u32x4*>(ob + (2 + q) * OPB + 16 * j)
+                                         : u32x4{0u, 0u, 0u, 0u};
+                int64_t cy[kMaxOut];
+#pragma unroll
+                for (int o = 0; o < kMaxOut; o++) cy[o] = 0;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (u > 0) {
+                        ++w, ++l;
+                        if (l == kw) l = 0, ++e;
+                    }
+                    if (l == 0) {
+                        qm |= 1 << u;
+#pragma unroll
+                        for (int o = 0; o < kMaxOut; o++) cy[o] = 0;
+                    }
+                    const i32x4 s4 = *reinterpret_cast<const i32x4*>(S + rw_rl * SP + 4 * mfma_sum_unit(w - w0));
+                    const int s0 = s4[0] + cpc, s1 = s4[1] + cpc, s2 = s4[2] + cpc, s3 = s4[3] + cpc;
+                    const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
+                    const int Ll = lv[u] & 0xFFFF, Lh = lv[u] >> 16, Rl = rv[u] & 0xFFFF, Rh = rv[u] >> 16;
+                    const int Gl = Gv & 0xFFFF, Gh = Gv >> 16;
+#pragma unroll
+                    for (int o = 0; o < kMaxOut; o++) {
+                        if (o < nout) {
+                            // P's limb = s0 + 2^8 s1 + 2^16 (s2 + 2^8 s3) with the byte sums
+                            // s below 2^20, so every partial sum stays below 2^31
+                            const int cP = it.cP[o], cL = it.cL[o], cR = it.cR[o], cG = it.cG[o];
+                            int A = __mul24(cP, s0) + (__mul24(cP, s1) << 8) + __mul24(cL, Ll) + __mul24(cR, Rl) +
+                                    __mul24(cG, Gl);
+                            int B = __mul24(cP, s2) + (__mul24(cP, s3) << 8) + __mul24(cL, Lh) + __mul24(cR, Rh) +
+                                    __mul24(cG, Gh);
+                            if (eso[o] >= 0) {
+                                const uint32_t x = eso[o] == 0 ? ev[0][u] : ev[kMaxE - 1][u];
+                                A += __mul24((int)it.cE[o], (int)(x & 0xFFFF));
+                                B += __mul24((int)it.cE[o], (int)(x >> 16));
+                            }
+                            const int64_t vv = cy[o] + (int64_t)A + (int64_t)B * 65536;
+                            oq[o][u] = (uint32_t)vv;
+                            cy[o] = vv >> 32;
                         }
                     }
                 }
-            }
-        }
+                if (l == kw - 1) qm |= 1 << 5;
 #pragma unroll
-        for (int i = 0; i < EPT; i++) {
-            const int f4 = 4 * (tid + i * THREADS);
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int fw = f4 + u;
-                if (fw < pw) {
-                    const int rl = fw / W, w = fw - rl * W;
-                    Le[rl * LP + w] = el[i][u];
-                    Re[rl * LP + w] = er[i][u];
-                }
+                for (int o = 0; o < kMaxOut; o++) cq[o] = (qm >> 5) ? 0 : (int32_t)cy[o];  // |carry| < 2^15
             }
-        }
-        __syncthreads();
-        // the chains of the pass, each cut into G runs of limbs when that keeps
-        // more threads busy: run gs starts from carry 0 and records its carry
-        // out; then one thread per (row, element, output) ripples each run's
-        // carry into the next run (it stops at the first limb that absorbs it)
-        const int nchain = rows_p > 0 ? rows_p * g.n1 : 0;
-        int G = 1;
-        while (G < 4 && 2 * G * nchain <= THREADS && 2 * G <= g.kw) G *= 2;
-        const int run = (g.kw + G - 1) / G;
-        for (int tk = tid; tk < nchain * G; tk += THREADS) {
-            const int ch = tk % nchain, gs = tk / nchain;
-            const int rl = ch % rows_p, e = ch / rows_p;
-            const int lb = gs * run, le = lb + run < g.kw ? lb + run : g.kw;
-            finish_bytes(bufs, g, it, S + rl * SP + e * 4 * g.kw, Pc[32 * p0 + rl], Le + rl * LP + e * g.kw,
-                         Re + rl * LP + e * g.kw, prow + rl, e, lb, le, G > 1 ? Cy + 4 * tk : nullptr);
-        }
-        __syncthreads();
-        if (G > 1) {
-            for (int tk = tid; tk < nchain * it.nout; tk += THREADS) {
-                const int ch = tk % nchain, o = tk / nchain;
-                const int rl = ch % rows_p, e = ch / rows_p;
-                int32_t* orow = S + rl * SP + e * 4 * g.kw + o;  // limb l of output o at orow[4 l]
-                int64_t c = 0;
-                for (int gs = 0; gs < G; gs++) {
-                    const int lb = gs * run, le = lb + run < g.kw ? lb + run : g.kw;
-                    if (lb >= le) break;
-                    for (int l = lb; l < le && c != 0; l++) {
-                        const int64_t v = (int64_t)(uint32_t)orow[4 * l] + c;
-                        orow[4 * l] = (int32_t)(uint32_t)v;
-                        c = v >> 32;
+            // 3. each quad takes the carry out of the lane before it (the
+            // quad before it in the row) unless it starts an element; until
+            // no carry leaves a quad
+            for (;;) {
+                int more_here = 0;
+#pragma unroll
+                for (int o = 0; o < kMaxOut; o++) {
+                    if (o >= nout) continue;
+                    int32_t c = __shfl_up(cq[o], 1);
+                    if (!rw_ok || (qm & 1)) c = 0;
+                    int64_t cc = c;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        if (u > 0 && (qm >> u & 1)) cc = 0;  // a new element: the carry stops
+                        const int64_t vv = (int64_t)oq[o][u] + cc;
+                        oq[o][u] = (uint32_t)vv;
+                        cc = vv >> 32;
                     }
-                    c += Cy[4 * (gs * nchain + ch) + o];
+                    cq[o] = (qm >> 5) ? 0 : (int32_t)cc;
+                    more_here |= cq[o] != 0;
                 }
+                if (!__any(more_here)) break;
             }
-            __syncthreads();
-        }
-        gword* dst[kMaxOut];
+            // 4. outputs
+            if (rw_ok) {
+                const size_t off = (size_t)(prow + rw_rl) * W + rw_w;
 #pragma unroll
-        for (int o = 0; o < kMaxOut; o++) dst[o] = o < it.nout ? ctp(bufs, it.dst[o]) + (size_t)prow * W : nullptr;
-        for (int fw = tid; fw < pw; fw += THREADS) {
-            const int rl = fw / W, w = fw - rl * W;
-            const i32x4 v4 = *reinterpret_cast<const i32x4*>(S + rl * SP + 4 * w);
-#pragma unroll
-            for (int o = 0; o < kMaxOut; o++)
-                if (dst[o]) dst[o][fw] = (uint32_t)v4[o];
+                for (int o = 0; o < kMaxOut; o++)
+                    if (o < nout) *reinterpret_cast<gu32x4*>(Do[o] + off) = oq[o];
+            }
         }
     }
 }
@@ -1276,6 +1751,20 @@ hipError_t launch_mfma_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
     return hipGetLastError();
 }
 
+template <int CF>
+hipError_t launch_mfma2_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                          const ProdItem& one, int64_t blocks, hipStream_t s)
+{
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)k_product_mfma2<CF>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_product_mfma2<CF>), dim3((unsigned)blocks), dim3(256), cfg.lds_bytes, s, d_segs, nseg, seg0,
+                       one, cfg.lds_bytes);
+    return hipGetLastError();
+}
+
 // Tilings: (threads, lanes per row, digit slots per lane, rows per lane,
 // lookup pipeline depth, 4-bit groups per chunk).  The first kDefaultTilings
 // are the defaults, one per width class; the rest are alternatives the tuner
@@ -1307,7 +1796,10 @@ constexpr int kDefaultTilings = 5;
 // group CF of them (the last fewer).
 struct MfmaTiling {
     int rg, cgw, cf;
-    bool pre;  // right operands transposed by k_rtrans before the launch
+    // right operands transposed by k_rtrans before the launch: 0 no, 1 into
+    // 128-row chunks (k_product_mfma), 2 into 64-row chunks (the 256-thread
+    // k_product_mfma2, two workgroups per CU)
+    int pre;
 };
 constexpr MfmaTiling kMfmaTilings[] = {
     {2, 4, 1, false}, {2, 4, 2, false}, {2, 4, 3, false},  // 512 threads, 128-row tiles
@@ -1316,6 +1808,8 @@ constexpr MfmaTiling kMfmaTilings[] = {
     {4, 2, 2, false}, {4, 2, 3, false}, {4, 2, 4, false},  // 512 threads, 256-row tiles
     {2, 4, 1, true},  {2, 4, 2, true},  {2, 4, 3, true},   // the same with a transposition pass
     {4, 2, 2, true},  {4, 2, 3, true},  {4, 2, 4, true},
+    {2, 2, 1, 2},     {2, 2, 2, 2},     {2, 2, 3, 2},      // 256 threads, 64-row chunks, <= 80 KB of LDS
+    {2, 2, 4, 2},
 };
 constexpr int kNumMfmaTilings = (int)(sizeof(kMfmaTilings) / sizeof(kMfmaTilings[0]));
 constexpr int kNumTilings = kNumLookupTilings + kNumMfmaTilings;
@@ -1325,8 +1819,10 @@ hipError_t dispatch_mfma(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
 {
 #define MCASE(I)                                                                                         \
     if (cfg.tiling == kNumLookupTilings + I)                                                             \
-        return launch_mfma_t<kMfmaTilings[I].rg, kMfmaTilings[I].cgw, kMfmaTilings[I].cf, kMfmaTilings[I].pre>( \
-            cfg, d_segs, nseg, seg0, one, blocks, s);
+        return launch_mfma_t<kMfmaTilings[I].rg, kMfmaTilings[I].cgw, kMfmaTilings[I].cf,                 \
+                             kMfmaTilings[I].pre == 1>(cfg, d_segs, nseg, seg0, one, blocks, s);
+#define MCASE2(I)                                                                                        \
+    if (cfg.tiling == kNumLookupTilings + I) return launch_mfma2_t<kMfmaTilings[I].cf>(cfg, d_segs, nseg, seg0, one, blocks, s);
     MCASE(0)
     MCASE(1)
     MCASE(2)
@@ -1345,8 +1841,13 @@ hipError_t dispatch_mfma(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
     MCASE(15)
     MCASE(16)
     MCASE(17)
+    MCASE2(18)
+    MCASE2(19)
+    MCASE2(20)
+    MCASE2(21)
 #undef MCASE
-    static_assert(kNumMfmaTilings == 18, "one MCASE per matrix-core tiling");
+#undef MCASE2
+    static_assert(kNumMfmaTilings == 22, "one MCASE per matrix-core tiling");
     return hipErrorInvalidValue;
 }
 
@@ -1409,12 +1910,12 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
 {
     const MfmaTiling& t = kMfmaTilings[ti - kNumLookupTilings];
     const int nf = (4 * g.W + 31) / 32;
-    if ((nf + t.cgw - 1) / t.cgw != t.cf) return false;
+    if (t.pre != 2 && (nf + t.cgw - 1) / t.cgw != t.cf) return false;
     // the staging blocks of a chunk (32 row quads x ceil(W/4) word quads,
     // 8 x 8 per wave) fit the threads' blocks
     const int threads = t.rg * t.cgw * 64;
     const int spt = (kMfmaChunk / 4 * 2 * t.cgw * t.cf + threads - 1) / threads;
-    if (4 * ((g.W + 31) / 32) > spt * threads / 64) return false;
+    if (t.pre != 2 && 4 * ((g.W + 31) / 32) > spt * threads / 64) return false;
     *cfg = ProdCfg{};
     cfg->tiling = ti;
     cfg->mfma = true;
@@ -1426,18 +1927,31 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
     cfg->tr = 64 * t.rg;
     cfg->nd = (g.k + kDigitBits - 1) / kDigitBits;
     cfg->wd = g.n1 * cfg->nd;
-    // LDS: two chunks of R by columns, then per epilogue pass spp slabs of 32
-    // rows of column sums (as many as the workgroup's share allows: all of a
-    // CU for 512 threads, half for 256), and a popcount per tile row
-    const int cap = cfg->threads >= 512 ? 160 * 1024 : 80 * 1024;
+    // LDS: the main loop's chunks, or the epilogue's slab of 32 rows of
+    // column sums and its carries between quads, and a popcount per tile row
     // (the transposition-pass tilings keep three chunks of R and of the bits
     // of L in flight, the others two chunks of R and of L as bytes)
+    // (the 256-thread kernel: three 64-row chunks of R and of the bits of L,
+    // or its epilogue's passes of 16 rows)
+    const int tail = cfg->tr * 4 + 16;  // popcounts, a flag
+    if (t.pre == 2) {
+        // column splits of whole elements (mfma2_eps), each filling more than
+        // 2 (CF - 1) of the tile's 2 CF fragments
+        const int eps = mfma2_eps(g, t.cf);
+        if (eps == 0 || nf > 12) return false;
+        const int cs = (g.n1 + eps - 1) / eps;
+        const int bytes = cs == 1 ? 4 * g.W : eps * g.k / 8;
+        if ((bytes + 31) / 32 <= 2 * (t.cf - 1)) return false;
+        const int ww = cs == 1 ? g.W : eps * g.kw;  // words of a split row
+        if (ww % 4 != 0 || ww / 4 > 16) return false;
+        const int qp = 16 * (ww / 4);
+        cfg->cs = cs;
+        cfg->lds_bytes = std::max(mfma2_main_bytes(t.cf), mfma2_epi_bytes(t.cf, qp)) + tail;
+        return cfg->lds_bytes <= 160 * 1024;
+    }
     const int chunks = t.pre ? 3 * nf * 32 * kMfmaPitch + 3 * cfg->tr * 16
                              : 2 * nf * 32 * kMfmaPitch + 2 * cfg->tr * kMfmaChunk;
-    const int slab = 32 * ((nf * 32 + 4) + 2 * (8 * ((g.W + 7) / 8) + 4)) * 4;
-    const int tail = cfg->tr * 4 + cfg->threads * 16;  // popcounts, chain-run carries
-    const int spp = std::max(chunks, 2 * slab) + tail <= cap ? 2 : 1;
-    cfg->lds_bytes = std::max(chunks, spp * slab) + tail;
+    cfg->lds_bytes = std::max(chunks, mfma_epi_bytes(nf, g.W)) + tail;
     return cfg->lds_bytes <= 160 * 1024;
 }
 }  // namespace
@@ -1492,11 +2006,12 @@ bool product_config(const Geo& g, ProdCfg* cfg)
         auto it = g_tuned.find({g.k, g.n1});
         if (it != g_tuned.end() && tiling_config(g, it->second, cfg)) return true;
     }
-    // matrix cores first (the plan tuner's choices on the workloads here):
+    // matrix cores first: the 256-thread kernel with two workgroups per CU
+    // where it serves the row (whole quads of words per split row), then
     // rows of up to 2 fragments on 256 threads, 3..8 on 256-row tiles with
     // the transposition pass, 9..12 on four column groups transposing
     // in-kernel
-    static const int order[] = {3, 15, 16, 17, 4, 0, 1, 2};
+    static const int order[] = {18, 19, 20, 21, 3, 15, 16, 17, 4, 0, 1, 2};
     for (int i : order)
         if (tiling_config(g, kNumLookupTilings + i, cfg)) return true;
     return lookup_config(g, cfg);
@@ -1511,21 +2026,31 @@ bool lookup_config(const Geo& g, ProdCfg* cfg)
 
 namespace {
 // the transposition of a launch's right operands (matrix-core tilings)
-hipError_t launch_rtrans(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                         const ProdItem& one, int64_t items, hipStream_t s)
+template <int KC>
+hipError_t launch_rtrans_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                           const ProdItem& one, int64_t items, hipStream_t s)
 {
-    constexpr int kMaxChunkBytes = 12 * 32 * kMfmaChunk;  // rows of up to 12 fragments
+    constexpr int kMaxChunkBytes = 12 * 32 * KC;  // rows of up to 12 fragments
     // once (thread-safe static initialisation)
     static const hipError_t attr =
-        hipFuncSetAttribute((const void*)k_rtrans, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxChunkBytes);
+        hipFuncSetAttribute((const void*)k_rtrans<KC>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxChunkBytes);
     if (attr != hipSuccess) return attr;
     if (items <= 0) return hipSuccess;
     if (items > 0x7FFFFFFF) return hipErrorInvalidValue;
-    // chunks of the widest row the tiling serves (Nct = 32 W <= 256 CG CF)
-    const unsigned chunks = (unsigned)((256 * cfg.cgw * cfg.cf + kMfmaChunk - 1) / kMfmaChunk);
-    hipLaunchKernelGGL(k_rtrans, dim3((unsigned)items, chunks), dim3(kRtransThreads), kMaxChunkBytes, s, d_segs, nseg,
-                       seg0, one);
+    // chunks of the widest row the tiling serves: Nct = 32 W <= 256 CG CF,
+    // or, split into whole elements, rows of up to 12 fragments (W <= 96)
+    const int max_nct = cfg.pre == 2 ? 32 * 96 : 256 * cfg.cgw * cfg.cf;
+    const unsigned chunks = (unsigned)((max_nct + KC - 1) / KC);
+    hipLaunchKernelGGL(k_rtrans<KC>, dim3((unsigned)items, chunks), dim3(kRtransThreads), kMaxChunkBytes, s, d_segs,
+                       nseg, seg0, one);
     return hipGetLastError();
+}
+
+hipError_t launch_rtrans(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                         const ProdItem& one, int64_t items, hipStream_t s)
+{
+    return cfg.pre == 2 ? launch_rtrans_t<64>(cfg, d_segs, nseg, seg0, one, items, s)
+                        : launch_rtrans_t<kMfmaChunk>(cfg, d_segs, nseg, seg0, one, items, s);
 }
 }  // namespace
 

@@ -249,30 +249,43 @@ Schedule lower(const Compact& c)
         if (li.X >= 0) li.X = home[li.X];
 
     // ---- items -----------------------------------------------------------------
+    // An item carries up to kMaxOut outputs of one product, whose extra
+    // operands are at most kMaxE distinct ciphertexts; the outputs of a
+    // product that need more take further items (the product is computed
+    // again).
     std::vector<std::vector<ProdItem>> prod_at(max_level + 1);
     for (int32_t p = 0; p < np; p++) {
         if (attached[p].empty()) continue;
         const auto& outs = attached[p];
-        for (size_t b0 = 0; b0 < outs.size(); b0 += kMaxOut) {
+        size_t k = 0;
+        while (k < outs.size()) {
             ProdItem it{};
             it.L = home[pl[p]];
             it.R = home[pr[p]];
             it.nout = 0;
-            for (size_t k = b0; k < outs.size() && k < b0 + kMaxOut; k++) {
+            int32_t eref[kMaxE];
+            int ne = 0;
+            for (; k < outs.size() && it.nout < kMaxOut; k++) {
                 const Form& f = form[outs[k]];
+                const int32_t e = f.nt == 1 ? home[f.tn[0]] : -1;
+                if (e >= 0) {
+                    bool seen = false;
+                    for (int q = 0; q < ne; q++) seen = seen || eref[q] == e;
+                    if (!seen) {
+                        if (ne == kMaxE) break;
+                        eref[ne++] = e;
+                    }
+                }
+                for (int c : {f.cL, f.cR, f.cP, f.cG, f.nt == 1 ? f.tc[0] : 0})
+                    if (c < -kMaxCoef || c > kMaxCoef) throw std::logic_error("gate coefficient out of range");
                 const int i = it.nout++;
                 it.dst[i] = home[outs[k]];
                 it.cL[i] = (int8_t)f.cL;
                 it.cR[i] = (int8_t)f.cR;
                 it.cP[i] = (int8_t)f.cP;
                 it.cG[i] = (int8_t)f.cG;
-                if (f.nt == 1) {
-                    it.E[i] = home[f.tn[0]];
-                    it.cE[i] = (int8_t)f.tc[0];
-                } else {
-                    it.E[i] = -1;
-                    it.cE[i] = 0;
-                }
+                it.E[i] = e;
+                it.cE[i] = (int8_t)(e >= 0 ? f.tc[0] : 0);
             }
             for (int i = it.nout; i < kMaxOut; i++) it.dst[i] = it.E[i] = -1;
             prod_at[plevel[p]].push_back(it);

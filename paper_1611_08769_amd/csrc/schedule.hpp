@@ -18,7 +18,9 @@
 
 namespace sfft {
 
-constexpr int kMaxOut = 4;  // epilogue outputs per product item
+constexpr int kMaxOut = 4;   // epilogue outputs per product item
+constexpr int kMaxE = 2;     // distinct extra operands per product item
+constexpr int kMaxCoef = 3;  // bound on |a|, |b|, |c|, |g|, |e| of every output form
 
 // Ciphertext reference: buffer in bits 31..29, index in bits 28..0.
 enum CtBuf : uint32_t { B_IN = 0, B_OUT = 1, B_WS = 2, B_AUX = 3 };
