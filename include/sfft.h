@@ -153,6 +153,17 @@ int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, cons
  * plan; the graph holds no memset nodes.  Same results as sfft_execute. */
 int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
                        int64_t ws_bytes, void* hip_stream);
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * as sfft_execute with the workspace in a fixed array of the library's own
+ * device memory, SFFT_NOALLOC_WS_BYTES (64 MiB) on each GPU it runs on, held
+ * until the process ends.  It allocates and frees nothing.  SFFT_ENOMEM if
+ * the plan's workspace (sfft_plan_workspace_bytes) is larger.  Every call on
+ * one GPU uses the same array, so calls that overlap on one GPU race:
+ * enqueue them on one stream, or let one finish before the next starts.
+ * Enqueues only. */
+#define SFFT_NOALLOC_WS_BYTES (64ll << 20)
+int sfft_execute_noalloc(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* hip_stream);
 /* Product items per step (counts has exec_steps entries). */
 int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n);
 

@@ -40,6 +40,7 @@ class sfft_plan_info(ctypes.Structure):
 
 
 SFFT_SERVER_DRYRUN = 1
+SFFT_NOALLOC_WS_BYTES = 64 << 20
 
 
 class sfft_server_cfg(ctypes.Structure):
@@ -103,6 +104,7 @@ _SIGS = {
     "sfft_server_submit": (ctypes.c_int, [_vp, _P(sfft_shape), _P(sfft_params), _vp, _vp, _P(ctypes.c_uint64)]),
     "sfft_server_submit_plan": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint64)]),
     "sfft_execute_graph": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "sfft_execute_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "sfft_tiling_count": (ctypes.c_int, []),
     "sfft_tiling_describe": (ctypes.c_int, [ctypes.c_int32, _P(ctypes.c_int32)]),
     "sfft_set_tiling": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32]),
@@ -211,6 +213,10 @@ def sfft_plan_destroy(plan: int) -> None:
 
 def sfft_execute(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
     _check(_lib.sfft_execute(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_execute_noalloc(plan, ct_in_ptr, ct_out_ptr, stream) -> None:
+    _check(_lib.sfft_execute_noalloc(plan, ct_in_ptr, ct_out_ptr, stream))
 
 
 def sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
