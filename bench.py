@@ -98,38 +98,75 @@ def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
     }
 
 
-def run_batch(args):
+def _mix_expect(kind):
+    """Expected decryptions of the batched or served mix: per request the
+    SHA-256 of the fixed-point emulation's output words, written by
+    tests/golden/make_mix_expect.py from the CPU oracle alone."""
+    with open(os.path.join(ROOT, "tests", "golden", "mix_decryptions.json")) as fh:
+        return json.load(fh)[kind]
+
+
+def _words_sha(words) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(np.asarray(words), dtype="<i8").tobytes()).hexdigest()
+
+
+def run_batch(args, count=None):
     """Independent 1D requests (length, word width and modulus differ per
-    request): all through the request loop at once vs one at a time."""
+    request), each encrypted right before it starts, its output decrypted
+    and checked against the expected decryptions (the fixed-point emulation,
+    stored by the oracle) as soon as it completes, its buffers freed then:
+    first one at a time, then all through the request loop, where they enter
+    in order while the ciphertexts of those in flight fit --io-gb.  Both
+    runs do the same encryptions and decryptions; each request's output
+    ciphertexts (first, middle and last) are compared between the two."""
+    import collections
+    import hashlib
     import torch
     from paper_1611_08769_amd import api
     from paper_1611_08769_amd import sfft as S
     from paper_1611_08769_amd import workloads as WL
 
     lengths = tuple(n for n in (8, 16, 32, 64, 128) if n <= args.max_len)
-    sigs = WL.batch_requests(seed=4, count=args.requests or 64, lengths=lengths)
+    count = count or args.requests or 256
+    sigs = WL.batch_requests(seed=4, count=count, lengths=lengths)
+    exp = _mix_expect("batch")
+    expect = (exp["requests"] if tuple(exp["lengths"]) == lengths and exp["seed"] == 4 and count <= exp["count"]
+              else None)
     reqs, plans = [], {}
-    for i, sig in enumerate(sigs):
+    for sig in sigs:
         p = api.size_params(1, sig.length, sig.F, sig.f, True, 1)
-        keys = api.keygen(p, 1000 + i)
-        ct_in = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=1000 + i)
         key = (sig.length, sig.F, p.k)
         if key not in plans:
             plans[key] = api.Plan(1, sig.length, sig.F, sig.f, True, p)
-        plan = plans[key]
-        ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
-        reqs.append((sig, p, plan, ct_in, ct_out))
-    # every distinct plan tuned once before the clock (the same plans run
-    # alone and in the batch)
+        reqs.append((sig, p, plans[key]))
+
+    def encrypt(i):
+        sig, p, plan = reqs[i]
+        keys = api.keygen(p, 1000 + i)
+        return keys, api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=1000 + i)
+
+    def finish(i, keys, ct_out):
+        sig = reqs[i][0]
+        dec = api.decrypt_words(keys, ct_out, 2 * sig.length, sig.F)
+        ok = expect is None or _words_sha(dec) == expect[i]["words_sha256"]
+        n = ct_out.shape[0]
+        fp = hashlib.sha256(ct_out[[0, n // 2, n - 1]].cpu().numpy().tobytes()).hexdigest()
+        return ok, fp
+
+    # every distinct plan tuned once before the clock, on an encryption of
+    # its first request (the same plans run alone and in the batch)
     tuned = {}
     if not args.no_tune:
-        done = set()
-        for sig, p, plan, ct_in, ct_out in reqs:
-            if id(plan) in done:
+        seen = set()
+        for i, (sig, p, plan) in enumerate(reqs):
+            if id(plan) in seen:
                 continue
-            done.add(id(plan))
-            best, _ = plan.tune(ct_in)
+            seen.add(id(plan))
+            _, ct = encrypt(i)
+            best, _ = plan.tune(ct)
             plan._ws = None
+            del ct
             tuned["%d/%d/k%d" % (sig.length, sig.F, p.k)] = list(S.sfft_tiling_describe(best))
         torch.cuda.empty_cache()
     torch.cuda.synchronize()
@@ -139,33 +176,65 @@ def run_batch(args):
     print("[bench] batch of %d requests: %d gates, %.2e bit-MACs, %d distinct plans" % (
         len(reqs), gates, bitmacs, len(plans)), file=sys.stderr, flush=True)
 
-    # one request at a time (same plans, same buffers)
+    # one request at a time (same plans)
+    ok_alone, fp_alone = [None] * len(reqs), [None] * len(reqs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for sig, p, plan, ct_in, ct_out in reqs:
+    for i, (sig, p, plan) in enumerate(reqs):
+        keys, ct_in = encrypt(i)
+        ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
         plan.execute(ct_in, ct_out)
         torch.cuda.synchronize()
+        ok_alone[i], fp_alone[i] = finish(i, keys, ct_out)
         plan._ws = None  # keep at most one plan workspace alive (stream-ordered reuse)
+        del ct_in, ct_out
     t_alone = time.perf_counter() - t0
     torch.cuda.empty_cache()
-    alone_out = [r[4].clone() for r in reqs]
     print("[bench] one at a time: %.2f s" % t_alone, file=sys.stderr, flush=True)
 
+    # batched: the request loop, fed while the ciphertexts in flight fit
     free, _ = torch.cuda.mem_get_info()
-    budget = int(min(free * 0.7, (args.budget_gb or 120.0) * 1e9))
-    srv = api.Server(budget, max_active=args.max_active, fill_blocks=max(0, args.fill_blocks))
+    io_cap = args.io_gb * 1e9
+    budget = int(min(free * 0.7 - io_cap, (args.budget_gb or 120.0) * 1e9))
+    fill = max(0, args.fill_blocks)
+    srv = api.Server(budget, max_active=args.max_active, fill_blocks=fill)
+    ok_batch, fp_batch, lat = [None] * len(reqs), [None] * len(reqs), [None] * len(reqs)
+    waiting = collections.deque(range(len(reqs)))
+    live, io_used, max_live = {}, 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tickets = [srv.submit_plan(r[2], r[3], r[4]) for r in reqs]  # the plans compiled above, shared
-    srv.drain()
+    while waiting or live:
+        while waiting:
+            i = waiting[0]
+            plan = reqs[i][2]
+            io = (plan.info.n_inputs + plan.info.n_outputs) * plan.ct_words * 4
+            if live and io_used + io > io_cap:
+                break
+            keys, ct_in = encrypt(i)
+            ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
+            live[srv.submit_plan(plan, ct_in, ct_out)] = (i, keys, ct_out, io, time.perf_counter())
+            io_used += io
+            waiting.popleft()
+        max_live = max(max_live, len(live))
+        srv.step()
+        for t in list(live):
+            done, _ = srv.poll(t)
+            if done:
+                i, keys, ct_out, io, t_sub = live.pop(t)
+                lat[i] = time.perf_counter() - t_sub
+                ok_batch[i], fp_batch[i] = finish(i, keys, ct_out)
+                io_used -= io
+                del ct_out
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     st = srv.stats()
-    lat = [srv.poll(t)[1] for t in tickets]
-    same = all(torch.equal(a, r[4]) for a, r in zip(alone_out, reqs))
     srv.close()
-    print("[bench] batched: %.2f s (%d steps, %d launches, max %d in flight); outputs identical to alone: %s" % (
-        t_batch, st.steps, st.launches, st.max_active, same), file=sys.stderr, flush=True)
+    same = fp_batch == fp_alone
+    dec_ok = all(ok_alone) and all(ok_batch)
+    print("[bench] batched: %.2f s (%d steps, %d launches, up to %d in flight); outputs identical to alone: %s; "
+          "decryptions equal the emulation: %s" % (t_batch, st.steps, st.launches, max_live, same, dec_ok),
+          file=sys.stderr, flush=True)
+    ops = bitmacs / 4.0 / t_batch
     return {
         "metric": "encrypted gates/s (1 GPU, batched)",
         "value": gates / t_batch,
@@ -180,16 +249,22 @@ def run_batch(args):
         "dtype": "i8",
         "data": "synthetic",
         "config": {"workload": "batch_1d_mixed", "requests": len(reqs), "lengths": "%d..%d" % (lengths[0], lengths[-1]),
-                   "F": "12/16/24",
-                   "n_lwe": 1, "distinct_plans": len(plans), "budget_gb": round(budget / 1e9, 1)},
+                   "F": "12/16/24", "n_lwe": 1, "distinct_plans": len(plans), "budget_gb": round(budget / 1e9, 1),
+                   "io_gb": args.io_gb, "fill_blocks": fill},
         "tilings": tuned,
         "one_at_a_time_gates_per_s": gates / t_alone,
+        "one_at_a_time_s": t_alone,
         "speedup_vs_one_at_a_time": t_alone / t_batch,
         "fft_points_per_s": points / t_batch,
         "bitmac_per_s": bitmacs / t_batch,
+        "roofline": {"bound": "mfma", "achieved": ops / 1e12, "peak": PEAK_MFMA_I8 / 1e12, "unit": "TOP/s",
+                     "frac": ops / PEAK_MFMA_I8, "dtype": "i8", "over": "whole batched run (wall time)"},
         "latency_p50_s": pct(lat, 50),
         "latency_p99_s": pct(lat, 99),
+        "max_in_flight": max_live,
         "outputs_identical_to_alone": same,
+        "all_decrypt_equal": dec_ok,
+        "decrypt_checked": expect is not None,
     }
 
 
@@ -344,7 +419,7 @@ def _kernel_names(path, kernel_prefix):
         return [r["Kernel_Name"] for r in csv.DictReader(f) if r["Kernel_Name"].startswith(kernel_prefix)]
 
 
-def run_serve(args):
+def run_serve(args, count=None):
     """Served traffic: requests (1D and 2D, Q(16,8), n_lwe=1, their own k)
     arrive as a Poisson process; each is encrypted on arrival, queued into
     the request loop, and its buffers freed when it completes.  Plans are
@@ -357,7 +432,10 @@ def run_serve(args):
     from paper_1611_08769_amd import sfft as S
     from paper_1611_08769_amd import workloads as WL
 
-    sigs = WL.served_requests(seed=5, count=args.requests or 40)
+    sigs = WL.served_requests(seed=5, count=count or args.requests or 40)
+    exp = _mix_expect("serve")
+    expect = exp["requests"] if exp["seed"] == 5 and len(sigs) <= exp["count"] else None
+    dec_ok = [None] * len(sigs)
     plans = {}
     for sig in sigs:
         key = (sig.dims, sig.length)
@@ -414,7 +492,7 @@ def run_serve(args):
             keys = api.keygen(p, 5000 + i)
             ct_in = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=5000 + i)
             ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
-            live[srv.submit_plan(plan, ct_in, ct_out)] = (i, io)
+            live[srv.submit_plan(plan, ct_in, ct_out)] = (i, io, keys, ct_out)
             io_used += io
             client_q.remove(i)
         if live:
@@ -422,9 +500,13 @@ def run_serve(args):
             now = time.perf_counter() - t0
             for t in list(live):
                 if srv.poll(t)[0]:
-                    i, io = live.pop(t)
+                    i, io, keys, ct_out = live.pop(t)
                     io_used -= io
                     lat[i], t_done[i] = now - arrivals[i], now
+                    # decrypted against the expected decryptions (the emulation)
+                    dec = api.decrypt_words(keys, ct_out, 2 * sigs[i].points, sigs[i].F)
+                    dec_ok[i] = expect is None or _words_sha(dec) == expect[i]["words_sha256"]
+                    del ct_out
                     print("[bench] request %d (%s %d) done: latency %.2f s" % (
                         i, "2D" if sigs[i].dims == 2 else "1D", sigs[i].length, lat[i]), file=sys.stderr, flush=True)
         elif waiting:
@@ -460,6 +542,8 @@ def run_serve(args):
         "latency_mean_s": float(np.mean(lat)),
         "steps_run": int(st.steps),
         "max_in_flight": int(st.max_active),
+        "all_decrypt_equal": all(dec_ok),
+        "decrypt_checked": expect is not None,
     }
 
 
@@ -912,6 +996,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fft1d_n64_cplx_q16.8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mix", action="store_true",
+                    help="default workload: skip the batched and served runs that follow the single request")
+    ap.add_argument("--batch-requests", type=int, default=256, help="default workload: requests of the batched run")
+    ap.add_argument("--serve-requests", type=int, default=16, help="default workload: requests of the served run")
     ap.add_argument("--no-tune", action="store_true", help="use the default tiling instead of tuning it first")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB three times (counter reference)")
@@ -1028,9 +1116,10 @@ def main():
     else:
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LOOKUP / 1e12, "unit": "Tbitmac/s",
                     "frac": achieved / PEAK_LOOKUP}
+    desc = S.sfft_tiling_describe(info.tiling)
     roofline.update({
         "traffic": None,
-        "kernel": "k_product_mfma" if mfma else "k_product",
+        "kernel": ("k_product_mfma2" if desc[4] == 2 else "k_product_mfma") if mfma else "k_product",
         "launches": n_launch,
         "avg_launch_ms": kern_ms / max(1, n_launch),
         "bitmac_per_s": achieved,
@@ -1085,6 +1174,24 @@ def main():
         out["cpu_baseline"] = cpu_baseline(nct, params.n_lwe + 1, params.k // 32, info.gates, info.products,
                                            args.cpu_budget)
     plan.close()
+    del ct_in, ct_out
+    torch.cuda.empty_cache()
+    if not args.no_mix:
+        # the batched mix (all requests through the request loop vs one at a
+        # time) and the served mix (Poisson arrivals), each output decrypted
+        # against the expected decryptions
+        bt = run_batch(args, count=args.batch_requests)
+        out["batch"] = {k: bt[k] for k in (
+            "value", "unit", "ms_per_step", "one_at_a_time_gates_per_s", "one_at_a_time_s",
+            "speedup_vs_one_at_a_time", "fft_points_per_s", "bitmac_per_s", "roofline", "latency_p50_s",
+            "latency_p99_s", "max_in_flight", "outputs_identical_to_alone", "all_decrypt_equal", "decrypt_checked")}
+        out["batch"]["config"] = bt["config"]
+        torch.cuda.empty_cache()
+        sv = run_serve(args, count=args.serve_requests)
+        out["serve"] = {k: sv[k] for k in (
+            "value", "unit", "ms_per_step", "fft_points_per_s", "bitmac_per_s", "latency_p50_s", "latency_p99_s",
+            "latency_mean_s", "max_in_flight", "all_decrypt_equal", "decrypt_checked")}
+        out["serve"]["config"] = sv["config"]
     print(json.dumps(out), flush=True)
 
 

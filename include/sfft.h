@@ -249,8 +249,7 @@ typedef struct {
      * fill_blocks, skipping any whose level alone exceeds fill_blocks.  The
      * others wait, so small requests are not held to the pace of a large
      * one's levels.  Admission then also lets a later request whose
-     * workspace fits pass one that does not yet.  (Both may starve a large
-     * request under a steady stream of small ones.) */
+     * workspace fits pass one that does not yet. */
     int64_t fill_blocks;
 } sfft_server_cfg;
 
@@ -275,8 +274,13 @@ int sfft_server_submit(sfft_server* srv, const sfft_shape* shape, const sfft_par
  * outlive the request. */
 int sfft_server_submit_plan(sfft_server* srv, const struct sfft_plan* plan, const uint32_t* ct_in_dev,
                             uint32_t* ct_out_dev, uint64_t* ticket);
-/* Admit what fits, run one global step on hip_stream and wait for it;
- * *pending = requests still queued or running. */
+/* Admit what fits and enqueue one global step on hip_stream (launches of
+ * different tilings overlap on the server's own streams, joined back on
+ * hip_stream), without waiting for the device: the host runs up to four
+ * steps ahead.  A request completes when the device has finished its last
+ * step; its workspace then returns to the budget.  *pending = requests
+ * still queued, running or finishing.  A request left out by the fill
+ * policy for 8 steps in a row runs in the next one. */
 int sfft_server_step(sfft_server* srv, void* hip_stream, int32_t* pending);
 /* done = 1 once the request's outputs are complete; latency = completion
  * minus submission (seconds; modelled in dry-run). */

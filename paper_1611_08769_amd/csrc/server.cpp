@@ -4,7 +4,13 @@
 // levels and the linear passes after them).  A global step advances every
 // admitted request by one of its own steps; the product items of all
 // requests whose kernel tiling matches go into one launch (one segment per
-// request, each with its own ciphertext geometry), then the linear passes.  Requests are admitted in
+// request, each with its own ciphertext geometry), then the linear passes.
+// Launches of different tilings within a step run concurrently on the
+// server's own streams, joined before the step's linear passes.  Steps are
+// enqueued without waiting for the device: a ring of segment buffers, each
+// with an event, lets the host run a few steps ahead, and a request is
+// retired (its workspace freed, its result reported) when the event
+// recorded after its last step has completed.  Requests are admitted in
 // arrival order while a workspace for their plan fits the device memory
 // budget and the number of requests in flight is below the limit, so
 // requests that arrive while others run join at their step 0 and overlap
@@ -106,7 +112,23 @@ struct Request {
     uint32_t* out;
     int64_t ws_off = -1;
     int32_t step = 0;
+    int32_t waited = 0;               // steps in a row the fill policy left it out
+    hipEvent_t fin = nullptr;         // recorded after its last step
     double arrival = 0, done_at = -1;
+};
+
+// Steps a request may be left out by the fill policy before it runs anyway.
+constexpr int kMaxWait = 8;
+// Segment buffers in flight (the host runs at most this many steps ahead of
+// the device) and streams of a step's concurrent launches beside the caller's.
+constexpr int kRing = 4;
+constexpr int kAux = 3;
+
+struct StepSlot {
+    void* host = nullptr;  // pinned
+    void* dev = nullptr;
+    hipEvent_t done = nullptr;  // recorded after the step that used the slot
+    bool busy = false;
 };
 
 }  // namespace
@@ -120,12 +142,15 @@ struct sfft_server {
     std::map<std::string, std::shared_ptr<PlanCore>> plans;
     std::deque<std::unique_ptr<Request>> queue;
     std::vector<std::unique_ptr<Request>> active;
+    std::vector<std::unique_ptr<Request>> finishing;  // every step enqueued, device not done yet
     std::map<uint64_t, std::unique_ptr<Request>> done;
     uint64_t next_ticket = 1;
-    // segment staging (host pinned + device), reused every step
-    void* seg_host = nullptr;
-    void* seg_dev = nullptr;
+    // segment staging (host pinned + device), a ring of step slots
+    StepSlot ring[kRing];
+    int64_t ring_next = 0;
     size_t seg_cap = 0;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t fork = nullptr, join[kAux] = {};
     sfft_server_stats st{};
 };
 
@@ -159,11 +184,20 @@ int sfft_server_create(const sfft_server_cfg* cfg, sfft_server** out)
             return sfft_fail(SFFT_ENOMEM, "cannot allocate the server's device memory budget");
         }
         sv->seg_cap = 1 << 20;  // bytes of segment lists per step
-        e = hipHostMalloc(&sv->seg_host, sv->seg_cap, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc(&sv->seg_dev, sv->seg_cap);
+        for (StepSlot& sl : sv->ring) {
+            if (e == hipSuccess) e = hipHostMalloc(&sl.host, sv->seg_cap, hipHostMallocDefault);
+            if (e == hipSuccess) e = hipMalloc(&sl.dev, sv->seg_cap);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        }
+        // default-priority streams that do not synchronise with the null stream
+        for (int a = 0; a < kAux && e == hipSuccess; a++) {
+            e = hipStreamCreateWithFlags(&sv->aux[a], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->join[a], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->fork, hipEventDisableTiming);
         if (e != hipSuccess) {
             sfft_server_destroy(sv);
-            return sfft_fail(SFFT_ENOMEM, "cannot allocate segment staging");
+            return sfft_fail(SFFT_ENOMEM, "cannot allocate segment staging, streams or events");
         }
     }
     *out = sv;
@@ -222,15 +256,48 @@ int sfft_server_submit_plan(sfft_server* sv, const sfft_plan* plan, const uint32
     return SFFT_OK;
 }
 
+// Requests whose last step the device has finished (every one, with `all`
+// after the caller's stream was synchronised): workspace back to the arena,
+// results reported.
+static int retire(sfft_server* sv, bool all)
+{
+    const double t = now_of(sv);
+    std::vector<std::unique_ptr<Request>> still;
+    for (auto& rp : sv->finishing) {
+        bool fin = all || sv->dry || !rp->fin;
+        if (!fin) {
+            const hipError_t q = hipEventQuery(rp->fin);
+            if (q == hipSuccess) fin = true;
+            else if (q != hipErrorNotReady) return sfft_hip_fail(q, "server request completion");
+        }
+        if (!fin) {
+            still.push_back(std::move(rp));
+            continue;
+        }
+        if (rp->fin) (void)hipEventDestroy(rp->fin), rp->fin = nullptr;
+        rp->done_at = t;
+        sv->arena.release(rp->ws_off);
+        rp->ws_off = -1;
+        sv->st.completed++;
+        sv->st.gates += rp->plan->info.gates;
+        sv->st.fft_points += rp->plan->points;
+        sv->done[rp->ticket] = std::move(rp);
+    }
+    sv->finishing.swap(still);
+    return SFFT_OK;
+}
+
 int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
 {
     if (!sv) return sfft_fail(SFFT_EINVAL, "null server");
     hipStream_t s = (hipStream_t)hip_stream;
+    int rc = retire(sv, false);
+    if (rc != SFFT_OK) return rc;
     // admission by workspace footprint and slot limit, in arrival order; with
     // the fill policy a request whose workspace does not fit yet lets later
     // ones that fit pass (no head-of-line blocking), lockstep keeps strict order
     for (auto it = sv->queue.begin(); it != sv->queue.end();) {
-        if (sv->cfg.max_active > 0 && (int)sv->active.size() >= sv->cfg.max_active) break;
+        if (sv->cfg.max_active > 0 && (int)(sv->active.size() + sv->finishing.size()) >= sv->cfg.max_active) break;
         Request* r = it->get();
         const int64_t off = sv->arena.alloc(std::max<int64_t>(r->plan->ws_bytes(), 1));
         if (off < 0) {
@@ -248,7 +315,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
     sv->st.max_active = std::max<int64_t>(sv->st.max_active, (int64_t)sv->active.size());
     sv->st.peak_ws_bytes = std::max<int64_t>(sv->st.peak_ws_bytes, sv->arena.peak());
     if (sv->active.empty()) {
-        if (pending) *pending = (int32_t)sv->queue.size();
+        if (pending) *pending = (int32_t)(sv->queue.size() + sv->finishing.size());
         return SFFT_OK;
     }
 
@@ -271,11 +338,14 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
     std::vector<LinGroup> lgroups;
     double model_s = 0;
     // which requests advance this step (all, or least remaining work first
-    // up to fill_blocks workgroups)
+    // up to fill_blocks workgroups; one left out kMaxWait steps in a row
+    // runs first, so that a steady stream of small requests cannot starve it)
     std::vector<Request*> run;
     for (auto& rp : sv->active) run.push_back(rp.get());
     if (sv->cfg.fill_blocks > 0) {
         std::stable_sort(run.begin(), run.end(), [](const Request* a, const Request* b) {
+            const bool wa = a->waited >= kMaxWait, wb = b->waited >= kMaxWait;
+            if (wa != wb) return wa;
             return a->plan->work_from[a->step] < b->plan->work_from[b->step];
         });
         // the first request always runs; others join while the step is below
@@ -285,7 +355,11 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         int64_t blocks = 0;
         for (Request* q : run) {
             const int64_t qb = q->plan->step_blocks[q->step];
-            if (!pick.empty() && (blocks >= sv->cfg.fill_blocks || qb > sv->cfg.fill_blocks)) continue;
+            if (!pick.empty() && q->waited < kMaxWait && (blocks >= sv->cfg.fill_blocks || qb > sv->cfg.fill_blocks)) {
+                q->waited++;
+                continue;
+            }
+            q->waited = 0;
             pick.push_back(q);
             blocks += qb;
         }
@@ -339,13 +413,22 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
     }
 
     if (!sv->dry) {
+        // a free slot of the ring: the step that used it last is done
+        StepSlot& sl = sv->ring[sv->ring_next % kRing];
+        sv->ring_next++;
+        hipError_t e = hipSuccess;
+        if (sl.busy) {
+            e = hipEventSynchronize(sl.done);
+            if (e != hipSuccess) return sfft_hip_fail(e, "server step slot");
+            sl.busy = false;
+        }
         // stage every segment list in one host->device copy
         size_t off = 0;
         auto place = [&](const void* src, size_t bytes) -> size_t {
             off = (off + 63) / 64 * 64;
             const size_t at = off;
             if (at + bytes > sv->seg_cap) return (size_t)-1;
-            std::memcpy((uint8_t*)sv->seg_host + at, src, bytes);
+            std::memcpy((uint8_t*)sl.host + at, src, bytes);
             off += bytes;
             return at;
         };
@@ -358,63 +441,88 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
             l_at.push_back(place(G.segs.data(), G.segs.size() * sizeof(LinSeg)));
             if (l_at.back() == (size_t)-1) return sfft_fail(SFFT_ENOMEM, "segment staging full");
         }
-        hipError_t e = hipMemcpyAsync(sv->seg_dev, sv->seg_host, off, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(sl.dev, sl.host, off, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return sfft_hip_fail(e, "segment upload");
-        // products first (one launch per tiling), then the linear passes in order
+        // products: the first tiling group on the caller's stream, the others
+        // on the server's streams (forked after the upload, joined back
+        // before the linear passes), so that their launches overlap
+        const int ng = (int)pgroups.size();
+        if (ng > 1) {
+            e = hipEventRecord(sv->fork, s);
+            if (e != hipSuccess) return sfft_hip_fail(e, "server fork");
+        }
         size_t gi = 0;
         for (auto& kv : pgroups) {
             const ProdGroup& G = kv.second;
-            e = launch_products(G.cfg, (const ProdSeg*)((uint8_t*)sv->seg_dev + p_at[gi++]), (int)G.segs.size(),
-                                G.segs[0], G.blocks, G.n, s);
+            const int a = gi == 0 ? -1 : (int)((gi - 1) % kAux);
+            hipStream_t gs = a < 0 ? s : sv->aux[a];
+            if (a >= 0 && gi <= (size_t)kAux) {
+                e = hipStreamWaitEvent(gs, sv->fork, 0);
+                if (e != hipSuccess) return sfft_hip_fail(e, "server fork wait");
+            }
+            e = launch_products(G.cfg, (const ProdSeg*)((uint8_t*)sl.dev + p_at[gi]), (int)G.segs.size(), G.segs[0],
+                                G.blocks, G.n, gs);
             if (e != hipSuccess) return sfft_hip_fail(e, "server product launch");
             sv->st.launches++;
+            gi++;
+        }
+        for (int a = 0; a < kAux && a + 1 < ng; a++) {
+            e = hipEventRecord(sv->join[a], sv->aux[a]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, sv->join[a], 0);
+            if (e != hipSuccess) return sfft_hip_fail(e, "server join");
         }
         for (size_t q = 0; q < lgroups.size(); q++) {
             const LinGroup& G = lgroups[q];
             if (!G.n) continue;
-            e = launch_linear(G.max_elems, (const LinSeg*)((uint8_t*)sv->seg_dev + l_at[q]), (int)G.segs.size(),
+            e = launch_linear(G.max_elems, (const LinSeg*)((uint8_t*)sl.dev + l_at[q]), (int)G.segs.size(),
                               G.segs[0], G.n, s);
             if (e != hipSuccess) return sfft_hip_fail(e, "server linear launch");
             sv->st.launches++;
         }
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return sfft_hip_fail(e, "server step");
+        e = hipEventRecord(sl.done, s);
+        if (e != hipSuccess) return sfft_hip_fail(e, "server step event");
+        sl.busy = true;
     } else {
         const double rate = sv->cfg.dry_bitmac_per_s > 0 ? sv->cfg.dry_bitmac_per_s : 1e15;
         sv->vclock += model_s / rate + 1e-5;
     }
     sv->st.steps++;
 
-    // advance the requests that ran; retire finished ones
+    // advance the requests that ran; those past their last step finish when
+    // the device is done with this step
     for (Request* r : run) r->step++;
-    const double t = now_of(sv);
     std::vector<std::unique_ptr<Request>> still;
     for (auto& rp : sv->active) {
         if (rp->step >= (int32_t)rp->plan->sched.levels.size() + 1) {
-            rp->done_at = t;
-            sv->arena.release(rp->ws_off);
-            rp->ws_off = -1;
-            sv->st.completed++;
-            sv->st.gates += rp->plan->info.gates;
-            sv->st.fft_points += rp->plan->points;
-            sv->done[rp->ticket] = std::move(rp);
+            if (!sv->dry) {
+                hipError_t e = hipEventCreateWithFlags(&rp->fin, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventRecord(rp->fin, s);
+                if (e != hipSuccess) return sfft_hip_fail(e, "server request event");
+            }
+            sv->finishing.push_back(std::move(rp));
         } else {
             still.push_back(std::move(rp));
         }
     }
     sv->active.swap(still);
-    if (pending) *pending = (int32_t)(sv->active.size() + sv->queue.size());
+    rc = retire(sv, false);
+    if (rc != SFFT_OK) return rc;
+    if (pending) *pending = (int32_t)(sv->active.size() + sv->queue.size() + sv->finishing.size());
     return SFFT_OK;
 }
 
 int sfft_server_poll(sfft_server* sv, uint64_t ticket, int32_t* done, double* latency_s)
 {
     if (!sv || !done) return sfft_fail(SFFT_EINVAL, "null argument");
+    int rc = retire(sv, false);
+    if (rc != SFFT_OK) return rc;
     auto it = sv->done.find(ticket);
     if (it == sv->done.end()) {
         *done = 0;
         if (latency_s) *latency_s = -1;
         for (auto& r : sv->active)
+            if (r->ticket == ticket) return SFFT_OK;
+        for (auto& r : sv->finishing)
             if (r->ticket == ticket) return SFFT_OK;
         for (auto& r : sv->queue)
             if (r->ticket == ticket) return SFFT_OK;
@@ -430,10 +538,23 @@ int sfft_server_drain(sfft_server* sv, void* hip_stream)
     if (!sv) return sfft_fail(SFFT_EINVAL, "null server");
     int32_t pending = 1;
     while (pending > 0) {
-        const size_t before = sv->active.size() + sv->queue.size();
+        const size_t before = sv->active.size() + sv->queue.size() + sv->finishing.size();
+        if (sv->active.empty() && sv->queue.empty()) {
+            // every step enqueued: wait for the device, then retire
+            if (!sv->dry) {
+                const hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+                if (e != hipSuccess) return sfft_hip_fail(e, "server drain");
+            }
+            return retire(sv, true);
+        }
+        if (sv->active.empty() && !sv->finishing.empty() && !sv->dry) {
+            // nothing runs until a finishing request frees its workspace
+            const hipError_t e = hipEventSynchronize(sv->finishing.front()->fin);
+            if (e != hipSuccess) return sfft_hip_fail(e, "server drain");
+        }
         const int rc = sfft_server_step(sv, hip_stream, &pending);
         if (rc != SFFT_OK) return rc;
-        if (sv->active.empty() && pending > 0 && before == (size_t)pending)
+        if (sv->active.empty() && sv->finishing.empty() && pending > 0 && before == (size_t)pending)
             return sfft_fail(SFFT_ENOMEM, "queued request cannot be admitted");
     }
     return SFFT_OK;
@@ -444,7 +565,7 @@ int sfft_server_stats_get(const sfft_server* sv, sfft_server_stats* out)
     if (!sv || !out) return sfft_fail(SFFT_EINVAL, "null argument");
     *out = sv->st;
     out->queued = (int64_t)sv->queue.size();
-    out->active = (int64_t)sv->active.size();
+    out->active = (int64_t)(sv->active.size() + sv->finishing.size());
     out->clock_s = sv->dry ? sv->vclock : now_s();
     return SFFT_OK;
 }
@@ -453,9 +574,19 @@ void sfft_server_destroy(sfft_server* sv)
 {
     if (!sv) return;
     if (sv->arena_dev) (void)hipDeviceSynchronize();  // enqueued steps may still use the arena
+    for (auto& rp : sv->finishing)
+        if (rp->fin) (void)hipEventDestroy(rp->fin);
+    for (StepSlot& sl : sv->ring) {
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.host) (void)hipHostFree(sl.host);
+    }
+    for (int a = 0; a < kAux; a++) {
+        if (sv->join[a]) (void)hipEventDestroy(sv->join[a]);
+        if (sv->aux[a]) (void)hipStreamDestroy(sv->aux[a]);
+    }
+    if (sv->fork) (void)hipEventDestroy(sv->fork);
     if (sv->arena_dev) (void)hipFree(sv->arena_dev);
-    if (sv->seg_dev) (void)hipFree(sv->seg_dev);
-    if (sv->seg_host) (void)hipHostFree(sv->seg_host);
     delete sv;
 }
 
