@@ -50,10 +50,84 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
-def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
-    """Time the oracle's product (the whole of its per-gate cost) on operands
-    of the workload's geometry until `budget_s` has passed."""
+class _Window:
+    """A run of consecutive nodes of a compacted netlist as a netlist of its
+    own, in the oracle's Compact form (t, a, b, outputs, n_inputs)."""
+
+
+def _oracle_window(cn, start, nprod):
+    """Nodes [start, end) of the compacted netlist cn that hold nprod distinct
+    products, as a netlist of their own: the earlier nodes they read become
+    its inputs, and every node of the run that is read after it (or is an
+    output) becomes one of its outputs, so the oracle evaluates each of its
+    gates, linear ones included."""
+    n = len(cn.t)
+    last = [-1] * n
+    for v in range(n):
+        if cn.t[v] >= 3:
+            last[cn.a[v]] = v
+        if cn.t[v] >= 4:
+            last[cn.b[v]] = v
+    for o in cn.outputs:
+        last[o] = n
+    seen, end = set(), start
+    while end < n and len(seen) < nprod:
+        if cn.t[end] in (4, 5, 6, 8):
+            seen.add((cn.a[end], cn.b[end]))
+        end += 1
+    w = _Window()
+    w.t, w.a, w.b = [1, 2], [-1, -1], [-1, -1]  # the constants keep ids 0 and 1
+    remap = {0: 0, 1: 1}
+    body = [v for v in range(start, end) if cn.t[v] >= 3]
+    for v in body:  # earlier nodes read by the run: its inputs
+        for u in ((cn.a[v],) if cn.t[v] == 3 else (cn.a[v], cn.b[v])):
+            if u < start and u not in remap:
+                remap[u] = len(w.t)
+                w.a.append(len(w.t) - 2)
+                w.t.append(0)
+                w.b.append(-1)
+    w.n_inputs = len(w.t) - 2
+    for v in body:
+        remap[v] = len(w.t)
+        w.t.append(cn.t[v])
+        w.a.append(remap[cn.a[v]])
+        w.b.append(remap[cn.b[v]] if cn.t[v] >= 4 else -1)
+    w.outputs = [remap[v] for v in body if last[v] >= end]
+    return w, len(seen)
+
+
+def cpu_baseline(workload, nct, n1, kw, gates, canon_products, budget_s=12.0):
+    """The oracle timed on the host: (1) a whole encrypted FFT of the small
+    1D N=8 real Q(8,4) workload (n = 1, k = 192), decrypted against the
+    fixed-point emulation; (2) on the named workload, a run of consecutive
+    nodes from the middle of its canonical netlist (products and the linear
+    gates between them, as the oracle evaluates them) sized to about
+    budget_s, extrapolated to the whole FFT by its canonical products; (3)
+    the oracle's product alone, on all threads and on one."""
+    from oracle import fixedpoint as fx
     from oracle import gsw
+    from oracle import netlist as N
+    from paper_1611_08769_amd import workloads as WL
+
+    threads = int(gsw.lib().or_threads())
+    # (1) the small workload end to end
+    sig, n_lwe, seed = WL.workload("fft1d_n8_real_q8.4")
+    cn1 = N.Compact(N.build_fft_netlist(sig.dims, sig.length, sig.F, sig.f, sig.is_complex))
+    keys = gsw.keygen(gsw.Params(n_lwe, 192), seed)
+    words = fx.quantize(np.asarray(sig.re).ravel(), sig.F, sig.f)
+    cts = gsw.encrypt(keys, fx.words_to_bits(words, sig.F), seed=seed)
+    t0 = time.perf_counter()
+    out = gsw.evaluate(keys.params, cn1, cts)
+    full_s = time.perf_counter() - t0
+    bits = gsw.decrypt_many(keys, out)
+    got = [sum(b << i for i, b in enumerate(bits[j * sig.F:(j + 1) * sig.F])) for j in range(len(bits) // sig.F)]
+    got = [v - (1 << sig.F) if v >= 1 << (sig.F - 1) else v for v in got]
+    er, ei = fx.fft1d_fixed(words[None], np.zeros((1, sig.length), np.int64), sig.F, sig.f)
+    exact = got == np.stack([er[0], ei[0]], 1).ravel().tolist()
+    print("[bench] oracle: N=8 FFT in %.2f s (decrypts %s)" % (full_s, "exactly" if exact else "WRONG"),
+          file=sys.stderr, flush=True)
+
+    # (3) the product alone (also sizes the window)
     p = gsw.Params(n1 - 1, 32 * kw)
     rng = np.random.default_rng(0)
     L = rng.integers(0, 2**32, p.dims(), dtype=np.uint64).astype(np.uint32)
@@ -69,14 +143,27 @@ def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
             if dt >= budget and n >= 2:
                 return dt / n, n
 
-    threads = int(gsw.lib().or_threads())
-    t_all, n_all = per_product(budget_s)
+    t_prod, n_prod = per_product(1.0)
     gsw.lib().or_set_threads(1)
     try:
-        t_one, n_one = per_product(budget_s / 2)
+        t_one, n_one = per_product(budget_s / 4)
     finally:
         gsw.lib().or_set_threads(threads)
-    fft_s = t_all * canon_products
+
+    # (2) a window of the named workload's own netlist
+    wsig, _, _ = WL.workload(workload)
+    cn = N.Compact(N.build_fft_netlist(wsig.dims, wsig.length, wsig.F, wsig.f, wsig.is_complex))
+
+    def run_window(nprod):
+        win, wprods = _oracle_window(cn, len(cn.t) // 2, nprod)
+        ins = rng.integers(0, 2**32, (win.n_inputs,) + p.dims(), dtype=np.uint64).astype(np.uint32)
+        t0 = time.perf_counter()
+        gsw.evaluate(p, win, ins)
+        return win, wprods, time.perf_counter() - t0
+
+    _, pilot_prods, pilot_s = run_window(64)  # sizes the timed window
+    win, wprods, win_s = run_window(max(64, int(budget_s * pilot_prods / pilot_s)))
+    fft_s = win_s / wprods * canon_products
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -88,12 +175,17 @@ def cpu_baseline(nct, n1, kw, gates, canon_products, budget_s=12.0):
         "unit": "gates/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "%d oracle products at Nct=%d (n+1=%d, k=%d), %.2f ms each; one FFT = %d canonical products "
-                  "-> %.0f s per FFT" % (n_all, nct, n1, 32 * kw, t_all * 1e3, canon_products, fft_s),
-        "bitmac_per_s": nct ** 3 / t_all,
+        "sample": "%d consecutive netlist nodes from the middle of the FFT's canonical netlist (%d distinct products "
+                  "and the linear gates between them) evaluated by the oracle in %.2f s at Nct=%d (n+1=%d, k=%d), "
+                  "random input ciphertexts; one FFT = %d canonical products -> %.0f s per FFT" % (
+                      len(win.t) - 2 - win.n_inputs, wprods, win_s, nct, n1, 32 * kw, canon_products, fft_s),
+        "small_fft_full_run": {"workload": "fft1d_n8_real_q8.4", "s_per_fft": full_s,
+                               "products": len(cn1.products()), "decrypts_exactly": exact},
+        "bitmac_per_s": nct ** 3 * wprods / win_s,
+        "product_only_ms": t_prod * 1e3,
         "value_1_core": gates / (t_one * canon_products),
         "bitmac_per_s_1_core": nct ** 3 / t_one,
-        "sample_1_core": "%d oracle products on 1 thread, %.2f ms each" % (n_one, t_one * 1e3),
+        "sample_1_core": "%d oracle products on 1 thread, %.2f ms each (product only)" % (n_one, t_one * 1e3),
         "cpu": model,
     }
 
@@ -284,7 +376,7 @@ def copy_probe():
 
 def _is_gate_product(name):
     """A gate-product launch of either kernel (encryption launches excluded)."""
-    return ("k_product<" in name and "false>" in name) or "k_product_mfma<" in name
+    return ("k_product<" in name and "false>" in name) or "k_product_mfma<" in name or "k_product_mfma2<" in name
 
 
 def _counter_rows(path, kernel_prefix):
@@ -315,9 +407,10 @@ def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_c
     fetch_scale, write_scale = gib / (cf * 1024), gib / (cw * 1024)
     fk, wk = sum(fetch) / len(fetch), sum(write) / len(write)
     src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "kernels.hip")
+    names = [n for n in _kernel_names(fetch_csv, prod) if _is_gate_product(n)][-levels:]
     out = {
         "workload": workload,
-        "kernel": "k_product",
+        "kernel": sorted(set(n.replace("void sfft::(anonymous namespace)::", "").split("(")[0] for n in names)),
         "kernels_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
         "launches": len(fetch),
         "fetch_kib_per_launch": fk,
@@ -411,6 +504,33 @@ def trace_summary(workload, db_path, steps):
     prods = [d for name, d in rows if _is_gate_product(name)]
     timed = prods[-steps * _product_levels(workload):]
     print("\ntimed product launches: %d, average %.3f ms" % (len(timed), sum(timed) / len(timed) / 1e6))
+
+
+def counter_summary(workload, csv_path):
+    """Per-launch averages of every counter in a rocprofv3 --pmc CSV over the
+    one timed FFT's product launches (the last one per level, after the
+    plan tuner's), with the ratios read from them."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        if _is_gate_product(r["Kernel_Name"]):
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    levels = _product_levels(workload)
+    avg = {k: sum(v[-levels:]) / len(v[-levels:]) for k, v in per.items()}
+    print("| counter | per launch |")
+    print("|:--|--:|")
+    for k in sorted(avg):
+        print("| %s | %.4g |" % (k, avg[k]))
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and "GRBM_GUI_ACTIVE" in avg:
+        # rocprofv3's MfmaUtil: MFMA-busy cycles summed over the 1024 SIMDs
+        # over the launch's GUI-active cycles of one XCD (the CSV sums
+        # GRBM_GUI_ACTIVE over the 8 XCDs)
+        print("\nMFMA utilisation (MFMA busy / (GUI active per XCD x 1024 SIMDs)): %.3f" % (
+            avg["SQ_VALU_MFMA_BUSY_CYCLES"] / (avg["GRBM_GUI_ACTIVE"] / 8 * 1024)))
+    if "SQ_INSTS_MFMA" in avg and "SQ_INSTS_VALU" in avg:
+        print("MFMA instructions / VALU instructions: %.3f" % (avg["SQ_INSTS_MFMA"] / avg["SQ_INSTS_VALU"]))
+    if "SQ_LDS_BANK_CONFLICT" in avg and "SQ_LDS_IDX_ACTIVE" in avg:
+        print("LDS bank-conflict cycles / LDS active cycles: %.3f" % (avg["SQ_LDS_BANK_CONFLICT"] / avg["SQ_LDS_IDX_ACTIVE"]))
 
 
 def _kernel_names(path, kernel_prefix):
@@ -1005,6 +1125,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB three times (counter reference)")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write profiles/traffic_k_product_<workload>.json from rocprofv3 counter CSVs")
+    ap.add_argument("--counter-summary", metavar="COUNTER_CSV",
+                    help="per-launch averages of a rocprofv3 --pmc CSV over the product launches of one FFT")
     ap.add_argument("--trace-summary", metavar="RESULTS_DB",
                     help="summarise a rocprofv3 kernel trace of a bench run (its --steps timed FFTs)")
     args = ap.parse_args()
@@ -1016,6 +1138,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args.workload, args.trace_summary, args.steps)
+        return
+    if args.counter_summary:
+        counter_summary(args.workload, args.counter_summary)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -1066,8 +1191,6 @@ def main():
               file=sys.stderr, flush=True)
     info = plan.info
     nct = (params.n_lwe + 1) * params.k
-    step_prods = plan.step_products()
-    nsteps = len(step_prods)
     print("[bench] workload=%s k=%d Nct=%d products=%d exec=%d levels=%d ws=%.1f GB" % (
         args.workload, params.k, nct, info.products, info.exec_products, info.levels, plan.ws_bytes / 1e9),
         file=sys.stderr, flush=True)
@@ -1077,32 +1200,22 @@ def main():
         torch.cuda.synchronize()
         print("[bench] warmup %d done" % w, file=sys.stderr, flush=True)
 
-    stream = torch.cuda.current_stream()
-    kern_ms = 0.0
-    n_launch = 0
+    # HIP events around each level's product kernel alone, recorded by the
+    # library on the stream the kernel runs on
+    plan.time_products(True)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         ts = time.perf_counter()
-        evs = []
-        for st in range(nsteps):
-            if step_prods[st]:
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                plan.execute_steps(st, 1, ct_in, ct_out)
-                b.record(stream)
-                evs.append((a, b))
-            else:
-                plan.execute_steps(st, 1, ct_in, ct_out)
+        plan.execute(ct_in, ct_out)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
-        kern_ms += sum(a.elapsed_time(b) for a, b in evs)
-        n_launch += len(evs)
         print("[bench] step %d: %.3f s" % (s, lat[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    plan.time_products(False)
+    kern_ms, n_launch = plan.product_time()
 
     step_s = total / args.steps
     bitmac_step = float(info.exec_products) * nct ** 3
@@ -1171,8 +1284,8 @@ def main():
             out["roofline"]["algorithmic_bytes_per_launch"] = alg
             out["roofline"]["traffic_vs_algorithmic_bytes"] = tr["traffic_bytes_per_launch"] / alg
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nct, params.n_lwe + 1, params.k // 32, info.gates, info.products,
-                                           args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.workload, nct, params.n_lwe + 1, params.k // 32, info.gates,
+                                           info.products, args.cpu_budget)
     plan.close()
     del ct_in, ct_out
     torch.cuda.empty_cache()

@@ -47,7 +47,6 @@ extern "C" {
 #define SFFT_ENOMEM (-2)        /* host or device allocation failed */
 #define SFFT_EDEVICE (-3)       /* HIP runtime error */
 #define SFFT_ENOISE (-4)        /* k too small for the circuit's noise bound */
-#define SFFT_EBUSY (-5)         /* server full (see sfft_server_submit) */
 #define SFFT_EUNSUPPORTED (-6)  /* valid but not implemented (e.g. eta != 1) */
 
 /* Scheme parameters: q = 2^k (k a positive multiple of 32), LWE dimension
@@ -124,6 +123,18 @@ int sfft_plan_info_get(const sfft_plan* plan, sfft_plan_info* info);
 /* Host-only compilation of the same circuit: fills `info` without touching
  * any device (no allocation, no HIP call).  Same errors as plan creation. */
 int sfft_analyze(const sfft_shape* shape, const sfft_params* params, sfft_plan_info* info);
+/* The same circuit with its workspace bounded by ws_limit_bytes (0: no
+ * bound, the plan of sfft_plan_create).  Levels are then formed by list
+ * scheduling instead of as soon as possible: products in order of first
+ * appearance in the netlist (the first rows' and stages' butterflies first),
+ * a level taking ready products while the workspace ciphertexts live
+ * through it fit the bound.  More levels of fewer products; the same
+ * ciphertexts.  sfft_plan_info.ws_bytes is the bounded workspace;
+ * SFFT_ENOMEM if the circuit cannot run within the bound. */
+int sfft_plan_create_bounded(const sfft_shape* shape, const sfft_params* params, int64_t ws_limit_bytes,
+                             sfft_plan** out);
+int sfft_analyze_bounded(const sfft_shape* shape, const sfft_params* params, int64_t ws_limit_bytes,
+                         sfft_plan_info* info);
 /* Device workspace the caller must pass to sfft_execute. */
 int sfft_plan_workspace_bytes(const sfft_plan* plan, int64_t* bytes);
 /* Waits for all device work (work enqueued with the plan reads its tables),
@@ -164,6 +175,15 @@ int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
  * Enqueues only. */
 #define SFFT_NOALLOC_WS_BYTES (64ll << 20)
 int sfft_execute_noalloc(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* hip_stream);
+/* Measurement aid.  With enable != 0, every later sfft_execute_steps (and
+ * sfft_execute) call on this plan records a pair of HIP events on its stream
+ * around each level's product kernel alone (after the right operands'
+ * transposition, before the level's linear gates); enable = 0 stops it.  Not
+ * for graph capture, and not thread-safe with other calls on the plan. */
+int sfft_plan_time_products(sfft_plan* plan, int32_t enable);
+/* Waits for the recorded pairs, returns the sum of their elapsed times (ms)
+ * and their number, and releases them. */
+int sfft_plan_product_time(sfft_plan* plan, double* total_ms, int64_t* launches);
 /* Product items per step (counts has exec_steps entries). */
 int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n);
 
@@ -396,12 +416,17 @@ int sfft_ring_keyswitch(int32_t d, int64_t n, const uint64_t* ksk_dev, const uin
  * the gate's bit in the same encoding under the same secret.  ws: at least
  * sfft_ring_gate_bootstrap_workspace_bytes.  NOT needs no bootstrap:
  * (0, .., 0, 2*floor(p/8)) - x. */
+int sfft_ring_gate_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes);
+int sfft_ring_gate_bootstrap(int32_t d, int32_t gate, const uint64_t* bkt_dev, int64_t n, const uint64_t* ksk_dev,
+                             const uint64_t* x_dev, const uint64_t* y_dev, int64_t m, uint64_t* out_dev, void* ws_dev,
+                             int64_t ws_bytes, void* hip_stream);
 /* Encrypted FFT plans on bootstrapped gates: the shape's canonical netlist
  * (as for sfft_plan_create; shared nodes merged) evaluated gate by gate on
  * LWE ciphertexts mod p of n+1 words, every binary gate a
  * sfft_ring_gate_bootstrap gate, so the circuit's depth puts no bound on the
  * parameters.  Binary nodes are levelised (NOT is free and takes its
- * operand's level); one batched bootstrapped call per level and gate kind.
+ * operand's level); one batched bootstrapped call per level, whatever the
+ * mix of gate kinds (every row carries its gate code), then the level's NOTs.
  * Input ciphertext order is that of sfft_execute (value, component, bit LSB
  * first), bits encoded as mu * 2 * floor(p/8) under the LWE secret; outputs
  * likewise, always complex.  The workspace holds a slot of n+1 words per node
@@ -423,10 +448,6 @@ int sfft_ring_plan_create(const sfft_shape* shape, int32_t d, int64_t n, sfft_ri
 int sfft_ring_fft_execute(const sfft_ring_plan* plan, const uint64_t* bkt_dev, const uint64_t* ksk_dev,
                           const uint64_t* in_dev, uint64_t* out_dev, void* ws_dev, int64_t ws_bytes, void* hip_stream);
 void sfft_ring_plan_destroy(sfft_ring_plan* plan);
-int sfft_ring_gate_bootstrap_workspace_bytes(int32_t d, int64_t n, int64_t m, int64_t* bytes);
-int sfft_ring_gate_bootstrap(int32_t d, int32_t gate, const uint64_t* bkt_dev, int64_t n, const uint64_t* ksk_dev,
-                             const uint64_t* x_dev, const uint64_t* y_dev, int64_t m, uint64_t* out_dev, void* ws_dev,
-                             int64_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -91,10 +91,13 @@ class Plan:
     """A compiled encrypted FFT for one shape and parameter set."""
 
     def __init__(self, dims: int, length: int, F: int, f: int, is_complex: bool, params: S.sfft_params,
-                 nand_only: bool = False):
+                 nand_only: bool = False, ws_limit_bytes: int = 0):
+        """ws_limit_bytes > 0 bounds the plan's workspace (levels by list
+        scheduling within it, sfft_plan_create_bounded)."""
         self.shape = S.shape(dims, length, F, f, is_complex, nand_only)
         self.params = params
-        self.handle = S.sfft_plan_create(self.shape, params)
+        self.handle = (S.sfft_plan_create_bounded(self.shape, params, ws_limit_bytes) if ws_limit_bytes > 0
+                       else S.sfft_plan_create(self.shape, params))
         self.info = S.sfft_plan_info_get(self.handle)
         self.ws_bytes = S.sfft_plan_workspace_bytes(self.handle)
         self.ct_words = S.sfft_ct_bytes(params) // 4
@@ -118,6 +121,16 @@ class Plan:
         ws = self.workspace()
         S.sfft_execute_steps(self.handle, first, count, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(),
                              ws.numel() * 4, _stream_ptr(stream))
+
+    def time_products(self, enable: bool) -> None:
+        """Record HIP events around each level's product kernel in later
+        execute / execute_steps calls (product_time() collects them)."""
+        S.sfft_plan_time_products(self.handle, enable)
+
+    def product_time(self):
+        """(total ms, launches) of the product kernels timed since the last
+        call; waits for them."""
+        return S.sfft_plan_product_time(self.handle)
 
     def execute_graph(self, ct_in: torch.Tensor, ct_out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """execute() through a HIP graph captured on first use for these

@@ -176,8 +176,76 @@ const PlanCore* plan_core_of(const sfft_plan* plan) { return plan; }
 namespace {
 // Compile the circuit of a shape for params: netlist, noise check, sharing,
 // lowering.  Host only.
-int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* sched, sfft_plan_info* info)
+// The plan's workspace: its slots, then one level's right operands in the
+// transposition layout.
+int64_t plan_ws_bytes(const Schedule& S, const Geo& g)
 {
+    return S.n_slots * ct_words(g) * 4 + S.max_level_products * rt_item_bytes(g);
+}
+
+// Levels within a workspace bound.  One level's transposition scratch takes
+// at most an eighth of it (and at most 8192 items, plenty to fill the GPU).
+// The products may run at most `window` ahead of the first one not yet run,
+// in order of first appearance (for an image: a few rows, then a few
+// columns, in lockstep); the widest window whose schedule fits is found by
+// halving from the whole circuit, then refined by bisection.  No slot bound
+// is set at first: under one, the list scheduler runs a single product per
+// level whenever the live set sits at the bound; it is the last resort.
+int schedule_within(const Compact& sc, const Geo& g, int64_t ws_limit, Schedule* sched)
+{
+    const int64_t rt = std::max<int64_t>(rt_item_bytes(g), 1);
+    LiveLimit lim;
+    lim.max_level_products = std::max<int64_t>(1, std::min<int64_t>(ws_limit / 8 / rt, 8192));
+    int64_t products = 0;
+    for (size_t v = 0; v < sc.size(); v++) products += is_product_type(sc.t[v]);
+    auto fits = [&](int64_t window, Schedule* out) {
+        lim.max_window = window;
+        *out = lower(sc, lim);
+        return plan_ws_bytes(*out, g) <= ws_limit;
+    };
+    int64_t hi = std::max<int64_t>(products, 1);  // the widest window tried
+    if (fits(hi, sched)) return SFFT_OK;
+    int64_t lo = 0;  // the widest window known to fit (0: none yet)
+    Schedule best;
+    while (hi > 1) {
+        const int64_t w = hi / 2;
+        if (fits(w, &best)) {
+            lo = w;
+            break;
+        }
+        hi = w;
+    }
+    if (lo == 0) {
+        // no window fits: a bound on the live slots themselves (levels of
+        // a single product wherever the live set sits at the bound)
+        lim.max_window = 0;
+        lim.max_slots = (ws_limit - lim.max_level_products * rt) / (ct_words(g) * 4);
+        if (lim.max_slots > 0) {
+            *sched = lower(sc, lim);
+            if (plan_ws_bytes(*sched, g) <= ws_limit) return SFFT_OK;
+        }
+        return fail(SFFT_ENOMEM, "the circuit cannot be scheduled within a workspace of " +
+                                     std::to_string(ws_limit) + " bytes");
+    }
+    // the widest fitting window lies in [lo, 2 lo): a few bisection steps
+    for (int step = 0; step < 3 && hi - lo > 1; step++) {
+        const int64_t w = lo + (hi - lo) / 2;
+        Schedule s;
+        if (fits(w, &s)) {
+            lo = w;
+            best = std::move(s);
+        } else {
+            hi = w;
+        }
+    }
+    *sched = std::move(best);
+    return SFFT_OK;
+}
+
+int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* sched, sfft_plan_info* info,
+                 int64_t ws_limit = 0)
+{
+    if (ws_limit < 0) return fail(SFFT_EINVAL, "negative workspace bound");
     std::string why;
     if (!shape_ok(shape, &why)) return fail(SFFT_EINVAL, why);
     if (!params_ok(params, &why)) return fail(SFFT_EINVAL, why);
@@ -191,7 +259,12 @@ int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* s
                                          " is below the circuit's noise bound (needs " + std::to_string(need) +
                                          " bits at this Nct)");
         const NetStats st = netlist_stats(c);
-        *sched = lower(share(c));
+        if (ws_limit > 0) {
+            const int rc = schedule_within(share(c), geo, ws_limit, sched);
+            if (rc != SFFT_OK) return rc;
+        } else {
+            *sched = lower(share(c));
+        }
         sfft_plan_info& in = *info;
         std::memset(&in, 0, sizeof(in));
         in.nodes = st.nodes;
@@ -203,7 +276,7 @@ int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* s
         in.n_inputs = c.n_inputs;
         in.n_outputs = (int64_t)c.outputs.size();
         in.ws_cts = sched->n_slots;
-        in.ws_bytes = sched->n_slots * ct_words(geo) * 4 + sched->max_level_products * rt_item_bytes(geo);
+        in.ws_bytes = plan_ws_bytes(*sched, geo);
         in.exec_steps = (int64_t)sched->levels.size() + 1;
         in.k_required = choose_k(c, params->n_lwe);
         for (const ProdItem& it : sched->prods) {
@@ -232,7 +305,11 @@ namespace sfft {
 PlanCore::~PlanCore()
 {
     // work enqueued with this plan may still read its tables
-    if (d_prods || d_lins || d_final) (void)hipDeviceSynchronize();
+    if (d_prods || d_lins || d_final || !prod_events.empty()) (void)hipDeviceSynchronize();
+    for (auto& pr : prod_events) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (d_prods) (void)hipFree(d_prods);
@@ -240,9 +317,9 @@ PlanCore::~PlanCore()
     if (d_final) (void)hipFree(d_final);
 }
 
-int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upload, PlanCore* pl)
+int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upload, PlanCore* pl, int64_t ws_limit)
 {
-    const int rc = compile_plan(shape, params, &pl->sched, &pl->info);
+    const int rc = compile_plan(shape, params, &pl->sched, &pl->info, ws_limit);
     if (rc != SFFT_OK) return rc;
     pl->shape = *shape;
     pl->params = *params;
@@ -380,13 +457,27 @@ int sfft_analyze(const sfft_shape* shape, const sfft_params* params, sfft_plan_i
     return compile_plan(shape, params, &sched, info);
 }
 
+int sfft_analyze_bounded(const sfft_shape* shape, const sfft_params* params, int64_t ws_limit_bytes,
+                         sfft_plan_info* info)
+{
+    if (!info) return fail(SFFT_EINVAL, "null info");
+    Schedule sched;
+    return compile_plan(shape, params, &sched, info, ws_limit_bytes);
+}
+
 int sfft_plan_create(const sfft_shape* shape, const sfft_params* params, sfft_plan** out)
+{
+    return sfft_plan_create_bounded(shape, params, 0, out);
+}
+
+int sfft_plan_create_bounded(const sfft_shape* shape, const sfft_params* params, int64_t ws_limit_bytes,
+                             sfft_plan** out)
 {
     if (!out) return fail(SFFT_EINVAL, "null plan pointer");
     *out = nullptr;
     sfft_plan* pl = new (std::nothrow) sfft_plan();
     if (!pl) return fail(SFFT_ENOMEM, "out of host memory");
-    const int rc = plan_core_build(shape, params, true, pl);
+    const int rc = plan_core_build(shape, params, true, pl, ws_limit_bytes);
     if (rc != SFFT_OK) {
         delete pl;
         return rc;
@@ -433,9 +524,21 @@ int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, cons
             if (lw.prod_count) {
                 const ProdSeg seg{plan->d_prods + lw.prod_begin, b, g, plan->cfg.nd, plan->cfg.wd, 0, 0,
                                   (uint8_t*)ws_dev + plan->slot_bytes()};
+                std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+                if (plan->time_products) {
+                    hipError_t e = hipEventCreate(&ev.first);
+                    if (e == hipSuccess) e = hipEventCreate(&ev.second);
+                    if (e != hipSuccess) {
+                        if (ev.first) (void)hipEventDestroy(ev.first);
+                        return hip_fail(e, "timing events");
+                    }
+                    plan->prod_events.push_back(ev);
+                }
                 hipError_t e = launch_products(plan->cfg, nullptr, 1, seg,
-                                               (int64_t)lw.prod_count * product_tiles(g, plan->cfg), lw.prod_count, s);
+                                               (int64_t)lw.prod_count * product_tiles(g, plan->cfg), lw.prod_count, s,
+                                               ev.first);
                 if (e != hipSuccess) return hip_fail(e, "product launch");
+                if (ev.second && (e = hipEventRecord(ev.second, s)) != hipSuccess) return hip_fail(e, "timing event");
             }
             for (const auto& pass : lw.lin) {
                 const LinSeg seg{plan->d_lins + pass.first, b, g, 0, 0};
@@ -497,6 +600,34 @@ int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
     }
     hipError_t e = hipGraphLaunch(plan->graph_exec, s);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SFFT_OK;
+}
+
+int sfft_plan_time_products(sfft_plan* plan, int32_t enable)
+{
+    if (!plan) return fail(SFFT_EINVAL, "null plan");
+    plan->time_products = enable != 0;
+    return SFFT_OK;
+}
+
+int sfft_plan_product_time(sfft_plan* plan, double* total_ms, int64_t* launches)
+{
+    if (!plan || !total_ms || !launches) return fail(SFFT_EINVAL, "null argument");
+    double sum = 0.0;
+    hipError_t err = hipSuccess;
+    for (auto& pr : plan->prod_events) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        sum += ms;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    *launches = (int64_t)plan->prod_events.size();
+    *total_ms = sum;
+    plan->prod_events.clear();
+    if (err != hipSuccess) return hip_fail(err, "product timing");
     return SFFT_OK;
 }
 

@@ -130,8 +130,9 @@ __host__ __device__ inline int mfma2_eps(const Geo& g, int cf)
 // memory when nseg > 1, else seg0 (by value).  cfg is the tiling shared by
 // the segments with lds_bytes the largest any of them needs.  Under a
 // matrix-core tiling a transposition launch first fills each segment's rt.
+// A non-null mark is recorded on s just before the product kernel itself.
 hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                           int64_t blocks, int64_t items, hipStream_t s);
+                           int64_t blocks, int64_t items, hipStream_t s, hipEvent_t mark = nullptr);
 // One product item passed by value (single gates); rt as in ProdSeg (one
 // item's worth, used under a matrix-core tiling).
 hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, const ProdItem& item, uint8_t* rt,

@@ -2055,11 +2055,15 @@ hipError_t launch_rtrans(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
 }  // namespace
 
 hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
-                           int64_t blocks, int64_t items, hipStream_t s)
+                           int64_t blocks, int64_t items, hipStream_t s, hipEvent_t mark)
 {
     ProdItem none{};
     if (cfg.mfma && cfg.pre) {
         hipError_t e = launch_rtrans(cfg, d_segs, nseg, seg0, none, blocks > 0 ? items : 0, s);
+        if (e != hipSuccess) return e;
+    }
+    if (mark) {
+        hipError_t e = hipEventRecord(mark, s);
         if (e != hipSuccess) return e;
     }
     return dispatch<false>(cfg, d_segs, nseg, seg0, none, blocks, 0, 0, nullptr, s);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/sfft.h"
@@ -32,6 +33,10 @@ struct PlanCore {
     const void* graph_in = nullptr;
     const void* graph_out = nullptr;
     const void* graph_ws = nullptr;
+    // product-kernel timing (sfft_plan_time_products): event pairs recorded
+    // around each level's product kernel by sfft_execute_steps while on
+    mutable bool time_products = false;
+    mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prod_events;
 
     int64_t ct_words() const { return (int64_t)geo.nct * geo.W; }
     // workspace: the slots, then (where a matrix-core tiling serves the
@@ -46,7 +51,9 @@ struct PlanCore {
 };
 
 // Compile (and, with upload, copy the work tables to the device).
-int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upload, PlanCore* out);
+// ws_limit > 0 bounds the workspace (levels by list scheduling within it).
+int plan_core_build(const sfft_shape* shape, const sfft_params* params, bool upload, PlanCore* out,
+                    int64_t ws_limit = 0);
 
 }  // namespace sfft
 

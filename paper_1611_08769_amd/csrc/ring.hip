@@ -295,10 +295,6 @@ __device__ __forceinline__ uint64_t small_mul(int cx, uint64_t v)
     return cx == 1 ? v : cx == 2 ? addp(v, v) : cx == -1 ? subp(0, v) : 0;
 }
 
-// Gate bootstrapping, step 1: for LWE ciphertext j, c = cx*x_j + cy*y_j
-// (+ cb on b) with c = (a_0..a_{n-1}, b), the rotations -a~_i mod 2D and
-// the accumulator (X^(b~ + D/2) * TV, 0), TV = delta * (1 + X + ... +
-// X^(D-1)).  y may be null (cy = 0).
 // The linear combination of a bootstrapped gate (bits encoded as mu * 2 *
 // floor(p/8)): c = cx*x + cy*y + (0, .., 0, k*floor(p/8)).
 __host__ __device__ __forceinline__ void gate_combination(int gate, int* cx, int* cy, uint64_t* cb)
@@ -313,6 +309,10 @@ __host__ __device__ __forceinline__ void gate_combination(int gate, int* cx, int
     *cb = k >= 0 ? (uint64_t)k * (kP / 8) : kP - (uint64_t)(-k) * (kP / 8);
 }
 
+// Gate bootstrapping, step 1: for LWE ciphertext j, c = cx*x_j + cy*y_j
+// (+ cb on b) with c = (a_0..a_{n-1}, b), the rotations -a~_i mod 2D and
+// the accumulator (X^(b~ + D/2) * TV, 0), TV = delta * (1 + X + ... +
+// X^(D-1)).  y may be null (cy = 0).
 template <int LOGD>
 __global__ __launch_bounds__(kT) void k_ring_br_init(const uint64_t* __restrict__ x, const uint64_t* __restrict__ y,
                                                      const int32_t* __restrict__ xi, const int32_t* __restrict__ yi,
@@ -637,9 +637,10 @@ constexpr int64_t kMaxGrid = 1 << 30;
 // ---- FFT plans on bootstrapped gates ---------------------------------------
 // Every node of the (shared) FFT netlist gets a slot of n+1 words: slot v
 // holds node v's LWE ciphertext.  Binary nodes are levelised (a NOT takes
-// its operand's level) and each level's nodes of one kind form one batched
-// bootstrapped gate: operands gathered from the slots by index, outputs
-// key-switched straight into theirs.  NOTs run after their level's gates, in
+// its operand's level) and each level's binary nodes, of whatever kinds,
+// form one batched bootstrapped gate (every row carries its gate code):
+// operands gathered from the slots by index, outputs key-switched straight
+// into theirs.  NOTs run after their level's gates, in
 // rank order (a NOT of a NOT of the same level one rank later).
 struct RingStep {
     bool is_not;

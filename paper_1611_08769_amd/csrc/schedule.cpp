@@ -2,6 +2,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <queue>
 #include <map>
 #include <stdexcept>
 #include <unordered_map>
@@ -67,9 +68,168 @@ bool add_forms(const Form& x, const Form& y, Form* out)
     return true;
 }
 
+// Levels under a bound on the live set (list scheduling).  Products are
+// taken in order of first appearance in the netlist (for the FFT, the
+// butterflies of the first rows and stages first) once their operands are in
+// memory; a level takes ready products while the workspace ciphertexts that
+// would be live through it stay within lim.max_slots, the level holds at
+// most lim.max_level_products and the product lies within lim.max_window of
+// the first product not yet run, and always takes at least the first ready
+// one.
+// A product-free linear node is computed right after the level that makes
+// its last term available (sub-passes as in the unbounded schedule).  A
+// workspace ciphertext is live from the level that writes it to the last
+// level that reads it, as the slot assignment that follows counts it.
+int32_t bounded_levels(const Compact& c, const std::vector<Form>& form, const std::vector<uint8_t>& mat,
+                       const std::vector<int32_t>& pl, const std::vector<int32_t>& pr,
+                       const std::vector<std::vector<int32_t>>& attached, const LiveLimit& lim,
+                       std::vector<int32_t>* plevel_out, std::vector<int32_t>* avail_out, std::vector<int32_t>* sub_out)
+{
+    const size_t n = c.size();
+    const int32_t np = (int32_t)pl.size();
+    std::vector<int32_t>& plevel = *plevel_out;
+    std::vector<int32_t>& avail = *avail_out;
+    std::vector<int32_t>& sub = *sub_out;
+    std::vector<uint8_t> is_output(n, 0);
+    for (int32_t o : c.outputs)
+        if (o >= 2 && c.t[o] != T_IN) is_output[o] = 1;
+    // slot holders: materialised nodes other than inputs and outputs
+    auto holds_slot = [&](size_t v) { return mat[v] && c.t[v] != T_IN && !is_output[v]; };
+
+    // readers of every node: products (as operands or extra terms) and
+    // linear nodes; pending operand counts of both
+    std::vector<std::vector<int32_t>> prod_readers(n), lin_readers(n);
+    std::vector<int32_t> uses(n, 0), p_wait(np, 0), l_wait(n, 0);
+    auto read_by_prod = [&](int32_t u, int32_t p) {
+        prod_readers[u].push_back(p);
+        uses[u]++;
+        p_wait[p]++;
+    };
+    for (int32_t p = 0; p < np; p++) {
+        if (attached[p].empty()) continue;
+        read_by_prod(pl[p], p);
+        read_by_prod(pr[p], p);
+        for (int32_t o : attached[p])
+            for (int i = 0; i < form[o].nt; i++) read_by_prod(form[o].tn[i], p);
+    }
+    std::vector<int32_t> lin_nodes;
+    for (size_t v = 0; v < n; v++) {
+        if (!mat[v] || c.t[v] == T_IN || form[v].prod >= 0) continue;
+        lin_nodes.push_back((int32_t)v);
+        for (int i = 0; i < form[v].nt; i++) {
+            lin_readers[form[v].tn[i]].push_back((int32_t)v);
+            uses[form[v].tn[i]]++;
+            l_wait[v]++;
+        }
+    }
+
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> ready;
+    std::vector<int32_t> dying;  // slot holders whose last reader ran at this level
+    auto read_once = [&](int32_t u) {
+        if (--uses[u] == 0 && holds_slot(u)) dying.push_back(u);
+    };
+    std::vector<int32_t> became;  // nodes that came into memory at the current level
+    int64_t live = 0;             // slot holders in memory and still to be read
+
+    // a node is in memory from level L on: wake its readers
+    std::function<void(int32_t, int32_t)> arrive = [&](int32_t v, int32_t L) {
+        avail[v] = L;
+        for (int32_t p : prod_readers[v])
+            if (--p_wait[p] == 0) ready.push(p);
+        for (int32_t w : lin_readers[v]) {
+            if (--l_wait[w] != 0) continue;
+            // a linear node: computed after level L in sub-pass order
+            int32_t s = 0;
+            for (int i = 0; i < form[w].nt; i++) {
+                const int32_t t = form[w].tn[i];
+                if (c.t[t] != T_IN && form[t].prod < 0 && avail[t] == L) s = std::max(s, sub[t] + 1);
+            }
+            sub[w] = s;
+            if (holds_slot(w)) live++;
+            for (int i = 0; i < form[w].nt; i++) read_once(form[w].tn[i]);  // read at level L
+            arrive(w, L);
+        }
+    };
+
+    for (size_t v = 0; v < n; v++)
+        if (c.t[v] == T_IN) arrive((int32_t)v, 0);
+    // linear nodes with no terms (constants) are in memory from level 0
+    for (int32_t v : lin_nodes)
+        if (form[v].nt == 0 && avail[v] < 0) {
+            sub[v] = 0;
+            if (holds_slot(v)) live++;
+            arrive(v, 0);
+        }
+    live -= (int64_t)dying.size();
+    dying.clear();
+
+    // product items of each product: a new item when kMaxOut outputs or
+    // kMaxE distinct extra operands are reached (the packing below)
+    std::vector<int32_t> items(np, 0);
+    for (int32_t p = 0; p < np; p++) {
+        int nout = 0, ne = 0;
+        int32_t es[kMaxE];
+        for (int32_t o : attached[p]) {
+            const int32_t e = form[o].nt == 1 ? form[o].tn[0] : -1;
+            bool seen = e < 0;
+            for (int q = 0; q < ne && !seen; q++) seen = es[q] == e;
+            if (nout == 0 || nout == kMaxOut || (!seen && ne == kMaxE)) {
+                items[p]++;
+                nout = 0;
+                ne = 0;
+                seen = e < 0;
+            }
+            if (!seen) es[ne++] = e;
+            nout++;
+        }
+    }
+    int32_t low = 0;  // the first product not yet scheduled
+    int64_t scheduled = 0, to_schedule = 0;
+    for (int32_t p = 0; p < np; p++) to_schedule += !attached[p].empty();
+    int32_t L = 0;
+    while (scheduled < to_schedule) {
+        L++;
+        if (ready.empty()) throw std::logic_error("bounded schedule: no ready product");
+        std::vector<int32_t> take;
+        int64_t born = 0, level_items = 0;
+        while (low < np && (attached[low].empty() || plevel[low] >= 0)) low++;
+        while (!ready.empty()) {
+            // in order: nothing passes a product that waits
+            const int32_t p = ready.top();
+            if (!take.empty() && lim.max_window > 0 && p >= low + lim.max_window) break;
+            int64_t b = 0;
+            for (int32_t o : attached[p]) b += holds_slot(o);
+            const bool fits = (lim.max_slots <= 0 || live + born + b <= lim.max_slots) &&
+                              (lim.max_level_products <= 0 || level_items + items[p] <= lim.max_level_products);
+            if (!take.empty() && !fits) break;
+            ready.pop();
+            take.push_back(p);
+            born += b;
+            level_items += items[p];
+        }
+        // the level's products read their operands and write their outputs
+        for (int32_t p : take) {
+            plevel[p] = L;
+            read_once(pl[p]);
+            read_once(pr[p]);
+            for (int32_t o : attached[p])
+                for (int i = 0; i < form[o].nt; i++) read_once(form[o].tn[i]);
+        }
+        live += born;
+        for (int32_t p : take)
+            for (int32_t o : attached[p]) arrive(o, L);
+        scheduled += (int64_t)take.size();
+        live -= (int64_t)dying.size();
+        dying.clear();
+    }
+    for (int32_t v : lin_nodes)
+        if (avail[v] < 0) throw std::logic_error("bounded schedule: linear node never computed");
+    return L;
+}
+
 }  // namespace
 
-Schedule lower(const Compact& c)
+Schedule lower(const Compact& c, const LiveLimit& lim)
 {
     const size_t n = c.size();
     std::vector<Form> form(n);
@@ -180,10 +340,15 @@ Schedule lower(const Compact& c)
         return a;
     };
     int32_t max_level = 0;
-    for (int32_t p = 0; p < np; p++)
-        if (!attached[p].empty()) max_level = std::max(max_level, level_of(p));
-    for (size_t v = 0; v < n; v++)
-        if (mat[v]) max_level = std::max(max_level, avail_of((int32_t)v));
+    if (lim.max_slots <= 0 && lim.max_level_products <= 0) {
+        // as soon as possible: a product runs one level after its last operand
+        for (int32_t p = 0; p < np; p++)
+            if (!attached[p].empty()) max_level = std::max(max_level, level_of(p));
+        for (size_t v = 0; v < n; v++)
+            if (mat[v]) max_level = std::max(max_level, avail_of((int32_t)v));
+    } else {
+        max_level = bounded_levels(c, form, mat, pl, pr, attached, lim, &plevel, &avail, &sub);
+    }
 
     // ---- homes -------------------------------------------------------------------
     std::vector<int32_t> home(n, -1);

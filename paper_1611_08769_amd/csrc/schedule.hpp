@@ -57,7 +57,20 @@ struct Schedule {
     int64_t max_level_products = 0;
 };
 
-// Build the schedule for a (DCE'd, optionally shared) netlist.
-Schedule lower(const Compact& c);
+// Bounds on the live set of a schedule (0: none).  max_slots bounds the
+// workspace ciphertexts live at once, max_level_products the product items
+// of one level (each level's right operands take transposition scratch),
+// max_window how far (in order of first appearance) a product may run ahead
+// of the first one not yet run, which keeps the schedule from opening more
+// independent parts of the circuit (rows of an image) than fit.
+struct LiveLimit {
+    int64_t max_slots = 0;
+    int64_t max_level_products = 0;
+    int64_t max_window = 0;
+};
+
+// Build the schedule for a (DCE'd, optionally shared) netlist: levels as
+// soon as possible, or, under a limit, by list scheduling within it.
+Schedule lower(const Compact& c, const LiveLimit& lim = LiveLimit{});
 
 }  // namespace sfft

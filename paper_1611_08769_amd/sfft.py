@@ -14,7 +14,6 @@ SFFT_EINVAL = -1
 SFFT_ENOMEM = -2
 SFFT_EDEVICE = -3
 SFFT_ENOISE = -4
-SFFT_EBUSY = -5
 SFFT_EUNSUPPORTED = -6
 
 GATE_NOT, GATE_AND, GATE_XOR, GATE_OR, GATE_XADD, GATE_NAND, GATE_PRODUCT = 3, 4, 5, 6, 7, 8, 9
@@ -92,11 +91,15 @@ _SIGS = {
     "sfft_plan_create": (ctypes.c_int, [_P(sfft_shape), _P(sfft_params), _P(_vp)]),
     "sfft_plan_info_get": (ctypes.c_int, [_vp, _P(sfft_plan_info)]),
     "sfft_analyze": (ctypes.c_int, [_P(sfft_shape), _P(sfft_params), _P(sfft_plan_info)]),
+    "sfft_analyze_bounded": (ctypes.c_int, [_P(sfft_shape), _P(sfft_params), ctypes.c_int64, _P(sfft_plan_info)]),
+    "sfft_plan_create_bounded": (ctypes.c_int, [_P(sfft_shape), _P(sfft_params), ctypes.c_int64, _P(_vp)]),
     "sfft_plan_workspace_bytes": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "sfft_plan_destroy": (None, [_vp]),
     "sfft_execute": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "sfft_execute_steps": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "sfft_plan_step_products": (ctypes.c_int, [_vp, _P(ctypes.c_int64), ctypes.c_int32]),
+    "sfft_plan_time_products": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "sfft_plan_product_time": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "sfft_decrypt": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, _vp]),
     "sfft_decrypt_bits": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
     "sfft_gate": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _vp, _vp, _vp, _vp]),
@@ -189,6 +192,18 @@ def sfft_plan_create(shp: sfft_shape, p: sfft_params) -> int:
     return h.value
 
 
+def sfft_plan_create_bounded(shp: sfft_shape, p: sfft_params, ws_limit_bytes: int) -> int:
+    h = _vp()
+    _check(_lib.sfft_plan_create_bounded(ctypes.byref(shp), ctypes.byref(p), int(ws_limit_bytes), ctypes.byref(h)))
+    return h.value
+
+
+def sfft_analyze_bounded(shp: sfft_shape, p: sfft_params, ws_limit_bytes: int) -> sfft_plan_info:
+    info = sfft_plan_info()
+    _check(_lib.sfft_analyze_bounded(ctypes.byref(shp), ctypes.byref(p), int(ws_limit_bytes), ctypes.byref(info)))
+    return info
+
+
 def sfft_plan_info_get(plan: int) -> sfft_plan_info:
     info = sfft_plan_info()
     _check(_lib.sfft_plan_info_get(plan, ctypes.byref(info)))
@@ -221,6 +236,16 @@ def sfft_execute_noalloc(plan, ct_in_ptr, ct_out_ptr, stream) -> None:
 
 def sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
     _check(_lib.sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_plan_time_products(plan, enable) -> None:
+    _check(_lib.sfft_plan_time_products(plan, int(enable)))
+
+
+def sfft_plan_product_time(plan):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.sfft_plan_product_time(plan, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def sfft_plan_step_products(plan, n):
