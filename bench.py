@@ -561,9 +561,14 @@ def run_serve(args, count=None):
         key = (sig.dims, sig.length)
         if key not in plans:
             p = api.size_params(sig.dims, sig.length, sig.F, sig.f, sig.is_complex, 1)
-            plans[key] = (p, api.Plan(sig.dims, sig.length, sig.F, sig.f, sig.is_complex, p))
-            print("[bench] plan %s: k=%d exec products %d ws %.1f GB" % (
-                key, p.k, plans[key][1].info.exec_products, plans[key][1].ws_bytes / 1e9), file=sys.stderr, flush=True)
+            # plans whose levels-as-soon-as-possible workspace passes the
+            # bound get list-scheduled levels within it
+            shp = S.shape(sig.dims, sig.length, sig.F, sig.f, sig.is_complex)
+            lim = int(args.plan_ws_gb * 1e9) if S.sfft_analyze(shp, p).ws_bytes > args.plan_ws_gb * 1e9 else 0
+            plans[key] = (p, api.Plan(sig.dims, sig.length, sig.F, sig.f, sig.is_complex, p, ws_limit_bytes=lim))
+            print("[bench] plan %s: k=%d exec products %d levels %d ws %.1f GB" % (
+                key, p.k, plans[key][1].info.exec_products, plans[key][1].info.levels, plans[key][1].ws_bytes / 1e9),
+                file=sys.stderr, flush=True)
     if not args.no_tune:
         # plans tuned before the clock, on an encryption of their first request
         for key, (p, plan) in plans.items():
@@ -654,7 +659,9 @@ def run_serve(args, count=None):
         "config": {"workload": "served_poisson", "requests": len(sigs), "mix": "1D 16..256 complex / 2D 8..32 real",
                    "F": 16, "f": 8, "n_lwe": 1, "rate_per_s": rate, "load": args.load,
                    "max_active": args.max_active, "fill_blocks": fill, "budget_gb": round(budget / 1e9, 1),
-                   "io_gb": args.io_gb},
+                   "io_gb": args.io_gb, "plan_ws_gb": args.plan_ws_gb,
+                   "plans": {"%dd_%d" % k: {"levels": int(pl.info.levels), "ws_gb": round(pl.ws_bytes / 1e9, 1)}
+                             for k, (_, pl) in plans.items()}},
         "fft_points_per_s": points / wall,
         "bitmac_per_s": bitmacs / wall,
         "latency_p50_s": pct(lat, 50),
@@ -993,6 +1000,15 @@ def run_ring_fft(args):
                    "max_batch": info.max_batch},
         "s_per_fft": per,
         "fft_points_per_s": sig.points / per,
+        # every binary gate is one refresh: n CMux steps of the blind
+        # rotation, which dominate the FFT's device time (the key switch and
+        # the modulus switch are below 3% of it); the whole FFT's device
+        # time is the denominator
+        "roofline": {"bound": "alu", "achieved": info.gates * n * ring_modmuls_per_cmux(d) / per / 1e9,
+                     "peak": PEAK_MODMUL / 1e9, "unit": "Gmodmul/s",
+                     "frac": info.gates * n * ring_modmuls_per_cmux(d) / per / PEAK_MODMUL, "traffic": None,
+                     "kernel": "k_ring_blind_rotate", "over": "whole FFT (device time, HIP events)",
+                     "modmul_per_gate": n * ring_modmuls_per_cmux(d)},
     }
 
 
@@ -1107,6 +1123,8 @@ def main():
     ap.add_argument("--load", type=float, default=0.7, help="serve mode: offered load as a fraction of capacity")
     ap.add_argument("--rate-bitmac", type=float, default=2.0e15, help="serve mode: capacity in bit-MAC/s")
     ap.add_argument("--io-gb", type=float, default=60.0, help="serve mode: ciphertexts of requests in flight")
+    ap.add_argument("--plan-ws-gb", type=float, default=40.0,
+                    help="serve mode: workspace bound of plans that would need more (list-scheduled levels)")
     ap.add_argument("--signals", type=int, default=4, help="accuracy mode: signals per length")
     ap.add_argument("--fill-blocks", type=int, default=-1,
                     help="batch/serve: request-loop fill target in workgroups, 0 = lockstep "
@@ -1237,6 +1255,7 @@ def main():
         "avg_launch_ms": kern_ms / max(1, n_launch),
         "bitmac_per_s": achieved,
         "frac_vs_popcount_ceiling": achieved / PEAK_POPCOUNT,
+        "frac_vs_valu_lookup_ceiling": achieved / PEAK_LOOKUP,
     })
     out = {
         "metric": "encrypted gates/s (1 GPU)",

@@ -27,7 +27,7 @@ def test_bounded_plan_matches_unbounded(shape):
     ct_in = api.encrypt_words(keys, words, F, seed=11)
     free = api.Plan(dims, L, F, f, cplx, p)
     want = free.execute(ct_in)
-    lim = free.ws_bytes // 3
+    lim = free.ws_bytes // 2
     bnd = api.Plan(dims, L, F, f, cplx, p, ws_limit_bytes=lim)
     assert bnd.ws_bytes <= lim and bnd.info.levels > free.info.levels
     got = bnd.execute(ct_in)
