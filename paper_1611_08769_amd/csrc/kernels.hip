@@ -1408,7 +1408,7 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const int nchunks = (nct + KC - 1) / KC;
     const gword* Lp = ctp(bufs, it.L);
     const gword* Rp = ctp(bufs, it.R);
-    const int QP = PR * (ww / 4);                   // quads of words of an epilogue pass
+    const int QP = PR * ww / 4;                     // quads of words of an epilogue pass (PR = 16)
     const int OPB = (16 * QP + 1023) / 1024 * 1024;     // LDS bytes of one operand's quads
     const int main_bytes = mfma2_main_bytes(CF);
     const int e_bytes = mfma2_epi_bytes(CF, QP);
@@ -1530,17 +1530,27 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
             }
         }
     }
-    // Each wave takes whole rows of a pass (rpw of them, the qr quads of 4
-    // words of a row in consecutive lanes; the host serves only geometries
-    // whose split rows are whole quads, at most 16), so the carries between
-    // quads pass from lane to lane, with no LDS and no barrier.
-    const int qr = ww / 4;  // quads per row of the split
-    const int rpw = 64 / qr;
-    const int rw_rl = wave * rpw + lane / qr;  // this lane's row of a pass
-    const int rw_jj = lane % qr;              // and quad of the row
-    const bool rw_ok = lane < rpw * qr && rw_rl < PR;
-    const int rw_w = w0 + 4 * rw_jj;  // its first word
+    // Each wave takes whole groups of rows of a pass, the qg quads of 4
+    // words of a group in consecutive lanes, so the carries between quads
+    // pass from lane to lane, with no LDS and no barrier.  A group is one
+    // row where the (split) row is whole quads (at most 16 of them: the host
+    // serves nothing else when a row is split); whole rows that are not are
+    // contiguous in memory, and go in groups of 2 (an even number of words)
+    // or 4 rows that are, a quad then possibly ending one row and starting
+    // the next.
+    const int rpg = cs > 1 || (ww & 3) == 0 ? 1 : (ww & 1) ? 4 : 2;
+    const int qr = ww / 4;        // whole quads per row (rpg = 1)
+    const int qg = rpg * ww / 4;  // quads per group
+    const int gpw = 64 / qg;      // groups per wave
+    const int rw_g = wave * gpw + lane / qg;  // this lane's group of a pass
+    const int rw_jj = lane % qg;             // and quad of the group
+    const bool rw_ok = lane < gpw * qg && rw_g * rpg < PR;
+    const int rw_rr = 4 * rw_jj / ww;              // row of the group where the quad starts
+    const int rw_rl = rw_g * rpg + rw_rr;          // and of the pass
+    const int rw_w = w0 + 4 * rw_jj - rw_rr * ww;  // its first word
     const int rw_e = rw_w / kw, rw_l = rw_w - rw_e * kw;
+    const int rw_j = rw_g * qg + rw_jj;  // the quad's place in the staged operands
+    const int rw_off = rpg > 1 ? 4 * rw_j : rw_rl * W + rw_w;  // its words from the pass's first row
     int32_t* S = reinterpret_cast<int32_t*>(lds);
     uint8_t* OPS = reinterpret_cast<uint8_t*>(S + PR * SP);  // 2 buffers x (2 + kMaxE) operands
     // every operand's quads of pass p into buffer b, 64 quads per wave
@@ -1549,8 +1559,9 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     auto stage_ops = [&](int p, int b) {
         for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < QP; blk += NW) {
             const int j = 64 * blk + lane < QP ? 64 * blk + lane : QP - 1;
-            const int rl = j / qr;
-            const size_t off = (size_t)(row_base + PR * p + rl) * W + w0 + 4 * (j - rl * qr);
+            const int rl = rpg > 1 ? 0 : j / qr;
+            const size_t off = rpg > 1 ? (size_t)(row_base + PR * p) * W + 4 * j
+                                       : (size_t)(row_base + PR * p + rl) * W + w0 + 4 * (j - rl * qr);
 #pragma unroll
             for (int s = 0; s < 2 + kMaxE; s++)
                 if (s < nops)
@@ -1559,7 +1570,7 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     };
     // store instructions this wave issues per pass: one per output, where
     // any of its lanes holds a quad
-    const int nst = wave * rpw < PR ? nout : 0;
+    const int nst = wave * gpw * rpg < PR ? nout : 0;
     stage_ops(0, 0);
     const int npass = (nct - row_base < TM ? nct - row_base : TM) / PR;  // Nct is a multiple of 32
     for (int p = 0; p < npass; p++) {
@@ -1601,11 +1612,11 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
 #pragma unroll
             for (int o = 0; o < kMaxOut; o++) oq[o] = u32x4{0u, 0u, 0u, 0u}, cq[o] = 0;
             if (rw_ok) {
-                const int j = rw_rl * qr + rw_jj;  // the quad's place in the staged operands
-                int w = rw_w, e = rw_e, l = rw_l;
-                const int row = prow + rw_rl;
-                const int br = row / kb, tr = row - br * kb;
-                const int cpc = 128 * Pc[PR * p + rw_rl];  // each byte sum misses 128 per set bit of the row of L
+                const int j = rw_j;
+                int w = rw_w, e = rw_e, l = rw_l, rl = rw_rl;
+                int row = prow + rl;
+                int br = row / kb, tr = row - br * kb;
+                int cpc = 128 * Pc[PR * p + rl];  // each byte sum misses 128 per set bit of the row of L
                 const u32x4 lv = *reinterpret_cast<const u32x4*>(ob + 16 * j);
                 const u32x4 rv = *reinterpret_cast<const u32x4*>(ob + OPB + 16 * j);
                 u32x4 ev[kMaxE];
@@ -1621,13 +1632,18 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
                     if (u > 0) {
                         ++w, ++l;
                         if (l == kw) l = 0, ++e;
+                        if (w - w0 == ww) {  // the next row of the group
+                            w = w0, e = 0, l = 0, ++rl, ++row;
+                            br = row / kb, tr = row - br * kb;
+                            cpc = 128 * Pc[PR * p + rl];
+                        }
                     }
                     if (l == 0) {
                         qm |= 1 << u;
 #pragma unroll
                         for (int o = 0; o < kMaxOut; o++) cy[o] = 0;
                     }
-                    const i32x4 s4 = *reinterpret_cast<const i32x4*>(S + rw_rl * SP + 4 * mfma_sum_unit(w - w0));
+                    const i32x4 s4 = *reinterpret_cast<const i32x4*>(S + rl * SP + 4 * mfma_sum_unit(w - w0));
                     const int s0 = s4[0] + cpc, s1 = s4[1] + cpc, s2 = s4[2] + cpc, s3 = s4[3] + cpc;
                     const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
                     const int Ll = lv[u] & 0xFFFF, Lh = lv[u] >> 16, Rl = rv[u] & 0xFFFF, Rh = rv[u] >> 16;
@@ -1682,7 +1698,7 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
             }
             // 4. outputs
             if (rw_ok) {
-                const size_t off = (size_t)(prow + rw_rl) * W + rw_w;
+                const size_t off = (size_t)prow * W + rw_off;
 #pragma unroll
                 for (int o = 0; o < kMaxOut; o++)
                     if (o < nout) *reinterpret_cast<gu32x4*>(Do[o] + off) = oq[o];
@@ -1943,8 +1959,10 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
         const int bytes = cs == 1 ? 4 * g.W : eps * g.k / 8;
         if ((bytes + 31) / 32 <= 2 * (t.cf - 1)) return false;
         const int ww = cs == 1 ? g.W : eps * g.kw;  // words of a split row
-        if (ww % 4 != 0 || ww / 4 > 16) return false;
-        const int qp = 16 * (ww / 4);
+        // split rows in whole quads, at most 16; whole rows (W <= 64) of any
+        // number of words, in groups of rows that are whole quads
+        if (cs > 1 && (ww % 4 != 0 || ww / 4 > 16)) return false;
+        const int qp = 16 * ww / 4;
         cfg->cs = cs;
         cfg->lds_bytes = std::max(mfma2_main_bytes(t.cf), mfma2_epi_bytes(t.cf, qp)) + tail;
         return cfg->lds_bytes <= 160 * 1024;

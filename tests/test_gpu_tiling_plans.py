@@ -1,8 +1,9 @@
 """GPU: every matrix-core tiling that transposes the right operands in a pass
 before the product launch (the 128-row chunk layout of the 512-thread kernel
 and the 64-row layout of the 256-thread kernel, with its column splits of
-whole elements), forced on a small encrypted FFT plan at chosen ciphertext
-geometries, gives the oracle's ciphertexts bit for bit.  The plan's products
+whole elements and its rows that are not whole quads of words), forced on a
+small encrypted FFT plan at chosen ciphertext geometries, gives the oracle's
+ciphertexts bit for bit.  The plan's products
 carry every epilogue form of the adders: AND, XOR and carries that add an
 extra operand (the paper's Lemma "evaluation": the encrypted circuit
 decrypts to the plain one)."""
@@ -45,7 +46,7 @@ def _served(n1, k, cf):
         return None
     cs = -(-n1 // e)
     ww = n1 * k // 32 if cs == 1 else e * k // 32  # words of a split row
-    if ww % 4 or ww // 4 > 16:
+    if cs > 1 and (ww % 4 or ww // 4 > 16):  # split rows: whole quads
         return None
     return cs if -(-(4 * ww) // 32) > 2 * (cf - 1) else None
 
@@ -66,10 +67,15 @@ def _geos(f):
     nf = cgw * cf
     if pre == 1:
         return [(1, 128 * nf), _ragged(nf)]  # rows filling nf fragments; a ragged odd row
-    # the 256-thread kernel serves rows of whole quads of words only: rows
-    # filling nf fragments; 4 elements of an odd number of limbs (elements
-    # end inside quads)
-    out = [(1, 128 * nf), (3, 32 * (4 * cf - 1))]
+    # the 256-thread kernel: rows filling nf fragments; 4 elements of an odd
+    # number of limbs (elements end inside quads); whole rows that are not
+    # whole quads of words, which its epilogue takes two rows (an even
+    # number of words: 2 elements of an odd number of limbs) or four rows
+    # (an odd number: 3 elements of an odd number of limbs) at a time, a
+    # quad then ending one row and starting the next
+    w2 = max(w for w in range(2, 16 * cf + 1, 4))
+    wodd = max(w for w in range(3, 16 * cf + 1, 6))
+    out = [(1, 128 * nf), (3, 32 * (4 * cf - 1)), (1, 32 * (w2 // 2)), (2, 32 * (wodd // 3))]
     # and the smallest geometry served in more than one column split
     best = None
     for n in (1, 2, 3):
