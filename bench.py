@@ -238,13 +238,32 @@ def run_batch(args, count=None):
         keys = api.keygen(p, 1000 + i)
         return keys, api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=1000 + i)
 
-    def finish(i, keys, ct_out):
+    def finish(i, keys, ct_out, stream=None):
         sig = reqs[i][0]
-        dec = api.decrypt_words(keys, ct_out, 2 * sig.length, sig.F)
+        dec = api.decrypt_words(keys, ct_out, 2 * sig.length, sig.F, stream=stream)
         ok = expect is None or _words_sha(dec) == expect[i]["words_sha256"]
         n = ct_out.shape[0]
         fp = hashlib.sha256(ct_out[[0, n // 2, n - 1]].cpu().numpy().tobytes()).hexdigest()
         return ok, fp
+
+    # The client's work in the batched run (keys, encryption, decryption,
+    # fingerprints) goes through a stream of its own, which does not wait for
+    # the request loop's steps on the default stream: a request's inputs are
+    # complete before it is submitted (this stream synchronised), and its
+    # outputs once the loop reports it done.
+    io = torch.cuda.Stream()
+
+    def encrypt_io(i):
+        with torch.cuda.stream(io):
+            sig, p, _ = reqs[i]
+            keys = api.keygen(p, 1000 + i)
+            ct = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=1000 + i, stream=io)
+        io.synchronize()
+        return keys, ct
+
+    def finish_io(i, keys, ct_out):
+        with torch.cuda.stream(io):
+            return finish(i, keys, ct_out, stream=io)
 
     # every distinct plan tuned once before the clock, on an encryption of
     # its first request (the same plans run alone and in the batch)
@@ -299,23 +318,23 @@ def run_batch(args, count=None):
         while waiting:
             i = waiting[0]
             plan = reqs[i][2]
-            io = (plan.info.n_inputs + plan.info.n_outputs) * plan.ct_words * 4
-            if live and io_used + io > io_cap:
+            io_b = (plan.info.n_inputs + plan.info.n_outputs) * plan.ct_words * 4
+            if live and io_used + io_b > io_cap:
                 break
-            keys, ct_in = encrypt(i)
+            keys, ct_in = encrypt_io(i)
             ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
-            live[srv.submit_plan(plan, ct_in, ct_out)] = (i, keys, ct_out, io, time.perf_counter())
-            io_used += io
+            live[srv.submit_plan(plan, ct_in, ct_out)] = (i, keys, ct_out, io_b, time.perf_counter())
+            io_used += io_b
             waiting.popleft()
         max_live = max(max_live, len(live))
         srv.step()
         for t in list(live):
             done, _ = srv.poll(t)
             if done:
-                i, keys, ct_out, io, t_sub = live.pop(t)
+                i, keys, ct_out, io_b, t_sub = live.pop(t)
                 lat[i] = time.perf_counter() - t_sub
-                ok_batch[i], fp_batch[i] = finish(i, keys, ct_out)
-                io_used -= io
+                ok_batch[i], fp_batch[i] = finish_io(i, keys, ct_out)
+                io_used -= io_b
                 del ct_out
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
@@ -326,6 +345,9 @@ def run_batch(args, count=None):
     print("[bench] batched: %.2f s (%d steps, %d launches, up to %d in flight); outputs identical to alone: %s; "
           "decryptions equal the emulation: %s" % (t_batch, st.steps, st.launches, max_live, same, dec_ok),
           file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    fixed = fixed_batch(reqs, encrypt, finish, fp_alone, gates_of=lambda r: r[2].info.gates,
+                        mem_gb=args.fixed_batch_gb)
     ops = bitmacs / 4.0 / t_batch
     return {
         "metric": "encrypted gates/s (1 GPU, batched)",
@@ -357,7 +379,73 @@ def run_batch(args, count=None):
         "outputs_identical_to_alone": same,
         "all_decrypt_equal": dec_ok,
         "decrypt_checked": expect is not None,
+        "fixed_batch_graph": fixed,
     }
+
+
+def fixed_batch(reqs, encrypt, finish, fp_alone, gates_of, mem_gb):
+    """The first requests of the mix whose ciphertexts and workspaces fit
+    mem_gb, inputs encrypted before the clock, run as one fixed batch
+    (sfft_batch: the merged levels compiled once, captured into a HIP graph
+    on the first execution, replayed after) against the same requests one at
+    a time (each plan executed and waited for in turn).  Device work only:
+    no encryption or decryption in the timed regions.  Every output is
+    compared with the one-at-a-time run of the batched bench and decrypted."""
+    import torch
+    from paper_1611_08769_amd import api
+
+    take, used = [], 0.0
+    for i, (sig, p, plan) in enumerate(reqs):
+        need = (plan.info.n_inputs + plan.info.n_outputs) * plan.ct_words * 4 + plan.ws_bytes
+        if take and used + need > mem_gb * 1e9:
+            break
+        take.append(i)
+        used += need
+    ins, outs, keyz = {}, {}, {}
+    for i in take:
+        keyz[i], ins[i] = encrypt(i)
+        plan = reqs[i][2]
+        outs[i] = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
+    gates = sum(gates_of(reqs[i]) for i in take)
+    # one at a time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in take:
+        reqs[i][2].execute(ins[i], outs[i])
+        torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    for i in take:
+        reqs[i][2]._ws = None
+    torch.cuda.empty_cache()
+    batch = api.Batch([(reqs[i][2], ins[i], outs[i]) for i in take])
+    stream = torch.cuda.Stream()
+    for i in take:
+        outs[i].zero_()
+    torch.cuda.synchronize()
+    batch.execute_graph(stream)  # capture, instantiate, run
+    stream.synchronize()
+    t0 = time.perf_counter()
+    batch.execute_graph(stream)
+    stream.synchronize()
+    t_graph = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch.execute()
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    res = [finish(i, keyz[i], outs[i]) for i in take]
+    same = all(res[j][1] == fp_alone[i] for j, i in enumerate(take))
+    dec_ok = all(r[0] for r in res)
+    out = {"requests": len(take), "ciphertexts_and_workspace_gb": round(used / 1e9, 1), "steps": batch.steps,
+           "launches": batch.launches, "graph_s": t_graph, "eager_s": t_eager, "one_at_a_time_s": t_alone,
+           "gates_per_s_graph": gates / t_graph, "gates_per_s_one_at_a_time": gates / t_alone,
+           "speedup_graph_vs_one_at_a_time": t_alone / t_graph, "outputs_identical_to_alone": same,
+           "all_decrypt_equal": dec_ok}
+    print("[bench] fixed batch of %d requests: graph %.2f s, eager %.2f s, one at a time %.2f s; identical %s, "
+          "decrypt %s" % (len(take), t_graph, t_eager, t_alone, same, dec_ok), file=sys.stderr, flush=True)
+    batch.close()
+    del ins, outs
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_probe():
@@ -594,6 +682,9 @@ def run_serve(args, count=None):
     print("[bench] serve: %d requests, rate %.4f /s (load %.2f of %.2e bit-MAC/s), budget %.0f GB" % (
         len(sigs), rate, args.load, args.rate_bitmac, budget / 1e9), file=sys.stderr, flush=True)
 
+    # client work (keys, encryption, decryption) on a stream of its own that
+    # does not wait for the request loop's steps (see run_batch)
+    io_s = torch.cuda.Stream()
     waiting = collections.deque(range(len(sigs)))
     client_q = collections.deque()
     live = {}
@@ -614,8 +705,10 @@ def run_serve(args, count=None):
                 if fill > 0:
                     continue
                 break
-            keys = api.keygen(p, 5000 + i)
-            ct_in = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=5000 + i)
+            with torch.cuda.stream(io_s):
+                keys = api.keygen(p, 5000 + i)
+                ct_in = api.encrypt_words(keys, api.signal_words(sig), sig.F, seed=5000 + i, stream=io_s)
+            io_s.synchronize()
             ct_out = torch.empty((plan.info.n_outputs, plan.ct_words), dtype=torch.int32, device="cuda")
             live[srv.submit_plan(plan, ct_in, ct_out)] = (i, io, keys, ct_out)
             io_used += io
@@ -629,7 +722,8 @@ def run_serve(args, count=None):
                     io_used -= io
                     lat[i], t_done[i] = now - arrivals[i], now
                     # decrypted against the expected decryptions (the emulation)
-                    dec = api.decrypt_words(keys, ct_out, 2 * sigs[i].points, sigs[i].F)
+                    with torch.cuda.stream(io_s):
+                        dec = api.decrypt_words(keys, ct_out, 2 * sigs[i].points, sigs[i].F, stream=io_s)
                     dec_ok[i] = expect is None or _words_sha(dec) == expect[i]["words_sha256"]
                     del ct_out
                     print("[bench] request %d (%s %d) done: latency %.2f s" % (
@@ -1137,6 +1231,8 @@ def main():
     ap.add_argument("--no-mix", action="store_true",
                     help="default workload: skip the batched and served runs that follow the single request")
     ap.add_argument("--batch-requests", type=int, default=256, help="default workload: requests of the batched run")
+    ap.add_argument("--fixed-batch-gb", type=float, default=100.0,
+                    help="batch mode: ciphertexts and workspaces of the fixed batch run through a HIP graph")
     ap.add_argument("--serve-requests", type=int, default=16, help="default workload: requests of the served run")
     ap.add_argument("--no-tune", action="store_true", help="use the default tiling instead of tuning it first")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -1316,7 +1412,8 @@ def main():
         out["batch"] = {k: bt[k] for k in (
             "value", "unit", "ms_per_step", "one_at_a_time_gates_per_s", "one_at_a_time_s",
             "speedup_vs_one_at_a_time", "fft_points_per_s", "bitmac_per_s", "roofline", "latency_p50_s",
-            "latency_p99_s", "max_in_flight", "outputs_identical_to_alone", "all_decrypt_equal", "decrypt_checked")}
+            "latency_p99_s", "max_in_flight", "outputs_identical_to_alone", "all_decrypt_equal", "decrypt_checked",
+            "fixed_batch_graph")}
         out["batch"]["config"] = bt["config"]
         torch.cuda.empty_cache()
         sv = run_serve(args, count=args.serve_requests)

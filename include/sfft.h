@@ -184,6 +184,34 @@ int sfft_plan_time_products(sfft_plan* plan, int32_t enable);
 /* Waits for the recorded pairs, returns the sum of their elapsed times (ms)
  * and their number, and releases them. */
 int sfft_plan_product_time(sfft_plan* plan, double* total_ms, int64_t* launches);
+/* Fixed batches: a set of requests known in advance, merged level by level
+ * as the request loop merges them (global step s advances every request
+ * that has a step s; the products of all requests whose kernel tiling
+ * matches run in one launch, one segment per request with its own
+ * geometry; then the linear passes), but compiled once: every step's
+ * segment lists are uploaded at creation into one device table, so an
+ * execution is the launch sequence alone (section "FFT in FHE": the
+ * butterflies of a stage, and independent requests, run side by side).
+ * Each request's ciphertexts equal those of its plan run alone.  plans,
+ * ct_in_dev, ct_out_dev: n entries (request r runs plans[r] from ct_in_dev[r]
+ * into ct_out_dev[r], layouts of sfft_execute); the plans must outlive the
+ * batch.  ws_dev: at least sfft_batch_workspace_bytes, each request's
+ * workspace in its own 256-byte-aligned part.  The buffers are fixed for the
+ * batch's life. */
+typedef struct sfft_batch sfft_batch;
+int sfft_batch_workspace_bytes(const sfft_plan* const* plans, int32_t n, int64_t* bytes);
+int sfft_batch_create(const sfft_plan* const* plans, const uint32_t* const* ct_in_dev, uint32_t* const* ct_out_dev,
+                      int32_t n, void* ws_dev, int64_t ws_bytes, sfft_batch** out);
+/* Global steps and launches of one execution. */
+int sfft_batch_info(const sfft_batch* batch, int64_t* steps, int64_t* launches);
+/* Enqueues the launch sequence on hip_stream. */
+int sfft_batch_execute(const sfft_batch* batch, void* hip_stream);
+/* The same through a HIP graph: the first call captures the sequence on
+ * hip_stream (not the null stream) and instantiates it; every call launches
+ * it with one graph launch.  The graph holds no memset nodes. */
+int sfft_batch_execute_graph(sfft_batch* batch, void* hip_stream);
+/* Waits for the device, then frees the batch's table and graph. */
+void sfft_batch_destroy(sfft_batch* batch);
 /* Product items per step (counts has exec_steps entries). */
 int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n);
 
@@ -193,6 +221,13 @@ int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n);
  * synchronises the null stream). */
 int sfft_decrypt(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct, int64_t n_values,
                  int32_t F, int ct_on_device, int32_t* fixed_out);
+/* sfft_decrypt of device ciphertexts whose rows k-1 are read on hip_stream
+ * alone (an asynchronous copy, then a wait for that stream only): work on
+ * other streams keeps running.  The caller makes sure the ciphertexts are
+ * complete (for example a request of the request loop that has finished,
+ * sfft_server_poll). */
+int sfft_decrypt_stream(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct_dev, int64_t n_values,
+                        int32_t F, void* hip_stream, int32_t* fixed_out);
 /* Decryption of n_ct single bits. */
 int sfft_decrypt_bits(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct, int64_t n_ct,
                       int ct_on_device, int32_t* bits_out);

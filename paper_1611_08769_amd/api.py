@@ -65,10 +65,17 @@ def encrypt_words(keys: Keys, words, F: int, seed: int, first_ct_id: int = 0, ou
     return out
 
 
-def decrypt_words(keys: Keys, cts: torch.Tensor, n_values: int, F: int) -> np.ndarray:
-    torch.cuda.synchronize()
+def decrypt_words(keys: Keys, cts: torch.Tensor, n_values: int, F: int, stream=None) -> np.ndarray:
+    """Decrypted words.  Without a stream the whole device is synchronised
+    first; with one, only that stream carries the copy (the caller makes sure
+    the ciphertexts are complete)."""
     out = np.zeros(n_values, dtype=np.int32)
-    S.sfft_decrypt(keys.params, keys.sk_host.ctypes.data, cts.data_ptr(), n_values, F, 1, out.ctypes.data)
+    if stream is None:
+        torch.cuda.synchronize()
+        S.sfft_decrypt(keys.params, keys.sk_host.ctypes.data, cts.data_ptr(), n_values, F, 1, out.ctypes.data)
+    else:
+        S.sfft_decrypt_stream(keys.params, keys.sk_host.ctypes.data, cts.data_ptr(), n_values, F,
+                              _stream_ptr(stream), out.ctypes.data)
     return out.astype(np.int64)
 
 
@@ -194,6 +201,40 @@ def signal_words(sig) -> np.ndarray:
         return re
     im = quantize(np.asarray(sig.im).ravel(), sig.F, sig.f)
     return np.stack([re, im], 1).ravel()
+
+
+class Batch:
+    """A fixed batch of (plan, ct_in, ct_out) requests merged level by level
+    and compiled once (sfft_batch_*); the workspace is allocated here."""
+
+    def __init__(self, requests):
+        self._keep = list(requests)
+        plans = [p.handle for p, _, _ in requests]
+        self.ws_bytes = S.sfft_batch_workspace_bytes(plans)
+        self._ws = torch.empty(max(1, self.ws_bytes // 4), dtype=torch.int32, device="cuda")
+        self.handle = S.sfft_batch_create(plans, [i.data_ptr() for _, i, _ in requests],
+                                          [o.data_ptr() for _, _, o in requests], self._ws.data_ptr(),
+                                          self._ws.numel() * 4)
+        self.steps, self.launches = S.sfft_batch_info(self.handle)
+
+    def execute(self, stream=None):
+        S.sfft_batch_execute(self.handle, _stream_ptr(stream))
+
+    def execute_graph(self, stream=None):
+        """One graph launch (captured on first use) on `stream`, a torch
+        stream other than the null stream (the current one by default)."""
+        S.sfft_batch_execute_graph(self.handle, _stream_ptr(stream))
+
+    def close(self):
+        if self.handle:
+            S.sfft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -23,7 +23,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", o
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["netlist.cpp", "schedule.cpp", "abi.cpp", "server.cpp", "tune.cpp", "kernels.hip", "ring.hip",
+SOURCES = ["netlist.cpp", "schedule.cpp", "abi.cpp", "server.cpp", "batch.cpp", "tune.cpp", "kernels.hip", "ring.hip",
            "noalloc.hip"]
 
 

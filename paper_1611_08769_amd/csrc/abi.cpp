@@ -641,8 +641,13 @@ int sfft_plan_step_products(const sfft_plan* plan, int64_t* counts, int32_t n)
     return SFFT_OK;
 }
 
-int sfft_decrypt_bits(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_ct,
-                      int ct_on_device, int32_t* bits_out)
+}  // extern "C"
+
+namespace {
+// Bits of n_ct ciphertexts (host, or device: row k-1 of each copied to the
+// host, on the null stream or, with on_stream, on hip_stream alone).
+int decrypt_bits_impl(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_ct,
+                      int ct_on_device, bool on_stream, void* hip_stream, int32_t* bits_out)
 {
     std::string why;
     if (!params_ok(p, &why)) return fail(SFFT_EINVAL, why);
@@ -655,8 +660,16 @@ int sfft_decrypt_bits(const sfft_params* p, const uint32_t* sk_host, const uint3
     int64_t stride = cw;
     if (ct_on_device && n_ct > 0) {
         rows.resize((size_t)n_ct * g.W);
-        hipError_t e = hipMemcpy2D(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
-                                   sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost);
+        hipError_t e;
+        if (on_stream) {
+            const hipStream_t s = (hipStream_t)hip_stream;
+            e = hipMemcpy2DAsync(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
+                                 sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        } else {
+            e = hipMemcpy2D(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
+                            sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost);
+        }
         if (e != hipSuccess) return hip_fail(e, "decrypt copy");
         src = rows.data();
         stride = g.W;
@@ -667,13 +680,13 @@ int sfft_decrypt_bits(const sfft_params* p, const uint32_t* sk_host, const uint3
     return SFFT_OK;
 }
 
-int sfft_decrypt(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_values, int32_t F,
-                 int ct_on_device, int32_t* fixed_out)
+int decrypt_impl(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_values, int32_t F,
+                 int ct_on_device, bool on_stream, void* hip_stream, int32_t* fixed_out)
 {
     if (F < 1 || F > 32 || n_values < 0) return fail(SFFT_EINVAL, "bad F or n_values");
     if (n_values > 0 && !fixed_out) return fail(SFFT_EINVAL, "null output");
     std::vector<int32_t> bits((size_t)(n_values * F));
-    const int rc = sfft_decrypt_bits(p, sk_host, ct, n_values * F, ct_on_device, bits.data());
+    const int rc = decrypt_bits_impl(p, sk_host, ct, n_values * F, ct_on_device, on_stream, hip_stream, bits.data());
     if (rc != SFFT_OK) return rc;
     for (int64_t v = 0; v < n_values; v++) {
         uint32_t u = 0;
@@ -682,6 +695,27 @@ int sfft_decrypt(const sfft_params* p, const uint32_t* sk_host, const uint32_t* 
         fixed_out[v] = (int32_t)u;
     }
     return SFFT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int sfft_decrypt_bits(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_ct,
+                      int ct_on_device, int32_t* bits_out)
+{
+    return decrypt_bits_impl(p, sk_host, ct, n_ct, ct_on_device, false, nullptr, bits_out);
+}
+
+int sfft_decrypt(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct, int64_t n_values, int32_t F,
+                 int ct_on_device, int32_t* fixed_out)
+{
+    return decrypt_impl(p, sk_host, ct, n_values, F, ct_on_device, false, nullptr, fixed_out);
+}
+
+int sfft_decrypt_stream(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct_dev, int64_t n_values,
+                        int32_t F, void* hip_stream, int32_t* fixed_out)
+{
+    return decrypt_impl(p, sk_host, ct_dev, n_values, F, 1, true, hip_stream, fixed_out);
 }
 
 }  // extern "C"

@@ -99,9 +99,16 @@ _SIGS = {
     "sfft_execute_steps": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "sfft_plan_step_products": (ctypes.c_int, [_vp, _P(ctypes.c_int64), ctypes.c_int32]),
     "sfft_plan_time_products": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "sfft_batch_workspace_bytes": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(ctypes.c_int64)]),
+    "sfft_batch_create": (ctypes.c_int, [_P(_vp), _P(_vp), _P(_vp), ctypes.c_int32, _vp, ctypes.c_int64, _P(_vp)]),
+    "sfft_batch_info": (ctypes.c_int, [_vp, _P(ctypes.c_int64), _P(ctypes.c_int64)]),
+    "sfft_batch_execute": (ctypes.c_int, [_vp, _vp]),
+    "sfft_batch_execute_graph": (ctypes.c_int, [_vp, _vp]),
+    "sfft_batch_destroy": (None, [_vp]),
     "sfft_plan_product_time": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "sfft_decrypt": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, _vp]),
     "sfft_decrypt_bits": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
+    "sfft_decrypt_stream": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp]),
     "sfft_gate": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "sfft_server_create": (ctypes.c_int, [_P(sfft_server_cfg), _P(_vp)]),
     "sfft_server_submit": (ctypes.c_int, [_vp, _P(sfft_shape), _P(sfft_params), _vp, _vp, _P(ctypes.c_uint64)]),
@@ -238,6 +245,41 @@ def sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_byt
     _check(_lib.sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
 
 
+def _ptr_array(ptrs):
+    return (_vp * len(ptrs))(*ptrs)
+
+
+def sfft_batch_workspace_bytes(plans) -> int:
+    v = ctypes.c_int64()
+    _check(_lib.sfft_batch_workspace_bytes(_ptr_array(plans), len(plans), ctypes.byref(v)))
+    return v.value
+
+
+def sfft_batch_create(plans, ins, outs, ws_ptr, ws_bytes) -> int:
+    h = _vp()
+    _check(_lib.sfft_batch_create(_ptr_array(plans), _ptr_array(ins), _ptr_array(outs), len(plans), ws_ptr, ws_bytes,
+                                  ctypes.byref(h)))
+    return h.value
+
+
+def sfft_batch_info(batch):
+    st, la = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.sfft_batch_info(batch, ctypes.byref(st), ctypes.byref(la)))
+    return st.value, la.value
+
+
+def sfft_batch_execute(batch, stream) -> None:
+    _check(_lib.sfft_batch_execute(batch, stream))
+
+
+def sfft_batch_execute_graph(batch, stream) -> None:
+    _check(_lib.sfft_batch_execute_graph(batch, stream))
+
+
+def sfft_batch_destroy(batch) -> None:
+    _lib.sfft_batch_destroy(batch)
+
+
 def sfft_plan_time_products(plan, enable) -> None:
     _check(_lib.sfft_plan_time_products(plan, int(enable)))
 
@@ -252,6 +294,10 @@ def sfft_plan_step_products(plan, n):
     arr = (ctypes.c_int64 * n)()
     _check(_lib.sfft_plan_step_products(plan, arr, n))
     return list(arr)
+
+
+def sfft_decrypt_stream(p, sk_host_ptr, ct_dev_ptr, n_values, F, stream, out_ptr) -> None:
+    _check(_lib.sfft_decrypt_stream(ctypes.byref(p), sk_host_ptr, ct_dev_ptr, n_values, F, stream, out_ptr))
 
 
 def sfft_decrypt(p, sk_host_ptr, ct_ptr, n_values, F, on_device, out_ptr) -> None:
