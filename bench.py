@@ -222,9 +222,11 @@ def run_batch(args, count=None):
     lengths = tuple(n for n in (8, 16, 32, 64, 128) if n <= args.max_len)
     count = count or args.requests or 256
     sigs = WL.batch_requests(seed=4, count=count, lengths=lengths)
-    exp = _mix_expect("batch")
-    expect = (exp["requests"] if tuple(exp["lengths"]) == lengths and exp["seed"] == 4 and count <= exp["count"]
-              else None)
+    expect = None
+    for kind in ("batch", "batch_small"):
+        exp = _mix_expect(kind)
+        if tuple(exp["lengths"]) == lengths and exp["seed"] == 4 and count <= exp["count"]:
+            expect = exp["requests"]
     reqs, plans = [], {}
     for sig in sigs:
         p = api.size_params(1, sig.length, sig.F, sig.f, True, 1)
@@ -346,8 +348,8 @@ def run_batch(args, count=None):
           "decryptions equal the emulation: %s" % (t_batch, st.steps, st.launches, max_live, same, dec_ok),
           file=sys.stderr, flush=True)
     torch.cuda.empty_cache()
-    fixed = fixed_batch(reqs, encrypt, finish, fp_alone, gates_of=lambda r: r[2].info.gates,
-                        mem_gb=args.fixed_batch_gb)
+    fixed = (fixed_batch(reqs, encrypt, finish, fp_alone, gates_of=lambda r: r[2].info.gates,
+                         mem_gb=args.fixed_batch_gb) if args.fixed_batch_gb > 0 else None)
     ops = bitmacs / 4.0 / t_batch
     return {
         "metric": "encrypted gates/s (1 GPU, batched)",
@@ -381,6 +383,77 @@ def run_batch(args, count=None):
         "decrypt_checked": expect is not None,
         "fixed_batch_graph": fixed,
     }
+
+
+def small_plan_latency(plan, ct_in, ct_out, args, reps=20):
+    """For a plan whose widest level needs at most two rounds of the GPU's
+    workgroup slots: the FFT in one persistent launch
+    (sfft_execute_persistent) against the launch per level, latency per FFT
+    from HIP events, and the outputs compared bit for bit."""
+    import torch
+    from paper_1611_08769_amd import sfft as S
+    if plan.info.max_level_products * 3 > 512:  # (128-row tiles; the small workloads have Nct <= 384)
+        return None
+    ref = ct_out.clone()
+    got = torch.zeros_like(ct_out)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    try:
+        per_level = timed(lambda: plan.execute(ct_in, got))
+        persistent = timed(lambda: plan.execute_persistent(ct_in, got))
+    except S.SfftError as e:
+        return {"persistent": "not served: %s" % e}
+    timeouts = S.sfft_plan_persistent_timeouts(plan.handle)
+    same = bool(torch.equal(got, ref))
+    print("[bench] small plan: launch per level %.3f ms, persistent %.3f ms per FFT (identical %s)" % (
+        per_level, persistent, same), file=sys.stderr, flush=True)
+    return {"ms_per_fft_launch_per_level": per_level, "ms_per_fft_persistent": persistent,
+            "outputs_identical": same, "barrier_timeouts": timeouts, "ffts": reps}
+
+
+def output_checks(workload, keys, ct_out, sig, info, params, samples=16):
+    """The timed run's outputs against the oracle's stored ones (SHA-256 of
+    the output ciphertexts and the decrypted words, tests/golden, written
+    from the oracle alone), and the noise measured on evenly spaced output
+    ciphertexts against the plan's worst-case bound."""
+    import hashlib
+    import torch
+    from paper_1611_08769_amd import api
+    from paper_1611_08769_amd import sfft as S
+
+    n_vals = 2 * sig.points
+    dec = api.decrypt_words(keys, ct_out, n_vals, sig.F)
+    parity = None
+    gpath = os.path.join(ROOT, "tests", "golden", "ciphertexts_%s.json" % workload)
+    if os.path.exists(gpath):
+        gd = json.load(open(gpath))
+        h = hashlib.sha256(np.ascontiguousarray(ct_out.cpu().numpy().view(np.uint32), dtype="<u4").tobytes())
+        parity = {"outputs_sha256_equal_oracle": h.hexdigest() == gd["outputs_sha256"],
+                  "decrypt_equal_oracle": dec.tolist() == gd["output_words"], "golden": os.path.basename(gpath)}
+    n_out = int(info.n_outputs)
+    idx = sorted({int(round(j * (n_out - 1) / (samples - 1))) for j in range(samples)})
+    mu = np.array([(int(dec[j // sig.F]) >> (j % sig.F)) & 1 for j in idx], dtype=np.int32)
+    sub = ct_out[torch.tensor(idx, device=ct_out.device)].contiguous()
+    torch.cuda.synchronize()
+    measured = S.sfft_noise_bits(keys.params, keys.sk_host.ctypes.data, sub.data_ptr(), len(idx), mu.ctypes.data,
+                                 torch.cuda.current_stream().cuda_stream)
+    noise = {"measured_max_bits": measured, "bound_bits": int(info.noise_bound_bits), "k": int(params.k),
+             "sampled_outputs": len(idx), "what": "bit length of the largest |e| over every row of the sampled "
+             "output ciphertexts (C' s = mu G s + e) against the plan's worst-case bound; decryption is correct "
+             "while it stays below k - 2 bits"}
+    print("[bench] outputs: parity %s; noise %d bits measured, bound %d, k = %d" % (
+        parity, measured, info.noise_bound_bits, params.k), file=sys.stderr, flush=True)
+    return parity, noise
 
 
 def fixed_batch(reqs, encrypt, finish, fp_alone, gates_of, mem_gb):
@@ -685,6 +758,8 @@ def run_serve(args, count=None):
     # client work (keys, encryption, decryption) on a stream of its own that
     # does not wait for the request loop's steps (see run_batch)
     io_s = torch.cuda.Stream()
+    noise, per_req = [None] * len(sigs), []
+    p_of = [plans[(sg.dims, sg.length)][0] for sg in sigs]
     waiting = collections.deque(range(len(sigs)))
     client_q = collections.deque()
     live = {}
@@ -724,10 +799,23 @@ def run_serve(args, count=None):
                     # decrypted against the expected decryptions (the emulation)
                     with torch.cuda.stream(io_s):
                         dec = api.decrypt_words(keys, ct_out, 2 * sigs[i].points, sigs[i].F, stream=io_s)
+                        # the noise of 4 output ciphertexts against the plan's bound
+                        n_out, Fi = ct_out.shape[0], sigs[i].F
+                        idx = [0, n_out // 3, (2 * n_out) // 3, n_out - 1]
+                        mu = np.array([(int(dec[j // Fi]) >> (j % Fi)) & 1 for j in idx], dtype=np.int32)
+                        sub = ct_out[torch.tensor(idx, device=ct_out.device)].contiguous()
+                        noise[i] = S.sfft_noise_bits(p_of[i], keys.sk_host.ctypes.data, sub.data_ptr(), len(idx),
+                                                     mu.ctypes.data, io_s.cuda_stream)
+                        del sub
                     dec_ok[i] = expect is None or _words_sha(dec) == expect[i]["words_sha256"]
                     del ct_out
-                    print("[bench] request %d (%s %d) done: latency %.2f s" % (
-                        i, "2D" if sigs[i].dims == 2 else "1D", sigs[i].length, lat[i]), file=sys.stderr, flush=True)
+                    bound = plans[(sigs[i].dims, sigs[i].length)][1].info.noise_bound_bits
+                    print("[bench] request %d (%s %d) done: latency %.2f s, noise %d bits (bound %d, k %d)" % (
+                        i, "2D" if sigs[i].dims == 2 else "1D", sigs[i].length, lat[i], noise[i], bound,
+                        p_of[i].k), file=sys.stderr, flush=True)
+                    per_req.append({"request": i, "shape": "%dD %d" % (sigs[i].dims, sigs[i].length),
+                                    "latency_s": lat[i], "noise_bits": noise[i], "noise_bound_bits": bound,
+                                    "k": p_of[i].k, "decrypt_equal": dec_ok[i]})
         elif waiting:
             time.sleep(max(0.0, min(0.05, arrivals[waiting[0]] - now)))
     torch.cuda.synchronize()
@@ -761,6 +849,8 @@ def run_serve(args, count=None):
         "latency_p50_s": pct(lat, 50),
         "latency_p99_s": pct(lat, 99),
         "latency_mean_s": float(np.mean(lat)),
+        "requests_detail": per_req,
+        "noise_within_bound": all(r["noise_bits"] <= r["noise_bound_bits"] for r in per_req),
         "steps_run": int(st.steps),
         "max_in_flight": int(st.max_active),
         "all_decrypt_equal": all(dec_ok),
@@ -1231,6 +1321,8 @@ def main():
     ap.add_argument("--no-mix", action="store_true",
                     help="default workload: skip the batched and served runs that follow the single request")
     ap.add_argument("--batch-requests", type=int, default=256, help="default workload: requests of the batched run")
+    ap.add_argument("--batch-small-requests", type=int, default=128,
+                    help="default workload: requests of the batched run of small requests (N = 8..32)")
     ap.add_argument("--fixed-batch-gb", type=float, default=100.0,
                     help="batch mode: ciphertexts and workspaces of the fixed batch run through a HIP graph")
     ap.add_argument("--serve-requests", type=int, default=16, help="default workload: requests of the served run")
@@ -1398,6 +1490,8 @@ def main():
             alg = (info.prod_ct_reads + info.prod_ct_writes) * nct * nct / 8 / max(1, info.levels)
             out["roofline"]["algorithmic_bytes_per_launch"] = alg
             out["roofline"]["traffic_vs_algorithmic_bytes"] = tr["traffic_bytes_per_launch"] / alg
+    out["parity"], out["noise"] = output_checks(args.workload, keys, ct_out, sig, info, params)
+    out["small_plan"] = small_plan_latency(plan, ct_in, ct_out, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, nct, params.n_lwe + 1, params.k // 32, info.gates,
                                            info.products, args.cpu_budget)
@@ -1416,10 +1510,22 @@ def main():
             "fixed_batch_graph")}
         out["batch"]["config"] = bt["config"]
         torch.cuda.empty_cache()
+        # the same comparison on small requests (N = 8..32), whose levels
+        # leave most of the GPU idle when run alone
+        bs_args = argparse.Namespace(**vars(args))
+        bs_args.max_len, bs_args.fixed_batch_gb = 32, 0.0
+        bs = run_batch(bs_args, count=args.batch_small_requests)
+        out["batch_small"] = {k: bs[k] for k in (
+            "value", "unit", "ms_per_step", "one_at_a_time_gates_per_s", "one_at_a_time_s",
+            "speedup_vs_one_at_a_time", "latency_p50_s", "latency_p99_s", "max_in_flight",
+            "outputs_identical_to_alone", "all_decrypt_equal", "decrypt_checked")}
+        out["batch_small"]["config"] = bs["config"]
+        torch.cuda.empty_cache()
         sv = run_serve(args, count=args.serve_requests)
         out["serve"] = {k: sv[k] for k in (
             "value", "unit", "ms_per_step", "fft_points_per_s", "bitmac_per_s", "latency_p50_s", "latency_p99_s",
-            "latency_mean_s", "max_in_flight", "all_decrypt_equal", "decrypt_checked")}
+            "latency_mean_s", "max_in_flight", "all_decrypt_equal", "decrypt_checked", "noise_within_bound",
+            "requests_detail")}
         out["serve"]["config"] = sv["config"]
     print(json.dumps(out), flush=True)
 

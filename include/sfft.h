@@ -88,6 +88,8 @@ typedef struct {
     int64_t ws_bytes;             /* workspace bytes sfft_execute needs (= sfft_plan_workspace_bytes):
                                      ws_cts slots, then the matrix-core kernel's copies of one level's
                                      right operands */
+    int32_t noise_bound_bits;     /* bit length of the worst-case output noise bound at this Nct
+                                     (k must exceed it by 3: the noise rule) */
 } sfft_plan_info;
 
 const char* sfft_last_error(void);
@@ -175,6 +177,24 @@ int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
  * Enqueues only. */
 #define SFFT_NOALLOC_WS_BYTES (64ll << 20)
 int sfft_execute_noalloc(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* hip_stream);
+/* sfft_execute in one persistent launch, for small plans whose levels are
+ * too small to fill the GPU (a kernel boundary per level then costs about as
+ * much as the level): a cooperative launch of the 512-thread matrix-core
+ * kernel with in-kernel transposition, as many workgroups as are resident at
+ * once (at most what the widest level uses), loops over every level's
+ * product tiles and linear items with a grid-wide barrier between levels
+ * (agent-scope release and acquire around a counter).  The barrier's waits
+ * are bounded (about 0.1 s): one that runs out sets a flag
+ * (sfft_plan_persistent_timeouts) instead of hanging.  The first call
+ * uploads the plan's level tables and allocates its barrier words.
+ * SFFT_EUNSUPPORTED for rows of more than 8 fragments (4 W > 256 bytes).
+ * Same ciphertexts as sfft_execute.  Executions on one plan must not
+ * overlap (they share the barrier words). */
+int sfft_execute_persistent(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                            int64_t ws_bytes, void* hip_stream);
+/* Waits for the device; *flag = 1 if a barrier wait of a persistent
+ * execution on this plan ran out since its last launch began, else 0. */
+int sfft_plan_persistent_timeouts(sfft_plan* plan, int32_t* flag);
 /* Measurement aid.  With enable != 0, every later sfft_execute_steps (and
  * sfft_execute) call on this plan records a pair of HIP events on its stream
  * around each level's product kernel alone (after the right operands'
@@ -228,6 +248,15 @@ int sfft_decrypt(const sfft_params* params, const uint32_t* sk_host, const uint3
  * sfft_server_poll). */
 int sfft_decrypt_stream(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct_dev, int64_t n_values,
                         int32_t F, void* hip_stream, int32_t* fixed_out);
+/* Measured noise (Lemma "decryption": C' s = mu G s + e, row r of G s being
+ * 2^t s_b for r = b k + t): for each of n_ct device ciphertexts whose bits
+ * are mu_bits, e_r = <C'_r, s> - mu 2^t s_b mod q, centred; *max_bits is the
+ * bit length of the largest |e_r| over every row of every ciphertext (0 for
+ * none).  Reads whole ciphertexts (Nct^2/8 bytes each) on hip_stream and
+ * waits for that stream; the caller makes sure they are complete.  Host
+ * arithmetic. */
+int sfft_noise_bits(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct_dev, int64_t n_ct,
+                    const int32_t* mu_bits, void* hip_stream, int32_t* max_bits);
 /* Decryption of n_ct single bits. */
 int sfft_decrypt_bits(const sfft_params* params, const uint32_t* sk_host, const uint32_t* ct, int64_t n_ct,
                       int ct_on_device, int32_t* bits_out);

@@ -129,6 +129,15 @@ class Plan:
         S.sfft_execute_steps(self.handle, first, count, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(),
                              ws.numel() * 4, _stream_ptr(stream))
 
+    def execute_persistent(self, ct_in: torch.Tensor, ct_out: torch.Tensor | None = None, stream=None):
+        """execute() in one persistent launch (small plans)."""
+        if ct_out is None:
+            ct_out = torch.empty((self.info.n_outputs, self.ct_words), dtype=torch.int32, device="cuda")
+        ws = self.workspace()
+        S.sfft_execute_persistent(self.handle, ct_in.data_ptr(), ct_out.data_ptr(), ws.data_ptr(), ws.numel() * 4,
+                                  _stream_ptr(stream))
+        return ct_out
+
     def time_products(self, enable: bool) -> None:
         """Record HIP events around each level's product kernel in later
         execute / execute_steps calls (product_time() collects them)."""

@@ -1,5 +1,6 @@
 // C ABI of libsfft: keys, encryption, plans, execution, decryption, gates.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdio>
 #include <cstring>
@@ -277,6 +278,7 @@ int compile_plan(const sfft_shape* shape, const sfft_params* params, Schedule* s
         in.n_outputs = (int64_t)c.outputs.size();
         in.ws_cts = sched->n_slots;
         in.ws_bytes = plan_ws_bytes(*sched, geo);
+        in.noise_bound_bits = need - 3;
         in.exec_steps = (int64_t)sched->levels.size() + 1;
         in.k_required = choose_k(c, params->n_lwe);
         for (const ProdItem& it : sched->prods) {
@@ -305,13 +307,15 @@ namespace sfft {
 PlanCore::~PlanCore()
 {
     // work enqueued with this plan may still read its tables
-    if (d_prods || d_lins || d_final || !prod_events.empty()) (void)hipDeviceSynchronize();
+    if (d_prods || d_lins || d_final || d_persist || !prod_events.empty()) (void)hipDeviceSynchronize();
     for (auto& pr : prod_events) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (d_persist) (void)hipFree(d_persist);
+    if (d_bar) (void)hipFree(d_bar);
     if (d_prods) (void)hipFree(d_prods);
     if (d_lins) (void)hipFree(d_lins);
     if (d_final) (void)hipFree(d_final);
@@ -519,6 +523,14 @@ int sfft_execute_steps(const sfft_plan* plan, int32_t first, int32_t count, cons
     Bufs b{const_cast<uint32_t*>(ct_in_dev), ct_out_dev, (uint32_t*)ws_dev, nullptr, ct_words(g)};
     hipStream_t s = (hipStream_t)hip_stream;
     for (int32_t st = first; st < first + count; st++) {
+        // a host range per step (its launches being enqueued), for marker traces
+        char label[64];
+        std::snprintf(label, sizeof label, "sfft level %d: %lld products", st,
+                      st < (int32_t)S.levels.size() ? (long long)S.levels[st].prod_count : 0ll);
+        roctxRangePushA(label);
+        struct PopRange {
+            ~PopRange() { roctxRangePop(); }
+        } pop_range;
         if (st < (int32_t)S.levels.size()) {
             const LevelWork& lw = S.levels[st];
             if (lw.prod_count) {
@@ -600,6 +612,86 @@ int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
     }
     hipError_t e = hipGraphLaunch(plan->graph_exec, s);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SFFT_OK;
+}
+
+int sfft_execute_persistent(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* ws_dev,
+                            int64_t ws_bytes, void* hip_stream)
+{
+    if (!plan) return fail(SFFT_EINVAL, "null plan");
+    int64_t need = 0;
+    sfft_plan_workspace_bytes(plan, &need);
+    if (ws_bytes < need) return fail(SFFT_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (!ct_out_dev || (plan->info.n_inputs > 0 && !ct_in_dev) || (need > 0 && !ws_dev))
+        return fail(SFFT_EINVAL, "null buffer");
+    const Geo& g = plan->geo;
+    ProdCfg cfg{};
+    if (!persistent_config(g, &cfg))
+        return fail(SFFT_EUNSUPPORTED, "no persistent kernel for rows of this width (more than 8 fragments)");
+    const Schedule& S = plan->sched;
+    const int64_t nl = (int64_t)S.levels.size();
+    if (!plan->d_persist) {
+        std::vector<int64_t> t(4 * nl);
+        std::vector<int64_t> passes;
+        for (int64_t L = 0; L < nl; L++) {
+            const LevelWork& lw = S.levels[L];
+            t[4 * L] = lw.prod_begin;
+            t[4 * L + 1] = lw.prod_count;
+            t[4 * L + 2] = (int64_t)passes.size() / 2;
+            t[4 * L + 3] = (int64_t)lw.lin.size();
+            for (const auto& pr : lw.lin) {
+                passes.push_back(pr.first);
+                passes.push_back(pr.second);
+            }
+        }
+        t.insert(t.end(), passes.begin(), passes.end());
+        int64_t* d = nullptr;
+        uint32_t* bar = nullptr;
+        hipError_t e = hipMalloc((void**)&d, sizeof(int64_t) * std::max<size_t>(t.size(), 1));
+        if (e == hipSuccess && !t.empty()) e = hipMemcpy(d, t.data(), sizeof(int64_t) * t.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc((void**)&bar, 2 * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            if (d) (void)hipFree(d);
+            return hip_fail(e, "persistent tables");
+        }
+        plan->d_persist = d;
+        plan->d_bar = bar;
+    }
+    PersistArgs a{};
+    a.prods = plan->d_prods;
+    a.lins = plan->d_lins;
+    a.finals = plan->d_final;
+    a.lv = plan->d_persist;
+    a.pass = plan->d_persist + 4 * nl;
+    a.nlevels = (int32_t)nl;
+    a.nfinal = (int32_t)S.final_lins.size();
+    a.bufs = Bufs{const_cast<uint32_t*>(ct_in_dev), ct_out_dev, (uint32_t*)ws_dev, nullptr, ct_words(g)};
+    a.geo = g;
+    a.nd = cfg.nd;
+    a.wd = cfg.wd;
+    a.tiles = (uint32_t)product_tiles(g, cfg);
+    a.bar = plan->d_bar;
+    // enough workgroups for the widest level's tiles and its linear tasks
+    int64_t widest = 1;
+    for (const LevelWork& lw : S.levels) {
+        widest = std::max<int64_t>(widest, lw.prod_count * a.tiles);
+        for (const auto& pr : lw.lin) widest = std::max<int64_t>(widest, (pr.second * g.nct * g.n1 + 511) / 512);
+    }
+    widest = std::max<int64_t>(widest, ((int64_t)S.final_lins.size() * g.nct * g.n1 + 511) / 512);
+    const hipError_t e = launch_plan_persistent(a, cfg, widest, (hipStream_t)hip_stream);
+    return e == hipSuccess ? SFFT_OK : hip_fail(e, "persistent launch");
+}
+
+int sfft_plan_persistent_timeouts(sfft_plan* plan, int32_t* flag)
+{
+    if (!plan || !flag) return fail(SFFT_EINVAL, "null argument");
+    *flag = 0;
+    if (!plan->d_bar) return SFFT_OK;
+    uint32_t w[2] = {0, 0};
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(w, plan->d_bar, sizeof w, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "persistent status");
+    *flag = (int32_t)w[1];
     return SFFT_OK;
 }
 
@@ -716,6 +808,57 @@ int sfft_decrypt_stream(const sfft_params* p, const uint32_t* sk_host, const uin
                         int32_t F, void* hip_stream, int32_t* fixed_out)
 {
     return decrypt_impl(p, sk_host, ct_dev, n_values, F, 1, true, hip_stream, fixed_out);
+}
+
+int sfft_noise_bits(const sfft_params* p, const uint32_t* sk_host, const uint32_t* ct_dev, int64_t n_ct,
+                    const int32_t* mu_bits, void* hip_stream, int32_t* max_bits)
+{
+    std::string why;
+    if (!params_ok(p, &why)) return fail(SFFT_EINVAL, why);
+    if (!max_bits || n_ct < 0 || (n_ct > 0 && (!sk_host || !ct_dev || !mu_bits))) return fail(SFFT_EINVAL, "bad buffers");
+    const Geo g = geo_of(p);
+    const int kw = g.kw, n1 = g.n1;
+    const int64_t cw = ct_words(g);
+    std::vector<uint32_t> ct((size_t)cw), x(kw), t(kw), e(kw);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    int worst = 0;
+    for (int64_t c = 0; c < n_ct; c++) {
+        hipError_t err = hipMemcpyAsync(ct.data(), ct_dev + c * cw, sizeof(uint32_t) * cw, hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) return hip_fail(err, "noise copy");
+        for (int r = 0; r < g.nct; r++) {
+            const uint32_t* row = ct.data() + (size_t)r * g.W;
+            std::fill(x.begin(), x.end(), 0u);
+            for (int b = 0; b < n1; b++) {
+                mul_mod(row + b * kw, sk_host + b * kw, kw, t.data());
+                add_mod(x.data(), t.data(), kw);
+            }
+            if (mu_bits[c] & 1) {
+                // - 2^t s_b: s_b shifted left by t bits mod 2^k, negated, added
+                const int b = r / p->k, sh = r % p->k, ls = sh / 32, bs = sh % 32;
+                std::fill(e.begin(), e.end(), 0u);
+                const uint32_t* sb = sk_host + b * kw;
+                for (int i = kw - 1; i >= ls; i--) {
+                    const uint64_t hi = (uint64_t)sb[i - ls] << bs;
+                    const uint64_t lo = (i - ls - 1 >= 0 && bs) ? (uint64_t)sb[i - ls - 1] >> (32 - bs) : 0;
+                    e[i] = (uint32_t)(hi | lo);
+                }
+                neg_mod(e.data(), kw, t.data());
+                add_mod(x.data(), t.data(), kw);
+            }
+            // centred: values with the top bit set stand for x - 2^k
+            if (x[kw - 1] >> 31) {
+                neg_mod(x.data(), kw, t.data());
+                x = t;
+            }
+            int bits = 0;
+            for (int i = kw - 1; i >= 0 && !bits; i--)
+                if (x[i]) bits = 32 * i + (32 - __builtin_clz(x[i]));
+            worst = std::max(worst, bits);
+        }
+    }
+    *max_bits = worst;
+    return SFFT_OK;
 }
 
 }  // extern "C"

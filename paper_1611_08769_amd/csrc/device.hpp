@@ -146,6 +146,27 @@ hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, cons
                          hipStream_t s);
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s);
 
+// A whole plan in one persistent launch (device tables of the schedule).
+struct PersistArgs {
+    const ProdItem* prods;
+    const LinItem* lins;
+    const LinItem* finals;
+    const int64_t* lv;    // per level: first product item, items, first pass, passes
+    const int64_t* pass;  // per linear pass: first item, items
+    int32_t nlevels;
+    int32_t nfinal;
+    Bufs bufs;
+    Geo geo;
+    int32_t nd, wd;
+    uint32_t tiles;  // workgroups per product item
+    uint32_t* bar;   // barrier counter, time-out flag (cleared by the launch)
+};
+// The tiling the persistent kernel uses for a geometry; false if none serves it.
+bool persistent_config(const Geo& g, ProdCfg* cfg);
+// Clears the barrier words, then one cooperative launch of at most
+// max_blocks workgroups, all resident at once.
+hipError_t launch_plan_persistent(const PersistArgs& a, const ProdCfg& cfg, int64_t max_blocks, hipStream_t s);
+
 // Encryption of n_ct bits: out[i] = mu_i G + R_i A with R_i drawn from
 // SplitMix64 domain 4 (ciphertext id first_id + i).  bits: one bit per
 // ciphertext, packed LSB first, at most kMaxEncPerLaunch per call.

@@ -762,9 +762,11 @@ __global__ void __launch_bounds__(kRtransThreads) k_rtrans(const ProdSeg* __rest
         *(gu32x4*)(dst + 16 * u) = *reinterpret_cast<const u32x4*>(Ts + 16 * u);
 }
 
+// The work of one workgroup (virtual block v of the launch's flat order),
+// shared by the launch per level and the whole-plan persistent kernel.
 template <int RG, int CG, int CF, bool PRE>
-__global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __restrict__ segs, int nseg,
-                                                               ProdSeg seg0, ProdItem one, int lds_bytes)
+__device__ __forceinline__ void product_mfma_block(const ProdSeg* __restrict__ segs, int nseg, const ProdSeg& seg0,
+                                                   const ProdItem& one, int lds_bytes, uint32_t v)
 {
     constexpr int THREADS = RG * CG * 64;
     constexpr int TM = 64 * RG;
@@ -780,7 +782,6 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     constexpr int NP = SPT < KC / 32 ? SPT : KC / 32;                     // staging parts per chunk
 
     extern __shared__ uint32_t lds[];
-    const uint32_t v = xcd_order(blockIdx.x, gridDim.x);
     ProdSeg sg = seg0;  // (a select between the two structs would copy both into vector registers)
     if (nseg > 1) sg = segs[find_segment(segs, nseg, v, [](const ProdSeg& q) { return q.first_block; })];
     const Geo g = sg.geo;
@@ -1350,6 +1351,13 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
     }
 }
 
+template <int RG, int CG, int CF, bool PRE>
+__global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __restrict__ segs, int nseg,
+                                                               ProdSeg seg0, ProdItem one, int lds_bytes)
+{
+    product_mfma_block<RG, CG, CF, PRE>(segs, nseg, seg0, one, lds_bytes, xcd_order(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // The matrix-core product with 256 threads and little LDS, so that two
 // workgroups share a CU and one's epilogue (carry chains: VALU, LDS and
@@ -1707,17 +1715,10 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_linear(const LinSeg* __restrict__ segs, int nseg, LinSeg seg0,
-                                                     LinItem one, uint32_t ybase)
+// One (row, element) of one linear item: dst = cX X + cY Y + cG G, limb by
+// limb with the carry.
+__device__ __forceinline__ void linear_task(const LinItem& it, const Bufs& bufs, const Geo& g, int task)
 {
-    const uint32_t y = blockIdx.y + ybase;
-    LinSeg sg = seg0;
-    if (nseg > 1) sg = segs[find_segment(segs, nseg, y, [](const LinSeg& q) { return q.first; })];
-    const Geo g = sg.geo;
-    const int task = blockIdx.x * kThreads + threadIdx.x;
-    if (task >= g.nct * g.n1) return;
-    const Bufs bufs = sg.bufs;
-    const LinItem it = sg.items ? load_global(sg.items + (y - sg.first)) : one;
     const int row = task / g.n1, e = task % g.n1;
     const int br = row / g.k, tr = row % g.k;
     gword* dst = ctp(bufs, it.dst);
@@ -1733,6 +1734,19 @@ __global__ void __launch_bounds__(kThreads) k_linear(const LinSeg* __restrict__ 
         dst[off] = (uint32_t)s;
         carry = s >> 32;
     }
+}
+
+__global__ void __launch_bounds__(kThreads) k_linear(const LinSeg* __restrict__ segs, int nseg, LinSeg seg0,
+                                                     LinItem one, uint32_t ybase)
+{
+    const uint32_t y = blockIdx.y + ybase;
+    LinSeg sg = seg0;
+    if (nseg > 1) sg = segs[find_segment(segs, nseg, y, [](const LinSeg& q) { return q.first; })];
+    const Geo g = sg.geo;
+    const int task = blockIdx.x * kThreads + threadIdx.x;
+    if (task >= g.nct * g.n1) return;
+    const LinItem it = sg.items ? load_global(sg.items + (y - sg.first)) : one;
+    linear_task(it, sg.bufs, g, task);
 }
 
 template <int THREADS, int LPR, int DPL, int RPL, int PD, int CG, bool ENC>
@@ -2123,6 +2137,117 @@ hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, cons
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Whole-plan persistent execution (small plans): one cooperative launch runs
+// every level, the workgroups looping over the level's product tiles and
+// linear tasks, with a grid-wide barrier where a kernel boundary was.  The
+// barrier: each workgroup releases its writes to the device (agent-scope
+// fence: the XCDs' L2s are written back), adds one to a counter, and waits
+// until the counter reaches its generation times the grid size, then
+// acquires (its caches invalidated).  Every wait is bounded: past the limit
+// the workgroup sets an error flag and goes on, so the kernel always ends.
+namespace {
+constexpr uint32_t kBarrierSpins = 1u << 22;  // s_sleep rounds (about 0.1 s)
+
+__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t target)
+{
+    __syncthreads();  // every wave's stores done (they are in this XCD's L2)
+    if (threadIdx.x == 0) {
+        // one release for the workgroup (L2 written back), a relaxed count,
+        // a relaxed poll (each poll would otherwise invalidate the L2), one
+        // acquire (the caches invalidated) for the workgroup
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins == kBarrierSpins) {
+                __hip_atomic_fetch_or(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+__global__ void k_zero_words(uint32_t* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+template <int RG, int CG, int CF>
+__global__ void __launch_bounds__(RG * CG * 64) k_plan_persistent(PersistArgs a, int lds_bytes)
+{
+    constexpr int THREADS = RG * CG * 64;
+    const uint32_t nb = gridDim.x;
+    const int64_t per = (int64_t)a.geo.nct * a.geo.n1;  // linear tasks per item
+    const int64_t t0 = (int64_t)blockIdx.x * THREADS + threadIdx.x, tstep = (int64_t)nb * THREADS;
+    const ProdItem none{};
+    uint32_t gen = 0;
+    for (int L = 0; L < a.nlevels; L++) {
+        const int64_t pb = a.lv[4 * L], pc = a.lv[4 * L + 1], p0 = a.lv[4 * L + 2], np = a.lv[4 * L + 3];
+        if (pc > 0) {
+            const ProdSeg seg{a.prods + pb, a.bufs, a.geo, a.nd, a.wd, 0, 0, nullptr};
+            const uint32_t blocks = (uint32_t)pc * a.tiles;
+            for (uint32_t v = blockIdx.x; v < blocks; v += nb) {
+                product_mfma_block<RG, CG, CF, false>(nullptr, 1, seg, none, lds_bytes, v);
+                __syncthreads();  // the next tile reuses the LDS
+            }
+            grid_barrier(a.bar, ++gen * nb);
+        }
+        for (int64_t q = 0; q < np; q++) {
+            const int64_t lb = a.pass[2 * (p0 + q)], tasks = a.pass[2 * (p0 + q) + 1] * per;
+            for (int64_t t = t0; t < tasks; t += tstep) linear_task(a.lins[lb + t / per], a.bufs, a.geo, (int)(t % per));
+            grid_barrier(a.bar, ++gen * nb);
+        }
+    }
+    const int64_t tasks = a.nfinal * per;
+    for (int64_t t = t0; t < tasks; t += tstep) linear_task(a.finals[t / per], a.bufs, a.geo, (int)(t % per));
+}
+
+template <int CF>
+hipError_t launch_persistent_t(const PersistArgs& a, const ProdCfg& cfg, int64_t max_blocks, hipStream_t s)
+{
+    const void* fn = (const void*)k_plan_persistent<2, 4, CF>;
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, cfg.lds_bytes);
+    if (e != hipSuccess) return e;
+    // every workgroup resident at once (the barriers wait for all of them)
+    const int64_t resident = (int64_t)cus * per_cu;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(resident, max_blocks));
+    if (resident < 1) return hipErrorCooperativeLaunchTooLarge;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, a.bar, 2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PersistArgs args = a;
+    int lds = cfg.lds_bytes;
+    void* params[] = {(void*)&args, (void*)&lds};
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(512), params, (unsigned)cfg.lds_bytes, s);
+}
+}  // namespace
+
+bool persistent_config(const Geo& g, ProdCfg* cfg)
+{
+    // the 512-thread matrix-core kernel with in-kernel transposition,
+    // 2 x 4 waves of 1 or 2 fragments: rows of up to 8 fragments
+    for (int i = 0; i < kNumMfmaTilings; i++) {
+        const MfmaTiling& t = kMfmaTilings[i];
+        if (t.pre == 0 && t.rg == 2 && t.cgw == 4 && t.cf <= 2 && tiling_config(g, kNumLookupTilings + i, cfg))
+            return true;
+    }
+    return false;
+}
+
+hipError_t launch_plan_persistent(const PersistArgs& a, const ProdCfg& cfg, int64_t max_blocks, hipStream_t s)
+{
+    return cfg.cf == 1 ? launch_persistent_t<1>(a, cfg, max_blocks, s) : launch_persistent_t<2>(a, cfg, max_blocks, s);
 }
 
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s)

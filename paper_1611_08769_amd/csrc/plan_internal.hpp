@@ -33,6 +33,10 @@ struct PlanCore {
     const void* graph_in = nullptr;
     const void* graph_out = nullptr;
     const void* graph_ws = nullptr;
+    // whole-plan persistent execution (sfft_execute_persistent): the level
+    // and pass tables on the device, the barrier words, built on first use
+    int64_t* d_persist = nullptr;
+    uint32_t* d_bar = nullptr;
     // product-kernel timing (sfft_plan_time_products): event pairs recorded
     // around each level's product kernel by sfft_execute_steps while on
     mutable bool time_products = false;

@@ -19,9 +19,11 @@
 // independent altogether, which is what makes the interleaving exact: each
 // request's ciphertexts are bit-identical alone and in the mix.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -116,6 +118,15 @@ struct Request {
     hipEvent_t fin = nullptr;         // recorded after its last step
     double arrival = 0, done_at = -1;
 };
+
+// A marker per request event (admitted, done), for marker traces.
+void mark_request(const Request& r, const char* what)
+{
+    char label[96];
+    std::snprintf(label, sizeof label, "sfft request %llu %s: %dD len %d F %d", (unsigned long long)r.ticket, what,
+                  r.plan->shape.dims, r.plan->shape.len, r.plan->shape.F);
+    roctxMarkA(label);
+}
 
 // Steps a request may be left out by the fill policy before it runs anyway.
 constexpr int kMaxWait = 8;
@@ -281,6 +292,7 @@ static int retire(sfft_server* sv, bool all)
         sv->st.completed++;
         sv->st.gates += rp->plan->info.gates;
         sv->st.fft_points += rp->plan->points;
+        mark_request(*rp, "done");
         sv->done[rp->ticket] = std::move(rp);
     }
     sv->finishing.swap(still);
@@ -308,6 +320,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
             break;
         }
         r->ws_off = off;
+        mark_request(*r, "admitted");
         sv->active.push_back(std::move(*it));
         it = sv->queue.erase(it);
         sv->st.admitted++;

@@ -35,7 +35,8 @@ class sfft_plan_info(ctypes.Structure):
                 ("n_outputs", ctypes.c_int64), ("ws_cts", ctypes.c_int64), ("exec_steps", ctypes.c_int64),
                 ("k_required", ctypes.c_int32),
                 ("netlist_sha256", ctypes.c_char * 65), ("tiling", ctypes.c_int32),
-                ("prod_ct_reads", ctypes.c_int64), ("prod_ct_writes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64)]
+                ("prod_ct_reads", ctypes.c_int64), ("prod_ct_writes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64),
+                ("noise_bound_bits", ctypes.c_int32)]
 
 
 SFFT_SERVER_DRYRUN = 1
@@ -99,6 +100,8 @@ _SIGS = {
     "sfft_execute_steps": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "sfft_plan_step_products": (ctypes.c_int, [_vp, _P(ctypes.c_int64), ctypes.c_int32]),
     "sfft_plan_time_products": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "sfft_execute_persistent": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "sfft_plan_persistent_timeouts": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
     "sfft_batch_workspace_bytes": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(ctypes.c_int64)]),
     "sfft_batch_create": (ctypes.c_int, [_P(_vp), _P(_vp), _P(_vp), ctypes.c_int32, _vp, ctypes.c_int64, _P(_vp)]),
     "sfft_batch_info": (ctypes.c_int, [_vp, _P(ctypes.c_int64), _P(ctypes.c_int64)]),
@@ -109,6 +112,7 @@ _SIGS = {
     "sfft_decrypt": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, _vp]),
     "sfft_decrypt_bits": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int, _vp]),
     "sfft_decrypt_stream": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp]),
+    "sfft_noise_bits": (ctypes.c_int, [_P(sfft_params), _vp, _vp, ctypes.c_int64, _vp, _vp, _P(ctypes.c_int32)]),
     "sfft_gate": (ctypes.c_int, [_P(sfft_params), ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "sfft_server_create": (ctypes.c_int, [_P(sfft_server_cfg), _P(_vp)]),
     "sfft_server_submit": (ctypes.c_int, [_vp, _P(sfft_shape), _P(sfft_params), _vp, _vp, _P(ctypes.c_uint64)]),
@@ -245,6 +249,16 @@ def sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_byt
     _check(_lib.sfft_execute_steps(plan, first, count, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
 
 
+def sfft_execute_persistent(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(_lib.sfft_execute_persistent(plan, ct_in_ptr, ct_out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sfft_plan_persistent_timeouts(plan) -> int:
+    v = ctypes.c_int32()
+    _check(_lib.sfft_plan_persistent_timeouts(plan, ctypes.byref(v)))
+    return v.value
+
+
 def _ptr_array(ptrs):
     return (_vp * len(ptrs))(*ptrs)
 
@@ -298,6 +312,12 @@ def sfft_plan_step_products(plan, n):
 
 def sfft_decrypt_stream(p, sk_host_ptr, ct_dev_ptr, n_values, F, stream, out_ptr) -> None:
     _check(_lib.sfft_decrypt_stream(ctypes.byref(p), sk_host_ptr, ct_dev_ptr, n_values, F, stream, out_ptr))
+
+
+def sfft_noise_bits(p, sk_host_ptr, ct_dev_ptr, n_ct, mu_bits_ptr, stream) -> int:
+    v = ctypes.c_int32()
+    _check(_lib.sfft_noise_bits(ctypes.byref(p), sk_host_ptr, ct_dev_ptr, n_ct, mu_bits_ptr, stream, ctypes.byref(v)))
+    return v.value
 
 
 def sfft_decrypt(p, sk_host_ptr, ct_ptr, n_values, F, on_device, out_ptr) -> None:

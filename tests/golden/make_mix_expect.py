@@ -25,6 +25,7 @@ from oracle import fixedpoint as fx  # noqa: E402
 from paper_1611_08769_amd import workloads as WL  # noqa: E402
 
 BATCH = dict(seed=4, count=256, lengths=(8, 16, 32, 64, 128))
+BATCH_SMALL = dict(seed=4, count=128, lengths=(8, 16, 32))
 SERVE = dict(seed=5, count=64)
 
 
@@ -52,12 +53,16 @@ def main():
                 "interleaved, natural order); written by tests/golden/make_mix_expect.py from oracle/ only",
         "batch": dict(BATCH, lengths=list(BATCH["lengths"]),
                       requests=[entry(s) for s in WL.batch_requests(BATCH["seed"], BATCH["count"], BATCH["lengths"])]),
+        "batch_small": dict(BATCH_SMALL, lengths=list(BATCH_SMALL["lengths"]),
+                            requests=[entry(s) for s in WL.batch_requests(BATCH_SMALL["seed"], BATCH_SMALL["count"],
+                                                                          BATCH_SMALL["lengths"])]),
         "serve": dict(SERVE, requests=[entry(s) for s in WL.served_requests(SERVE["seed"], SERVE["count"])]),
     }
     path = os.path.join(HERE, "mix_decryptions.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=0)
-    print("wrote", path, len(out["batch"]["requests"]), len(out["serve"]["requests"]))
+    print("wrote", path, len(out["batch"]["requests"]), len(out["batch_small"]["requests"]),
+          len(out["serve"]["requests"]))
 
 
 if __name__ == "__main__":

@@ -15,6 +15,7 @@ def test_mix_expectations_match_the_emulation():
     spec.loader.exec_module(m)
     stored = json.load(open(os.path.join(HERE, "golden", "mix_decryptions.json")))
     sigs = {"batch": m.WL.batch_requests(m.BATCH["seed"], m.BATCH["count"], m.BATCH["lengths"]),
+            "batch_small": m.WL.batch_requests(m.BATCH_SMALL["seed"], m.BATCH_SMALL["count"], m.BATCH_SMALL["lengths"]),
             "serve": m.WL.served_requests(m.SERVE["seed"], m.SERVE["count"])}
     for kind, ss in sigs.items():
         assert len(stored[kind]["requests"]) == len(ss)
