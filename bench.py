@@ -310,7 +310,7 @@ def run_batch(args, count=None):
     io_cap = args.io_gb * 1e9
     budget = int(min(free * 0.7 - io_cap, (args.budget_gb or 120.0) * 1e9))
     fill = max(0, args.fill_blocks)
-    srv = api.Server(budget, max_active=args.max_active, fill_blocks=fill)
+    srv = api.Server(budget, max_active=args.max_active, fill_blocks=fill, serial=args.serial_groups)
     ok_batch, fp_batch, lat = [None] * len(reqs), [None] * len(reqs), [None] * len(reqs)
     waiting = collections.deque(range(len(reqs)))
     live, io_used, max_live = {}, 0, 0
@@ -344,6 +344,10 @@ def run_batch(args, count=None):
     srv.close()
     same = fp_batch == fp_alone
     dec_ok = all(ok_alone) and all(ok_batch)
+    if not dec_ok or not same:
+        print("[bench] requests whose decryption differs: alone %s, batched %s; outputs differing: %s" % (
+            [i for i, o in enumerate(ok_alone) if not o], [i for i, o in enumerate(ok_batch) if not o],
+            [i for i in range(len(reqs)) if fp_batch[i] != fp_alone[i]]), file=sys.stderr, flush=True)
     print("[bench] batched: %.2f s (%d steps, %d launches, up to %d in flight); outputs identical to alone: %s; "
           "decryptions equal the emulation: %s" % (t_batch, st.steps, st.launches, max_live, same, dec_ok),
           file=sys.stderr, flush=True)
@@ -366,7 +370,7 @@ def run_batch(args, count=None):
         "data": "synthetic",
         "config": {"workload": "batch_1d_mixed", "requests": len(reqs), "lengths": "%d..%d" % (lengths[0], lengths[-1]),
                    "F": "12/16/24", "n_lwe": 1, "distinct_plans": len(plans), "budget_gb": round(budget / 1e9, 1),
-                   "io_gb": args.io_gb, "fill_blocks": fill},
+                   "io_gb": args.io_gb, "fill_blocks": fill, "serial_groups": bool(args.serial_groups)},
         "tilings": tuned,
         "one_at_a_time_gates_per_s": gates / t_alone,
         "one_at_a_time_s": t_alone,
@@ -1323,6 +1327,8 @@ def main():
     ap.add_argument("--batch-requests", type=int, default=256, help="default workload: requests of the batched run")
     ap.add_argument("--batch-small-requests", type=int, default=128,
                     help="default workload: requests of the batched run of small requests (N = 8..32)")
+    ap.add_argument("--serial-groups", action="store_true",
+                    help="batch mode: a step's launches of different tilings in turn on one stream")
     ap.add_argument("--fixed-batch-gb", type=float, default=100.0,
                     help="batch mode: ciphertexts and workspaces of the fixed batch run through a HIP graph")
     ap.add_argument("--serve-requests", type=int, default=16, help="default workload: requests of the served run")

@@ -321,11 +321,13 @@ int sfft_plan_tune(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_
  * its plan alone.  Requests are independent FFTs (the paper's workflow,
  * section "Introduction", repeated per client signal). */
 #define SFFT_SERVER_DRYRUN 1  /* no device work: admission/scheduling only, modelled time */
+#define SFFT_SERVER_SERIAL 2  /* a step's launches of different tilings in turn on the caller's stream
+                                 (by default they overlap on the server's own streams) */
 
 typedef struct {
     int64_t mem_budget_bytes;  /* device memory for request workspaces (allocated at create) */
     int32_t max_active;        /* requests in flight at once; 0 = no limit */
-    int32_t flags;             /* SFFT_SERVER_DRYRUN */
+    int32_t flags;             /* SFFT_SERVER_DRYRUN, SFFT_SERVER_SERIAL */
     double dry_bitmac_per_s;   /* modelled product rate in dry-run mode (0 = 1e15) */
     /* 0: every step advances every admitted request (lockstep).  > 0: a step
      * advances admitted requests in order of least remaining work: the first

@@ -250,9 +250,10 @@ class Server:
     """Continuous-batching request loop over libsfft's sfft_server_*."""
 
     def __init__(self, mem_budget_bytes: int, max_active: int = 0, dry_run: bool = False,
-                 dry_bitmac_per_s: float = 0.0, fill_blocks: int = 0):
-        cfg = S.sfft_server_cfg(int(mem_budget_bytes), int(max_active), S.SFFT_SERVER_DRYRUN if dry_run else 0,
-                                float(dry_bitmac_per_s), int(fill_blocks))
+                 dry_bitmac_per_s: float = 0.0, fill_blocks: int = 0, serial: bool = False):
+        flags = (S.SFFT_SERVER_DRYRUN if dry_run else 0) | (S.SFFT_SERVER_SERIAL if serial else 0)
+        cfg = S.sfft_server_cfg(int(mem_budget_bytes), int(max_active), flags, float(dry_bitmac_per_s),
+                                int(fill_blocks))
         self.dry = dry_run
         self.handle = S.sfft_server_create(cfg)
         self._keep = {}

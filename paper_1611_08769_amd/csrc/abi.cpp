@@ -752,16 +752,14 @@ int decrypt_bits_impl(const sfft_params* p, const uint32_t* sk_host, const uint3
     int64_t stride = cw;
     if (ct_on_device && n_ct > 0) {
         rows.resize((size_t)n_ct * g.W);
-        hipError_t e;
-        if (on_stream) {
-            const hipStream_t s = (hipStream_t)hip_stream;
-            e = hipMemcpy2DAsync(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
-                                 sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-        } else {
-            e = hipMemcpy2D(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
-                            sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost);
-        }
+        // one copy path with or without a stream: an asynchronous copy and a
+        // wait for its stream (the null stream unless one is given).  The
+        // synchronous 2D copy gave wrong rows in a kernel-traced run in which
+        // this form gave the right ones.
+        const hipStream_t s = on_stream ? (hipStream_t)hip_stream : nullptr;
+        hipError_t e = hipMemcpy2DAsync(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
+                                        sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "decrypt copy");
         src = rows.data();
         stride = g.W;

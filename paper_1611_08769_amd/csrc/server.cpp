@@ -459,7 +459,9 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         // products: the first tiling group on the caller's stream, the others
         // on the server's streams (forked after the upload, joined back
         // before the linear passes), so that their launches overlap
-        const int ng = (int)pgroups.size();
+        // (SFFT_SERVER_SERIAL: every group on the caller's stream, in turn)
+        const bool serial = (sv->cfg.flags & SFFT_SERVER_SERIAL) != 0;
+        const int ng = serial ? 1 : (int)pgroups.size();
         if (ng > 1) {
             e = hipEventRecord(sv->fork, s);
             if (e != hipSuccess) return sfft_hip_fail(e, "server fork");
@@ -467,7 +469,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         size_t gi = 0;
         for (auto& kv : pgroups) {
             const ProdGroup& G = kv.second;
-            const int a = gi == 0 ? -1 : (int)((gi - 1) % kAux);
+            const int a = gi == 0 || serial ? -1 : (int)((gi - 1) % kAux);
             hipStream_t gs = a < 0 ? s : sv->aux[a];
             if (a >= 0 && gi <= (size_t)kAux) {
                 e = hipStreamWaitEvent(gs, sv->fork, 0);

@@ -40,6 +40,7 @@ class sfft_plan_info(ctypes.Structure):
 
 
 SFFT_SERVER_DRYRUN = 1
+SFFT_SERVER_SERIAL = 2
 SFFT_NOALLOC_WS_BYTES = 64 << 20
 
 
