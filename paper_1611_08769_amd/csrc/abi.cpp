@@ -752,13 +752,22 @@ int decrypt_bits_impl(const sfft_params* p, const uint32_t* sk_host, const uint3
     int64_t stride = cw;
     if (ct_on_device && n_ct > 0) {
         rows.resize((size_t)n_ct * g.W);
-        // one copy path with or without a stream: an asynchronous copy and a
-        // wait for its stream (the null stream unless one is given).  The
-        // synchronous 2D copy gave wrong rows in a kernel-traced run in which
-        // this form gave the right ones.
+        // the rows gathered on the device into a stream-ordered buffer, then
+        // one linear copy to the host and a wait for the stream (the null
+        // stream unless one is given).  A strided 2D copy to pageable memory
+        // on the null stream returned wrong words under a kernel-tracing
+        // profiler while the device data was right; this form does not
+        // depend on the runtime's 2D copy.
         const hipStream_t s = on_stream ? (hipStream_t)hip_stream : nullptr;
-        hipError_t e = hipMemcpy2DAsync(rows.data(), sizeof(uint32_t) * g.W, ct + row_off, sizeof(uint32_t) * cw,
-                                        sizeof(uint32_t) * g.W, (size_t)n_ct, hipMemcpyDeviceToHost, s);
+        const size_t bytes = sizeof(uint32_t) * rows.size();
+        uint32_t* d_rows = nullptr;
+        hipError_t e = hipMallocAsync((void**)&d_rows, bytes, s);
+        if (e == hipSuccess) e = launch_gather_rows(ct, cw, (int64_t)row_off, g.W, n_ct, d_rows, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(rows.data(), d_rows, bytes, hipMemcpyDeviceToHost, s);
+        if (d_rows) {
+            const hipError_t ef = hipFreeAsync(d_rows, s);
+            if (e == hipSuccess) e = ef;
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "decrypt copy");
         src = rows.data();

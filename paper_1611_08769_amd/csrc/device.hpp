@@ -145,6 +145,10 @@ bool inkernel_twin(const Geo& g, ProdCfg* cfg);
 hipError_t launch_linear(int64_t max_elems, const LinSeg* d_segs, int nseg, const LinSeg& seg0, int64_t total,
                          hipStream_t s);
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s);
+// row_off..row_off+W of each of n ciphertexts (cw words apart) packed into
+// dst (n x W words, device)
+hipError_t launch_gather_rows(const uint32_t* ct, int64_t cw, int64_t row_off, int W, int64_t n, uint32_t* dst,
+                              hipStream_t s);
 
 // A whole plan in one persistent launch (device tables of the schedule).
 struct PersistArgs {

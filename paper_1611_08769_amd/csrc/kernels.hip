@@ -2250,6 +2250,29 @@ hipError_t launch_plan_persistent(const PersistArgs& a, const ProdCfg& cfg, int6
     return cfg.cf == 1 ? launch_persistent_t<1>(a, cfg, max_blocks, s) : launch_persistent_t<2>(a, cfg, max_blocks, s);
 }
 
+// Words [row_off, row_off + W) of each of n ciphertexts of cw words (the
+// row that decryption reads) packed into dst, n x W words.
+__global__ void k_gather_rows(const uint32_t* __restrict__ ct, int64_t cw, int64_t row_off, int W, int64_t n,
+                              uint32_t* __restrict__ dst)
+{
+    const int64_t total = n * W, step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
+        const int64_t c = i / W;
+        dst[i] = ct[c * cw + row_off + (i - c * W)];
+    }
+}
+
+hipError_t launch_gather_rows(const uint32_t* ct, int64_t cw, int64_t row_off, int W, int64_t n, uint32_t* dst,
+                              hipStream_t s)
+{
+    if (n <= 0 || W <= 0) return hipSuccess;
+    const int64_t total = n * W;
+    const int64_t want = (total + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)(want < 8192 ? want : 8192)), dim3(kThreads), 0, s, ct, cw,
+                       row_off, W, n, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_linear_one(const Bufs& b, const Geo& g, const LinItem& item, hipStream_t s)
 {
     const int blocks = (g.nct * g.n1 + kThreads - 1) / kThreads;
