@@ -141,7 +141,7 @@ int sfft_batch_create(const sfft_plan* const* plans, const uint32_t* const* ct_i
         int64_t n = 0, max_elems = 0;
     };
     for (int64_t st = 0; st < max_steps; st++) {
-        std::map<std::pair<int, int>, ProdGroup> pgroups;  // (tiling, workgroups per CU by LDS)
+        std::map<std::pair<int, int>, ProdGroup> pgroups;  // (8 tiling + epilogue pass rows / 16, workgroups per CU by LDS)
         std::vector<LinGroup> lgroups;
         auto add_lin = [&](size_t q, const LinItem* items, const Bufs& b, const Geo& g, int64_t count) {
             if (lgroups.size() <= q) lgroups.resize(q + 1);
@@ -158,7 +158,7 @@ int sfft_batch_create(const sfft_plan* const* plans, const uint32_t* const* ct_i
             if (st < (int64_t)S.levels.size()) {
                 const LevelWork& lw = S.levels[st];
                 if (lw.prod_count) {
-                    ProdGroup& G = pgroups[{pc.cfg.tiling, 160 * 1024 / std::max(pc.cfg.lds_bytes, 1)}];
+                    ProdGroup& G = pgroups[{8 * pc.cfg.tiling + pc.cfg.pm, 160 * 1024 / std::max(pc.cfg.lds_bytes, 1)}];
                     if (G.segs.empty()) G.cfg = pc.cfg;
                     G.cfg.lds_bytes = std::max(G.cfg.lds_bytes, pc.cfg.lds_bytes);
                     // first / first_block hold the item and tile counts until numbered below

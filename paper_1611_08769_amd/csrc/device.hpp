@@ -42,6 +42,7 @@ struct ProdCfg {
     int rg, cgw, cf;
     int pre;   // right operands transposed into rt by a pass before the launch (1: 128-row chunks, 2: 64-row)
     int cs;    // workgroups per row tile: column splits of whole elements (the 256-thread kernel), else 1
+    int pm = 1;  // the 256-thread kernel's epilogue passes: 16 pm rows (1, 2 or 4)
 };
 
 // Passed to the kernel by value.

@@ -583,8 +583,8 @@ __host__ __device__ constexpr int mfma_epi_bytes(int nf, int W)
 }
 // LDS bytes of the 256-thread kernel (k_product_mfma2): its main loop's
 // chunks in flight of 2 x 2 CF 1 KB units of R and of 128 rows' 64 bits of
-// L, and its epilogue's passes of 16 rows (qp quads of words): column sums
-// and two passes' quads of L, R and up to kMaxE extra operands.
+// L, and its epilogue's passes of 16 pm rows (qp quads of words): column
+// sums and two passes' quads of L, R and up to kMaxE extra operands.
 // Chunks of R in flight: as many as about 78 KB hold, at most 6 (a chunk
 // keeps the matrix cores busy for a short time, so the requests must be
 // issued several chunks ahead to cover the memory latency).
@@ -593,9 +593,9 @@ __host__ __device__ constexpr int mfma2_depth(int cf)
     return (78 * 1024) / (4 * cf * 1024 + 1024) < 6 ? (78 * 1024) / (4 * cf * 1024 + 1024) : 6;
 }
 __host__ __device__ constexpr int mfma2_main_bytes(int cf) { return mfma2_depth(cf) * (4 * cf * 1024 + 128 * 8); }
-__host__ __device__ constexpr int mfma2_epi_bytes(int cf, int qp)
+__host__ __device__ constexpr int mfma2_epi_bytes(int cf, int qp, int pm)
 {
-    return 16 * mfma_sum_pitch(2 * cf) * 4 + 2 * (2 + kMaxE) * ((16 * qp + 1023) / 1024 * 1024);
+    return 16 * pm * mfma_sum_pitch(2 * cf) * 4 + 2 * (2 + kMaxE) * ((16 * qp + 1023) / 1024 * 1024);
 }
 
 // r[i] holds bytes (i, 0..3) of a 4x4 byte block; c[j] gets bytes (0..3, j)
@@ -1373,13 +1373,15 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
 // bytes contiguous, its 16-byte units permuted by swz64), the split's 1 KB
 // units of it straight from global memory into LDS three chunks deep, with
 // the chunk's 64 bits of each tile row of L; one barrier per chunk.  The
-// epilogue is that of k_product_mfma in passes of 16 rows.
-template <int CF>
+// epilogue is that of k_product_mfma in passes of PR = 16 PM rows (PM > 1
+// where a row is so short that the four waves' lanes hold more than 16 rows'
+// quads at once: fewer, fuller passes).
+template <int CF, int PM>
 __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
                                                            ProdItem one, int lds_bytes)
 {
     constexpr int RG = 2, CG = 2, NW = RG * CG, THREADS = 64 * NW, TM = 64 * RG, KC = 64;
-    constexpr int PR = 16;                  // rows per epilogue pass
+    constexpr int PR = 16 * PM;             // rows per epilogue pass
     constexpr int UT = 2 * CG * CF;         // 1 KB units of a chunk a tile reads
     constexpr int DR = (UT + NW - 1) / NW;  // of them per wave
     constexpr int SP = mfma_sum_pitch(CG * CF);
@@ -1416,10 +1418,10 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const int nchunks = (nct + KC - 1) / KC;
     const gword* Lp = ctp(bufs, it.L);
     const gword* Rp = ctp(bufs, it.R);
-    const int QP = PR * ww / 4;                     // quads of words of an epilogue pass (PR = 16)
+    const int QP = PR * ww / 4;                     // quads of words of an epilogue pass
     const int OPB = (16 * QP + 1023) / 1024 * 1024;     // LDS bytes of one operand's quads
     const int main_bytes = mfma2_main_bytes(CF);
-    const int e_bytes = mfma2_epi_bytes(CF, QP);
+    const int e_bytes = mfma2_epi_bytes(CF, QP, PM);
     int32_t* Pc = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) + (main_bytes > e_bytes ? main_bytes : e_bytes));
 
     // ---- main loop ----
@@ -1552,7 +1554,7 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const int gpw = 64 / qg;      // groups per wave
     const int rw_g = wave * gpw + lane / qg;  // this lane's group of a pass
     const int rw_jj = lane % qg;             // and quad of the group
-    const bool rw_ok = lane < gpw * qg && rw_g * rpg < PR;
+    const bool rw_in = lane < gpw * qg;  // (and its group's rows in the pass: rw_g rpg < the pass's rows)
     const int rw_rr = 4 * rw_jj / ww;              // row of the group where the quad starts
     const int rw_rl = rw_g * rpg + rw_rr;          // and of the pass
     const int rw_w = w0 + 4 * rw_jj - rw_rr * ww;  // its first word
@@ -1561,12 +1563,17 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const int rw_off = rpg > 1 ? 4 * rw_j : rw_rl * W + rw_w;  // its words from the pass's first row
     int32_t* S = reinterpret_cast<int32_t*>(lds);
     uint8_t* OPS = reinterpret_cast<uint8_t*>(S + PR * SP);  // 2 buffers x (2 + kMaxE) operands
+    // rows of the tile (Nct is a multiple of 32: 32, 64, 96 or 128) and of
+    // each pass (every pass but the last holds PR, a multiple of 16)
+    const int trows = nct - row_base < TM ? nct - row_base : TM;
+    auto pass_rows = [&](int p) { return trows - PR * p < PR ? trows - PR * p : PR; };
     // every operand's quads of pass p into buffer b, 64 quads per wave
-    // instruction (lanes past the pass re-read its last quad and land in the
-    // buffer's padding)
+    // instruction (lanes past the pass's rows re-read its last quad and land
+    // in the buffer's padding)
     auto stage_ops = [&](int p, int b) {
-        for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < QP; blk += NW) {
-            const int j = 64 * blk + lane < QP ? 64 * blk + lane : QP - 1;
+        const int qv = pass_rows(p) * ww / 4;
+        for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < qv; blk += NW) {
+            const int j = 64 * blk + lane < qv ? 64 * blk + lane : qv - 1;
             const int rl = rpg > 1 ? 0 : j / qr;
             const size_t off = rpg > 1 ? (size_t)(row_base + PR * p) * W + 4 * j
                                        : (size_t)(row_base + PR * p + rl) * W + w0 + 4 * (j - rl * qr);
@@ -1577,26 +1584,31 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
         }
     };
     // store instructions this wave issues per pass: one per output, where
-    // any of its lanes holds a quad
+    // any of its lanes holds a quad (the count waited for is that of a full
+    // pass: only the last may be partial)
     const int nst = wave * gpw * rpg < PR ? nout : 0;
     stage_ops(0, 0);
-    const int npass = (nct - row_base < TM ? nct - row_base : TM) / PR;  // Nct is a multiple of 32
+    const int npass = (trows + PR - 1) / PR;
     for (int p = 0; p < npass; p++) {
         const int prow = row_base + PR * p;  // first row of the pass
         const int b = p & 1;
+        const bool rw_ok = rw_in && rw_g * rpg < pass_rows(p);
         // this pass's operands in LDS: each wave waits for its own loads of
         // them, issued before its stores of the pass before, which need not
         // be done; the pass before is done with S and the other buffer
         wait_vmcnt_upto<kMaxOut, 1>(p > 0 ? nst : 0);
         lds_barrier();
         if (p + 1 < npass) stage_ops(p + 1, b ^ 1);
-        // 1. column sums of the pass's rows: rows 16 h .. 16 h + 15 of
-        // fragment f of row group wr, i.e. its registers r = 8 h .. 8 h + 7
+        // 1. column sums of the pass's rows: tile rows 16 u .. 16 u + 15,
+        // u = 4 wr + 2 f + h, are rows 16 h .. 16 h + 15 of fragment f of
+        // row group wr, i.e. its registers r = 8 h .. 8 h + 7, and rows
+        // 16 (u % PM) .. of pass u / PM
 #pragma unroll
         for (int f = 0; f < 2; f++) {
 #pragma unroll
             for (int h = 0; h < 2; h++) {
-                if (p != 4 * wr + 2 * f + h) continue;
+                const int u = 4 * wr + 2 * f + h;
+                if (u / PM != p) continue;
 #pragma unroll
                 for (int q = 0; q < CF; q++) {
                     const int col = 32 * (wc * CF + q) + (lane & 31);  // of the split
@@ -1604,7 +1616,7 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
                         const int cu = 4 * mfma_sum_unit(col >> 2) + (col & 3);
 #pragma unroll
                         for (int r = 8 * h; r < 8 * h + 8; r++)
-                            S[(8 * ((r >> 2) - 2 * h) + 4 * half + (r & 3)) * SP + cu] = acc[f][q][r];
+                            S[(16 * (u % PM) + 8 * ((r >> 2) - 2 * h) + 4 * half + (r & 3)) * SP + cu] = acc[f][q][r];
                     }
                 }
             }
@@ -1781,18 +1793,30 @@ hipError_t launch_mfma_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
     return hipGetLastError();
 }
 
+template <int CF, int PM>
+hipError_t launch_mfma2_pm(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
+                           const ProdItem& one, int64_t blocks, hipStream_t s)
+{
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_product_mfma2<CF, PM>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_product_mfma2<CF, PM>), dim3((unsigned)blocks), dim3(256), cfg.lds_bytes, s, d_segs, nseg,
+                       seg0, one, cfg.lds_bytes);
+    return hipGetLastError();
+}
+
 template <int CF>
 hipError_t launch_mfma2_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
                           const ProdItem& one, int64_t blocks, hipStream_t s)
 {
-    static const hipError_t attr =
-        hipFuncSetAttribute((const void*)k_product_mfma2<CF>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (attr != hipSuccess) return attr;
-    if (blocks <= 0) return hipSuccess;
-    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_product_mfma2<CF>), dim3((unsigned)blocks), dim3(256), cfg.lds_bytes, s, d_segs, nseg, seg0,
-                       one, cfg.lds_bytes);
-    return hipGetLastError();
+    switch (cfg.pm) {
+    case 1: return launch_mfma2_pm<CF, 1>(cfg, d_segs, nseg, seg0, one, blocks, s);
+    case 2: return launch_mfma2_pm<CF, 2>(cfg, d_segs, nseg, seg0, one, blocks, s);
+    case 4: return launch_mfma2_pm<CF, 4>(cfg, d_segs, nseg, seg0, one, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // Tilings: (threads, lanes per row, digit slots per lane, rows per lane,
@@ -1976,9 +2000,21 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
         // split rows in whole quads, at most 16; whole rows (W <= 64) of any
         // number of words, in groups of rows that are whole quads
         if (cs > 1 && (ww % 4 != 0 || ww / 4 > 16)) return false;
-        const int qp = 16 * ww / 4;
         cfg->cs = cs;
-        cfg->lds_bytes = std::max(mfma2_main_bytes(t.cf), mfma2_epi_bytes(t.cf, qp)) + tail;
+        // epilogue passes of 16 pm rows: as many (up to 64) as the four
+        // waves' lanes take at once (groups of rpg rows, qg quads each), as
+        // long as the LDS stays within two workgroups per CU or what 16 rows
+        // need
+        const int rpg = cs > 1 || ww % 4 == 0 ? 1 : (ww & 1) ? 4 : 2;
+        const int qg = rpg * ww / 4;
+        const int sweep = 4 * (64 / qg) * rpg;
+        auto lds_for = [&](int pm) {
+            return std::max(mfma2_main_bytes(t.cf), mfma2_epi_bytes(t.cf, 16 * pm * ww / 4, pm)) + tail;
+        };
+        const int lim = std::max(lds_for(1), 80 * 1024);
+        cfg->pm = sweep >= 64 ? 4 : sweep >= 32 ? 2 : 1;
+        while (cfg->pm > 1 && lds_for(cfg->pm) > lim) cfg->pm /= 2;
+        cfg->lds_bytes = lds_for(cfg->pm);
         return cfg->lds_bytes <= 160 * 1024;
     }
     const int chunks = t.pre ? 3 * nf * 32 * kMfmaPitch + 3 * cfg->tr * 16

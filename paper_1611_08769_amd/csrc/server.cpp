@@ -347,7 +347,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         std::vector<LinSeg> segs;
         int64_t n = 0, max_elems = 0;
     };
-    std::map<std::pair<int, int>, ProdGroup> pgroups;  // (tiling, workgroups per CU by LDS)
+    std::map<std::pair<int, int>, ProdGroup> pgroups;  // (8 tiling + epilogue pass rows / 16, workgroups per CU by LDS)
     std::vector<LinGroup> lgroups;
     double model_s = 0;
     // which requests advance this step (all, or least remaining work first
@@ -394,7 +394,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
         if (st < (int32_t)S.levels.size()) {
             const LevelWork& lw = S.levels[st];
             if (lw.prod_count) {
-                ProdGroup& G = pgroups[{pc.cfg.tiling, 160 * 1024 / std::max(pc.cfg.lds_bytes, 1)}];
+                ProdGroup& G = pgroups[{8 * pc.cfg.tiling + pc.cfg.pm, 160 * 1024 / std::max(pc.cfg.lds_bytes, 1)}];
                 if (G.segs.empty()) G.cfg = pc.cfg;
                 G.cfg.lds_bytes = std::max(G.cfg.lds_bytes, pc.cfg.lds_bytes);
                 G.segs.push_back(ProdSeg{pc.d_prods + lw.prod_begin, b, pc.geo, pc.cfg.nd, pc.cfg.wd,

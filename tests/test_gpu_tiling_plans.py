@@ -72,10 +72,15 @@ def _geos(f):
     # whole quads of words, which its epilogue takes two rows (an even
     # number of words: 2 elements of an odd number of limbs) or four rows
     # (an odd number: 3 elements of an odd number of limbs) at a time, a
-    # quad then ending one row and starting the next
+    # quad then ending one row and starting the next (short rows: passes of
+    # 32 or 64 rows, the last one partial where the tile is 32 or 96 rows)
     w2 = max(w for w in range(2, 16 * cf + 1, 4))
     wodd = max(w for w in range(3, 16 * cf + 1, 6))
     out = [(1, 128 * nf), (3, 32 * (4 * cf - 1)), (1, 32 * (w2 // 2)), (2, 32 * (wodd // 3))]
+    if cf == 1:
+        # rows of 5 words (Nct = 160): epilogue passes of 64 rows, the
+        # second row tile's 32 rows a partial pass
+        out.append((4, 32))
     # and the smallest geometry served in more than one column split
     best = None
     for n in (1, 2, 3):
