@@ -391,9 +391,10 @@ def run_batch(args, count=None):
 
 def small_plan_latency(plan, ct_in, ct_out, args, reps=20):
     """For a plan whose widest level needs at most two rounds of the GPU's
-    workgroup slots: the FFT in one persistent launch
-    (sfft_execute_persistent) against the launch per level, latency per FFT
-    from HIP events, and the outputs compared bit for bit."""
+    workgroup slots: the FFT as a launch per level, as those launches
+    replayed in one HIP graph (sfft_execute_graph) and in one persistent
+    launch (sfft_execute_persistent), latency per FFT from HIP events, and
+    the outputs of each compared bit for bit."""
     import torch
     from paper_1611_08769_amd import sfft as S
     if plan.info.max_level_products * 3 > 512:  # (128-row tiles; the small workloads have Nct <= 384)
@@ -412,16 +413,27 @@ def small_plan_latency(plan, ct_in, ct_out, args, reps=20):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
+    per_level = timed(lambda: plan.execute(ct_in, got))
+    same = bool(torch.equal(got, ref))
+    # the same launches replayed as one HIP graph (captured on a side stream)
+    got.zero_()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        graph = timed(lambda: plan.execute_graph(ct_in, got, stream=side))
+    torch.cuda.synchronize()
+    same = same and bool(torch.equal(got, ref))
     try:
-        per_level = timed(lambda: plan.execute(ct_in, got))
+        got.zero_()
         persistent = timed(lambda: plan.execute_persistent(ct_in, got))
     except S.SfftError as e:
-        return {"persistent": "not served: %s" % e}
+        return {"ms_per_fft_launch_per_level": per_level, "ms_per_fft_graph": graph, "outputs_identical": same,
+                "persistent": "not served: %s" % e}
     timeouts = S.sfft_plan_persistent_timeouts(plan.handle)
-    same = bool(torch.equal(got, ref))
-    print("[bench] small plan: launch per level %.3f ms, persistent %.3f ms per FFT (identical %s)" % (
-        per_level, persistent, same), file=sys.stderr, flush=True)
-    return {"ms_per_fft_launch_per_level": per_level, "ms_per_fft_persistent": persistent,
+    same = same and bool(torch.equal(got, ref))
+    print("[bench] small plan: launch per level %.3f ms, graph %.3f ms, persistent %.3f ms per FFT (identical %s)" % (
+        per_level, graph, persistent, same), file=sys.stderr, flush=True)
+    return {"ms_per_fft_launch_per_level": per_level, "ms_per_fft_graph": graph, "ms_per_fft_persistent": persistent,
             "outputs_identical": same, "barrier_timeouts": timeouts, "ffts": reps}
 
 

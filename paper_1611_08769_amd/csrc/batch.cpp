@@ -161,6 +161,7 @@ int sfft_batch_create(const sfft_plan* const* plans, const uint32_t* const* ct_i
                     ProdGroup& G = pgroups[{8 * pc.cfg.tiling + pc.cfg.pm, 160 * 1024 / std::max(pc.cfg.lds_bytes, 1)}];
                     if (G.segs.empty()) G.cfg = pc.cfg;
                     G.cfg.lds_bytes = std::max(G.cfg.lds_bytes, pc.cfg.lds_bytes);
+                    G.cfg.max_nct = std::max(G.cfg.max_nct, pc.geo.nct);
                     // first / first_block hold the item and tile counts until numbered below
                     G.segs.push_back(ProdSeg{pc.d_prods + lw.prod_begin, b, pc.geo, pc.cfg.nd, pc.cfg.wd,
                                              (uint32_t)lw.prod_count, (uint32_t)product_tiles(pc.geo, pc.cfg),

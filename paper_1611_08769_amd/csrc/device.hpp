@@ -43,6 +43,9 @@ struct ProdCfg {
     int pre;   // right operands transposed into rt by a pass before the launch (1: 128-row chunks, 2: 64-row)
     int cs;    // workgroups per row tile: column splits of whole elements (the 256-thread kernel), else 1
     int pm = 1;  // the 256-thread kernel's epilogue passes: 16 pm rows (1, 2 or 4)
+    // rows of the transposition pass's grid: the largest Nct among a
+    // launch's segments (0: the largest the tiling serves)
+    int max_nct = 0;
 };
 
 // Passed to the kernel by value.

@@ -1375,8 +1375,12 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
 // the chunk's 64 bits of each tile row of L; one barrier per chunk.  The
 // epilogue is that of k_product_mfma in passes of PR = 16 PM rows (PM > 1
 // where a row is so short that the four waves' lanes hold more than 16 rows'
-// quads at once: fewer, fuller passes).
-template <int CF, int PM>
+// quads at once: fewer, fuller passes).  DIRECT (small products, where the
+// latency of a level matters more than its rate): the workgroup reads R's
+// rows itself and transposes them into every chunk of the layout above, all
+// chunks held in LDS at once, so that no transposition pass runs before the
+// launch and the main loop waits on nothing.
+template <int CF, int PM, bool DIRECT>
 __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
                                                            ProdItem one, int lds_bytes)
 {
@@ -1420,13 +1424,14 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const gword* Rp = ctp(bufs, it.R);
     const int QP = PR * ww / 4;                     // quads of words of an epilogue pass
     const int OPB = (16 * QP + 1023) / 1024 * 1024;     // LDS bytes of one operand's quads
-    const int main_bytes = mfma2_main_bytes(CF);
+    const int nbuf = DIRECT ? nchunks : D;  // chunk buffers of the main loop
+    const int main_bytes = DIRECT ? nchunks * (UT * 1024 + TM * 8) : mfma2_main_bytes(CF);
     const int e_bytes = mfma2_epi_bytes(CF, QP, PM);
     int32_t* Pc = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) + (main_bytes > e_bytes ? main_bytes : e_bytes));
 
     // ---- main loop ----
     uint8_t* Rb = reinterpret_cast<uint8_t*>(lds);  // D chunks of the split's columns of R
-    uint8_t* Lb = Rb + D * UT * 1024;               // D chunks of L: 8 bytes (64 bits) per tile row
+    uint8_t* Lb = Rb + nbuf * UT * 1024;            // the chunks of L: 8 bytes (64 bits) per tile row
     const uint8_t* rsrc = sg.rt + (size_t)yl * rt_item_bytes(g);
     const uint8_t* Lbytes = (const uint8_t*)Lp;
     const int u0 = w0 / 4;  // the split's first unit (16 columns) of a chunk
@@ -1465,18 +1470,85 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const int arow8 = (64 * wr + (lane & 31)) * 8;  // A fragment f: + 256 f
     uint32_t pc[2] = {0u, 0u};
 
+    if constexpr (DIRECT) {
+        // every chunk's bits of L straight into LDS; R's rows read in blocks
+        // of 4 rows x 4 words (a word quad of the split; lanes along the
+        // row), each block transposed into 4 byte columns of 4 rows per word
+        // and stored, bytes xor 0x80, where the chunk layout puts them:
+        // column n of the split at 64 n, its 16-byte unit of rows 16 a ..
+        // 16 a + 15 at unit a ^ swz64(n).  Columns past the split and rows
+        // past the product are left unwritten: their sums are never used, and
+        // the bits of L for such rows are 0.
+        for (int c = 0; c < nchunks; c++) {
+            int row = row_base + 32 * wave + (lane >> 1);
+            row = row < nct ? row : nct - 1;
+            int word = 2 * c + (lane & 1);
+            word = word < W ? word : W - 1;
+            load_to_lds<4>(Lbytes + ((size_t)row * W + word) * 4, Lb + c * TM * 8 + wave * 256);
+        }
+        const int nwq = (ww + 3) / 4;
+        const int nblk = nchunks * 16 * nwq;
+        const bool vec = (W & 3) == 0;  // (the split starts on a multiple of 4 words)
+        for (int b0 = 0; b0 < nblk; b0 += 2 * THREADS) {
+            uint32_t rs[2][4][4];
 #pragma unroll
-    for (int c = 0; c < D - 1; c++)
-        if (c < nchunks) request(c);
+            for (int i = 0; i < 2; i++) {
+                const int bi = b0 + i * THREADS + tid;
+                const int cq = bi / nwq, wq = bi - cq * nwq;  // (row quad of the product, word quad)
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) {
+                    const int row = 4 * cq + rr;
+                    const bool ok = bi < nblk && row < nct;
+                    const gword* src = Rp + (size_t)(ok ? row : 0) * W + w0 + 4 * wq;
+                    if (ok && vec && 4 * wq + 4 <= ww) {
+                        const u32x4 x = *reinterpret_cast<const gu32x4*>(src);
+                        rs[i][rr][0] = x[0], rs[i][rr][1] = x[1], rs[i][rr][2] = x[2], rs[i][rr][3] = x[3];
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; u++) rs[i][rr][u] = ok && 4 * wq + u < ww ? src[u] : 0u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                const int bi = b0 + i * THREADS + tid;
+                const int cq = bi / nwq, wq = bi - cq * nwq;
+                if (bi < nblk && 4 * cq < nct) {
+                    const int c = cq >> 4, jq = cq & 15;  // chunk, row quad within it
+                    uint8_t* cb = Rb + c * UT * 1024;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const uint32_t blk[4] = {rs[i][0][u], rs[i][1][u], rs[i][2][u], rs[i][3][u]};
+                        uint32_t col[4];
+                        transpose4x4(blk, col);
+#pragma unroll
+                        for (int cc = 0; cc < 4; cc++) {
+                            const int n = 16 * wq + 4 * u + cc;
+                            *reinterpret_cast<uint32_t*>(cb + n * KC + 16 * ((jq >> 2) ^ swz64(n)) + 4 * (jq & 3)) =
+                                col[cc] ^ 0x80808080u;
+                        }
+                    }
+                }
+            }
+        }
+        wait_vmcnt<0>();
+        lds_barrier();
+    } else {
+#pragma unroll
+        for (int c = 0; c < D - 1; c++)
+            if (c < nchunks) request(c);
+    }
     for (int c = 0; c < nchunks; c++) {
-        // chunk c has landed once at most the requests of the chunks after it
-        // are outstanding (every chunk's are DR + 1 per wave)
-        const int later = nchunks - 1 - c < D - 2 ? nchunks - 1 - c : D - 2;
-        wait_vmcnt_upto<(D - 2) * (DR + 1), DR + 1>(later);
-        barrier_only();
-        if (c + D - 1 < nchunks) request(c + D - 1);
-        const uint8_t* Bc = Rb + (c % D) * UT * 1024;
-        const uint8_t* Lc = Lb + (c % D) * TM * 8;
+        if constexpr (!DIRECT) {
+            // chunk c has landed once at most the requests of the chunks after
+            // it are outstanding (every chunk's are DR + 1 per wave)
+            const int later = nchunks - 1 - c < D - 2 ? nchunks - 1 - c : D - 2;
+            wait_vmcnt_upto<(D - 2) * (DR + 1), DR + 1>(later);
+            barrier_only();
+            if (c + D - 1 < nchunks) request(c + D - 1);
+        }
+        const uint8_t* Bc = Rb + (DIRECT ? c : c % D) * UT * 1024;
+        const uint8_t* Lc = Lb + (DIRECT ? c : c % D) * TM * 8;
         const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
         uint32_t lw[2][2];
 #pragma unroll
@@ -1793,28 +1865,28 @@ hipError_t launch_mfma_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
     return hipGetLastError();
 }
 
-template <int CF, int PM>
+template <int CF, int PM, bool DIRECT>
 hipError_t launch_mfma2_pm(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
                            const ProdItem& one, int64_t blocks, hipStream_t s)
 {
-    static const hipError_t attr = hipFuncSetAttribute((const void*)k_product_mfma2<CF, PM>,
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_product_mfma2<CF, PM, DIRECT>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (attr != hipSuccess) return attr;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_product_mfma2<CF, PM>), dim3((unsigned)blocks), dim3(256), cfg.lds_bytes, s, d_segs, nseg,
-                       seg0, one, cfg.lds_bytes);
+    hipLaunchKernelGGL((k_product_mfma2<CF, PM, DIRECT>), dim3((unsigned)blocks), dim3(256), cfg.lds_bytes, s, d_segs,
+                       nseg, seg0, one, cfg.lds_bytes);
     return hipGetLastError();
 }
 
-template <int CF>
+template <int CF, bool DIRECT>
 hipError_t launch_mfma2_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, const ProdSeg& seg0,
                           const ProdItem& one, int64_t blocks, hipStream_t s)
 {
     switch (cfg.pm) {
-    case 1: return launch_mfma2_pm<CF, 1>(cfg, d_segs, nseg, seg0, one, blocks, s);
-    case 2: return launch_mfma2_pm<CF, 2>(cfg, d_segs, nseg, seg0, one, blocks, s);
-    case 4: return launch_mfma2_pm<CF, 4>(cfg, d_segs, nseg, seg0, one, blocks, s);
+    case 1: return launch_mfma2_pm<CF, 1, DIRECT>(cfg, d_segs, nseg, seg0, one, blocks, s);
+    case 2: return launch_mfma2_pm<CF, 2, DIRECT>(cfg, d_segs, nseg, seg0, one, blocks, s);
+    case 4: return launch_mfma2_pm<CF, 4, DIRECT>(cfg, d_segs, nseg, seg0, one, blocks, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1864,6 +1936,7 @@ constexpr MfmaTiling kMfmaTilings[] = {
     {4, 2, 2, true},  {4, 2, 3, true},  {4, 2, 4, true},
     {2, 2, 1, 2},     {2, 2, 2, 2},     {2, 2, 3, 2},      // 256 threads, 64-row chunks, <= 80 KB of LDS
     {2, 2, 4, 2},
+    {2, 2, 1, 3},     {2, 2, 2, 3},                        // the same, R transposed in the workgroup, all chunks in LDS
 };
 constexpr int kNumMfmaTilings = (int)(sizeof(kMfmaTilings) / sizeof(kMfmaTilings[0]));
 constexpr int kNumTilings = kNumLookupTilings + kNumMfmaTilings;
@@ -1876,7 +1949,8 @@ hipError_t dispatch_mfma(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
         return launch_mfma_t<kMfmaTilings[I].rg, kMfmaTilings[I].cgw, kMfmaTilings[I].cf,                 \
                              kMfmaTilings[I].pre == 1>(cfg, d_segs, nseg, seg0, one, blocks, s);
 #define MCASE2(I)                                                                                        \
-    if (cfg.tiling == kNumLookupTilings + I) return launch_mfma2_t<kMfmaTilings[I].cf>(cfg, d_segs, nseg, seg0, one, blocks, s);
+    if (cfg.tiling == kNumLookupTilings + I)                                                             \
+        return launch_mfma2_t<kMfmaTilings[I].cf, kMfmaTilings[I].pre == 3>(cfg, d_segs, nseg, seg0, one, blocks, s);
     MCASE(0)
     MCASE(1)
     MCASE(2)
@@ -1899,9 +1973,11 @@ hipError_t dispatch_mfma(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, co
     MCASE2(19)
     MCASE2(20)
     MCASE2(21)
+    MCASE2(22)
+    MCASE2(23)
 #undef MCASE
 #undef MCASE2
-    static_assert(kNumMfmaTilings == 22, "one MCASE per matrix-core tiling");
+    static_assert(kNumMfmaTilings == 24, "one MCASE per matrix-core tiling");
     return hipErrorInvalidValue;
 }
 
@@ -1964,12 +2040,12 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
 {
     const MfmaTiling& t = kMfmaTilings[ti - kNumLookupTilings];
     const int nf = (4 * g.W + 31) / 32;
-    if (t.pre != 2 && (nf + t.cgw - 1) / t.cgw != t.cf) return false;
+    if (t.pre < 2 && (nf + t.cgw - 1) / t.cgw != t.cf) return false;
     // the staging blocks of a chunk (32 row quads x ceil(W/4) word quads,
     // 8 x 8 per wave) fit the threads' blocks
     const int threads = t.rg * t.cgw * 64;
     const int spt = (kMfmaChunk / 4 * 2 * t.cgw * t.cf + threads - 1) / threads;
-    if (t.pre != 2 && 4 * ((g.W + 31) / 32) > spt * threads / 64) return false;
+    if (t.pre < 2 && 4 * ((g.W + 31) / 32) > spt * threads / 64) return false;
     *cfg = ProdCfg{};
     cfg->tiling = ti;
     cfg->mfma = true;
@@ -1978,6 +2054,7 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
     cfg->cgw = t.cgw;
     cfg->cf = t.cf;
     cfg->pre = t.pre;
+    cfg->max_nct = g.nct;
     cfg->tr = 64 * t.rg;
     cfg->nd = (g.k + kDigitBits - 1) / kDigitBits;
     cfg->wd = g.n1 * cfg->nd;
@@ -1988,7 +2065,7 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
     // (the 256-thread kernel: three 64-row chunks of R and of the bits of L,
     // or its epilogue's passes of 16 rows)
     const int tail = cfg->tr * 4 + 16;  // popcounts, a flag
-    if (t.pre == 2) {
+    if (t.pre >= 2) {
         // column splits of whole elements (mfma2_eps), each filling more than
         // 2 (CF - 1) of the tile's 2 CF fragments
         const int eps = mfma2_eps(g, t.cf);
@@ -2008,8 +2085,11 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
         const int rpg = cs > 1 || ww % 4 == 0 ? 1 : (ww & 1) ? 4 : 2;
         const int qg = rpg * ww / 4;
         const int sweep = 4 * (64 / qg) * rpg;
+        // (pre 3: every 64-row chunk of R and of the bits of L at once)
+        const int main_bytes =
+            t.pre == 3 ? (g.nct + 63) / 64 * (4 * t.cf * 1024 + cfg->tr * 8) : mfma2_main_bytes(t.cf);
         auto lds_for = [&](int pm) {
-            return std::max(mfma2_main_bytes(t.cf), mfma2_epi_bytes(t.cf, 16 * pm * ww / 4, pm)) + tail;
+            return std::max(main_bytes, mfma2_epi_bytes(t.cf, 16 * pm * ww / 4, pm)) + tail;
         };
         const int lim = std::max(lds_for(1), 80 * 1024);
         cfg->pm = sweep >= 64 ? 4 : sweep >= 32 ? 2 : 1;
@@ -2105,9 +2185,10 @@ hipError_t launch_rtrans_t(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, 
     if (attr != hipSuccess) return attr;
     if (items <= 0) return hipSuccess;
     if (items > 0x7FFFFFFF) return hipErrorInvalidValue;
-    // chunks of the widest row the tiling serves: Nct = 32 W <= 256 CG CF,
-    // or, split into whole elements, rows of up to 12 fragments (W <= 96)
-    const int max_nct = cfg.pre == 2 ? 32 * 96 : 256 * cfg.cgw * cfg.cf;
+    // chunks of the launch's largest Nct, else of the widest row the tiling
+    // serves: Nct = 32 W <= 256 CG CF, or, split into whole elements, rows
+    // of up to 12 fragments (W <= 96)
+    const int max_nct = cfg.max_nct > 0 ? cfg.max_nct : cfg.pre == 2 ? 32 * 96 : 256 * cfg.cgw * cfg.cf;
     const unsigned chunks = (unsigned)((max_nct + KC - 1) / KC);
     hipLaunchKernelGGL(k_rtrans<KC>, dim3((unsigned)items, chunks), dim3(kRtransThreads), kMaxChunkBytes, s, d_segs,
                        nseg, seg0, one);
@@ -2126,7 +2207,7 @@ hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, 
                            int64_t blocks, int64_t items, hipStream_t s, hipEvent_t mark)
 {
     ProdItem none{};
-    if (cfg.mfma && cfg.pre) {
+    if (cfg.mfma && (cfg.pre == 1 || cfg.pre == 2)) {
         hipError_t e = launch_rtrans(cfg, d_segs, nseg, seg0, none, blocks > 0 ? items : 0, s);
         if (e != hipSuccess) return e;
     }
@@ -2139,7 +2220,7 @@ hipError_t launch_products(const ProdCfg& cfg, const ProdSeg* d_segs, int nseg, 
 
 bool inkernel_twin(const Geo& g, ProdCfg* cfg)
 {
-    if (!cfg->mfma || !cfg->pre) return true;
+    if (!cfg->mfma || cfg->pre == 0 || cfg->pre == 3) return true;
     for (int i = 0; i < kNumMfmaTilings; i++) {
         const MfmaTiling& t = kMfmaTilings[i];
         if (!t.pre && t.rg == cfg->rg && t.cgw == cfg->cgw && t.cf == cfg->cf)
@@ -2153,7 +2234,7 @@ hipError_t launch_product_one(const Bufs& b, const Geo& g, const ProdCfg& cfg, c
 {
     ProdSeg seg = single_segment(b, g, cfg);
     seg.rt = rt;
-    if (cfg.mfma && cfg.pre) {
+    if (cfg.mfma && (cfg.pre == 1 || cfg.pre == 2)) {
         hipError_t e = launch_rtrans(cfg, nullptr, 1, seg, item, 1, s);
         if (e != hipSuccess) return e;
     }

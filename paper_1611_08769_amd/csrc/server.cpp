@@ -397,6 +397,7 @@ int sfft_server_step(sfft_server* sv, void* hip_stream, int32_t* pending)
                 ProdGroup& G = pgroups[{8 * pc.cfg.tiling + pc.cfg.pm, 160 * 1024 / std::max(pc.cfg.lds_bytes, 1)}];
                 if (G.segs.empty()) G.cfg = pc.cfg;
                 G.cfg.lds_bytes = std::max(G.cfg.lds_bytes, pc.cfg.lds_bytes);
+                G.cfg.max_nct = std::max(G.cfg.max_nct, pc.geo.nct);
                 G.segs.push_back(ProdSeg{pc.d_prods + lw.prod_begin, b, pc.geo, pc.cfg.nd, pc.cfg.wd,
                                          (uint32_t)lw.prod_count, (uint32_t)product_tiles(pc.geo, pc.cfg),
                                          sv->dry ? nullptr : sv->arena_dev + r->ws_off + pc.slot_bytes()});

@@ -90,6 +90,10 @@ def _geos(f):
                 best = (n, k)
     if best:
         out.append(best)
+    if pre == 3:
+        # the tilings that transpose R in the workgroup hold all of its
+        # chunks (64 rows of 4 cf KB, and 1 KB of bits of L) in 160 KB
+        out = [(n, k) for n, k in out if -(-(n + 1) * k // 64) * (4 * cf + 1) * 1024 + 528 <= 160 * 1024]
     return out
 
 

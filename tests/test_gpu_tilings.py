@@ -33,7 +33,7 @@ def _cases():
         f = S.sfft_tiling_describe(ti)
         if f[6] == 0:
             out.append((ti, GEOS[f[1] * f[2]]))
-        elif f[4] == 2:
+        elif f[4] >= 2:
             # the 256-thread kernel serves rows of whole quads of words only
             # (its other geometries: tests/test_gpu_tiling_plans.py)
             out.append((ti, _mfma_geos(f[2] * f[3])[0]))
