@@ -1390,7 +1390,6 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     constexpr int DR = (UT + NW - 1) / NW;  // of them per wave
     constexpr int SP = mfma_sum_pitch(CG * CF);
     constexpr int D = mfma2_depth(CF);      // chunks in flight (D - 1 ahead of the one multiplied)
-    (void)lds_bytes;
     extern __shared__ uint32_t lds[];
     const uint32_t v = xcd_order(blockIdx.x, gridDim.x);
     ProdSeg sg0 = seg0;
@@ -1427,8 +1426,62 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const int nbuf = DIRECT ? nchunks : D;  // chunk buffers of the main loop
     const int main_bytes = DIRECT ? nchunks * (UT * 1024 + TM * 8) : mfma2_main_bytes(CF);
     const int e_bytes = mfma2_epi_bytes(CF, QP, PM);
-    int32_t* Pc = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) + (main_bytes > e_bytes ? main_bytes : e_bytes));
 
+    // ---- the epilogue's operands: L, R and the item's distinct extra operands ----
+    const int nout = it.nout;
+    int eso[kMaxOut];
+    gword* Do[kMaxOut];
+    const gword* opsrc[2 + kMaxE] = {Lp, Rp};
+    int32_t eref[kMaxE];
+    int nops = 2;
+#pragma unroll
+    for (int o = 0; o < kMaxOut; o++) {
+        Do[o] = o < nout ? ctp(bufs, it.dst[o]) : nullptr;
+        eso[o] = -1;
+        if (o < nout && it.E[o] >= 0) {
+#pragma unroll
+            for (int q = 0; q < kMaxE; q++)
+                if (q + 2 < nops && eref[q] == it.E[o]) eso[o] = q;
+            if (eso[o] < 0 && nops < 2 + kMaxE) {  // (the plan keeps at most kMaxE per item)
+                eref[nops - 2] = it.E[o];
+                opsrc[nops] = ctp(bufs, it.E[o]);
+                eso[o] = nops - 2;
+                ++nops;
+            }
+        }
+    }
+    // rows per group of the epilogue's lane mapping (below) and whole quads
+    // per row
+    const int rpg = cs > 1 || (ww & 3) == 0 ? 1 : (ww & 1) ? 4 : 2;
+    const int qr = ww / 4;
+    // the epilogue's column sums and operand buffers: over the chunk buffers,
+    // or (early) past them, where the workgroup's LDS holds both, so that
+    // the first pass's operands load while the main loop runs
+    const bool early = DIRECT && main_bytes + e_bytes + TM * 4 + 16 <= lds_bytes;
+    int32_t* S = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) + (early ? main_bytes : 0));
+    uint8_t* OPS = reinterpret_cast<uint8_t*>(S + PR * SP);  // 2 buffers x (2 + kMaxE) operands
+    int32_t* Pc = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) +
+                                             (early ? main_bytes + e_bytes : main_bytes > e_bytes ? main_bytes : e_bytes));
+    // rows of the tile (Nct is a multiple of 32: 32, 64, 96 or 128) and of
+    // each pass (every pass but the last holds PR, a multiple of 16)
+    const int trows = nct - row_base < TM ? nct - row_base : TM;
+    auto pass_rows = [&](int p) { return trows - PR * p < PR ? trows - PR * p : PR; };
+    // every operand's quads of pass p into buffer b, 64 quads per wave
+    // instruction (lanes past the pass's rows re-read its last quad and land
+    // in the buffer's padding)
+    auto stage_ops = [&](int p, int b) {
+        const int qv = pass_rows(p) * ww / 4;
+        for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < qv; blk += NW) {
+            const int j = 64 * blk + lane < qv ? 64 * blk + lane : qv - 1;
+            const int rl = rpg > 1 ? 0 : j / qr;
+            const size_t off = rpg > 1 ? (size_t)(row_base + PR * p) * W + 4 * j
+                                       : (size_t)(row_base + PR * p + rl) * W + w0 + 4 * (j - rl * qr);
+#pragma unroll
+            for (int s = 0; s < 2 + kMaxE; s++)
+                if (s < nops)
+                    load_to_lds<16>((const uint8_t*)(opsrc[s] + off), OPS + (b * (2 + kMaxE) + s) * OPB + 1024 * blk);
+        }
+    };
     // ---- main loop ----
     uint8_t* Rb = reinterpret_cast<uint8_t*>(lds);  // D chunks of the split's columns of R
     uint8_t* Lb = Rb + nbuf * UT * 1024;            // the chunks of L: 8 bytes (64 bits) per tile row
@@ -1533,6 +1586,7 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
         }
         wait_vmcnt<0>();
         lds_barrier();
+        if (early) stage_ops(0, 0);
     } else {
 #pragma unroll
         for (int c = 0; c < D - 1; c++)
@@ -1590,28 +1644,6 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     }
 
     // ---- epilogue: passes of PR = 16 rows (see k_product_mfma) ----
-    const int nout = it.nout;
-    int eso[kMaxOut];
-    gword* Do[kMaxOut];
-    const gword* opsrc[2 + kMaxE] = {Lp, Rp};
-    int32_t eref[kMaxE];
-    int nops = 2;
-#pragma unroll
-    for (int o = 0; o < kMaxOut; o++) {
-        Do[o] = o < nout ? ctp(bufs, it.dst[o]) : nullptr;
-        eso[o] = -1;
-        if (o < nout && it.E[o] >= 0) {
-#pragma unroll
-            for (int q = 0; q < kMaxE; q++)
-                if (q + 2 < nops && eref[q] == it.E[o]) eso[o] = q;
-            if (eso[o] < 0 && nops < 2 + kMaxE) {  // (the plan keeps at most kMaxE per item)
-                eref[nops - 2] = it.E[o];
-                opsrc[nops] = ctp(bufs, it.E[o]);
-                eso[o] = nops - 2;
-                ++nops;
-            }
-        }
-    }
     // Each wave takes whole groups of rows of a pass, the qg quads of 4
     // words of a group in consecutive lanes, so the carries between quads
     // pass from lane to lane, with no LDS and no barrier.  A group is one
@@ -1620,8 +1652,6 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     // contiguous in memory, and go in groups of 2 (an even number of words)
     // or 4 rows that are, a quad then possibly ending one row and starting
     // the next.
-    const int rpg = cs > 1 || (ww & 3) == 0 ? 1 : (ww & 1) ? 4 : 2;
-    const int qr = ww / 4;        // whole quads per row (rpg = 1)
     const int qg = rpg * ww / 4;  // quads per group
     const int gpw = 64 / qg;      // groups per wave
     const int rw_g = wave * gpw + lane / qg;  // this lane's group of a pass
@@ -1633,33 +1663,11 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     const int rw_e = rw_w / kw, rw_l = rw_w - rw_e * kw;
     const int rw_j = rw_g * qg + rw_jj;  // the quad's place in the staged operands
     const int rw_off = rpg > 1 ? 4 * rw_j : rw_rl * W + rw_w;  // its words from the pass's first row
-    int32_t* S = reinterpret_cast<int32_t*>(lds);
-    uint8_t* OPS = reinterpret_cast<uint8_t*>(S + PR * SP);  // 2 buffers x (2 + kMaxE) operands
-    // rows of the tile (Nct is a multiple of 32: 32, 64, 96 or 128) and of
-    // each pass (every pass but the last holds PR, a multiple of 16)
-    const int trows = nct - row_base < TM ? nct - row_base : TM;
-    auto pass_rows = [&](int p) { return trows - PR * p < PR ? trows - PR * p : PR; };
-    // every operand's quads of pass p into buffer b, 64 quads per wave
-    // instruction (lanes past the pass's rows re-read its last quad and land
-    // in the buffer's padding)
-    auto stage_ops = [&](int p, int b) {
-        const int qv = pass_rows(p) * ww / 4;
-        for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < qv; blk += NW) {
-            const int j = 64 * blk + lane < qv ? 64 * blk + lane : qv - 1;
-            const int rl = rpg > 1 ? 0 : j / qr;
-            const size_t off = rpg > 1 ? (size_t)(row_base + PR * p) * W + 4 * j
-                                       : (size_t)(row_base + PR * p + rl) * W + w0 + 4 * (j - rl * qr);
-#pragma unroll
-            for (int s = 0; s < 2 + kMaxE; s++)
-                if (s < nops)
-                    load_to_lds<16>((const uint8_t*)(opsrc[s] + off), OPS + (b * (2 + kMaxE) + s) * OPB + 1024 * blk);
-        }
-    };
     // store instructions this wave issues per pass: one per output, where
     // any of its lanes holds a quad (the count waited for is that of a full
     // pass: only the last may be partial)
     const int nst = wave * gpw * rpg < PR ? nout : 0;
-    stage_ops(0, 0);
+    if (!early) stage_ops(0, 0);
     const int npass = (trows + PR - 1) / PR;
     for (int p = 0; p < npass; p++) {
         const int prow = row_base + PR * p;  // first row of the pass
@@ -2095,6 +2103,10 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
         cfg->pm = sweep >= 64 ? 4 : sweep >= 32 ? 2 : 1;
         while (cfg->pm > 1 && lds_for(cfg->pm) > lim) cfg->pm /= 2;
         cfg->lds_bytes = lds_for(cfg->pm);
+        // pre 3: the epilogue's buffers past the chunks where both fit, so
+        // that its first pass's operands load during the main loop
+        const int both = main_bytes + mfma2_epi_bytes(t.cf, 16 * cfg->pm * ww / 4, cfg->pm) + tail;
+        if (t.pre == 3 && both <= 160 * 1024) cfg->lds_bytes = both;
         return cfg->lds_bytes <= 160 * 1024;
     }
     const int chunks = t.pre ? 3 * nf * 32 * kMfmaPitch + 3 * cfg->tr * 16
