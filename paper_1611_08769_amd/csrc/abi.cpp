@@ -627,7 +627,7 @@ int sfft_execute_persistent(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t
     const Geo& g = plan->geo;
     ProdCfg cfg{};
     if (!persistent_config(g, &cfg))
-        return fail(SFFT_EUNSUPPORTED, "no persistent kernel for rows of this width (more than 8 fragments)");
+        return fail(SFFT_EUNSUPPORTED, "no persistent kernel for this geometry (rows of more than 8 fragments)");
     const Schedule& S = plan->sched;
     const int64_t nl = (int64_t)S.levels.size();
     if (!plan->d_persist) {
@@ -675,9 +675,10 @@ int sfft_execute_persistent(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t
     int64_t widest = 1;
     for (const LevelWork& lw : S.levels) {
         widest = std::max<int64_t>(widest, lw.prod_count * a.tiles);
-        for (const auto& pr : lw.lin) widest = std::max<int64_t>(widest, (pr.second * g.nct * g.n1 + 511) / 512);
+        for (const auto& pr : lw.lin)
+            widest = std::max<int64_t>(widest, (pr.second * g.nct * g.n1 + cfg.threads - 1) / cfg.threads);
     }
-    widest = std::max<int64_t>(widest, ((int64_t)S.final_lins.size() * g.nct * g.n1 + 511) / 512);
+    widest = std::max<int64_t>(widest, ((int64_t)S.final_lins.size() * g.nct * g.n1 + cfg.threads - 1) / cfg.threads);
     const hipError_t e = launch_plan_persistent(a, cfg, widest, (hipStream_t)hip_stream);
     return e == hipSuccess ? SFFT_OK : hip_fail(e, "persistent launch");
 }

@@ -1381,8 +1381,8 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
 // chunks held in LDS at once, so that no transposition pass runs before the
 // launch and the main loop waits on nothing.
 template <int CF, int PM, bool DIRECT>
-__global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
-                                                           ProdItem one, int lds_bytes)
+__device__ __forceinline__ void product_mfma2_block(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
+                                                    ProdItem one, int lds_bytes, uint32_t v)
 {
     constexpr int RG = 2, CG = 2, NW = RG * CG, THREADS = 64 * NW, TM = 64 * RG, KC = 64;
     constexpr int PR = 16 * PM;             // rows per epilogue pass
@@ -1391,7 +1391,6 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
     constexpr int SP = mfma_sum_pitch(CG * CF);
     constexpr int D = mfma2_depth(CF);      // chunks in flight (D - 1 ahead of the one multiplied)
     extern __shared__ uint32_t lds[];
-    const uint32_t v = xcd_order(blockIdx.x, gridDim.x);
     ProdSeg sg0 = seg0;
     if (nseg > 1) sg0 = segs[find_segment(segs, nseg, v, [](const ProdSeg& q) { return q.first_block; })];
     // the segment and the item are the same for the whole workgroup: scalar
@@ -1805,6 +1804,13 @@ __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restr
             }
         }
     }
+}
+
+template <int CF, int PM, bool DIRECT>
+__global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
+                                                           ProdItem one, int lds_bytes)
+{
+    product_mfma2_block<CF, PM, DIRECT>(segs, nseg, seg0, one, lds_bytes, xcd_order(blockIdx.x, gridDim.x));
 }
 
 // One (row, element) of one linear item: dst = cX X + cY Y + cG G, limb by
@@ -2307,14 +2313,15 @@ __global__ void k_zero_words(uint32_t* p, int n)
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
-template <int RG, int CG, int CF>
-__global__ void __launch_bounds__(RG * CG * 64) k_plan_persistent(PersistArgs a, int lds_bytes)
+// The level loop of a persistent plan: each level's product tiles (tile(seg,
+// v) runs tile v of the level's items), then its linear passes, with a grid
+// barrier after each; the output forms last.
+template <int THREADS, typename Tile>
+__device__ __forceinline__ void plan_persistent(const PersistArgs& a, Tile tile)
 {
-    constexpr int THREADS = RG * CG * 64;
     const uint32_t nb = gridDim.x;
     const int64_t per = (int64_t)a.geo.nct * a.geo.n1;  // linear tasks per item
     const int64_t t0 = (int64_t)blockIdx.x * THREADS + threadIdx.x, tstep = (int64_t)nb * THREADS;
-    const ProdItem none{};
     uint32_t gen = 0;
     for (int L = 0; L < a.nlevels; L++) {
         const int64_t pb = a.lv[4 * L], pc = a.lv[4 * L + 1], p0 = a.lv[4 * L + 2], np = a.lv[4 * L + 3];
@@ -2322,7 +2329,7 @@ __global__ void __launch_bounds__(RG * CG * 64) k_plan_persistent(PersistArgs a,
             const ProdSeg seg{a.prods + pb, a.bufs, a.geo, a.nd, a.wd, 0, 0, nullptr};
             const uint32_t blocks = (uint32_t)pc * a.tiles;
             for (uint32_t v = blockIdx.x; v < blocks; v += nb) {
-                product_mfma_block<RG, CG, CF, false>(nullptr, 1, seg, none, lds_bytes, v);
+                tile(seg, v);
                 __syncthreads();  // the next tile reuses the LDS
             }
             grid_barrier(a.bar, ++gen * nb);
@@ -2337,16 +2344,35 @@ __global__ void __launch_bounds__(RG * CG * 64) k_plan_persistent(PersistArgs a,
     for (int64_t t = t0; t < tasks; t += tstep) linear_task(a.finals[t / per], a.bufs, a.geo, (int)(t % per));
 }
 
-template <int CF>
-hipError_t launch_persistent_t(const PersistArgs& a, const ProdCfg& cfg, int64_t max_blocks, hipStream_t s)
+// products on the 512-thread body with in-kernel transposition
+template <int RG, int CG, int CF>
+__global__ void __launch_bounds__(RG * CG * 64) k_plan_persistent(PersistArgs a, int lds_bytes)
 {
-    const void* fn = (const void*)k_plan_persistent<2, 4, CF>;
-    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (attr != hipSuccess) return attr;
+    const ProdItem none{};
+    plan_persistent<RG * CG * 64>(a, [&](const ProdSeg& seg, uint32_t v) {
+        product_mfma_block<RG, CG, CF, false>(nullptr, 1, seg, none, lds_bytes, v);
+    });
+}
+
+// products on the 256-thread body that transposes R in the workgroup
+template <int CF, int PM>
+__global__ void __launch_bounds__(256, 2) k_plan_persistent2(PersistArgs a, int lds_bytes)
+{
+    const ProdItem none{};
+    plan_persistent<256>(a, [&](const ProdSeg& seg, uint32_t v) {
+        product_mfma2_block<CF, PM, true>(nullptr, 1, seg, none, lds_bytes, v);
+    });
+}
+
+// One cooperative launch of fn (threads per workgroup) with as many
+// workgroups as are resident at once, at most max_blocks.
+hipError_t launch_cooperative(const void* fn, int threads, const PersistArgs& a, const ProdCfg& cfg,
+                              int64_t max_blocks, hipStream_t s)
+{
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, cfg.lds_bytes);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, cfg.lds_bytes);
     if (e != hipSuccess) return e;
     // every workgroup resident at once (the barriers wait for all of them)
     const int64_t resident = (int64_t)cus * per_cu;
@@ -2358,14 +2384,38 @@ hipError_t launch_persistent_t(const PersistArgs& a, const ProdCfg& cfg, int64_t
     PersistArgs args = a;
     int lds = cfg.lds_bytes;
     void* params[] = {(void*)&args, (void*)&lds};
-    return hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(512), params, (unsigned)cfg.lds_bytes, s);
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(threads), params, (unsigned)cfg.lds_bytes, s);
+}
+
+template <int CF>
+hipError_t launch_persistent_t(const PersistArgs& a, const ProdCfg& cfg, int64_t max_blocks, hipStream_t s)
+{
+    const void* fn = (const void*)k_plan_persistent<2, 4, CF>;
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    return launch_cooperative(fn, 512, a, cfg, max_blocks, s);
+}
+
+template <int CF, int PM>
+hipError_t launch_persistent2_t(const PersistArgs& a, const ProdCfg& cfg, int64_t max_blocks, hipStream_t s)
+{
+    const void* fn = (const void*)k_plan_persistent2<CF, PM>;
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    return launch_cooperative(fn, 256, a, cfg, max_blocks, s);
 }
 }  // namespace
 
 bool persistent_config(const Geo& g, ProdCfg* cfg)
 {
-    // the 512-thread matrix-core kernel with in-kernel transposition,
-    // 2 x 4 waves of 1 or 2 fragments: rows of up to 8 fragments
+    // the 256-thread kernel that transposes R in the workgroup (every chunk
+    // in LDS), 1 or 2 fragments per wave; else the 512-thread kernel with
+    // in-kernel transposition, 2 x 4 waves of 1 or 2 fragments: rows of up to
+    // 8 fragments
+    for (int i = 0; i < kNumMfmaTilings; i++) {
+        const MfmaTiling& t = kMfmaTilings[i];
+        if (t.pre == 3 && tiling_config(g, kNumLookupTilings + i, cfg)) return true;
+    }
     for (int i = 0; i < kNumMfmaTilings; i++) {
         const MfmaTiling& t = kMfmaTilings[i];
         if (t.pre == 0 && t.rg == 2 && t.cgw == 4 && t.cf <= 2 && tiling_config(g, kNumLookupTilings + i, cfg))
@@ -2376,6 +2426,18 @@ bool persistent_config(const Geo& g, ProdCfg* cfg)
 
 hipError_t launch_plan_persistent(const PersistArgs& a, const ProdCfg& cfg, int64_t max_blocks, hipStream_t s)
 {
+    if (cfg.pre == 3) {
+        const int k = 4 * (cfg.cf - 1) + (cfg.pm == 4 ? 2 : cfg.pm == 2 ? 1 : 0);
+        switch (k) {
+        case 0: return launch_persistent2_t<1, 1>(a, cfg, max_blocks, s);
+        case 1: return launch_persistent2_t<1, 2>(a, cfg, max_blocks, s);
+        case 2: return launch_persistent2_t<1, 4>(a, cfg, max_blocks, s);
+        case 4: return launch_persistent2_t<2, 1>(a, cfg, max_blocks, s);
+        case 5: return launch_persistent2_t<2, 2>(a, cfg, max_blocks, s);
+        case 6: return launch_persistent2_t<2, 4>(a, cfg, max_blocks, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     return cfg.cf == 1 ? launch_persistent_t<1>(a, cfg, max_blocks, s) : launch_persistent_t<2>(a, cfg, max_blocks, s);
 }
 

@@ -38,6 +38,25 @@ def test_persistent_matches_per_level_launches(shape):
     plan.close()
 
 
+def test_persistent_512_thread_body():
+    # n = 1, k = 640: Nct = 1280 rows of 160 bytes, too many chunks for the
+    # LDS of the 256-thread body, so the 512-thread body runs the products
+    print("[gpu-case] persistent 512-thread body", flush=True)
+    sys.stdout.flush()
+    p = S.params(1, 640)
+    words = np.random.default_rng(5).integers(-128, 128, 8).astype(np.int64)
+    keys = api.keygen(p, 17)
+    ct_in = api.encrypt_words(keys, words, 8, seed=17)
+    plan = api.Plan(1, 4, 8, 4, True, p)
+    want = plan.execute(ct_in).clone()
+    got = torch.zeros_like(want)
+    plan.execute_persistent(ct_in, got)
+    torch.cuda.synchronize()
+    assert S.sfft_plan_persistent_timeouts(plan.handle) == 0
+    assert torch.equal(got, want)
+    plan.close()
+
+
 def test_persistent_refuses_wide_rows():
     # n = 3, k = 704: rows of 352 bytes, 11 fragments
     p = S.params(3, 704)
