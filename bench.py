@@ -198,6 +198,17 @@ def _mix_expect(kind):
         return json.load(fh)[kind]
 
 
+def _kernel_source_sha() -> str:
+    """SHA-256 of the product kernels' source (kernels.hip, then the kernel
+    body it includes): traffic figures taken with rocprofv3 hold only for it."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "mfma2_body.inc"):
+        with open(os.path.join(ROOT, "paper_1611_08769_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _words_sha(words) -> str:
     import hashlib
     return hashlib.sha256(np.ascontiguousarray(np.asarray(words), dtype="<i8").tobytes()).hexdigest()
@@ -570,7 +581,6 @@ def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_c
     """HBM bytes per k_product launch (encryption launches excluded) from the
     rocprofv3 counter CSVs of one bench step, each counter scaled by what it
     reads for the 1 GiB copy; written next to the kernel trace summaries."""
-    import hashlib
     prod = "void sfft::(anonymous namespace)::k_product"
     fetch = [v for v, n in zip(_counter_rows(fetch_csv, prod), _kernel_names(fetch_csv, prod)) if _is_gate_product(n)]
     write = [v for v, n in zip(_counter_rows(write_csv, prod), _kernel_names(write_csv, prod)) if _is_gate_product(n)]
@@ -583,12 +593,11 @@ def traffic_summary(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_c
     gib = float(1 << 30)
     fetch_scale, write_scale = gib / (cf * 1024), gib / (cw * 1024)
     fk, wk = sum(fetch) / len(fetch), sum(write) / len(write)
-    src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "kernels.hip")
     names = [n for n in _kernel_names(fetch_csv, prod) if _is_gate_product(n)][-levels:]
     out = {
         "workload": workload,
         "kernel": sorted(set(n.replace("void sfft::(anonymous namespace)::", "").split("(")[0] for n in names)),
-        "kernels_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "kernel_source_sha256": _kernel_source_sha(),
         "launches": len(fetch),
         "fetch_kib_per_launch": fk,
         "write_kib_per_launch": wk,
@@ -1498,10 +1507,8 @@ def main():
     # command, valid only for the kernel source they were taken with
     tpath = os.path.join(ROOT, "profiles", "traffic_k_product_%s.json" % args.workload)
     if os.path.exists(tpath):
-        import hashlib
         tr = json.load(open(tpath))
-        src = os.path.join(ROOT, "paper_1611_08769_amd", "csrc", "kernels.hip")
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() == tr.get("kernels_hip_sha256"):
+        if _kernel_source_sha() == tr.get("kernel_source_sha256"):
             out["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
             # algorithmic bytes: each ciphertext a product item reads (L, R and
             # extra operands) or writes, once

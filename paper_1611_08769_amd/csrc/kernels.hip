@@ -1381,437 +1381,24 @@ __global__ void __launch_bounds__(RG * CG * 64) k_product_mfma(const ProdSeg* __
 // chunks held in LDS at once, so that no transposition pass runs before the
 // launch and the main loop waits on nothing.
 template <int CF, int PM, bool DIRECT>
-__device__ __forceinline__ void product_mfma2_block(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
-                                                    ProdItem one, int lds_bytes, uint32_t v)
-{
-    constexpr int RG = 2, CG = 2, NW = RG * CG, THREADS = 64 * NW, TM = 64 * RG, KC = 64;
-    constexpr int PR = 16 * PM;             // rows per epilogue pass
-    constexpr int UT = 2 * CG * CF;         // 1 KB units of a chunk a tile reads
-    constexpr int DR = (UT + NW - 1) / NW;  // of them per wave
-    constexpr int SP = mfma_sum_pitch(CG * CF);
-    constexpr int D = mfma2_depth(CF);      // chunks in flight (D - 1 ahead of the one multiplied)
-    extern __shared__ uint32_t lds[];
-    ProdSeg sg0 = seg0;
-    if (nseg > 1) sg0 = segs[find_segment(segs, nseg, v, [](const ProdSeg& q) { return q.first_block; })];
-    // the segment and the item are the same for the whole workgroup: scalar
-    // registers keep the vector ones for the accumulators
-    const ProdSeg sg = wave_uniform(sg0);
-    const Geo g = sg.geo;
-    const int W = g.W, nct = g.nct, kw = g.kw, kb = g.k;
-    const int eps = mfma2_eps(g, CF);  // (> 0: the host launches only geometries it serves)
-    const int cs = (g.n1 + eps - 1) / eps;
-    const uint32_t tiles = ((uint32_t)nct + TM - 1) / TM * cs;
-    const uint32_t local = v - sg.first_block;
-    const uint32_t yl = local / tiles;
-    const int rem = (int)(local % tiles);
-    const int row_base = rem / cs * TM;
-    const int split = rem % cs;
-    const bool whole = cs == 1;
-    const int e0 = split * eps;
-    const int ww = whole ? W : (g.n1 - e0 < eps ? g.n1 - e0 : eps) * kw;  // words of the split per row
-    const int w0 = e0 * kw;                                                 // its first word (a multiple of 4)
-    const Bufs bufs = sg.bufs;
-    const ProdItem it = wave_uniform(sg.items ? load_global(sg.items + yl) : one);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave % RG, wc = wave / RG;
-    const int half = lane >> 5;
-    const int NF = (4 * W + 31) / 32;
-    const int gsz = NF * 32 * KC;  // bytes per chunk of R in global memory
-    const int nchunks = (nct + KC - 1) / KC;
-    const gword* Lp = ctp(bufs, it.L);
-    const gword* Rp = ctp(bufs, it.R);
-    const int QP = PR * ww / 4;                     // quads of words of an epilogue pass
-    const int OPB = (16 * QP + 1023) / 1024 * 1024;     // LDS bytes of one operand's quads
-    const int nbuf = DIRECT ? nchunks : D;  // chunk buffers of the main loop
-    const int main_bytes = DIRECT ? nchunks * (UT * 1024 + TM * 8) : mfma2_main_bytes(CF);
-    const int e_bytes = mfma2_epi_bytes(CF, QP, PM);
-
-    // ---- the epilogue's operands: L, R and the item's distinct extra operands ----
-    const int nout = it.nout;
-    int eso[kMaxOut];
-    gword* Do[kMaxOut];
-    const gword* opsrc[2 + kMaxE] = {Lp, Rp};
-    int32_t eref[kMaxE];
-    int nops = 2;
-#pragma unroll
-    for (int o = 0; o < kMaxOut; o++) {
-        Do[o] = o < nout ? ctp(bufs, it.dst[o]) : nullptr;
-        eso[o] = -1;
-        if (o < nout && it.E[o] >= 0) {
-#pragma unroll
-            for (int q = 0; q < kMaxE; q++)
-                if (q + 2 < nops && eref[q] == it.E[o]) eso[o] = q;
-            if (eso[o] < 0 && nops < 2 + kMaxE) {  // (the plan keeps at most kMaxE per item)
-                eref[nops - 2] = it.E[o];
-                opsrc[nops] = ctp(bufs, it.E[o]);
-                eso[o] = nops - 2;
-                ++nops;
-            }
-        }
-    }
-    // rows per group of the epilogue's lane mapping (below) and whole quads
-    // per row
-    const int rpg = cs > 1 || (ww & 3) == 0 ? 1 : (ww & 1) ? 4 : 2;
-    const int qr = ww / 4;
-    // the epilogue's column sums and operand buffers: over the chunk buffers,
-    // or (early) past them, where the workgroup's LDS holds both, so that
-    // the first pass's operands load while the main loop runs
-    const bool early = DIRECT && main_bytes + e_bytes + TM * 4 + 16 <= lds_bytes;
-    int32_t* S = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) + (early ? main_bytes : 0));
-    uint8_t* OPS = reinterpret_cast<uint8_t*>(S + PR * SP);  // 2 buffers x (2 + kMaxE) operands
-    int32_t* Pc = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(lds) +
-                                             (early ? main_bytes + e_bytes : main_bytes > e_bytes ? main_bytes : e_bytes));
-    // rows of the tile (Nct is a multiple of 32: 32, 64, 96 or 128) and of
-    // each pass (every pass but the last holds PR, a multiple of 16)
-    const int trows = nct - row_base < TM ? nct - row_base : TM;
-    auto pass_rows = [&](int p) { return trows - PR * p < PR ? trows - PR * p : PR; };
-    // every operand's quads of pass p into buffer b, 64 quads per wave
-    // instruction (lanes past the pass's rows re-read its last quad and land
-    // in the buffer's padding)
-    auto stage_ops = [&](int p, int b) {
-        const int qv = pass_rows(p) * ww / 4;
-        for (int blk = __builtin_amdgcn_readfirstlane(wave); 64 * blk < qv; blk += NW) {
-            const int j = 64 * blk + lane < qv ? 64 * blk + lane : qv - 1;
-            const int rl = rpg > 1 ? 0 : j / qr;
-            const size_t off = rpg > 1 ? (size_t)(row_base + PR * p) * W + 4 * j
-                                       : (size_t)(row_base + PR * p + rl) * W + w0 + 4 * (j - rl * qr);
-#pragma unroll
-            for (int s = 0; s < 2 + kMaxE; s++)
-                if (s < nops)
-                    load_to_lds<16>((const uint8_t*)(opsrc[s] + off), OPS + (b * (2 + kMaxE) + s) * OPB + 1024 * blk);
-        }
-    };
-    // ---- main loop ----
-    uint8_t* Rb = reinterpret_cast<uint8_t*>(lds);  // D chunks of the split's columns of R
-    uint8_t* Lb = Rb + nbuf * UT * 1024;            // the chunks of L: 8 bytes (64 bits) per tile row
-    const uint8_t* rsrc = sg.rt + (size_t)yl * rt_item_bytes(g);
-    const uint8_t* Lbytes = (const uint8_t*)Lp;
-    const int u0 = w0 / 4;  // the split's first unit (16 columns) of a chunk
-    // Every wave issues DR + 1 requests per chunk (units past the row repeat
-    // its last unit, rows past the product its last row, words past the row
-    // its last word: all in bounds), so that the wait is a constant count.
-    auto request = [&](int c) {
-        const int buf = c % D;
-        const uint8_t* src = rsrc + (size_t)c * gsz;
-        uint8_t* dst = Rb + buf * UT * 1024;
-#pragma unroll
-        for (int t = 0; t < DR; t++) {
-            const int lu = wave + NW * t < UT ? wave + NW * t : UT - 1;
-            const int su = u0 + lu < 2 * NF ? u0 + lu : 2 * NF - 1;
-            load_to_lds<16>(src + (size_t)su * 1024 + lane * 16, dst + lu * 1024);
-        }
-        int row = row_base + 32 * wave + (lane >> 1);  // rows 32 wave .. 32 wave + 31 of the tile, 2 words each
-        row = row < nct ? row : nct - 1;
-        int word = 2 * c + (lane & 1);
-        word = word < W ? word : W - 1;
-        load_to_lds<4>(Lbytes + ((size_t)row * W + word) * 4, Lb + buf * TM * 8 + wave * 256);
-    };
-    i32x16 acc[2][CF];
-#pragma unroll
-    for (int f = 0; f < 2; f++)
-#pragma unroll
-        for (int q = 0; q < CF; q++)
-#pragma unroll
-            for (int r = 0; r < 16; r++) acc[f][q][r] = 0;
-    // B fragment q of this lane: the split's column 32 (wc CF + q) + lane %
-    // 32, at bcol + 2048 q; its unit permutation swz64 is the same for every
-    // q (the split starts on a multiple of 16 columns).  Columns past the
-    // split are read from in-bounds LDS and their sums never used.
-    const int bcol = (32 * wc * CF + (lane & 31)) * KC;
-    const int bswz = swz64(lane & 31);
-    const int arow8 = (64 * wr + (lane & 31)) * 8;  // A fragment f: + 256 f
-    uint32_t pc[2] = {0u, 0u};
-
-    if constexpr (DIRECT) {
-        // every chunk's bits of L straight into LDS; R's rows read in blocks
-        // of 4 rows x 4 words (a word quad of the split; lanes along the
-        // row), each block transposed into 4 byte columns of 4 rows per word
-        // and stored, bytes xor 0x80, where the chunk layout puts them:
-        // column n of the split at 64 n, its 16-byte unit of rows 16 a ..
-        // 16 a + 15 at unit a ^ swz64(n).  Columns past the split and rows
-        // past the product are left unwritten: their sums are never used, and
-        // the bits of L for such rows are 0.
-        for (int c = 0; c < nchunks; c++) {
-            int row = row_base + 32 * wave + (lane >> 1);
-            row = row < nct ? row : nct - 1;
-            int word = 2 * c + (lane & 1);
-            word = word < W ? word : W - 1;
-            load_to_lds<4>(Lbytes + ((size_t)row * W + word) * 4, Lb + c * TM * 8 + wave * 256);
-        }
-        const int nwq = (ww + 3) / 4;
-        const int nblk = nchunks * 16 * nwq;
-        const bool vec = (W & 3) == 0;  // (the split starts on a multiple of 4 words)
-        for (int b0 = 0; b0 < nblk; b0 += 2 * THREADS) {
-            uint32_t rs[2][4][4];
-#pragma unroll
-            for (int i = 0; i < 2; i++) {
-                const int bi = b0 + i * THREADS + tid;
-                const int cq = bi / nwq, wq = bi - cq * nwq;  // (row quad of the product, word quad)
-#pragma unroll
-                for (int rr = 0; rr < 4; rr++) {
-                    const int row = 4 * cq + rr;
-                    const bool ok = bi < nblk && row < nct;
-                    const gword* src = Rp + (size_t)(ok ? row : 0) * W + w0 + 4 * wq;
-                    if (ok && vec && 4 * wq + 4 <= ww) {
-                        const u32x4 x = *reinterpret_cast<const gu32x4*>(src);
-                        rs[i][rr][0] = x[0], rs[i][rr][1] = x[1], rs[i][rr][2] = x[2], rs[i][rr][3] = x[3];
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < 4; u++) rs[i][rr][u] = ok && 4 * wq + u < ww ? src[u] : 0u;
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 2; i++) {
-                const int bi = b0 + i * THREADS + tid;
-                const int cq = bi / nwq, wq = bi - cq * nwq;
-                if (bi < nblk && 4 * cq < nct) {
-                    const int c = cq >> 4, jq = cq & 15;  // chunk, row quad within it
-                    uint8_t* cb = Rb + c * UT * 1024;
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const uint32_t blk[4] = {rs[i][0][u], rs[i][1][u], rs[i][2][u], rs[i][3][u]};
-                        uint32_t col[4];
-                        transpose4x4(blk, col);
-#pragma unroll
-                        for (int cc = 0; cc < 4; cc++) {
-                            const int n = 16 * wq + 4 * u + cc;
-                            *reinterpret_cast<uint32_t*>(cb + n * KC + 16 * ((jq >> 2) ^ swz64(n)) + 4 * (jq & 3)) =
-                                col[cc] ^ 0x80808080u;
-                        }
-                    }
-                }
-            }
-        }
-        wait_vmcnt<0>();
-        lds_barrier();
-        if (early) stage_ops(0, 0);
-    } else {
-#pragma unroll
-        for (int c = 0; c < D - 1; c++)
-            if (c < nchunks) request(c);
-    }
-    for (int c = 0; c < nchunks; c++) {
-        if constexpr (!DIRECT) {
-            // chunk c has landed once at most the requests of the chunks after
-            // it are outstanding (every chunk's are DR + 1 per wave)
-            const int later = nchunks - 1 - c < D - 2 ? nchunks - 1 - c : D - 2;
-            wait_vmcnt_upto<(D - 2) * (DR + 1), DR + 1>(later);
-            barrier_only();
-            if (c + D - 1 < nchunks) request(c + D - 1);
-        }
-        const uint8_t* Bc = Rb + (DIRECT ? c : c % D) * UT * 1024;
-        const uint8_t* Lc = Lb + (DIRECT ? c : c % D) * TM * 8;
-        const int rows_c = nct - KC * c < KC ? nct - KC * c : KC;
-        uint32_t lw[2][2];
-#pragma unroll
-        for (int f = 0; f < 2; f++) {
-            // (two 4-byte reads: an 8-byte read here makes the compiler wait
-            // for every outstanding load into LDS, the chunks in flight too)
-            lw[f][0] = *reinterpret_cast<const uint32_t*>(Lc + arow8 + 256 * f);
-            lw[f][1] = *reinterpret_cast<const uint32_t*>(Lc + arow8 + 256 * f + 4);
-        }
-#pragma unroll
-        for (int st = 0; st < KC / 32; st++) {
-            const uint8_t* bp = Bc + bcol + 16 * ((2 * st + half) ^ bswz);
-            i32x4 Bx[CF];
-#pragma unroll
-            for (int q = 0; q < CF; q++) Bx[q] = *reinterpret_cast<const i32x4*>(bp + 2048 * q);
-            i32x4 Af[2];
-#pragma unroll
-            for (int f = 0; f < 2; f++) {
-                // bits of L past the product (rows of R past Nct) count as 0
-                const uint32_t w = 32 * st < rows_c ? lw[f][st] : 0u;
-                const uint32_t b16 = (w >> (16 * half)) & 0xFFFFu;
-                pc[f] += __builtin_popcount(b16);
-                Af[f] = spread_bits(b16);
-            }
-#pragma unroll
-            for (int q = 0; q < CF; q++) {
-                acc[0][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[0], Bx[q], acc[0][q], 0, 0, 0);
-                acc[1][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[1], Bx[q], acc[1][q], 0, 0, 0);
-            }
-        }
-    }
-    // every wave done with the chunk buffers before the epilogue reuses them;
-    // the popcount of a row is the sum over its two half-lanes
-    lds_barrier();
-#pragma unroll
-    for (int f = 0; f < 2; f++) {
-        const uint32_t tot = pc[f] + __shfl_xor(pc[f], 32);
-        if (wc == 0 && half == 0) Pc[64 * wr + 32 * f + (lane & 31)] = (int32_t)tot;
-    }
-
-    // ---- epilogue: passes of PR = 16 rows (see k_product_mfma) ----
-    // Each wave takes whole groups of rows of a pass, the qg quads of 4
-    // words of a group in consecutive lanes, so the carries between quads
-    // pass from lane to lane, with no LDS and no barrier.  A group is one
-    // row where the (split) row is whole quads (at most 16 of them: the host
-    // serves nothing else when a row is split); whole rows that are not are
-    // contiguous in memory, and go in groups of 2 (an even number of words)
-    // or 4 rows that are, a quad then possibly ending one row and starting
-    // the next.
-    const int qg = rpg * ww / 4;  // quads per group
-    const int gpw = 64 / qg;      // groups per wave
-    const int rw_g = wave * gpw + lane / qg;  // this lane's group of a pass
-    const int rw_jj = lane % qg;             // and quad of the group
-    const bool rw_in = lane < gpw * qg;  // (and its group's rows in the pass: rw_g rpg < the pass's rows)
-    const int rw_rr = 4 * rw_jj / ww;              // row of the group where the quad starts
-    const int rw_rl = rw_g * rpg + rw_rr;          // and of the pass
-    const int rw_w = w0 + 4 * rw_jj - rw_rr * ww;  // its first word
-    const int rw_e = rw_w / kw, rw_l = rw_w - rw_e * kw;
-    const int rw_j = rw_g * qg + rw_jj;  // the quad's place in the staged operands
-    const int rw_off = rpg > 1 ? 4 * rw_j : rw_rl * W + rw_w;  // its words from the pass's first row
-    // store instructions this wave issues per pass: one per output, where
-    // any of its lanes holds a quad (the count waited for is that of a full
-    // pass: only the last may be partial)
-    const int nst = wave * gpw * rpg < PR ? nout : 0;
-    if (!early) stage_ops(0, 0);
-    const int npass = (trows + PR - 1) / PR;
-    for (int p = 0; p < npass; p++) {
-        const int prow = row_base + PR * p;  // first row of the pass
-        const int b = p & 1;
-        const bool rw_ok = rw_in && rw_g * rpg < pass_rows(p);
-        // this pass's operands in LDS: each wave waits for its own loads of
-        // them, issued before its stores of the pass before, which need not
-        // be done; the pass before is done with S and the other buffer
-        wait_vmcnt_upto<kMaxOut, 1>(p > 0 ? nst : 0);
-        lds_barrier();
-        if (p + 1 < npass) stage_ops(p + 1, b ^ 1);
-        // 1. column sums of the pass's rows: tile rows 16 u .. 16 u + 15,
-        // u = 4 wr + 2 f + h, are rows 16 h .. 16 h + 15 of fragment f of
-        // row group wr, i.e. its registers r = 8 h .. 8 h + 7, and rows
-        // 16 (u % PM) .. of pass u / PM
-#pragma unroll
-        for (int f = 0; f < 2; f++) {
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int u = 4 * wr + 2 * f + h;
-                if (u / PM != p) continue;
-#pragma unroll
-                for (int q = 0; q < CF; q++) {
-                    const int col = 32 * (wc * CF + q) + (lane & 31);  // of the split
-                    if (col < 4 * ww) {
-                        const int cu = 4 * mfma_sum_unit(col >> 2) + (col & 3);
-#pragma unroll
-                        for (int r = 8 * h; r < 8 * h + 8; r++)
-                            S[(16 * (u % PM) + 8 * ((r >> 2) - 2 * h) + 4 * half + (r & 3)) * SP + cu] = acc[f][q][r];
-                    }
-                }
-            }
-        }
-        lds_barrier();
-        const uint8_t* ob = OPS + b * (2 + kMaxE) * OPB;
-        {
-            // 2. this lane's quad (row rw_rl, words rw_w ..): limbs of every
-            // output rippled within the quad, kept in registers
-            u32x4 oq[kMaxOut];
-            int32_t cq[kMaxOut];
-            int qm = 0;
-#pragma unroll
-            for (int o = 0; o < kMaxOut; o++) oq[o] = u32x4{0u, 0u, 0u, 0u}, cq[o] = 0;
-            if (rw_ok) {
-                const int j = rw_j;
-                int w = rw_w, e = rw_e, l = rw_l, rl = rw_rl;
-                int row = prow + rl;
-                int br = row / kb, tr = row - br * kb;
-                int cpc = 128 * Pc[PR * p + rl];  // each byte sum misses 128 per set bit of the row of L
-                const u32x4 lv = *reinterpret_cast<const u32x4*>(ob + 16 * j);
-                const u32x4 rv = *reinterpret_cast<const u32x4*>(ob + OPB + 16 * j);
-                u32x4 ev[kMaxE];
-#pragma unroll
-                for (int q = 0; q < kMaxE; q++)
-                    ev[q] = q + 2 < nops ? *reinterpret_cast<const u32x4*>(ob + (2 + q) * OPB + 16 * j)
-                                         : u32x4{0u, 0u, 0u, 0u};
-                int64_t cy[kMaxOut];
-#pragma unroll
-                for (int o = 0; o < kMaxOut; o++) cy[o] = 0;
-#pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    if (u > 0) {
-                        ++w, ++l;
-                        if (l == kw) l = 0, ++e;
-                        if (w - w0 == ww) {  // the next row of the group
-                            w = w0, e = 0, l = 0, ++rl, ++row;
-                            br = row / kb, tr = row - br * kb;
-                            cpc = 128 * Pc[PR * p + rl];
-                        }
-                    }
-                    if (l == 0) {
-                        qm |= 1 << u;
-#pragma unroll
-                        for (int o = 0; o < kMaxOut; o++) cy[o] = 0;
-                    }
-                    const i32x4 s4 = *reinterpret_cast<const i32x4*>(S + rl * SP + 4 * mfma_sum_unit(w - w0));
-                    const int s0 = s4[0] + cpc, s1 = s4[1] + cpc, s2 = s4[2] + cpc, s3 = s4[3] + cpc;
-                    const uint32_t Gv = (e == br && l == (tr >> 5)) ? (1u << (tr & 31)) : 0u;
-                    const int Ll = lv[u] & 0xFFFF, Lh = lv[u] >> 16, Rl = rv[u] & 0xFFFF, Rh = rv[u] >> 16;
-                    const int Gl = Gv & 0xFFFF, Gh = Gv >> 16;
-#pragma unroll
-                    for (int o = 0; o < kMaxOut; o++) {
-                        if (o < nout) {
-                            // P's limb = s0 + 2^8 s1 + 2^16 (s2 + 2^8 s3) with the byte sums
-                            // s below 2^20, so every partial sum stays below 2^31
-                            const int cP = it.cP[o], cL = it.cL[o], cR = it.cR[o], cG = it.cG[o];
-                            int A = __mul24(cP, s0) + (__mul24(cP, s1) << 8) + __mul24(cL, Ll) + __mul24(cR, Rl) +
-                                    __mul24(cG, Gl);
-                            int B = __mul24(cP, s2) + (__mul24(cP, s3) << 8) + __mul24(cL, Lh) + __mul24(cR, Rh) +
-                                    __mul24(cG, Gh);
-                            if (eso[o] >= 0) {
-                                const uint32_t x = eso[o] == 0 ? ev[0][u] : ev[kMaxE - 1][u];
-                                A += __mul24((int)it.cE[o], (int)(x & 0xFFFF));
-                                B += __mul24((int)it.cE[o], (int)(x >> 16));
-                            }
-                            const int64_t vv = cy[o] + (int64_t)A + (int64_t)B * 65536;
-                            oq[o][u] = (uint32_t)vv;
-                            cy[o] = vv >> 32;
-                        }
-                    }
-                }
-                if (l == kw - 1) qm |= 1 << 5;
-#pragma unroll
-                for (int o = 0; o < kMaxOut; o++) cq[o] = (qm >> 5) ? 0 : (int32_t)cy[o];  // |carry| < 2^15
-            }
-            // 3. each quad takes the carry out of the lane before it (the
-            // quad before it in the row) unless it starts an element; until
-            // no carry leaves a quad
-            for (;;) {
-                int more_here = 0;
-#pragma unroll
-                for (int o = 0; o < kMaxOut; o++) {
-                    if (o >= nout) continue;
-                    int32_t c = __shfl_up(cq[o], 1);
-                    if (!rw_ok || (qm & 1)) c = 0;
-                    int64_t cc = c;
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        if (u > 0 && (qm >> u & 1)) cc = 0;  // a new element: the carry stops
-                        const int64_t vv = (int64_t)oq[o][u] + cc;
-                        oq[o][u] = (uint32_t)vv;
-                        cc = vv >> 32;
-                    }
-                    cq[o] = (qm >> 5) ? 0 : (int32_t)cc;
-                    more_here |= cq[o] != 0;
-                }
-                if (!__any(more_here)) break;
-            }
-            // 4. outputs
-            if (rw_ok) {
-                const size_t off = (size_t)prow * W + rw_off;
-#pragma unroll
-                for (int o = 0; o < kMaxOut; o++)
-                    if (o < nout) *reinterpret_cast<gu32x4*>(Do[o] + off) = oq[o];
-            }
-        }
-    }
-}
-
-template <int CF, int PM, bool DIRECT>
 __global__ void __launch_bounds__(256, 2) k_product_mfma2(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
                                                            ProdItem one, int lds_bytes)
 {
-    product_mfma2_block<CF, PM, DIRECT>(segs, nseg, seg0, one, lds_bytes, xcd_order(blockIdx.x, gridDim.x));
+#define SFFT_MFMA2_TILE xcd_order(blockIdx.x, gridDim.x)
+#include "mfma2_body.inc"
+#undef SFFT_MFMA2_TILE
 }
+
+// The same body for tile `tile` of a segment (the persistent plan kernel).
+template <int CF, int PM, bool DIRECT>
+__device__ __forceinline__ void product_mfma2_block(const ProdSeg* __restrict__ segs, int nseg, ProdSeg seg0,
+                                                    ProdItem one, int lds_bytes, uint32_t tile)
+{
+#define SFFT_MFMA2_TILE tile
+#include "mfma2_body.inc"
+#undef SFFT_MFMA2_TILE
+}
+
 
 // One (row, element) of one linear item: dst = cX X + cY Y + cG G, limb by
 // limb with the carry.
@@ -2109,10 +1696,6 @@ bool mfma_config(const Geo& g, int ti, ProdCfg* cfg)
         cfg->pm = sweep >= 64 ? 4 : sweep >= 32 ? 2 : 1;
         while (cfg->pm > 1 && lds_for(cfg->pm) > lim) cfg->pm /= 2;
         cfg->lds_bytes = lds_for(cfg->pm);
-        // pre 3: the epilogue's buffers past the chunks where both fit, so
-        // that its first pass's operands load during the main loop
-        const int both = main_bytes + mfma2_epi_bytes(t.cf, 16 * cfg->pm * ww / 4, cfg->pm) + tail;
-        if (t.pre == 3 && both <= 160 * 1024) cfg->lds_bytes = both;
         return cfg->lds_bytes <= 160 * 1024;
     }
     const int chunks = t.pre ? 3 * nf * 32 * kMfmaPitch + 3 * cfg->tr * 16
