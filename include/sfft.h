@@ -179,9 +179,11 @@ int sfft_execute_graph(sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_
 int sfft_execute_noalloc(const sfft_plan* plan, const uint32_t* ct_in_dev, uint32_t* ct_out_dev, void* hip_stream);
 /* sfft_execute in one persistent launch, for small plans whose levels are
  * too small to fill the GPU (a kernel boundary per level then costs about as
- * much as the level): a cooperative launch of the 512-thread matrix-core
- * kernel with in-kernel transposition, as many workgroups as are resident at
- * once (at most what the widest level uses), loops over every level's
+ * much as the level): a cooperative launch of the 256-thread matrix-core
+ * kernel that transposes R in the workgroup (where its LDS holds every chunk
+ * of R: Nct up to 512 or 1024 by fragments per wave), else of the 512-thread
+ * one with in-kernel transposition; as many workgroups as are resident at
+ * once (at most what the widest level uses) loop over every level's
  * product tiles and linear items with a grid-wide barrier between levels
  * (agent-scope release and acquire around a counter).  The barrier's waits
  * are bounded (about 0.1 s): one that runs out sets a flag
@@ -287,9 +289,12 @@ int sfft_tiling_count(void);
 /* fields[7]: fields[6] = 0 for a lookup tiling, then fields[0..5] = threads,
  * lanes per row, digit slots per lane, rows per lane, pipeline depth, groups
  * per chunk; fields[6] = 1 for a matrix-core tiling, then fields[0..4] =
- * threads, row groups, column groups, fragments per wave, and 1 where the
- * right operands are transposed into the workspace by a pass before each
- * launch (0 where each workgroup transposes its chunks itself); fields[5] = 0.
+ * threads, row groups, column groups, fragments per wave, and how the right
+ * operands reach the kernel: 0 each workgroup transposes its chunks itself
+ * (512-thread layout), 1 a pass before each launch transposes them into the
+ * workspace in 128-row chunks, 2 the same in 64-row chunks (256-thread
+ * kernel), 3 the 256-thread kernel's workgroup transposes all its chunks into
+ * LDS itself (small products); fields[5] = 0.
  * SFFT_EINVAL for an unknown tiling. */
 int sfft_tiling_describe(int32_t tiling, int32_t* fields);
 /* Record a tiling for params' geometry (-1: back to the default).
