@@ -1755,11 +1755,14 @@ bool product_config(const Geo& g, ProdCfg* cfg)
         auto it = g_tuned.find({g.k, g.n1});
         if (it != g_tuned.end() && tiling_config(g, it->second, cfg)) return true;
     }
-    // matrix cores first: the 256-thread kernel with two workgroups per CU
-    // where it serves the row (whole quads of words per split row), then
-    // rows of up to 2 fragments on 256 threads, 3..8 on 256-row tiles with
-    // the transposition pass, 9..12 on four column groups transposing
-    // in-kernel
+    // matrix cores first: products of at most 512 rows (levels too small to
+    // fill the GPU, bound by a workgroup's latency) on the 256-thread kernel
+    // that transposes R in the workgroup; else the 256-thread kernel with
+    // two workgroups per CU where it serves the row (whole quads of words per
+    // split row), then rows of up to 2 fragments on 256 threads, 3..8 on
+    // 256-row tiles with the transposition pass, 9..12 on four column groups
+    // transposing in-kernel
+    if (g.nct <= 512 && tiling_config(g, kNumLookupTilings + 22, cfg)) return true;
     static const int order[] = {18, 19, 20, 21, 3, 15, 16, 17, 4, 0, 1, 2};
     for (int i : order)
         if (tiling_config(g, kNumLookupTilings + i, cfg)) return true;
